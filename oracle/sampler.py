@@ -1,0 +1,340 @@
+"""Per-pixel Poisson star counts and pixel fluxes (oracle side).
+
+Sec. 2.1: for every pixel of an Nim x Nim image the number of stars at each
+weighted isochrone point is an independent Poisson draw with the point's weight
+as its mean; the stars' fluxes are reddened by dust, dimmed by the distance
+modulus and summed into the pixel.  Sec. 2.2 (dust models E1-E3): a thin dust
+screen with log E(B-V) fixed (E1) or log-normal per pixel (E2/E3), covering a
+fraction F_dust of the stars; distance enters as the distance modulus mu_d.
+
+How a Poisson count is drawn is not fixed by the paper.  The rule here:
+
+* C1, lambda < 10 -- inversion in the integer domain.  p_0 = exp(-lambda),
+  p_k = p_{k-1} * lambda / k, F_k = F_{k-1} + p_k (FP64, in that order);
+  T_k = floor(F_k * 2^32).  K is the first k with T_k >= 2^32, or 63.  With u a
+  32-bit word, n = #{k < K : T_k <= u}, i.e. the least k with u < T_k.  Exact to
+  2^-32 per outcome.
+* C2, lambda >= 10 -- transformed rejection with squeeze (Hormann 1993, "The
+  transformed rejection method for generating Poisson random variables"),
+  decisions taken in IEEE FP32 operation by operation, with a logarithm written
+  here from the atanh series and ln k! from an FP64-built table (k < 256) or a
+  Stirling series.  Both sides of the parity test take the same FP32 steps.
+* C3, dust split -- each of the n stars is reddened independently with
+  probability F_dust (reading of "fraction of stars that are reddened").  For
+  F_dust = 1/2 one random bit per star, otherwise one 32-bit word per star
+  compared with floor(F * 2^32).
+
+Random words come from Philox4x32-10 keyed by the seed with counters
+(pixel, entry // 4, TAG_MAIN, 0) word entry % 4 (inversion),
+(pixel, entry, TAG_PTRS, j) (rejection attempts 2j and 2j+1),
+(pixel, entry // 4, TAG_SPLIT, 0) word entry % 4 and (pixel, entry, TAG_SPLIT_X, j)
+(dust split), and (pixel, 0, TAG_DUST, 0) (per-pixel dust).
+
+Pins: threshold tables against the Poisson pmf to 2^-32; the PTRS sampler by
+chi-square and moment tests; the project logarithm against np.log; the split
+by exact enumeration; pixel flux mean sum(lambda f) and variance
+sum(lambda f^2) (the surface-brightness-fluctuation signal); distance and dust
+invariants (tests/test_oracle_sampler.py).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .rng import (TAG_DUST, TAG_MAIN, TAG_PTRS, TAG_SPLIT, TAG_SPLIT_X, box_muller_f64,
+                  philox4x32_10, u01_open_f32)
+
+LAM_SWITCH = 10.0
+KMAX = 63
+TWO32 = 2 ** 32
+F32 = np.float32
+
+
+# ---------------------------------------------------------------------------
+# C1: inversion thresholds
+# ---------------------------------------------------------------------------
+
+
+def inversion_thresholds(lam: float) -> list[int]:
+    """Thresholds T_0..T_{K-1} (all < 2^32) of the integer inversion rule."""
+    lam = float(lam)
+    p = math.exp(-lam)
+    F = p
+    out = []
+    for k in range(KMAX):
+        if k > 0:
+            p = p * lam / k
+            F = F + p
+        t = math.floor(F * 4294967296.0)
+        if t >= TWO32:
+            break
+        out.append(int(t))
+    return out
+
+
+def count_from_thresholds(u: np.ndarray, thr: list[int]) -> np.ndarray:
+    """n = #{k : T_k <= u}."""
+    u = np.asarray(u, dtype=np.uint64)
+    n = np.zeros(u.shape, dtype=np.uint32)
+    for t in thr:
+        n += (u >= np.uint64(t)).astype(np.uint32)
+    return n
+
+
+# ---------------------------------------------------------------------------
+# C2: transformed rejection in FP32
+# ---------------------------------------------------------------------------
+
+LN2_HI = F32(0.693145751953125)
+LN2_LO = F32(1.428606765330187e-06)
+SQRT2_F32 = F32(1.41421353816986083984375)
+LN_COEF = [F32(2.0 / (2 * j + 1)) for j in range(6)]   # 2, 2/3, 2/5, 2/7, 2/9, 2/11
+
+
+def ln32(x):
+    """Natural log in FP32 from frexp and the series ln m = 2 atanh((m-1)/(m+1)).
+
+    x must be positive, finite and normal.  Every step is one IEEE FP32 operation."""
+    x = np.asarray(x, dtype=np.float32)
+    bits = x.view(np.uint32)
+    e = ((bits >> np.uint32(23)) & np.uint32(0xFF)).astype(np.int32) - 127
+    m = ((bits & np.uint32(0x007FFFFF)) | np.uint32(0x3F800000)).view(np.float32)
+    big = m > SQRT2_F32
+    m = np.where(big, m * F32(0.5), m).astype(np.float32)
+    e = e + big.astype(np.int32)
+    s = (m - F32(1.0)) / (m + F32(1.0))
+    z = s * s
+    P = LN_COEF[5]
+    for c in (LN_COEF[4], LN_COEF[3], LN_COEF[2], LN_COEF[1], LN_COEF[0]):
+        P = P * z + c
+    ef = e.astype(np.float32)
+    return ef * LN2_HI + (ef * LN2_LO + s * P)
+
+
+def lnfact_table() -> np.ndarray:
+    """ln k! for k < 256: FP64 running sum of ln j, rounded to FP32."""
+    t = np.zeros(256, dtype=np.float64)
+    acc = 0.0
+    for k in range(2, 256):
+        acc = acc + math.log(k)
+        t[k] = acc
+    return t.astype(np.float32)
+
+
+_LNFACT = lnfact_table()
+HALF_LN_2PI = F32(0.9189385332046727)
+INV12 = F32(1.0 / 12.0)
+INV360 = F32(1.0 / 360.0)
+
+
+def lnfact32(kf: np.ndarray) -> np.ndarray:
+    """ln k! in FP32: table below 256, Stirling series with x = k + 1 above."""
+    kf = np.asarray(kf, dtype=np.float32)
+    small = kf < F32(256.0)
+    ki = np.clip(kf, 0, 255).astype(np.int64)
+    x = kf + F32(1.0)
+    xs = np.where(small, F32(300.0), x).astype(np.float32)   # keep ln32 away from the table range
+    lx = ln32(xs)
+    t = (xs - F32(0.5)) * lx
+    t = t - xs
+    t = t + HALF_LN_2PI
+    r = F32(1.0) / xs
+    t = t + r * INV12
+    r3 = (r * r) * r
+    t = t - r3 * INV360
+    return np.where(small, _LNFACT[ki], t).astype(np.float32)
+
+
+def ptrs_constants(lam: float) -> dict:
+    """Per-entry constants, computed in FP64 and rounded to FP32."""
+    lam = float(lam)
+    slam = math.sqrt(lam)
+    b = 0.931 + 2.53 * slam
+    a = -0.059 + 0.02483 * b
+    inv_alpha = 1.1239 + 1.1328 / (b - 3.4)
+    vr = 0.9277 - 3.6224 / (b - 2.0)
+    return dict(mu=F32(lam), lnmu=F32(math.log(lam)), b=F32(b), a=F32(a), twoa=F32(2.0 * a),
+                lninva=F32(math.log(inv_alpha)), vr=F32(vr))
+
+
+def ptrs_draw(c: dict, seed: int, px: np.ndarray, entry: int, max_attempts: int = 64):
+    """Transformed-rejection Poisson draw for each pixel in `px` (entry fixed).
+
+    Attempt j uses words (2(j%2), 2(j%2)+1) of Philox(pixel, entry, TAG_PTRS, j//2).
+    Returns (counts, attempts_used)."""
+    npx = px.shape[0]
+    out = np.zeros(npx, dtype=np.int64)
+    done = np.zeros(npx, dtype=bool)
+    used = np.zeros(npx, dtype=np.int32)
+    words = None
+    for j in range(max_attempts):
+        if j % 2 == 0:
+            words = philox4x32_10(px, entry, TAG_PTRS, j // 2, seed)
+        u = u01_open_f32(words[2 * (j % 2)])
+        V = u01_open_f32(words[2 * (j % 2) + 1])
+        U = u - F32(0.5)
+        us = F32(0.5) - np.abs(U)
+        t = c["twoa"] / us
+        t = t + c["b"]
+        t = t * U
+        t = t + c["mu"]
+        t = t + F32(0.43)
+        kf = np.floor(t).astype(np.float32)
+        fast = (us >= F32(0.07)) & (V <= c["vr"])
+        rej = (kf < F32(0.0)) | ((us < F32(0.013)) & (V > us))
+        q = c["a"] / (us * us)
+        q = q + c["b"]
+        lhs = (ln32(V) + c["lninva"]) - ln32(q)
+        kpos = np.maximum(kf, F32(0.0)).astype(np.float32)
+        rhs = ((-c["mu"]) + kpos * c["lnmu"]) - lnfact32(kpos)
+        acc = fast | (~rej & (lhs <= rhs))
+        new = acc & ~done
+        out[new] = kf[new].astype(np.int64)
+        used[new] = j + 1
+        done |= acc
+        if done.all():
+            return out, used
+    raise RuntimeError("transformed rejection exceeded its attempt limit")
+
+
+# ---------------------------------------------------------------------------
+# C3: dust split
+# ---------------------------------------------------------------------------
+
+
+def popcount32(w: np.ndarray) -> np.ndarray:
+    w = np.asarray(w, dtype=np.uint64)
+    c = np.zeros(w.shape, dtype=np.int64)
+    for b in range(32):
+        c += ((w >> np.uint64(b)) & np.uint64(1)).astype(np.int64)
+    return c
+
+
+def split_reddened(n: np.ndarray, first_word: np.ndarray, frac: float, seed: int,
+                   px: np.ndarray, entry: int) -> np.ndarray:
+    """Number of the n stars that sit behind the dust screen (C3)."""
+    n = np.asarray(n, dtype=np.int64)
+    if frac <= 0.0:
+        return np.zeros_like(n)
+    if frac >= 1.0:
+        return n.copy()
+    r = np.zeros_like(n)
+    if frac == 0.5:
+        m = np.minimum(n, 32)
+        mask = np.where(m >= 32, np.uint64(0xFFFFFFFF),
+                        (np.uint64(1) << m.astype(np.uint64)) - np.uint64(1))
+        r += popcount32(np.asarray(first_word, dtype=np.uint64) & mask)
+        extra = n - 32
+        j = 0
+        while np.any(extra > 128 * j):
+            w = philox4x32_10(px, entry, TAG_SPLIT_X, j, seed)
+            for q in range(4):
+                base = 128 * j + 32 * q
+                cnt = np.clip(extra - base, 0, 32)
+                mk = np.where(cnt >= 32, np.uint64(0xFFFFFFFF),
+                              (np.uint64(1) << cnt.astype(np.uint64)) - np.uint64(1))
+                r += popcount32(np.asarray(w[q], dtype=np.uint64) & mk)
+            j += 1
+        return r
+    fq = np.uint64(int(math.floor(frac * 4294967296.0)))
+    r += ((n >= 1) & (np.asarray(first_word, dtype=np.uint64) < fq)).astype(np.int64)
+    j = 0
+    while np.any(n - 1 > 4 * j):
+        w = philox4x32_10(px, entry, TAG_SPLIT_X, j, seed)
+        for q in range(4):
+            s = 1 + 4 * j + q
+            r += ((n > s) & (np.asarray(w[q], dtype=np.uint64) < fq)).astype(np.int64)
+        j += 1
+    return r
+
+
+# ---------------------------------------------------------------------------
+# counts and fluxes over a pixel window
+# ---------------------------------------------------------------------------
+
+
+def sample_window(lam: np.ndarray, flux32: np.ndarray, seed: int, px0: int, px1: int,
+                  dust_model: int = 0, dust_frac: float = 0.5, want_counts: bool = False):
+    """Star counts and unreddened / reddened flux sums for pixels [px0, px1).
+
+    Returns dict with F_clr, F_red ([B][npx] FP64) and, if asked, counts n and
+    reddened counts r ([npx][E] int64)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    E = lam.shape[0]
+    B = flux32.shape[0]
+    f = np.asarray(flux32, dtype=np.float32).astype(np.float64)
+    px = np.arange(px0, px1, dtype=np.int64)
+    npx = px.shape[0]
+    split = dust_model != 0
+    frac = float(dust_frac) if split else 0.0
+    F_clr = np.zeros((B, npx))
+    F_red = np.zeros((B, npx))
+    counts = np.zeros((npx, E), dtype=np.int64) if want_counts else None
+    red = np.zeros((npx, E), dtype=np.int64) if want_counts else None
+    thr_cache = {}
+    for g in range((E + 3) // 4):
+        words = philox4x32_10(px, g, TAG_MAIN, 0, seed)
+        swords = None
+        for q in range(4):
+            i = 4 * g + q
+            if i >= E:
+                break
+            li = lam[i]
+            if li < LAM_SWITCH:
+                thr = thr_cache.get(li)
+                if thr is None:
+                    thr = inversion_thresholds(li)
+                    thr_cache[li] = thr
+                n = count_from_thresholds(words[q], thr).astype(np.int64)
+            else:
+                n, _ = ptrs_draw(ptrs_constants(li), seed, px, i)
+            if split and 0.0 < frac < 1.0:
+                if swords is None:
+                    swords = philox4x32_10(px, g, TAG_SPLIT, 0, seed)
+                r = split_reddened(n, swords[q], frac, seed, px, i)
+            elif split and frac >= 1.0:
+                r = n
+            else:
+                r = np.zeros_like(n)
+            F_clr += np.outer(f[:, i], (n - r).astype(np.float64))
+            F_red += np.outer(f[:, i], r.astype(np.float64))
+            if want_counts:
+                counts[:, i] = n
+                red[:, i] = r
+    return dict(F_clr=F_clr, F_red=F_red, counts=counts, red=red)
+
+
+def dust_ebv(px: np.ndarray, seed: int, dust_model: int, mu: float, sigma: float) -> np.ndarray:
+    """E(B-V) per pixel: 10^mu (E1) or 10^(mu + sigma z_p) (E2/E3)."""
+    px = np.asarray(px, dtype=np.int64)
+    if dust_model == 1:
+        return np.full(px.shape, 10.0 ** mu)
+    w = philox4x32_10(px, 0, TAG_DUST, 0, seed)
+    z = box_muller_f64(w[0], w[1])
+    return 10.0 ** (mu + sigma * z)
+
+
+def pixel_flux(F_clr, F_red, px, seed, dmod, dust_model=0, dust_mu=-0.5, dust_sigma=0.2,
+               dust_R=(3.6, 1.9, 1.3)):
+    """F_b = 10^(-0.4 mu_d) (F_clr_b + F_red_b 10^(-0.4 R_b E_p))  (FP64)."""
+    B = F_clr.shape[0]
+    dist = 10.0 ** (-0.4 * dmod)
+    if dust_model == 0:
+        return dist * (F_clr + F_red)
+    ebv = dust_ebv(px, seed, dust_model, dust_mu, dust_sigma)
+    out = np.empty_like(F_clr)
+    for b in range(B):
+        out[b] = dist * (F_clr[b] + F_red[b] * 10.0 ** (-0.4 * dust_R[b] * ebv))
+    return out
+
+
+def simulate_flux(lam, flux32, obs, px0=0, px1=None, want_counts=False):
+    """Pre-PSF pixel fluxes [B][npx] (FP64) for pixels [px0, px1)."""
+    npx_all = obs.nim * obs.nim
+    px1 = npx_all if px1 is None else px1
+    s = sample_window(lam, flux32, obs.seed, px0, px1, obs.dust_model, obs.dust_frac, want_counts)
+    px = np.arange(px0, px1, dtype=np.int64)
+    F = pixel_flux(s["F_clr"], s["F_red"], px, obs.seed, obs.dmod, obs.dust_model, obs.dust_mu,
+                   obs.dust_sigma, obs.dust_R[:flux32.shape[0]])
+    return F, s

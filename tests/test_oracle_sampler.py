@@ -1,0 +1,182 @@
+"""Oracle a1/a2 pins: Poisson rules against the Poisson law, the dust split by
+enumeration, and the flux moments, distance and dust invariants of Sec. 2."""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import synth_inputs as si
+from oracle import entries as E
+from oracle import rng, sampler as S
+
+
+@pytest.mark.parametrize("lam", [0.0, 1e-6, 3e-3, 0.2, 1.0, 3.7, 9.99])
+def test_inversion_thresholds_match_poisson_cdf(lam):
+    T = S.inversion_thresholds(lam)
+    cdf = stats.poisson.cdf(np.arange(len(T)), lam) if len(T) else np.array([])
+    for k, t in enumerate(T):
+        # T_k / 2^32 is the cdf to within 2^-32 (floor) plus FP64 summation error
+        assert abs(t / 2 ** 32 - cdf[k]) <= 2 ** -32 + 1e-14
+    # past the table, the cdf has reached 1 within 2^-32 (or the table is capped at 63)
+    if len(T) < S.KMAX:
+        assert 1 - stats.poisson.cdf(len(T) - 1, lam) < 2 ** -31 or len(T) == 0
+
+
+@pytest.mark.parametrize("lam", [0.05, 0.9, 6.0])
+def test_inversion_counts_on_stratified_words(lam):
+    # 65536 equally spaced words: P(n <= k) is hit to within 2^-16
+    u = (np.arange(65536, dtype=np.uint64) << np.uint64(16)) + np.uint64(12345)
+    n = S.count_from_thresholds(u, S.inversion_thresholds(lam))
+    emp = np.array([(n <= k).mean() for k in range(12)])
+    assert np.all(np.abs(emp - stats.poisson.cdf(np.arange(12), lam)) <= 2 ** -16 + 1e-12)
+
+
+def test_ln32_accuracy():
+    x = np.geomspace(2.0 ** -24, 2.0 ** 24, 200001).astype(np.float32)
+    got = S.ln32(x).astype(np.float64)
+    ref = np.log(x.astype(np.float64))
+    assert np.max(np.abs(got - ref)) < 1.5e-6
+    far = np.abs(ref) > 0.01
+    ulp = np.spacing(np.abs(ref[far]).astype(np.float32)).astype(np.float64)
+    assert np.max(np.abs(got[far] - ref[far]) / ulp) <= 3.0
+
+
+def test_lnfact32():
+    k = np.arange(0, 5000, dtype=np.float32)
+    got = S.lnfact32(k).astype(np.float64)
+    ref = np.array([math.lgamma(v + 1.0) for v in range(5000)])
+    assert np.all(np.abs(got - ref) <= 3e-7 * np.maximum(ref, 1.0))
+
+
+@pytest.mark.parametrize("lam", [10.0, 30.0, 100.0, 1000.0, 1e4])
+def test_ptrs_moments(lam):
+    n, used = S.ptrs_draw(S.ptrs_constants(lam), 11, np.arange(300000), 3)
+    N = len(n)
+    assert abs(n.mean() - lam) < 5 * math.sqrt(lam / N)
+    # Var of the sample variance for Poisson: (mu4 - sigma^4)/N with mu4 = lam + 3 lam^2
+    sd_var = math.sqrt((lam + 3 * lam * lam - lam * lam) / N)
+    assert abs(n.var() - lam) < 5 * sd_var
+    assert used.max() < 64
+
+
+@pytest.mark.parametrize("lam", [10.0, 27.5, 140.0])
+def test_ptrs_chi_square(lam):
+    n, _ = S.ptrs_draw(S.ptrs_constants(lam), 5, np.arange(400000), 9)
+    lo, hi = int(lam - 4 * math.sqrt(lam)), int(lam + 4 * math.sqrt(lam))
+    edges = np.arange(max(lo, 1), hi + 1)
+    obs = np.array([(n < edges[0]).sum()] + [(n == k).sum() for k in edges] + [(n > edges[-1]).sum()])
+    p = np.concatenate([[stats.poisson.cdf(edges[0] - 1, lam)], stats.poisson.pmf(edges, lam),
+                        [stats.poisson.sf(edges[-1], lam)]])
+    exp = p * len(n)
+    chi2 = ((obs - exp) ** 2 / exp).sum()
+    assert stats.chi2.sf(chi2, len(obs) - 1) > 1e-4
+
+
+def test_split_half_enumeration():
+    # for n <= 16 stars, over all 2^16 values of the low word bits, r ~ Binomial(n, 1/2) exactly
+    W = np.arange(65536, dtype=np.uint32)
+    px = np.zeros(65536, dtype=np.int64)
+    for n in range(0, 17):
+        r = S.split_reddened(np.full(65536, n), W, 0.5, 1, px, 0)
+        cnt = np.bincount(r, minlength=n + 1)
+        expect = np.array([math.comb(n, k) * 2 ** (16 - n) for k in range(n + 1)])
+        assert np.array_equal(cnt[:n + 1], expect)
+
+
+def test_split_large_n_and_general_fraction():
+    px = np.arange(100000)
+    w = rng.philox4x32_10(px, 0, rng.TAG_SPLIT, 0, 3)[0]
+    for n in (40, 300):
+        r = S.split_reddened(np.full(len(px), n), w, 0.5, 3, px, 7)
+        assert abs(r.mean() - n / 2) < 5 * math.sqrt(n / 4 / len(px))
+        assert abs(r.var() - n / 4) < 5 * (n / 4) * math.sqrt(2 / len(px))
+    for F in (0.3, 0.85):
+        for n in (1, 9):
+            r = S.split_reddened(np.full(len(px), n), w, F, 3, px, 7)
+            assert abs(r.mean() - n * F) < 5 * math.sqrt(n * F * (1 - F) / len(px))
+    assert np.array_equal(S.split_reddened(np.full(5, 4), w[:5], 0.0, 3, px[:5], 0), np.zeros(5))
+    assert np.array_equal(S.split_reddened(np.full(5, 4), w[:5], 1.0, 3, px[:5], 0), np.full(5, 4))
+
+
+def _small():
+    g, m, o = si.small_case()
+    lam, f64, f32 = E.build_entries(m, g)
+    return lam, f32, o
+
+
+def test_flux_mean_and_variance_closed_form():
+    # pre-PSF pixel flux: mean sum(lam f), variance sum(lam f^2) (surface-brightness fluctuation)
+    lam, f32, o = _small()
+    s = S.sample_window(lam, f32, 77, 0, 40000)
+    f = f32.astype(np.float64)
+    for b in range(2):
+        F = s["F_clr"][b]
+        mu = (lam * f[b]).sum()
+        var = (lam * f[b] ** 2).sum()
+        mu4 = (lam * f[b] ** 4).sum() + 3 * var ** 2     # fourth central moment of a compound Poisson sum
+        N = len(F)
+        assert abs(F.mean() - mu) < 5 * math.sqrt(var / N)
+        assert abs(F.var() - var) < 5 * math.sqrt((mu4 - var ** 2) / N)
+    cov = (lam * f[0] * f[1]).sum()
+    c = np.cov(s["F_clr"][0], s["F_clr"][1])[0, 1]
+    assert abs(c - cov) < 0.1 * cov
+
+
+def test_total_star_count_is_poisson_npix():
+    lam, f32, o = _small()
+    s = S.sample_window(lam, f32, 5, 0, 8000, want_counts=True)
+    tot = s["counts"].sum(axis=1)
+    edges = np.arange(70, 131)
+    obs = np.array([(tot < 70).sum()] + [(tot == k).sum() for k in edges] + [(tot > 130).sum()])
+    p = np.concatenate([[stats.poisson.cdf(69, 100)], stats.poisson.pmf(edges, 100), [stats.poisson.sf(130, 100)]])
+    chi2 = ((obs - p * len(tot)) ** 2 / (p * len(tot))).sum()
+    assert stats.chi2.sf(chi2, len(obs) - 1) > 1e-4
+
+
+def test_distance_scales_flux_only_and_npix_degeneracy():
+    lam, f32, o = _small()
+    o1 = si.Obs(nim=32, seed=3, dmod=25.0)
+    o2 = si.Obs(nim=32, seed=3, dmod=26.25)
+    F1, s1 = S.simulate_flux(lam, f32, o1, want_counts=True)
+    F2, s2 = S.simulate_flux(lam, f32, o2, want_counts=True)
+    assert np.array_equal(s1["counts"], s2["counts"])
+    assert np.allclose(F2, F1 * 10 ** (-0.4 * 1.25), rtol=1e-14, atol=0)
+    # equal Npix * 10^(-0.4 mu_d) -> equal expected flux, dispersion differs by the Npix ratio
+    f = f32.astype(np.float64)
+    mean1 = (lam * f[1]).sum() * 10 ** (-0.4 * 25.0)
+    mean2 = (10 * lam * f[1]).sum() * 10 ** (-0.4 * 27.5)
+    assert mean1 == pytest.approx(mean2, rel=1e-12)
+    var1 = (lam * f[1] ** 2).sum() * 10 ** (-0.8 * 25.0)
+    var2 = (10 * lam * f[1] ** 2).sum() * 10 ** (-0.8 * 27.5)
+    assert var2 == pytest.approx(var1 / 10, rel=1e-12)
+
+
+def test_dust_invariants():
+    lam, f32, o = _small()
+    base = S.sample_window(lam, f32, 9, 0, 512, dust_model=0, want_counts=True)
+    for F, expect_r in ((0.0, "zero"), (1.0, "all"), (0.5, None)):
+        s = S.sample_window(lam, f32, 9, 0, 512, dust_model=2, dust_frac=F, want_counts=True)
+        assert np.array_equal(s["counts"], base["counts"])      # counts never depend on the dust
+        if expect_r == "zero":
+            assert s["red"].sum() == 0
+        elif expect_r == "all":
+            assert np.array_equal(s["red"], s["counts"])
+        else:
+            assert 0 < s["red"].sum() < s["counts"].sum()
+    # fixed screen (E1) with F = 1 scales every band by 10^(-0.4 R_b E)
+    s = S.sample_window(lam, f32, 9, 0, 512, dust_model=1, dust_frac=1.0)
+    px = np.arange(512)
+    F_d = S.pixel_flux(s["F_clr"], s["F_red"], px, 9, 25.0, 1, -0.5, 0.0, (3.6, 1.9))
+    F_0 = S.pixel_flux(base["F_clr"], base["F_red"], px, 9, 25.0, 0)
+    E_ = 10 ** -0.5
+    for b, R in enumerate((3.6, 1.9)):
+        assert np.allclose(F_d[b], F_0[b] * 10 ** (-0.4 * R * E_), rtol=1e-14)
+
+
+def test_lognormal_dust_draws():
+    px = np.arange(100000)
+    e = S.dust_ebv(px, 4, 2, -0.5, 0.2)
+    le = np.log10(e)
+    assert abs(le.mean() + 0.5) < 5 * 0.2 / math.sqrt(len(px))
+    assert abs(le.std() - 0.2) < 0.01
