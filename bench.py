@@ -1,0 +1,171 @@
+"""Benchmark: pCMD likelihood evaluations per second on one MI355X.
+
+One step = one full likelihood evaluation of the 256x256, 3-band, 52,500-entry workload
+(7 log-age bins x 5 [Fe/H] x 1500 masses, tau-model SFH, Gaussian MDF, log-normal dust with
+F_dust = 1/2, 31x31 PSF, shot noise, 100x100 Hess, Poisson likelihood against a data Hess):
+weighted entries -> Poisson sampler with flux sums -> dust / distance -> PSF -> noise ->
+magnitudes -> Hess -> log-likelihood.  Parameters are drawn per step from the mock-test priors
+(log Npix ~ U[2, 5], tau ~ U[0.1, 8] Gyr, mu_[Fe/H] ~ U[-0.5, 0.25], mu_dust ~ U[-1, 0],
+mu_d ~ U[24, 30]) with seeds 1000, 1001, ...; the data Hess comes from seed 2.  All inputs are
+synthetic and resident on the GPU before the timed region starts.
+
+Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published figures: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 VALU lane-ops/s.
+VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
+# Algorithmic lane-ops of one pixel x entry draw: a quarter of one Philox4x32-10 evaluation
+# (10 rounds x (2 32x32->64-bit products + 4 XORs) = 60 lane-ops for 4 words) plus the
+# threshold compare.  Data-dependent work (accumulation, extra thresholds, rejection, dust
+# split) is not counted, so the fraction is a lower bound.
+OPS_PER_DRAW = 60 / 4 + 1
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pixels", type=int, default=256, help="pixels in the oracle's timed sampler window")
+    ap.add_argument("--conv", type=int, default=0, help="0 auto, 1 direct, 2 fft")
+    return ap.parse_args()
+
+
+def cpu_baseline(grid, model, obs, hgrid, n_px_sample):
+    """Time the oracle (single thread) on a bounded sample of one evaluation."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import entries as oe
+    from oracle import hess as oh
+    from oracle import loglike as ol
+    from oracle import noise as on
+    from oracle import psf as ops
+    from oracle import sampler as osamp
+
+    N = obs.nim
+    npx = N * N
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        lam, _, f32 = oe.build_entries(model, grid)
+        t1 = time.perf_counter()
+        F, _ = osamp.simulate_flux(lam, f32, obs, 0, n_px_sample)
+        t2 = time.perf_counter()
+        # image-plane steps at full size on an image tiled from the sampled window
+        reps = int(np.ceil(npx / n_px_sample))
+        Ffull = np.tile(F, (1, reps))[:, :npx].reshape(F.shape[0], N, N)
+        G = ops.convolve_periodic(Ffull, obs.psf)
+        m = on.magnitudes(G.reshape(F.shape[0], npx), obs)
+        H, mom = oh.hess(m, hgrid)
+        ol.loglike(H, H, mom, mom, ol.POISSON, 0.01)
+        t3 = time.perf_counter()
+    t_eval = (t1 - t0) + (t2 - t1) * (npx / n_px_sample) + (t3 - t2)
+    return dict(value=1.0 / t_eval, unit="evals/s", cores=1, kind="oracle",
+                sample=(f"oracle in one thread: entries + sampler on {n_px_sample} of {npx} pixels "
+                        f"(time scaled x{npx / n_px_sample:g}) + PSF, noise, Hess and logL at full size; "
+                        f"log Npix = {model.log_npix:.3f}; measured {t3 - t0:.1f} s"),
+                sampler_draws_per_s=n_px_sample * len(lam) / (t2 - t1))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is "
+              "described in DESIGN.md but not built", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import paper_1904_00011_amd as P
+    import synth_inputs as si
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    ctx = P.Context(0)
+    grid = si.headline_grid()
+    model_d, obs_d = si.draw_headline_params(2)
+    # data image and Hess grid (untimed set-up)
+    ev = P.Evaluator(ctx, grid, obs_d.nim, obs_d.psf, dict(x0=0.0, dx=0.05, y0=0.0, dy=0.05, nx=100, ny=100))
+    mags_d = ev.simulate(model_d, obs_d, args.conv).clone()
+    ctx.sync()
+    md = mags_d.cpu().numpy().astype(np.float64)
+    fin = np.isfinite(md).all(axis=0)
+    hgrid = si.hess_grid_from_median(float(np.median((md[0] - md[1])[fin])), float(np.median(md[1][fin])), 100, 100)
+    ev.hess_grid = hgrid
+    data_hess = torch.empty(100 * 100, dtype=torch.int32, device=dev)
+    data_mom = torch.empty(3, dtype=torch.float64, device=dev)
+    ev.hess_of(mags_d, data_hess, data_mom)
+    params = [si.draw_headline_params(1000 + k) for k in range(args.steps + args.warmup)]
+    logls = torch.empty(args.steps + args.warmup, dtype=torch.float64, device=dev)
+    for k in range(args.warmup):
+        m, o = params[k]
+        logls[k:k + 1].copy_(ev.loglike(m, o, data_hess, data_mom, P.LL_POISSON, 0.01, args.conv))
+    torch.cuda.synchronize()
+    ctx.timer_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        m, o = params[k]
+        logls[k:k + 1].copy_(ev.loglike(m, o, data_hess, data_mom, P.LL_POISSON, 0.01, args.conv))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    s_ms, s_n, s_units = ctx.timer_read(P._lib.TIMER_SAMPLE)
+    c_ms, c_n, _ = ctx.timer_read(P._lib.TIMER_CONV)
+    h_ms, h_n, _ = ctx.timer_read(P._lib.TIMER_HESS)
+    ctx.timer_enable(False)
+    ll = logls.cpu().numpy()[args.warmup:]
+    assert np.all(np.isfinite(ll)), "non-finite log-likelihood"
+    elapsed = t1 - t0
+    evals_per_s = args.steps / elapsed
+    draws_per_launch = s_units / max(s_n, 1)
+    avg_sample_s = s_ms / max(s_n, 1) / 1e3
+    achieved = OPS_PER_DRAW * draws_per_launch / avg_sample_s
+    res = {
+        "metric": "likelihood evals/sec (256^2 image, 52,500 isochrone points)",
+        "value": evals_per_s,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32 counts / f64 sums / f32 images",
+        "data": "synthetic",
+        "config": {"workload": "256x256 px, 3 bands, 52,500 entries (7 ages x 5 [Fe/H] x 1500 masses), "
+                               "log Npix ~ U[2,5], log-normal dust F=0.5, 31x31 PSF, shot noise, 100x100 Hess, "
+                               "Poisson logL",
+                   "nim": 256, "entries": 52500, "bands": 3, "psf_k": 31, "hess": [100, 100],
+                   "parallelism": "1 GPU"},
+        "poisson_draws_per_s": s_units / (s_ms / 1e3) if s_ms > 0 else None,
+        "draws_per_eval": draws_per_launch,
+        "kernel_ms_per_eval": {"sample": s_ms / max(s_n, 1), "conv": c_ms / max(c_n, 1), "hess": h_ms / max(h_n, 1)},
+        "roofline": {"bound": "alu", "kernel": "k_sample", "achieved": achieved / 1e12,
+                     "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "TOP/s (VALU lane-ops)",
+                     "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": None,
+                     "ops_per_draw": OPS_PER_DRAW, "avg_launch_ms": avg_sample_s * 1e3},
+        "mean_logL": float(ll.mean()),
+    }
+    if not args.no_cpu_baseline:
+        m, o = params[args.warmup]
+        res["cpu_baseline"] = cpu_baseline(grid, m, o, hgrid, args.cpu_pixels)
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,241 @@
+/*
+ * pcmd.h -- C ABI of the MI355X (gfx950) pixel colour-magnitude-diagram forward model.
+ *
+ * The library evaluates the stochastic forward model of Cook, Conroy, van Dokkum & Speagle,
+ * "Measuring Star-Formation Histories, Distances, and Metallicities with Pixel Color-Magnitude
+ * Diagrams I" (arXiv:1904.00011): weighted isochrone points -> per-pixel Poisson star counts ->
+ * dust, distance and flux sums -> PSF -> sky and noise -> magnitudes -> Hess diagram ->
+ * binned likelihood (Sec. 2.1 and 2.5, Fig. 1).
+ *
+ * Conventions for every call:
+ *  - Pointers marked [dev] are device memory on the context's GPU, owned by the caller; the
+ *    library never frees or keeps them past the call.  Pointers marked [host] are read during
+ *    the call only.
+ *  - All device work is queued on `stream` (a hipStream_t; NULL = the null stream) and the call
+ *    returns without waiting for it.  Results are valid once the stream has reached them.
+ *  - Every scalar, shape and pointer argument is validated before anything is launched; on
+ *    failure the call returns a negative PCMD_E_* code, sets the message returned by
+ *    pcmd_last_error(), and has no side effect.  A failed HIP launch returns PCMD_E_HIP.
+ *    The contents of device arrays are checked by the kernels themselves (so that no call
+ *    waits for the device): a bad value is replaced as documented and reported by pcmd_sync().
+ *  - The context owns scratch buffers.  They grow on the first call that needs more and are
+ *    then reused, so repeated calls with the same shapes allocate nothing.  Calls that share a
+ *    context must not run concurrently on different streams.
+ *  - Results are a pure function of the inputs and the seed: they do not depend on launch
+ *    shapes, batching, or the stream used.
+ */
+#ifndef PCMD_H
+#define PCMD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PCMD_MAX_BANDS 4
+#define PCMD_MAX_ISO 512
+#define PCMD_MAX_PSF_K 127
+
+enum {
+  PCMD_OK = 0,
+  PCMD_E_INVAL = -1,        /* an argument failed validation                         */
+  PCMD_E_HIP = -2,          /* a HIP runtime call or kernel launch failed            */
+  PCMD_E_NOMEM = -3,        /* device scratch could not be allocated                 */
+  PCMD_E_UNSUPPORTED = -4,  /* valid request this build does not implement           */
+  PCMD_E_PTRS_RETRY = -5    /* a rejection draw used up its attempts (see pcmd_sync) */
+};
+
+typedef struct pcmd_ctx pcmd_ctx;
+typedef void *pcmd_stream; /* hipStream_t */
+
+/* Create a context bound to HIP device `hip_device`.  *out receives the handle. */
+int pcmd_create(pcmd_ctx **out, int hip_device);
+/* Free the context and its scratch.  Waits for the device to finish work that uses it. */
+void pcmd_destroy(pcmd_ctx *ctx);
+/* Message of the last failed call on this context ("" if none).  Valid until the next call. */
+const char *pcmd_last_error(const pcmd_ctx *ctx);
+/* Wait for `stream`, then report device-side findings of earlier calls and clear them:
+ * PCMD_E_INVAL if an expected star count was NaN, negative or >= 2^22 or an isochrone index was
+ * out of range (that point was given no stars), or if a PSF band had a negative or non-finite
+ * value or did not sum to 1 within 1e-3 (the image is still convolved with it);
+ * PCMD_E_PTRS_RETRY if a transformed-rejection draw exhausted its 64 attempts (probability
+ * below 1e-60 per draw; that draw's count is 0). */
+int pcmd_sync(pcmd_ctx *ctx, pcmd_stream stream);
+/* Name of the library build, e.g. "pcmd gfx950 ...". */
+const char *pcmd_version(void);
+
+/* ---------------------------------------------------------------------------------------
+ * a0: weighted isochrone entries (Sec. 2.1: age x [Fe/H] x mass points weighted by the SFH,
+ * the metallicity distribution and the IMF, normalised to Npix; Sec. 2.2 and Table 1: the
+ * model menu).
+ * ------------------------------------------------------------------------------------- */
+
+enum { PCMD_SFH_SSP = 0, PCMD_SFH_CONST = 1, PCMD_SFH_TAU = 2, PCMD_SFH_DTAU = 3, PCMD_SFH_NONPARAM = 4 };
+enum { PCMD_MDF_SINGLE = 0, PCMD_MDF_GAUSS = 1 };
+
+/* Shape of an isochrone set: isochrone k stands for age bin iso_age[k] (edges age_edges, log10
+ * yr) and [Fe/H] grid point iso_feh[k].  All pointers [host]. */
+typedef struct {
+  int32_t n_iso, n_age, n_feh;
+  const double *age_edges; /* [n_age + 1] log10 yr, increasing          */
+  const double *feh_grid;  /* [n_feh]                                   */
+  const int32_t *iso_age;  /* [n_iso] in [0, n_age)                     */
+  const int32_t *iso_feh;  /* [n_iso] in [0, n_feh)                     */
+} pcmd_isoset;
+
+/* Physical model of one evaluation (Table 1).  S1 SSP uses ssp_age_index; S2 constant SFR;
+ * S3 tau model SFR ~ exp(-t/tau); S4 delayed tau SFR ~ t exp(-t/tau) (t = time since onset at
+ * 10^10.2 yr); S5 non-parametric with log_sfh[a] = log10 stars per pixel formed in age bin a
+ * (Npix = their sum).  M1 single [Fe/H] grid point feh_index; M2/M3 Gaussian weights at the
+ * grid points, weights under mdf_prune dropped and the rest renormalised. */
+typedef struct {
+  int32_t sfh, mdf;
+  int32_t ssp_age_index, feh_index;
+  double log_npix, tau_gyr;
+  double feh_mu, feh_sigma, mdf_prune;
+  const double *log_sfh; /* [host][n_age], S5 only */
+} pcmd_model;
+
+/* Host helper: IMF weight of every point (Salpeter-type power law m^-alpha integrated over the
+ * point's mass bin, edges at geometric midpoints, outer edges half a log-step out; Sec. 2.2,
+ * Table 2) and the star flux 10^(-0.4 M) per band.  Points of one isochrone must be contiguous
+ * with increasing mass.  mass [host][E]; absmag [host][B][E]; imf_w_out [host][E];
+ * flux_out [host][B][E] (FP32). */
+int pcmd_grid_prepare(int32_t n_entries, int32_t n_bands, const int32_t *iso_of_entry,
+                      const double *mass, const double *absmag, double alpha,
+                      double *imf_w_out, float *flux_out);
+
+/* Host helper: per-isochrone SFH x MDF weight and Npix for `model` (Sec. 2.2). w_out [host][n_iso]. */
+int pcmd_iso_weights(const pcmd_model *model, const pcmd_isoset *set, double *w_out, double *npix_out);
+
+/* Device grid: per-point isochrone index and IMF weight, uploaded once per fit. */
+typedef struct {
+  int32_t n_entries, n_iso;
+  const int32_t *iso_of_entry; /* [dev][E] */
+  const double *imf_w;         /* [dev][E] */
+  const double *iso_imf_sum;   /* [host][n_iso] sum of imf_w over each isochrone's points */
+} pcmd_grid;
+
+/* lambda_i = Npix * w_iso(i) * imf_w_i / sum_k w_k S_k  (expected stars per pixel; sum = Npix).
+ * iso_w [host][n_iso] from pcmd_iso_weights; lam_out [dev][E] FP64. */
+int pcmd_entries(pcmd_ctx *ctx, const pcmd_grid *grid, const double *iso_w, double npix,
+                 double *lam_out, pcmd_stream stream);
+
+/* ---------------------------------------------------------------------------------------
+ * a1-a4: one simulated image (Sec. 2.1; dust models Sec. 2.2; noise Sec. 2.1 and Table 2).
+ * ------------------------------------------------------------------------------------- */
+
+/* Weighted points: lam [dev][E] expected stars per pixel (finite, 0 <= lam < 2^22);
+ * flux [dev][B][E] star flux 10^(-0.4 M_abs) (FP32, finite, >= 0). */
+typedef struct {
+  int32_t n_entries, n_bands;
+  const double *lam;
+  const float *flux;
+} pcmd_iso;
+
+enum { PCMD_DUST_NONE = 0, PCMD_DUST_SCREEN = 1, PCMD_DUST_LOGNORMAL = 2 };
+enum { PCMD_CONV_AUTO = 0, PCMD_CONV_DIRECT = 1, PCMD_CONV_FFT = 2 };
+enum { PCMD_NOISE_NONE = 0, PCMD_NOISE_GAUSS_MAG = 1, PCMD_NOISE_SHOT = 2 };
+
+/* Observation and nuisance model of one simulation.
+ *  nim            image side (pixels = nim*nim), 1..8192
+ *  seed           64-bit key of every random draw
+ *  dmod           distance modulus mu_d; every flux is scaled by 10^(-0.4 mu_d)
+ *  dust_model     NONE, SCREEN (E1: log10 E(B-V) = dust_mu everywhere) or LOGNORMAL
+ *                 (E2/E3: log10 E(B-V) ~ N(dust_mu, dust_sigma) per pixel)
+ *  dust_frac      F_dust in [0, 1]: each star is behind the screen with this probability
+ *  dust_R[b]      A_b / E(B-V)
+ *  psf_k, psf     odd K <= nim and <= PCMD_MAX_PSF_K; psf [dev][B][K][K] FP32, each band sums to 1
+ *                 (checked to 1e-3); the convolution is periodic.  psf_k = 1 with psf NULL = no PSF
+ *  conv_path      AUTO, DIRECT or FFT (FFT needs nim a power of two, 8..4096)
+ *  noise_model    NONE, GAUSS_MAG (m += sigma_b z) or SHOT (c = G t_b 10^(0.4 zp_b) + sky_b,
+ *                 c' = c + sqrt(c) z, m = -2.5 log10((c' - sky_b)/t_b) + zp_b; +inf if <= 0) */
+typedef struct {
+  int32_t nim;
+  int32_t dust_model;
+  uint64_t seed;
+  double dmod;
+  double dust_mu, dust_sigma, dust_frac;
+  double dust_R[PCMD_MAX_BANDS];
+  int32_t psf_k, conv_path;
+  const float *psf;
+  int32_t noise_model, pad_;
+  double noise_sigma_mag[PCMD_MAX_BANDS];
+  double exptime[PCMD_MAX_BANDS];
+  double zp[PCMD_MAX_BANDS];
+  double sky[PCMD_MAX_BANDS];
+} pcmd_obs;
+
+/* Optional debug outputs (any pointer may be NULL):
+ *  counts   [dev][px1 - px0][E] u32 star count of each pixel in [px0, px1) and point
+ *  reddened [dev][px1 - px0][E] u32 how many of them sit behind the dust screen
+ *  flux_pre [dev][B][nim*nim] FP32 pixel flux after dust and distance, before the PSF
+ *  flux_psf [dev][B][nim*nim] FP32 pixel flux after the PSF */
+typedef struct {
+  uint32_t *counts;
+  uint32_t *reddened;
+  int64_t px0, px1;
+  float *flux_pre;
+  float *flux_psf;
+} pcmd_debug;
+
+/* Simulate one image: mags_out [dev][B][nim*nim] FP32 apparent magnitudes (+inf where the
+ * flux or noisy count is not positive).  dbg may be NULL. */
+int pcmd_simulate(pcmd_ctx *ctx, const pcmd_iso *iso, const pcmd_obs *obs, float *mags_out,
+                  const pcmd_debug *dbg, pcmd_stream stream);
+
+/* ---------------------------------------------------------------------------------------
+ * a5: Hess diagram (Sec. 2.1, 2.5; 0.05 mag bins, Table 2).
+ * ------------------------------------------------------------------------------------- */
+
+/* x = m[b_blue] - m[b_red], y = m[b_mag] (computed in FP64 from the FP32 magnitudes);
+ * ix = clamp(floor((x - x0)/dx), 0, nx-1) with NaN -> 0, likewise iy; H[iy][ix] += 1, so the
+ * Hess total equals the pixel count.  Requires nx, ny >= 1, nx*ny <= 65536, dx, dy > 0. */
+typedef struct {
+  double x0, dx, y0, dy;
+  int32_t nx, ny;
+  int32_t b_blue, b_red, b_mag, pad_;
+} pcmd_hess_grid;
+
+/* mags [dev][n_bands][n_px] -> hess [dev][ny][nx] u32 (overwritten) and
+ * moments [dev][3] FP64 = (sum x, sum y, count) over pixels whose three magnitudes are finite. */
+int pcmd_hess(pcmd_ctx *ctx, const float *mags, int32_t n_bands, int64_t n_px,
+              const pcmd_hess_grid *grid, uint32_t *hess, double *moments, pcmd_stream stream);
+
+/* ---------------------------------------------------------------------------------------
+ * a6: binned log-likelihood (Sec. 2.5).
+ * ------------------------------------------------------------------------------------- */
+
+enum { PCMD_LL_POISSON = 0, PCMD_LL_GAUSS_PAPER = 1, PCMD_LL_GAUSS_LITERAL = 2 };
+
+/* POISSON: lam_j = N_d (m_j + eps) / (N_m + eps n_bins), logL = sum d_j ln lam_j - lam_j - ln d_j!
+ * GAUSS_PAPER: mh_j = m_j N_d / N_m, sigma_j = max(sqrt(d_j + mh_j), 2),
+ *   logL = -sum (d_j - mh_j)^2 / (2 sigma_j^2) + C
+ * GAUSS_LITERAL: the printed form -sum (d_j/N_d - m_j/N_m)^2 / (2 sigma_j^2) + C with
+ *   sigma_j = max(sqrt(d_j^2 + m_j^2), 2)
+ * C = -(C_d - C_m)^2 / (2 0.05^2) - (M_d - M_m)^2 / (2 0.05^2) from the moments (mean colour and
+ * magnitude).  hess_* [dev][n_bins] u32; mom_* [dev][3]; out [dev][1] FP64.  eps > 0 (POISSON). */
+int pcmd_loglike(pcmd_ctx *ctx, const uint32_t *hess_model, const uint32_t *hess_data, int32_t n_bins,
+                 const double *mom_model, const double *mom_data, int32_t mode, double eps,
+                 double *out, pcmd_stream stream);
+
+/* ---------------------------------------------------------------------------------------
+ * Kernel timing for benchmarks: HIP events recorded on the launch stream around each
+ * launch of the timed kernels while enabled.
+ * ------------------------------------------------------------------------------------- */
+
+enum { PCMD_TIMER_SAMPLE = 0, PCMD_TIMER_CONV = 1, PCMD_TIMER_HESS = 2, PCMD_TIMER_KINDS = 3 };
+
+/* Start (on != 0) or stop recording.  Starting discards earlier records. */
+int pcmd_timer_enable(pcmd_ctx *ctx, int on);
+/* Wait for the recorded launches of kernel `which` and return their summed duration (ms),
+ * their number and the algorithmic units they processed (SAMPLE: pixel x entry draws;
+ * CONV: image values read and written; HESS: pixels binned).  Consumes those records. */
+int pcmd_timer_read(pcmd_ctx *ctx, int which, double *total_ms, int64_t *launches, double *units);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCMD_H */

@@ -204,11 +204,7 @@ def ptrs_draw(c: dict, seed: int, px: np.ndarray, entry: int, max_attempts: int 
 
 
 def popcount32(w: np.ndarray) -> np.ndarray:
-    w = np.asarray(w, dtype=np.uint64)
-    c = np.zeros(w.shape, dtype=np.int64)
-    for b in range(32):
-        c += ((w >> np.uint64(b)) & np.uint64(1)).astype(np.int64)
-    return c
+    return np.bitwise_count(np.asarray(w, dtype=np.uint64)).astype(np.int64)
 
 
 def split_reddened(n: np.ndarray, first_word: np.ndarray, frac: float, seed: int,
@@ -254,17 +250,36 @@ def split_reddened(n: np.ndarray, first_word: np.ndarray, frac: float, seed: int
 # ---------------------------------------------------------------------------
 
 
-def sample_window(lam: np.ndarray, flux32: np.ndarray, seed: int, px0: int, px1: int,
-                  dust_model: int = 0, dust_frac: float = 0.5, want_counts: bool = False):
-    """Star counts and unreddened / reddened flux sums for pixels [px0, px1).
+def _popcount_masked(w: np.ndarray, cnt: np.ndarray) -> np.ndarray:
+    """popcount of the low `cnt` bits (cnt in [0, 32]) of uint32 words."""
+    w = np.asarray(w, dtype=np.uint64)
+    cnt = np.asarray(cnt, dtype=np.int64)
+    mask = np.where(cnt >= 32, np.uint64(0xFFFFFFFF),
+                    (np.uint64(1) << np.clip(cnt, 0, 31).astype(np.uint64)) - np.uint64(1))
+    return popcount32(w & mask)
 
-    Returns dict with F_clr, F_red ([B][npx] FP64) and, if asked, counts n and
-    reddened counts r ([npx][E] int64)."""
+
+def sample_window(lam: np.ndarray, flux32: np.ndarray, seed: int, px0: int, px1: int,
+                  dust_model: int = 0, dust_frac: float = 0.5, want_counts: bool = False,
+                  block: int = 1024):
+    """Star counts and flux sums for the pixel window [px0, px1) (see sample_pixels)."""
+    return sample_pixels(lam, flux32, seed, np.arange(px0, px1, dtype=np.int64), dust_model, dust_frac,
+                         want_counts, block)
+
+
+def sample_pixels(lam: np.ndarray, flux32: np.ndarray, seed: int, px: np.ndarray,
+                  dust_model: int = 0, dust_frac: float = 0.5, want_counts: bool = False,
+                  block: int = 1024):
+    """Star counts and unreddened / reddened flux sums for the pixels listed in `px`.
+
+    Entries are handled a block at a time, vectorised over (pixel, entry); each count follows
+    the C1 / C2 rule of its entry and each split the C3 rule.  Returns dict with F_clr, F_red
+    ([B][npx] FP64) and, if asked, counts n and reddened counts r ([npx][E] int64)."""
     lam = np.asarray(lam, dtype=np.float64)
     E = lam.shape[0]
     B = flux32.shape[0]
     f = np.asarray(flux32, dtype=np.float32).astype(np.float64)
-    px = np.arange(px0, px1, dtype=np.int64)
+    px = np.asarray(px, dtype=np.int64)
     npx = px.shape[0]
     split = dust_model != 0
     frac = float(dust_frac) if split else 0.0
@@ -272,37 +287,73 @@ def sample_window(lam: np.ndarray, flux32: np.ndarray, seed: int, px0: int, px1:
     F_red = np.zeros((B, npx))
     counts = np.zeros((npx, E), dtype=np.int64) if want_counts else None
     red = np.zeros((npx, E), dtype=np.int64) if want_counts else None
-    thr_cache = {}
-    for g in range((E + 3) // 4):
-        words = philox4x32_10(px, g, TAG_MAIN, 0, seed)
-        swords = None
-        for q in range(4):
-            i = 4 * g + q
-            if i >= E:
-                break
-            li = lam[i]
-            if li < LAM_SWITCH:
-                thr = thr_cache.get(li)
-                if thr is None:
-                    thr = inversion_thresholds(li)
-                    thr_cache[li] = thr
-                n = count_from_thresholds(words[q], thr).astype(np.int64)
-            else:
-                n, _ = ptrs_draw(ptrs_constants(li), seed, px, i)
-            if split and 0.0 < frac < 1.0:
-                if swords is None:
-                    swords = philox4x32_10(px, g, TAG_SPLIT, 0, seed)
-                r = split_reddened(n, swords[q], frac, seed, px, i)
-            elif split and frac >= 1.0:
-                r = n
-            else:
-                r = np.zeros_like(n)
-            F_clr += np.outer(f[:, i], (n - r).astype(np.float64))
-            F_red += np.outer(f[:, i], r.astype(np.float64))
-            if want_counts:
-                counts[:, i] = n
-                red[:, i] = r
+    block = max(4, block - block % 4)
+    for e0 in range(0, E, block):
+        e1 = min(E, e0 + block)
+        ents = np.arange(e0, e1)
+        g = np.arange(e0 // 4, (e1 + 3) // 4)
+        w = philox4x32_10(px[:, None], g[None, :], TAG_MAIN, 0, seed)
+        U = np.stack(w, axis=-1).reshape(npx, 4 * len(g))[:, : e1 - e0].astype(np.uint64)
+        n = np.zeros((npx, e1 - e0), dtype=np.int64)
+        lb = lam[e0:e1]
+        inv = np.nonzero(lb < LAM_SWITCH)[0]
+        tables = [inversion_thresholds(lb[j]) for j in inv]
+        K = np.array([len(t) for t in tables], dtype=np.int64)
+        # n = #{k : T_k <= u}; entries bucketed by table length, tables padded with 2^32
+        for lo, hi in ((1, 4), (5, 8), (9, 16), (17, 32), (33, KMAX)):
+            sel = np.nonzero((K >= lo) & (K <= hi))[0]
+            if len(sel) == 0:
+                continue
+            T = np.full((len(sel), hi), TWO32, dtype=np.uint64)
+            for r_, j in enumerate(sel):
+                T[r_, : K[j]] = tables[j]
+            cols = inv[sel]
+            n[:, cols] = (U[:, cols, None] >= T[None, :, :]).sum(axis=-1)
+        for j in np.nonzero(lb >= LAM_SWITCH)[0]:
+            n[:, j], _ = ptrs_draw(ptrs_constants(lb[j]), seed, px, e0 + j)
+        if split and 0.0 < frac < 1.0:
+            sw = philox4x32_10(px[:, None], g[None, :], TAG_SPLIT, 0, seed)
+            W = np.stack(sw, axis=-1).reshape(npx, 4 * len(g))[:, : e1 - e0].astype(np.uint64)
+            r = split_block(n, W, frac, seed, px, ents)
+        elif split and frac >= 1.0:
+            r = n.copy()
+        else:
+            r = np.zeros_like(n)
+        fb = f[:, e0:e1]
+        F_clr += fb @ (n - r).T.astype(np.float64)
+        F_red += fb @ r.T.astype(np.float64)
+        if want_counts:
+            counts[:, e0:e1] = n
+            red[:, e0:e1] = r
     return dict(F_clr=F_clr, F_red=F_red, counts=counts, red=red)
+
+
+def split_block(n: np.ndarray, W: np.ndarray, frac: float, seed: int, px: np.ndarray, ents: np.ndarray):
+    """C3 for a block: n [npx][nent] counts, W [npx][nent] first split words."""
+    r = np.zeros_like(n)
+    if frac == 0.5:
+        r += _popcount_masked(W, np.minimum(n, 32))
+        extra = n - 32
+        j = 0
+        while np.any(extra > 128 * j):
+            cols = np.nonzero(np.any(extra > 128 * j, axis=0))[0]
+            x = philox4x32_10(px[:, None], ents[cols][None, :], TAG_SPLIT_X, j, seed)
+            for q in range(4):
+                cnt = np.clip(extra[:, cols] - (128 * j + 32 * q), 0, 32)
+                r[:, cols] += _popcount_masked(x[q], cnt)
+            j += 1
+        return r
+    fq = np.uint64(int(math.floor(frac * 4294967296.0)))
+    r += ((n >= 1) & (W < fq)).astype(np.int64)
+    j = 0
+    while np.any(n - 1 > 4 * j):
+        cols = np.nonzero(np.any(n - 1 > 4 * j, axis=0))[0]
+        x = philox4x32_10(px[:, None], ents[cols][None, :], TAG_SPLIT_X, j, seed)
+        for q in range(4):
+            s = 1 + 4 * j + q
+            r[:, cols] += ((n[:, cols] > s) & (np.asarray(x[q], dtype=np.uint64) < fq)).astype(np.int64)
+        j += 1
+    return r
 
 
 def dust_ebv(px: np.ndarray, seed: int, dust_model: int, mu: float, sigma: float) -> np.ndarray:
@@ -329,12 +380,14 @@ def pixel_flux(F_clr, F_red, px, seed, dmod, dust_model=0, dust_mu=-0.5, dust_si
     return out
 
 
-def simulate_flux(lam, flux32, obs, px0=0, px1=None, want_counts=False):
-    """Pre-PSF pixel fluxes [B][npx] (FP64) for pixels [px0, px1)."""
+def simulate_flux(lam, flux32, obs, px0=0, px1=None, want_counts=False, px=None):
+    """Pre-PSF pixel fluxes [B][npx] (FP64) for pixels [px0, px1) or the list `px`."""
     npx_all = obs.nim * obs.nim
     px1 = npx_all if px1 is None else px1
-    s = sample_window(lam, flux32, obs.seed, px0, px1, obs.dust_model, obs.dust_frac, want_counts)
-    px = np.arange(px0, px1, dtype=np.int64)
+    if px is None:
+        px = np.arange(px0, px1, dtype=np.int64)
+    px = np.asarray(px, dtype=np.int64)
+    s = sample_pixels(lam, flux32, obs.seed, px, obs.dust_model, obs.dust_frac, want_counts)
     F = pixel_flux(s["F_clr"], s["F_red"], px, obs.seed, obs.dmod, obs.dust_model, obs.dust_mu,
                    obs.dust_sigma, obs.dust_R[:flux32.shape[0]])
     return F, s

@@ -1,0 +1,221 @@
+// Hess diagram (LDS-privatised histogram) and binned log-likelihood reduction (gfx950).
+// Sec. 2.5 of the paper: pixels are binned in colour and magnitude (0.05 mag bins) and the
+// model and data Hess diagrams are compared bin by bin, with a term for the difference of the
+// mean colour and magnitude.
+#include <math.h>
+
+#include "pcmd_device.h"
+#include "pcmd_internal.h"
+
+namespace pcmd {
+
+__global__ void __launch_bounds__(256) k_fill_u32(uint32_t *__restrict__ p, uint32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+constexpr int HESS_THREADS = 512;
+constexpr int HESS_MAX_BLOCKS = 256;
+constexpr int HESS_LDS_MAX_BINS = 40000;  // 160,000 bytes of LDS (of 163,840 per workgroup)
+int hess_max_blocks() { return HESS_MAX_BLOCKS; }
+
+__device__ __forceinline__ int bin_of(double t, int n) {
+  // clamp(floor(t), 0, n-1), NaN -> 0
+  if (!(t >= 0.0)) return 0;
+  if (t >= (double)n) return n - 1;
+  return (int)t;
+}
+
+struct HessArgs {
+  const float *mags;
+  int64_t npx;
+  double x0, dx, y0, dy;
+  int nx, ny, bb, br, bm;
+  uint32_t *hess;
+  double *mom_part;  // [gridDim.x][3]
+  uint32_t *counter;
+  double *moments;
+  int use_lds;
+};
+
+__device__ __forceinline__ double block_sum(double v, double *red) {
+  // fixed-order tree: within each wave by shuffles, then over the waves in order (deterministic)
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int wave = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[wave] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int w = 0; w < HESS_THREADS / 64; ++w) r += red[w];
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(HESS_THREADS) k_hess(HessArgs a) {
+  extern __shared__ uint32_t lh[];
+  __shared__ double red[HESS_THREADS / 64];
+  __shared__ bool last;
+  const int nb = a.nx * a.ny;
+  if (a.use_lds) {
+    for (int j = threadIdx.x; j < nb; j += HESS_THREADS) lh[j] = 0u;
+    __syncthreads();
+  }
+  double sx = 0.0, sy = 0.0, cnt = 0.0;
+  const float *mb = a.mags + (size_t)a.bb * a.npx;
+  const float *mr = a.mags + (size_t)a.br * a.npx;
+  const float *mm = a.mags + (size_t)a.bm * a.npx;
+  for (int64_t p = (int64_t)blockIdx.x * HESS_THREADS + threadIdx.x; p < a.npx;
+       p += (int64_t)gridDim.x * HESS_THREADS) {
+    const double vb = (double)mb[p], vr = (double)mr[p], vm = (double)mm[p];
+    const double x = vb - vr, y = vm;
+    const int ix = bin_of((x - a.x0) / a.dx, a.nx);
+    const int iy = bin_of((y - a.y0) / a.dy, a.ny);
+    const int j = iy * a.nx + ix;
+    if (a.use_lds)
+      atomicAdd(&lh[j], 1u);
+    else
+      atomicAdd(&a.hess[j], 1u);
+    if (isfinite(vb) && isfinite(vr) && isfinite(vm)) {
+      sx += x;
+      sy += y;
+      cnt += 1.0;
+    }
+  }
+  if (a.use_lds) {
+    __syncthreads();
+    for (int j = threadIdx.x; j < nb; j += HESS_THREADS) {
+      const uint32_t v = lh[j];
+      if (v) atomicAdd(&a.hess[j], v);
+    }
+  }
+  sx = block_sum(sx, red);
+  sy = block_sum(sy, red);
+  cnt = block_sum(cnt, red);
+  if (threadIdx.x == 0) {
+    a.mom_part[blockIdx.x * 3 + 0] = sx;
+    a.mom_part[blockIdx.x * 3 + 1] = sy;
+    a.mom_part[blockIdx.x * 3 + 2] = cnt;
+    __threadfence();
+    const uint32_t prev = atomicAdd(a.counter, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last) {
+    // every block's partial is visible: combine in block order
+    if (threadIdx.x == 0) {
+      __threadfence();
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+      for (unsigned k = 0; k < gridDim.x; ++k) {
+        s0 += __builtin_nontemporal_load(&a.mom_part[k * 3 + 0]);
+        s1 += __builtin_nontemporal_load(&a.mom_part[k * 3 + 1]);
+        s2 += __builtin_nontemporal_load(&a.mom_part[k * 3 + 2]);
+      }
+      a.moments[0] = s0;
+      a.moments[1] = s1;
+      a.moments[2] = s2;
+      *a.counter = 0u;  // ready for the next call (also under graph replay)
+    }
+  }
+}
+
+hipError_t launch_hess(const float *mags, int B, int64_t npx, const pcmd_hess_grid &g, uint32_t *hess,
+                       double *moments, double *mom_part, uint32_t *counter, hipStream_t s) {
+  (void)B;
+  const int nb = g.nx * g.ny;
+  hipError_t e = launch_fill_u32(hess, 0u, nb, s);
+  if (e != hipSuccess) return e;
+  HessArgs a;
+  a.mags = mags;
+  a.npx = npx;
+  a.x0 = g.x0;
+  a.dx = g.dx;
+  a.y0 = g.y0;
+  a.dy = g.dy;
+  a.nx = g.nx;
+  a.ny = g.ny;
+  a.bb = g.b_blue;
+  a.br = g.b_red;
+  a.bm = g.b_mag;
+  a.hess = hess;
+  a.mom_part = mom_part;
+  a.counter = counter;
+  a.moments = moments;
+  a.use_lds = nb <= HESS_LDS_MAX_BINS;
+  // enough pixels per block to amortise clearing and merging the private histogram
+  int64_t blocks = (npx + 4095) / 4096;
+  if (blocks < 1) blocks = 1;
+  if (blocks > HESS_MAX_BLOCKS) blocks = HESS_MAX_BLOCKS;
+  const size_t lds = a.use_lds ? (size_t)nb * sizeof(uint32_t) : 0;
+  hipLaunchKernelGGL(k_hess, dim3((unsigned)blocks), dim3(HESS_THREADS), lds, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Log-likelihood: one block, fixed-order reduction in FP64.
+// ---------------------------------------------------------------------------------------
+constexpr int LL_THREADS = 1024;
+
+__global__ void __launch_bounds__(LL_THREADS) k_loglike(const uint32_t *__restrict__ hm, const uint32_t *__restrict__ hd,
+                                                        int nbins, const double *__restrict__ mom_m,
+                                                        const double *__restrict__ mom_d, int mode, double eps,
+                                                        double *__restrict__ out) {
+  __shared__ double red[LL_THREADS];
+  __shared__ unsigned long long tot[2];
+  const int t = threadIdx.x;
+  if (t < 2) tot[t] = 0ull;
+  __syncthreads();
+  unsigned long long sm = 0, sd = 0;
+  for (int j = t; j < nbins; j += LL_THREADS) {
+    sm += hm[j];
+    sd += hd[j];
+  }
+  atomicAdd(&tot[0], sm);
+  atomicAdd(&tot[1], sd);
+  __syncthreads();
+  const double Nm = (double)tot[0], Nd = (double)tot[1];
+  double acc = 0.0;
+  for (int j = t; j < nbins; j += LL_THREADS) {
+    const double m = (double)hm[j], d = (double)hd[j];
+    if (mode == PCMD_LL_POISSON) {
+      const double lam = Nd * (m + eps) / (Nm + eps * (double)nbins);
+      acc += d * log(lam) - lam - lgamma(d + 1.0);
+    } else if (mode == PCMD_LL_GAUSS_PAPER) {
+      const double mh = m * Nd / Nm;
+      const double sig = fmax(sqrt(d + mh), 2.0);
+      const double df = d - mh;
+      acc -= df * df / (2.0 * sig * sig);
+    } else {
+      const double sig = fmax(sqrt(d * d + m * m), 2.0);
+      const double df = d / Nd - m / Nm;
+      acc -= df * df / (2.0 * sig * sig);
+    }
+  }
+  red[t] = acc;
+  __syncthreads();
+  for (int s = LL_THREADS / 2; s > 0; s >>= 1) {
+    if (t < s) red[t] = red[t] + red[t + s];
+    __syncthreads();
+  }
+  if (t == 0) {
+    double r = red[0];
+    if (mode != PCMD_LL_POISSON) {
+      const double Cm = mom_m[0] / mom_m[2], Mm = mom_m[1] / mom_m[2];
+      const double Cd = mom_d[0] / mom_d[2], Md = mom_d[1] / mom_d[2];
+      r += -(Cd - Cm) * (Cd - Cm) / (2.0 * 0.05 * 0.05) - (Md - Mm) * (Md - Mm) / (2.0 * 0.05 * 0.05);
+    }
+    out[0] = r;
+  }
+}
+
+hipError_t launch_loglike(const uint32_t *hm, const uint32_t *hd, int nbins, const double *mom_m, const double *mom_d,
+                          int mode, double eps, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_loglike, dim3(1), dim3(LL_THREADS), 0, s, hm, hd, nbins, mom_m, mom_d, mode, eps, out);
+  return hipGetLastError();
+}
+
+}  // namespace pcmd

@@ -1,0 +1,320 @@
+// Weighted entries, per-entry sampler tables, the pixel x entry Poisson sampler with fused
+// flux accumulation, and the chunk reduction with the dust / distance epilogue (gfx950).
+//
+// Sec. 2.1 of the paper: every pixel draws an independent Poisson count for every weighted
+// isochrone point, the stars' fluxes are reddened by dust, dimmed by the distance modulus and
+// summed into the pixel.  One lane owns one pixel; the entry table is wave-uniform, so it is
+// read through the scalar cache.  A wave handles 64 pixels x one chunk of CHUNK entries and
+// keeps the per-band sums in FP64 registers; chunk partials are written once and combined in
+// ascending chunk order by the reduction kernel, which fixes the summation order independently
+// of the launch shape.
+#include <math.h>
+
+#include "pcmd_device.h"
+#include "pcmd_internal.h"
+
+namespace pcmd {
+
+// ---------------------------------------------------------------------------------------
+// a0: lambda_i = scale[iso(i)] * imf_w_i   (scale_k = Npix w_k / sum_k w_k S_k)
+// ---------------------------------------------------------------------------------------
+struct IsoScale {
+  double v[PCMD_MAX_ISO];
+};
+
+__global__ void __launch_bounds__(256) k_entries(int E, int n_iso, const int32_t *__restrict__ iso,
+                                                 const double *__restrict__ imf_w, IsoScale scale,
+                                                 double *__restrict__ lam, uint32_t *__restrict__ status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= E) return;
+  const int k = iso[i];
+  if (k < 0 || k >= n_iso) {  // malformed grid: no stars, reported by pcmd_sync
+    atomicOr(status, STATUS_BAD_LAMBDA);
+    lam[i] = 0.0;
+    return;
+  }
+  lam[i] = scale.v[k] * imf_w[i];
+}
+
+hipError_t launch_entries(const pcmd_grid *g, const double *scale, double *lam, uint32_t *status, hipStream_t s) {
+  IsoScale sc;
+  for (int k = 0; k < PCMD_MAX_ISO; ++k) sc.v[k] = k < g->n_iso ? scale[k] : 0.0;
+  const int E = g->n_entries;
+  hipLaunchKernelGGL(k_entries, dim3((E + 255) / 256), dim3(256), 0, s, E, g->n_iso, g->iso_of_entry, g->imf_w, sc,
+                     lam, status);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Per-entry tables: inversion thresholds (lambda < 10) or rejection constants (lambda >= 10)
+// and FP64 star fluxes laid out [E][BP] for scalar loads.
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_prep(int E, int B, int BP, const double *__restrict__ lam,
+                                              const float *__restrict__ flux, EntryRec *__restrict__ rec,
+                                              uint32_t *__restrict__ thr, PtrsConst *__restrict__ pc,
+                                              double *__restrict__ fl64, uint32_t *__restrict__ status) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= E) return;
+  for (int b = 0; b < BP; ++b) fl64[(size_t)i * BP + b] = b < B ? (double)flux[(size_t)b * E + i] : 0.0;
+  double l = lam[i];
+  if (!(l >= 0.0 && l < 4194304.0)) {  // NaN, negative or too large: drawn as zero, reported
+    atomicOr(status, STATUS_BAD_LAMBDA);
+    l = 0.0;
+  }
+  EntryRec r{0u, 0u, KIND_ZERO, 0u};
+  if (l >= 10.0) {
+    const double slam = sqrt(l);
+    const double b = 0.931 + 2.53 * slam;
+    const double a = -0.059 + 0.02483 * b;
+    const double inv_alpha = 1.1239 + 1.1328 / (b - 3.4);
+    const double vr = 0.9277 - 3.6224 / (b - 2.0);
+    PtrsConst c;
+    c.mu = (float)l;
+    c.lnmu = (float)log(l);
+    c.b = (float)b;
+    c.a = (float)a;
+    c.twoa = (float)(2.0 * a);
+    c.lninva = (float)log(inv_alpha);
+    c.vr = (float)vr;
+    c.pad = 0.0f;
+    pc[i] = c;
+    r.kind = KIND_PTRS;
+  } else if (l > 0.0) {
+    double p = exp(-l);
+    double F = p;
+    uint32_t K = 0;
+    uint32_t *t = thr + (size_t)i * THR_STRIDE;
+    for (int k = 0; k < THR_STRIDE - 1; ++k) {
+      if (k > 0) {
+        p = p * l / (double)k;
+        F = F + p;
+      }
+      const double tk = floor(F * 4294967296.0);
+      if (tk >= 4294967296.0) break;
+      t[k] = (uint32_t)tk;
+      K = (uint32_t)(k + 1);
+    }
+    if (K > 0) {
+      r.kind = KIND_INV;
+      r.T0 = t[0];
+      r.K = K;
+    }
+  }
+  rec[i] = r;
+}
+
+hipError_t launch_prep(const double *lam, const float *flux, EntryTables &t, uint32_t *status, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep, dim3((t.E + 255) / 256), dim3(256), 0, s, t.E, t.B, t.BP, lam, flux, t.rec, t.thr,
+                     (PtrsConst *)t.pc, t.fl64, status);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
+// Sampler.
+// ---------------------------------------------------------------------------------------
+__device__ __forceinline__ bool wave_any(bool v) { return __ballot(v) != 0ull; }
+
+__device__ __forceinline__ uint32_t low_mask(uint32_t cnt) { return cnt >= 32u ? 0xFFFFFFFFu : ((1u << cnt) - 1u); }
+
+// Transformed-rejection draw for entry i at pixel p (attempts 2j, 2j+1 share one Philox call).
+__device__ __forceinline__ uint32_t ptrs_draw(const PtrsConst &c, uint32_t p, uint32_t i, uint32_t k0, uint32_t k1,
+                                              const float *__restrict__ lnfact, uint32_t *status) {
+  int k = 0;
+  bool done = false;
+  for (uint32_t j = 0; j < (uint32_t)(PTRS_MAX_ATTEMPTS / 2); ++j) {
+    const u4 w = philox10(p, i, TAG_PTRS, j, k0, k1);
+    int kk;
+    if (!done && ptrs_attempt(c, w.x, w.y, lnfact, kk)) {
+      k = kk;
+      done = true;
+    }
+    if (!done && ptrs_attempt(c, w.z, w.w, lnfact, kk)) {
+      k = kk;
+      done = true;
+    }
+    if (!wave_any(!done)) break;
+  }
+  if (!done) {
+    atomicOr(status, STATUS_PTRS_RETRY);
+    k = 0;
+  }
+  return (uint32_t)k;
+}
+
+// Reddened stars among n (dust split), first word W from the group split block.
+__device__ __forceinline__ uint32_t split_count(uint32_t n, uint32_t W, int mode, uint32_t fq, uint32_t p,
+                                                uint32_t i, uint32_t k0, uint32_t k1) {
+  if (mode == SPLIT_ALL) return n;
+  uint32_t red = 0;
+  if (mode == SPLIT_HALF) {
+    red = __popc(W & low_mask(n));
+    const uint32_t extra = n > 32u ? n - 32u : 0u;
+    for (uint32_t j = 0; wave_any(extra > 128u * j); ++j) {
+      const u4 x = philox10(p, i, TAG_SPLIT_X, j, k0, k1);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t base = 128u * j + 32u * (uint32_t)q;
+        const uint32_t cnt = extra > base ? min(extra - base, 32u) : 0u;
+        red += __popc(word_of(x, q) & low_mask(cnt));
+      }
+    }
+    return red;
+  }
+  // general fraction: one word per star
+  red = (n >= 1u && W < fq) ? 1u : 0u;
+  const uint32_t rest = n > 1u ? n - 1u : 0u;  // stars 1..n-1
+  for (uint32_t j = 0; wave_any(rest > 4u * j); ++j) {
+    const u4 x = philox10(p, i, TAG_SPLIT_X, j, k0, k1);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t s = 4u * j + (uint32_t)q;  // star index minus one
+      red += (rest > s && word_of(x, q) < fq) ? 1u : 0u;
+    }
+  }
+  return red;
+}
+
+template <int B, int S>
+__global__ void __launch_bounds__(256) k_sample(SampleArgs a, const EntryRec *__restrict__ rec,
+                                                const uint32_t *__restrict__ thr, const PtrsConst *__restrict__ pc,
+                                                const double *__restrict__ fl64) {
+  constexpr int BP = B <= 2 ? 2 : 4;
+  const int nblk_px = (a.npx + 255) >> 8;
+  const int chunk = blockIdx.x / nblk_px;
+  const int pblk = blockIdx.x - chunk * nblk_px;
+  const uint32_t p = (uint32_t)(pblk * 256 + threadIdx.x);
+  const bool live = p < (uint32_t)a.npx;
+  const int e0 = chunk * CHUNK;
+  const int e1 = min(a.E, e0 + CHUNK);
+  const bool dbg = a.dbg_counts != nullptr && live && (int64_t)p >= a.px0 && (int64_t)p < a.px1;
+
+  double acc_c[B], acc_r[B];
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    acc_c[b] = 0.0;
+    acc_r[b] = 0.0;
+  }
+
+  for (int g0 = e0; g0 < e1; g0 += 4) {
+    const uint32_t g = (uint32_t)(g0 >> 2);
+    EntryRec r[4];
+    bool need_main = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      r[q] = (g0 + q < e1) ? rec[g0 + q] : EntryRec{0u, 0u, KIND_ZERO, 0u};
+      need_main |= r[q].kind == KIND_INV;
+    }
+    u4 w{0u, 0u, 0u, 0u};
+    if (need_main) w = philox10(p, g, TAG_MAIN, 0u, a.k0, a.k1);
+    u4 sw{0u, 0u, 0u, 0u};
+    bool have_split = false;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t i = (uint32_t)(g0 + q);
+      uint32_t n = 0;
+      if (r[q].kind == KIND_INV) {
+        const uint32_t u = word_of(w, q);
+        n = u >= r[q].T0 ? 1u : 0u;
+        if (wave_any(n != 0u)) {
+          const uint32_t *t = thr + (size_t)i * THR_STRIDE;
+          for (uint32_t k = 1; k < r[q].K; ++k) {
+            const uint32_t c = u >= t[k] ? 1u : 0u;
+            if (!wave_any(c != 0u)) break;
+            n += c;
+          }
+        }
+      } else if (r[q].kind == KIND_PTRS) {
+        n = ptrs_draw(pc[i], p, i, a.k0, a.k1, a.lnfact, a.status);
+      } else {
+        continue;
+      }
+      if (!wave_any(n != 0u)) continue;
+      uint32_t red = 0u;
+      if (S == 2) {
+        if (a.split_mode != SPLIT_ALL && !have_split) {
+          sw = philox10(p, g, TAG_SPLIT, 0u, a.k0, a.k1);
+          have_split = true;
+        }
+        red = split_count(n, word_of(sw, q), a.split_mode, a.split_q, p, i, a.k0, a.k1);
+      }
+      const double *f = fl64 + (size_t)i * BP;
+      const double dc = (double)(n - red);
+#pragma unroll
+      for (int b = 0; b < B; ++b) acc_c[b] = fma(dc, f[b], acc_c[b]);
+      if (S == 2) {
+        const double dr = (double)red;
+#pragma unroll
+        for (int b = 0; b < B; ++b) acc_r[b] = fma(dr, f[b], acc_r[b]);
+      }
+      if (dbg) {
+        const size_t o = (size_t)((int64_t)p - a.px0) * (size_t)a.E + i;
+        a.dbg_counts[o] = n;
+        if (a.dbg_red) a.dbg_red[o] = red;
+      }
+    }
+  }
+  if (!live) return;
+  const size_t plane = (size_t)a.npx;
+#pragma unroll
+  for (int b = 0; b < B; ++b) {
+    a.part[((size_t)(chunk * S + 0) * B + b) * plane + p] = acc_c[b];
+    if (S == 2) a.part[((size_t)(chunk * S + 1) * B + b) * plane + p] = acc_r[b];
+  }
+}
+
+template <int B>
+static hipError_t launch_sample_b(const EntryTables &t, const SampleArgs &a, hipStream_t s) {
+  const int nblk_px = (a.npx + 255) / 256;
+  dim3 grid((unsigned)(nblk_px * a.nchunks));
+  if (a.S == 2)
+    hipLaunchKernelGGL((k_sample<B, 2>), grid, dim3(256), 0, s, a, t.rec, t.thr, (const PtrsConst *)t.pc, t.fl64);
+  else
+    hipLaunchKernelGGL((k_sample<B, 1>), grid, dim3(256), 0, s, a, t.rec, t.thr, (const PtrsConst *)t.pc, t.fl64);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample(const EntryTables &t, const SampleArgs &a, hipStream_t s) {
+  switch (a.B) {
+    case 1: return launch_sample_b<1>(t, a, s);
+    case 2: return launch_sample_b<2>(t, a, s);
+    case 3: return launch_sample_b<3>(t, a, s);
+    case 4: return launch_sample_b<4>(t, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Chunk reduction + epilogue: F_b = 10^(-0.4 mu_d) (F_clr_b + F_red_b 10^(-0.4 R_b E_p)).
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= a.npx) return;
+  double ebv = 0.0;
+  if (a.dust_model == PCMD_DUST_SCREEN) {
+    ebv = exp10(a.dust_mu);
+  } else if (a.dust_model == PCMD_DUST_LOGNORMAL) {
+    const u4 w = philox10((uint32_t)p, 0u, TAG_DUST, 0u, a.k0, a.k1);
+    ebv = exp10(a.dust_mu + a.dust_sigma * box_muller(w.x, w.y));
+  }
+  const size_t plane = (size_t)a.npx;
+  for (int b = 0; b < a.B; ++b) {
+    double c = 0.0, r = 0.0;
+    for (int ch = 0; ch < a.nchunks; ++ch) {
+      c += a.part[((size_t)(ch * a.S + 0) * a.B + b) * plane + p];
+      if (a.S == 2) r += a.part[((size_t)(ch * a.S + 1) * a.B + b) * plane + p];
+    }
+    double F;
+    if (a.dust_model == PCMD_DUST_NONE)
+      F = a.dist * (c + r);
+    else
+      F = a.dist * (c + r * exp10(-0.4 * a.dust_R[b] * ebv));
+    a.F[(size_t)b * plane + p] = (float)F;
+  }
+}
+
+hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3((a.npx + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace pcmd

@@ -1,0 +1,584 @@
+// C ABI of the pCMD forward model: context, argument validation, scratch management and the
+// host-side model helpers.  Every device step runs in the gfx950 kernels of k_*.hip.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "pcmd_device.h"
+#include "pcmd_internal.h"
+
+using namespace pcmd;
+
+struct Buf {
+  void *p = nullptr;
+  size_t n = 0;
+};
+
+struct TimerRec {
+  int which;
+  hipEvent_t start, stop;
+  double units;
+};
+
+struct pcmd_ctx {
+  int device = 0;
+  std::string err;
+  bool timing = false;
+  std::vector<TimerRec> timers;
+  Buf rec, thr, pc, fl64, part, F, G, psf64, mom_part, fft;
+  float *lnfact = nullptr;     // [256]
+  uint32_t *status = nullptr;  // [1]
+  uint32_t *counter = nullptr; // [1]
+};
+
+namespace {
+
+int fail(pcmd_ctx *c, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+int hip_fail(pcmd_ctx *c, hipError_t e, const char *what) {
+  return fail(c, PCMD_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Grow-only device buffer.
+int ensure(pcmd_ctx *c, Buf &b, size_t bytes, const char *what) {
+  if (bytes <= b.n) return PCMD_OK;
+  if (b.p) {
+    hipError_t e = hipFree(b.p);
+    if (e != hipSuccess) return hip_fail(c, e, "hipFree");
+    b.p = nullptr;
+    b.n = 0;
+  }
+  size_t want = bytes + bytes / 8 + 256;
+  hipError_t e = hipMalloc(&b.p, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    b.p = nullptr;
+    return fail(c, PCMD_E_NOMEM, "cannot allocate %zu bytes of scratch for %s", want, what);
+  }
+  b.n = want;
+  return PCMD_OK;
+}
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+
+// Event pair around one launch when timing is enabled.
+struct ScopedTimer {
+  pcmd_ctx *c;
+  hipStream_t s;
+  TimerRec r{};
+  bool on;
+  ScopedTimer(pcmd_ctx *c_, int which, double units, hipStream_t s_) : c(c_), s(s_), on(c_->timing) {
+    if (!on) return;
+    r.which = which;
+    r.units = units;
+    if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) {
+      on = false;
+      return;
+    }
+    (void)hipEventRecord(r.start, s);
+  }
+  ~ScopedTimer() {
+    if (!on) return;
+    (void)hipEventRecord(r.stop, s);
+    c->timers.push_back(r);
+  }
+};
+
+void clear_timers(pcmd_ctx *c) {
+  for (auto &t : c->timers) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  c->timers.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pcmd_version(void) { return "pcmd gfx950 HIP 1.0 (philox4x32-10, chunk 2048)"; }
+
+int pcmd_create(pcmd_ctx **out, int hip_device) {
+  if (!out) return PCMD_E_INVAL;
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess) return PCMD_E_HIP;
+  if (hip_device < 0 || hip_device >= ndev) return PCMD_E_INVAL;
+  pcmd_ctx *c = new pcmd_ctx();
+  c->device = hip_device;
+  DeviceGuard g(hip_device);
+  // ln k! for k < 256: FP64 running sum of ln j, rounded to FP32.
+  float tab[256];
+  double acc = 0.0;
+  tab[0] = tab[1] = 0.0f;
+  for (int k = 2; k < 256; ++k) {
+    acc = acc + log((double)k);
+    tab[k] = (float)acc;
+  }
+  if (hipMalloc(&c->lnfact, sizeof tab) != hipSuccess || hipMalloc(&c->status, 8) != hipSuccess ||
+      hipMalloc(&c->counter, 8) != hipSuccess) {
+    (void)hipGetLastError();
+    pcmd_destroy(c);
+    return PCMD_E_NOMEM;
+  }
+  uint32_t zeros[2] = {0u, 0u};
+  if (hipMemcpy(c->lnfact, tab, sizeof tab, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->status, zeros, 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->counter, zeros, 8, hipMemcpyHostToDevice) != hipSuccess) {
+    pcmd_destroy(c);
+    return PCMD_E_HIP;
+  }
+  *out = c;
+  return PCMD_OK;
+}
+
+void pcmd_destroy(pcmd_ctx *c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  (void)hipDeviceSynchronize();
+  clear_timers(c);
+  Buf *bufs[] = {&c->rec, &c->thr, &c->pc, &c->fl64, &c->part, &c->F, &c->G, &c->psf64, &c->mom_part, &c->fft};
+  for (Buf *b : bufs)
+    if (b->p) (void)hipFree(b->p);
+  if (c->lnfact) (void)hipFree(c->lnfact);
+  if (c->status) (void)hipFree(c->status);
+  if (c->counter) (void)hipFree(c->counter);
+  delete c;
+}
+
+const char *pcmd_last_error(const pcmd_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+int pcmd_sync(pcmd_ctx *c, pcmd_stream stream) {
+  if (!c) return PCMD_E_INVAL;
+  DeviceGuard g(c->device);
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t st = 0;
+  hipError_t e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = hipMemcpy(&st, c->status, 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(c, e, "pcmd_sync");
+  if (st) {
+    uint32_t z = 0;
+    e = hipMemcpy(c->status, &z, 4, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(c, e, "pcmd_sync");
+    if (st & STATUS_BAD_LAMBDA) return fail(c, PCMD_E_INVAL, "an expected star count was negative, not finite or >= 2^22 (drawn as 0)");
+    if (st & STATUS_BAD_PSF) return fail(c, PCMD_E_INVAL, "a PSF band has a negative or non-finite value or does not sum to 1 within 1e-3");
+    return fail(c, PCMD_E_PTRS_RETRY, "a transformed-rejection draw exhausted its %d attempts", PTRS_MAX_ATTEMPTS);
+  }
+  c->err.clear();
+  return PCMD_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// a0 host helpers
+// ------------------------------------------------------------------------------------------
+
+int pcmd_grid_prepare(int32_t E, int32_t B, const int32_t *iso, const double *mass, const double *absmag,
+                      double alpha, double *imf_w, float *flux) {
+  if (E <= 0 || B < 1 || B > PCMD_MAX_BANDS || !iso || !mass || !absmag || !imf_w || !flux) return PCMD_E_INVAL;
+  if (!(alpha > 1.0) || !isfinite(alpha)) return PCMD_E_INVAL;
+  int start = 0;
+  while (start < E) {
+    int end = start + 1;
+    while (end < E && iso[end] == iso[start]) ++end;
+    const int P = end - start;
+    for (int i = start; i < end; ++i) {
+      if (!(mass[i] > 0.0) || !isfinite(mass[i])) return PCMD_E_INVAL;
+      if (i > start && !(mass[i] > mass[i - 1])) return PCMD_E_INVAL;
+    }
+    for (int i = start; i < end; ++i) {
+      double lo, hi;
+      if (P == 1) {
+        lo = mass[i] * 0.99;
+        hi = mass[i] * 1.01;
+      } else {
+        const double l = log(mass[i]);
+        const double lprev = i > start ? log(mass[i - 1]) : l - (log(mass[i + 1]) - l);
+        const double lnext = i + 1 < end ? log(mass[i + 1]) : l + (l - log(mass[i - 1]));
+        lo = exp(0.5 * (lprev + l));
+        hi = exp(0.5 * (l + lnext));
+      }
+      imf_w[i] = (pow(lo, 1.0 - alpha) - pow(hi, 1.0 - alpha)) / (alpha - 1.0);
+    }
+    start = end;
+  }
+  for (int b = 0; b < B; ++b)
+    for (int i = 0; i < E; ++i) {
+      const double m = absmag[(size_t)b * E + i];
+      if (!isfinite(m)) return PCMD_E_INVAL;
+      flux[(size_t)b * E + i] = (float)pow(10.0, -0.4 * m);
+    }
+  return PCMD_OK;
+}
+
+int pcmd_iso_weights(const pcmd_model *m, const pcmd_isoset *set, double *w_out, double *npix_out) {
+  if (!m || !set || !w_out || !npix_out) return PCMD_E_INVAL;
+  const int na = set->n_age, nf = set->n_feh, ni = set->n_iso;
+  if (na < 1 || nf < 1 || ni < 1 || ni > PCMD_MAX_ISO || !set->age_edges || !set->feh_grid || !set->iso_age ||
+      !set->iso_feh)
+    return PCMD_E_INVAL;
+  std::vector<double> wa(na, 0.0), wz(nf, 0.0);
+  const double T = pow(10.0, 10.2);
+  double npix = pow(10.0, m->log_npix);
+  switch (m->sfh) {
+    case PCMD_SFH_SSP:
+      if (m->ssp_age_index < 0 || m->ssp_age_index >= na) return PCMD_E_INVAL;
+      wa[m->ssp_age_index] = 1.0;
+      break;
+    case PCMD_SFH_CONST:
+      for (int a = 0; a < na; ++a) wa[a] = pow(10.0, set->age_edges[a + 1]) - pow(10.0, set->age_edges[a]);
+      break;
+    case PCMD_SFH_TAU:
+    case PCMD_SFH_DTAU: {
+      if (!(m->tau_gyr > 0.0)) return PCMD_E_INVAL;
+      const double tau = m->tau_gyr * 1e9;
+      for (int a = 0; a < na; ++a) {
+        const double t1 = T - pow(10.0, set->age_edges[a + 1]);  // onset-relative time at the older edge
+        const double t2 = T - pow(10.0, set->age_edges[a]);
+        if (m->sfh == PCMD_SFH_TAU) {
+          wa[a] = tau * (exp(-t1 / tau) - exp(-t2 / tau));
+        } else {
+          wa[a] = -tau * (t2 + tau) * exp(-t2 / tau) + tau * (t1 + tau) * exp(-t1 / tau);
+        }
+      }
+      break;
+    }
+    case PCMD_SFH_NONPARAM: {
+      if (!m->log_sfh) return PCMD_E_INVAL;
+      npix = 0.0;
+      for (int a = 0; a < na; ++a) {
+        wa[a] = pow(10.0, m->log_sfh[a]);
+        npix += wa[a];
+      }
+      break;
+    }
+    default:
+      return PCMD_E_INVAL;
+  }
+  if (m->mdf == PCMD_MDF_SINGLE) {
+    if (m->feh_index < 0 || m->feh_index >= nf) return PCMD_E_INVAL;
+    wz[m->feh_index] = 1.0;
+  } else if (m->mdf == PCMD_MDF_GAUSS) {
+    if (!(m->feh_sigma > 0.0)) return PCMD_E_INVAL;
+    double s = 0.0;
+    for (int f = 0; f < nf; ++f) {
+      const double z = (set->feh_grid[f] - m->feh_mu) / m->feh_sigma;
+      wz[f] = exp(-0.5 * z * z);
+      s += wz[f];
+    }
+    double s2 = 0.0;
+    for (int f = 0; f < nf; ++f) {
+      wz[f] /= s;
+      if (wz[f] < m->mdf_prune) wz[f] = 0.0;
+      s2 += wz[f];
+    }
+    if (!(s2 > 0.0)) return PCMD_E_INVAL;
+    for (int f = 0; f < nf; ++f) wz[f] /= s2;
+  } else {
+    return PCMD_E_INVAL;
+  }
+  for (int k = 0; k < ni; ++k) {
+    const int a = set->iso_age[k], f = set->iso_feh[k];
+    if (a < 0 || a >= na || f < 0 || f >= nf) return PCMD_E_INVAL;
+    w_out[k] = wa[a] * wz[f];
+  }
+  if (!(npix > 0.0) || !isfinite(npix)) return PCMD_E_INVAL;
+  *npix_out = npix;
+  return PCMD_OK;
+}
+
+int pcmd_entries(pcmd_ctx *c, const pcmd_grid *g, const double *iso_w, double npix, double *lam_out,
+                 pcmd_stream stream) {
+  if (!c) return PCMD_E_INVAL;
+  if (!g || !iso_w || !lam_out) return fail(c, PCMD_E_INVAL, "pcmd_entries: null argument");
+  if (g->n_entries <= 0 || g->n_iso <= 0 || g->n_iso > PCMD_MAX_ISO || !g->iso_of_entry || !g->imf_w ||
+      !g->iso_imf_sum)
+    return fail(c, PCMD_E_INVAL, "pcmd_entries: bad grid (E=%d, n_iso=%d)", g->n_entries, g->n_iso);
+  if (!(npix > 0.0) || !isfinite(npix)) return fail(c, PCMD_E_INVAL, "pcmd_entries: npix must be positive");
+  double norm = 0.0;
+  for (int k = 0; k < g->n_iso; ++k) {
+    if (!(iso_w[k] >= 0.0) || !isfinite(iso_w[k])) return fail(c, PCMD_E_INVAL, "pcmd_entries: bad iso weight %d", k);
+    norm += iso_w[k] * g->iso_imf_sum[k];
+  }
+  if (!(norm > 0.0) || !isfinite(norm)) return fail(c, PCMD_E_INVAL, "pcmd_entries: all weights are zero");
+  double scale[PCMD_MAX_ISO];
+  for (int k = 0; k < g->n_iso; ++k) scale[k] = npix * iso_w[k] / norm;
+  DeviceGuard dg(c->device);
+  hipError_t e = launch_entries(g, scale, lam_out, c->status, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "k_entries");
+  c->err.clear();
+  return PCMD_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// a1-a4
+// ------------------------------------------------------------------------------------------
+
+int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *mags, const pcmd_debug *dbg,
+                  pcmd_stream stream) {
+  if (!c) return PCMD_E_INVAL;
+  if (!iso || !o || !mags) return fail(c, PCMD_E_INVAL, "pcmd_simulate: null argument");
+  const int E = iso->n_entries, B = iso->n_bands;
+  if (E <= 0 || E > (1 << 26)) return fail(c, PCMD_E_INVAL, "pcmd_simulate: n_entries %d out of range", E);
+  if (B < 1 || B > PCMD_MAX_BANDS) return fail(c, PCMD_E_INVAL, "pcmd_simulate: n_bands %d out of range", B);
+  if (!iso->lam || !iso->flux) return fail(c, PCMD_E_INVAL, "pcmd_simulate: null lam/flux");
+  const int N = o->nim;
+  if (N < 1 || N > 8192) return fail(c, PCMD_E_INVAL, "pcmd_simulate: nim %d out of range", N);
+  const int64_t npx = (int64_t)N * N;
+  if (!isfinite(o->dmod)) return fail(c, PCMD_E_INVAL, "pcmd_simulate: dmod not finite");
+  if (o->dust_model < 0 || o->dust_model > 2) return fail(c, PCMD_E_INVAL, "pcmd_simulate: bad dust_model");
+  if (o->dust_model != PCMD_DUST_NONE) {
+    if (!(o->dust_frac >= 0.0 && o->dust_frac <= 1.0)) return fail(c, PCMD_E_INVAL, "pcmd_simulate: dust_frac outside [0,1]");
+    if (!isfinite(o->dust_mu) || !(o->dust_sigma >= 0.0) || !isfinite(o->dust_sigma))
+      return fail(c, PCMD_E_INVAL, "pcmd_simulate: bad dust parameters");
+    for (int b = 0; b < B; ++b)
+      if (!isfinite(o->dust_R[b])) return fail(c, PCMD_E_INVAL, "pcmd_simulate: dust_R not finite");
+  }
+  const int K = o->psf_k;
+  if (K < 1 || (K & 1) == 0 || K > N || K > PCMD_MAX_PSF_K)
+    return fail(c, PCMD_E_INVAL, "pcmd_simulate: psf_k %d must be odd, <= nim and <= %d", K, PCMD_MAX_PSF_K);
+  if (K > 1 && !o->psf) return fail(c, PCMD_E_INVAL, "pcmd_simulate: psf is NULL");
+  if (o->conv_path < 0 || o->conv_path > 2) return fail(c, PCMD_E_INVAL, "pcmd_simulate: bad conv_path");
+  if (o->noise_model < 0 || o->noise_model > 2) return fail(c, PCMD_E_INVAL, "pcmd_simulate: bad noise_model");
+  for (int b = 0; b < B; ++b) {
+    if (o->noise_model == PCMD_NOISE_GAUSS_MAG && !(o->noise_sigma_mag[b] >= 0.0 && isfinite(o->noise_sigma_mag[b])))
+      return fail(c, PCMD_E_INVAL, "pcmd_simulate: bad noise_sigma_mag");
+    if (o->noise_model == PCMD_NOISE_SHOT &&
+        (!(o->exptime[b] > 0.0) || !isfinite(o->exptime[b]) || !isfinite(o->zp[b]) || !(o->sky[b] >= 0.0)))
+      return fail(c, PCMD_E_INVAL, "pcmd_simulate: bad exptime/zp/sky");
+  }
+  int64_t px0 = 0, px1 = 0;
+  if (dbg && (dbg->counts || dbg->reddened)) {
+    px0 = dbg->px0;
+    px1 = dbg->px1;
+    if (!dbg->counts || px0 < 0 || px1 <= px0 || px1 > npx)
+      return fail(c, PCMD_E_INVAL, "pcmd_simulate: bad debug window [%lld, %lld)", (long long)px0, (long long)px1);
+  }
+  const bool use_fft = o->conv_path == PCMD_CONV_FFT || (o->conv_path == PCMD_CONV_AUTO && K >= 31 && fft_supported(N));
+  if (K > 1 && use_fft && !fft_supported(N))
+    return fail(c, PCMD_E_UNSUPPORTED, "pcmd_simulate: FFT path needs nim a power of two in [8, 4096]");
+  hipStream_t s = (hipStream_t)stream;
+  DeviceGuard dg(c->device);
+  const int BP = B <= 2 ? 2 : 4;
+  const int nchunks = (E + CHUNK - 1) / CHUNK;
+  const bool split = o->dust_model != PCMD_DUST_NONE && o->dust_frac > 0.0;
+  const int S = split ? 2 : 1;
+  int r;
+  if ((r = ensure(c, c->rec, (size_t)E * sizeof(EntryRec), "entry records"))) return r;
+  if ((r = ensure(c, c->thr, (size_t)E * THR_STRIDE * 4, "thresholds"))) return r;
+  if ((r = ensure(c, c->pc, (size_t)E * sizeof(PtrsConst), "rejection constants"))) return r;
+  if ((r = ensure(c, c->fl64, (size_t)E * BP * 8, "fluxes"))) return r;
+  if ((r = ensure(c, c->part, (size_t)nchunks * S * B * npx * 8, "partial sums"))) return r;
+  if ((r = ensure(c, c->F, (size_t)B * npx * 4, "image"))) return r;
+  if ((r = ensure(c, c->G, (size_t)B * npx * 4, "convolved image"))) return r;
+  if (K > 1 && (r = ensure(c, c->psf64, (size_t)B * K * K * 8, "psf"))) return r;
+  if (K > 1 && use_fft && (r = ensure(c, c->fft, fft_scratch_bytes(B, N), "fft"))) return r;
+
+  EntryTables t;
+  t.E = E;
+  t.B = B;
+  t.BP = BP;
+  t.rec = (EntryRec *)c->rec.p;
+  t.thr = (uint32_t *)c->thr.p;
+  t.pc = c->pc.p;
+  t.fl64 = (double *)c->fl64.p;
+  hipError_t e = launch_prep(iso->lam, iso->flux, t, c->status, s);
+  if (e != hipSuccess) return hip_fail(c, e, "k_prep");
+
+  const uint32_t k0 = (uint32_t)(o->seed & 0xFFFFFFFFu), k1 = (uint32_t)(o->seed >> 32);
+  if (dbg && dbg->counts) {
+    e = launch_fill_u32(dbg->counts, 0u, (px1 - px0) * E, s);
+    if (e == hipSuccess && dbg->reddened) e = launch_fill_u32(dbg->reddened, 0u, (px1 - px0) * E, s);
+    if (e != hipSuccess) return hip_fail(c, e, "clearing debug counts");
+  }
+  SampleArgs a;
+  a.E = E;
+  a.B = B;
+  a.BP = BP;
+  a.npx = (int)npx;
+  a.nchunks = nchunks;
+  a.S = S;
+  a.k0 = k0;
+  a.k1 = k1;
+  a.split_mode = !split ? SPLIT_NONE : (o->dust_frac >= 1.0 ? SPLIT_ALL : (o->dust_frac == 0.5 ? SPLIT_HALF : SPLIT_GENERAL));
+  a.split_q = (uint32_t)fmin(floor(o->dust_frac * 4294967296.0), 4294967295.0);
+  a.part = (double *)c->part.p;
+  a.dbg_counts = dbg ? dbg->counts : nullptr;
+  a.dbg_red = dbg ? dbg->reddened : nullptr;
+  a.px0 = px0;
+  a.px1 = px1;
+  a.status = c->status;
+  a.lnfact = c->lnfact;
+  {
+    ScopedTimer tm(c, PCMD_TIMER_SAMPLE, (double)npx * (double)E, s);
+    e = launch_sample(t, a, s);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "k_sample");
+
+  ReduceArgs ra;
+  ra.B = B;
+  ra.npx = (int)npx;
+  ra.nchunks = nchunks;
+  ra.S = S;
+  ra.part = (const double *)c->part.p;
+  ra.F = (float *)c->F.p;
+  ra.dist = pow(10.0, -0.4 * o->dmod);
+  ra.dust_model = o->dust_model;
+  ra.dust_mu = o->dust_mu;
+  ra.dust_sigma = o->dust_sigma;
+  for (int b = 0; b < PCMD_MAX_BANDS; ++b) ra.dust_R[b] = b < B ? o->dust_R[b] : 0.0;
+  ra.k0 = k0;
+  ra.k1 = k1;
+  e = launch_reduce(ra, s);
+  if (e != hipSuccess) return hip_fail(c, e, "k_reduce");
+  if (dbg && dbg->flux_pre) {
+    e = launch_copy_f32((const float *)c->F.p, dbg->flux_pre, (int64_t)B * npx, s);
+    if (e != hipSuccess) return hip_fail(c, e, "copy flux_pre");
+  }
+  const float *Gp = (const float *)c->F.p;
+  if (K > 1) {
+    e = launch_psf64(o->psf, B, K, (double *)c->psf64.p, c->status, s);
+    if (e != hipSuccess) return hip_fail(c, e, "psf check");
+    ScopedTimer tm(c, PCMD_TIMER_CONV, 2.0 * (double)B * (double)npx, s);
+    if (use_fft) {
+      e = launch_conv_fft((const float *)c->F.p, o->psf, B, N, K, (float *)c->G.p, c->fft.p, s);
+      if (e != hipSuccess) return hip_fail(c, e, "fft convolution");
+    } else {
+      e = launch_conv_direct((const float *)c->F.p, (const double *)c->psf64.p, B, N, K, (float *)c->G.p, s);
+      if (e != hipSuccess) return hip_fail(c, e, "direct convolution");
+    }
+    Gp = (const float *)c->G.p;
+  }
+  if (dbg && dbg->flux_psf) {
+    e = launch_copy_f32(Gp, dbg->flux_psf, (int64_t)B * npx, s);
+    if (e != hipSuccess) return hip_fail(c, e, "copy flux_psf");
+  }
+  NoiseArgs na;
+  na.B = B;
+  na.npx = (int)npx;
+  na.G = Gp;
+  na.mags = mags;
+  na.noise_model = o->noise_model;
+  for (int b = 0; b < PCMD_MAX_BANDS; ++b) {
+    na.sigma[b] = b < B ? o->noise_sigma_mag[b] : 0.0;
+    na.exptime[b] = b < B ? o->exptime[b] : 1.0;
+    na.zp[b] = b < B ? o->zp[b] : 0.0;
+    na.sky[b] = b < B ? o->sky[b] : 0.0;
+  }
+  na.k0 = k0;
+  na.k1 = k1;
+  e = launch_noise_mag(na, s);
+  if (e != hipSuccess) return hip_fail(c, e, "k_noise_mag");
+  c->err.clear();
+  return PCMD_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// a5, a6
+// ------------------------------------------------------------------------------------------
+
+int pcmd_hess(pcmd_ctx *c, const float *mags, int32_t B, int64_t npx, const pcmd_hess_grid *g, uint32_t *hess,
+              double *moments, pcmd_stream stream) {
+  if (!c) return PCMD_E_INVAL;
+  if (!mags || !g || !hess || !moments) return fail(c, PCMD_E_INVAL, "pcmd_hess: null argument");
+  if (B < 1 || B > PCMD_MAX_BANDS) return fail(c, PCMD_E_INVAL, "pcmd_hess: n_bands %d out of range", B);
+  if (npx < 1 || npx > (int64_t)1 << 31) return fail(c, PCMD_E_INVAL, "pcmd_hess: n_px out of range");
+  if (g->nx < 1 || g->ny < 1 || (int64_t)g->nx * g->ny > 65536)
+    return fail(c, PCMD_E_INVAL, "pcmd_hess: grid %d x %d out of range", g->nx, g->ny);
+  if (!(g->dx > 0.0) || !(g->dy > 0.0) || !isfinite(g->x0) || !isfinite(g->y0) || !isfinite(g->dx) || !isfinite(g->dy))
+    return fail(c, PCMD_E_INVAL, "pcmd_hess: bad grid origin or width");
+  if (g->b_blue < 0 || g->b_blue >= B || g->b_red < 0 || g->b_red >= B || g->b_mag < 0 || g->b_mag >= B)
+    return fail(c, PCMD_E_INVAL, "pcmd_hess: band index out of range");
+  DeviceGuard dg(c->device);
+  int r = ensure(c, c->mom_part, (size_t)hess_max_blocks() * 3 * 8, "moment partials");
+  if (r) return r;
+  hipError_t e;
+  {
+    ScopedTimer tm(c, PCMD_TIMER_HESS, (double)npx, (hipStream_t)stream);
+    e = launch_hess(mags, B, npx, *g, hess, moments, (double *)c->mom_part.p, c->counter, (hipStream_t)stream);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "k_hess");
+  c->err.clear();
+  return PCMD_OK;
+}
+
+int pcmd_loglike(pcmd_ctx *c, const uint32_t *hm, const uint32_t *hd, int32_t nbins, const double *mom_m,
+                 const double *mom_d, int32_t mode, double eps, double *out, pcmd_stream stream) {
+  if (!c) return PCMD_E_INVAL;
+  if (!hm || !hd || !out) return fail(c, PCMD_E_INVAL, "pcmd_loglike: null argument");
+  if (nbins < 1 || nbins > 65536) return fail(c, PCMD_E_INVAL, "pcmd_loglike: n_bins %d out of range", nbins);
+  if (mode < 0 || mode > 2) return fail(c, PCMD_E_INVAL, "pcmd_loglike: bad mode %d", mode);
+  if (mode == PCMD_LL_POISSON && !(eps > 0.0 && isfinite(eps))) return fail(c, PCMD_E_INVAL, "pcmd_loglike: eps must be > 0");
+  if (mode != PCMD_LL_POISSON && (!mom_m || !mom_d)) return fail(c, PCMD_E_INVAL, "pcmd_loglike: moments needed");
+  DeviceGuard dg(c->device);
+  hipError_t e = launch_loglike(hm, hd, nbins, mom_m, mom_d, mode, eps, out, (hipStream_t)stream);
+  if (e != hipSuccess) return hip_fail(c, e, "k_loglike");
+  c->err.clear();
+  return PCMD_OK;
+}
+
+int pcmd_timer_enable(pcmd_ctx *c, int on) {
+  if (!c) return PCMD_E_INVAL;
+  DeviceGuard dg(c->device);
+  if (on) {
+    (void)hipDeviceSynchronize();
+    clear_timers(c);
+  }
+  c->timing = on != 0;
+  return PCMD_OK;
+}
+
+int pcmd_timer_read(pcmd_ctx *c, int which, double *total_ms, int64_t *launches, double *units) {
+  if (!c) return PCMD_E_INVAL;
+  if (which < 0 || which >= PCMD_TIMER_KINDS || !total_ms || !launches || !units)
+    return fail(c, PCMD_E_INVAL, "pcmd_timer_read: bad argument");
+  DeviceGuard dg(c->device);
+  double ms = 0.0, u = 0.0;
+  int64_t n = 0;
+  std::vector<TimerRec> keep;
+  for (auto &t : c->timers) {
+    if (t.which != which) {
+      keep.push_back(t);
+      continue;
+    }
+    float dt = 0.0f;
+    hipError_t e = hipEventSynchronize(t.stop);
+    if (e == hipSuccess) e = hipEventElapsedTime(&dt, t.start, t.stop);
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+    if (e != hipSuccess) return hip_fail(c, e, "pcmd_timer_read");
+    ms += dt;
+    u += t.units;
+    ++n;
+  }
+  c->timers.swap(keep);
+  *total_ms = ms;
+  *launches = n;
+  *units = u;
+  return PCMD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,139 @@
+// Device-side building blocks shared by the gfx950 kernels: the counter-based generator, the
+// FP32 logarithm and ln k! used by the rejection sampler, and the sampler rules themselves.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pcmd {
+
+// Philox4x32-10 (Salmon et al., SC'11): multipliers and Weyl key increments.
+constexpr uint32_t PH_M0 = 0xD2511F53u;
+constexpr uint32_t PH_M1 = 0xCD9E8D57u;
+constexpr uint32_t PH_W0 = 0x9E3779B9u;
+constexpr uint32_t PH_W1 = 0xBB67AE85u;
+
+// Stream tags (counter word 2).
+constexpr uint32_t TAG_MAIN = 0, TAG_SPLIT = 1, TAG_SPLIT_X = 2, TAG_PTRS = 3, TAG_DUST = 4, TAG_NOISE = 5;
+
+// Entry kinds written by the preparation kernel.
+constexpr uint32_t KIND_ZERO = 0, KIND_INV = 1, KIND_PTRS = 2;
+constexpr int THR_STRIDE = 64;       // thresholds per entry slot (K <= 63)
+constexpr int CHUNK = 2048;          // canonical accumulation chunk (entries)
+constexpr int PTRS_MAX_ATTEMPTS = 64;
+
+struct u4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ u4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                       uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)PH_M0 * c0;
+    const uint64_t p1 = (uint64_t)PH_M1 * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+    k0 += PH_W0;
+    k1 += PH_W1;
+  }
+  return u4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ uint32_t word_of(const u4 &w, int q) {
+  return q == 0 ? w.x : q == 1 ? w.y : q == 2 ? w.z : w.w;
+}
+
+// 32-bit word -> (0,1) with 24 significant bits, exact in FP32.
+__device__ __forceinline__ float u01_f32(uint32_t w) {
+  return ((float)(w >> 9) + 0.5f) * 1.1920928955078125e-07f;  // 2^-23
+}
+// 32-bit word -> (0,1), exact in FP64.
+__device__ __forceinline__ double u01_f64(uint32_t w) {
+  return ((double)w + 0.5) * 2.3283064365386963e-10;  // 2^-32
+}
+
+__device__ __forceinline__ double box_muller(uint32_t w0, uint32_t w1) {
+  const double u1 = u01_f64(w0), u2 = u01_f64(w1);
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+// ---------------------------------------------------------------------------------------
+// FP32 decision path of the rejection sampler.  Every step is a single correctly rounded
+// IEEE operation; contraction into fused multiply-adds is off so that the result is the same
+// integer on every IEEE implementation that takes the same steps.
+// ---------------------------------------------------------------------------------------
+#pragma clang fp contract(off)
+
+// ln x for positive normal x: x = m 2^e with m in [sqrt(1/2), sqrt(2)),
+// ln m = 2 atanh(s) = s (2 + s^2 (2/3 + s^2 (2/5 + ...))), s = (m - 1)/(m + 1).
+__device__ __forceinline__ float ln_f32(float x) {
+  const uint32_t bits = __float_as_uint(x);
+  int e = (int)((bits >> 23) & 0xFFu) - 127;
+  float m = __uint_as_float((bits & 0x007FFFFFu) | 0x3F800000u);
+  if (m > 1.41421353816986083984375f) {
+    m = m * 0.5f;
+    e += 1;
+  }
+  const float s = (m - 1.0f) / (m + 1.0f);
+  const float z = s * s;
+  float P = (float)(2.0 / 11.0);
+  P = P * z + (float)(2.0 / 9.0);
+  P = P * z + (float)(2.0 / 7.0);
+  P = P * z + (float)(2.0 / 5.0);
+  P = P * z + (float)(2.0 / 3.0);
+  P = P * z + 2.0f;
+  const float ef = (float)e;
+  const float ln2_hi = 0.693145751953125f;
+  const float ln2_lo = 1.428606765330187e-06f;
+  return ef * ln2_hi + (ef * ln2_lo + s * P);
+}
+
+// ln k! : table below 256 (FP64-built, rounded), Stirling series in x = k + 1 above.
+__device__ __forceinline__ float lnfact_f32(float kf, const float *__restrict__ table) {
+  if (kf < 256.0f) return table[(int)kf];
+  const float x = kf + 1.0f;
+  const float lx = ln_f32(x);
+  float t = (x - 0.5f) * lx;
+  t = t - x;
+  t = t + 0.9189385332046727f;
+  const float r = 1.0f / x;
+  t = t + r * (float)(1.0 / 12.0);
+  const float r3 = (r * r) * r;
+  t = t - r3 * (float)(1.0 / 360.0);
+  return t;
+}
+
+// Per-entry constants of the transformed rejection (Hormann 1993), FP32.
+struct PtrsConst {
+  float mu, lnmu, b, a, twoa, lninva, vr, pad;
+};
+
+// One attempt.  Returns true if accepted and writes k.
+__device__ __forceinline__ bool ptrs_attempt(const PtrsConst &c, uint32_t wu, uint32_t wv,
+                                             const float *__restrict__ lnfact_table, int &k_out) {
+  const float u = u01_f32(wu);
+  const float V = u01_f32(wv);
+  const float U = u - 0.5f;
+  const float us = 0.5f - fabsf(U);
+  float t = c.twoa / us;
+  t = t + c.b;
+  t = t * U;
+  t = t + c.mu;
+  t = t + 0.43f;
+  const float kf = floorf(t);
+  k_out = (int)kf;
+  if (us >= 0.07f && V <= c.vr) return true;
+  if (kf < 0.0f || (us < 0.013f && V > us)) return false;
+  float q = c.a / (us * us);
+  q = q + c.b;
+  const float lhs = (ln_f32(V) + c.lninva) - ln_f32(q);
+  const float rhs = ((-c.mu) + kf * c.lnmu) - lnfact_f32(kf, lnfact_table);
+  return lhs <= rhs;
+}
+
+#pragma clang fp contract(on)
+
+}  // namespace pcmd

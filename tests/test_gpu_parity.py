@@ -1,0 +1,320 @@
+"""GPU parity: the HIP path through the C ABI against the oracle on the same seeded inputs."""
+import math
+
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import entries as oe
+from oracle import hess as oh
+from oracle import loglike as ol
+from oracle import noise as on
+from oracle import pipeline as op
+from oracle import psf as ops
+from oracle import sampler as osamp
+from tests import parity_utils as pu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1904_00011_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _print_case(name, **kw):
+    print(f"[case] {name} " + " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def _full_compare(ctx, lam, f32, obs, conv_path=0, hgrid=None, bands=(0, 1, 1)):
+    """Whole image on both sides: counts, fluxes, magnitudes, Hess."""
+    npx = obs.nim * obs.nim
+    g = pu.gpu_simulate(ctx, lam, f32, obs, conv_path, window=(0, npx))
+    ora = op.simulate(lam, f32, obs, want_counts=True)
+    bad = pu.explain_count_mismatches(lam, obs.seed, 0, g["counts"], ora["counts"])
+    assert not bad, f"count mismatches at {bad[:5]}"
+    assert np.array_equal(g["red"], ora["red"])
+    assert np.max(pu.rel_err(g["flux_pre"], ora["F"])) <= pu.FLUX_RTOL
+    assert np.max(pu.rel_err(g["flux_psf"], ora["G"])) <= pu.FLUX_RTOL
+    ok = pu.mags_close(g["mags"], ora["mags64"])
+    assert ok.all(), f"{(~ok).sum()} magnitudes differ by more than 1e-4"
+    if hgrid is not None:
+        hg, mg = pu.gpu_hess(ctx, g["mags"], hgrid, bands)
+        ho, mo = oh.hess(ora["mags64"], hgrid, *bands)
+        near = pu.near_edge_pixels(ora["mags64"], hgrid, bands).sum()
+        assert hg.sum() == npx
+        assert pu.hess_diff_explained(hg, ho, near), (np.abs(hg - ho).sum(), near)
+    return g, ora
+
+
+def test_small_case_end_to_end(ctx):
+    """64x64, 2 bands, 500 Salpeter points at Npix=100, 5x5 PSF, 0.02 mag noise: all 2.05M counts."""
+    grid, model, obs = si.small_case()
+    lam, _, f32 = oe.build_entries(model, grid)
+    _print_case("small_case_end_to_end", nim=obs.nim, E=len(lam))
+    g, ora = _full_compare(ctx, lam, f32, obs)
+    x = np.median(ora["mags64"][0] - ora["mags64"][1])
+    y = np.median(ora["mags64"][1])
+    hgrid = si.hess_grid_from_median(x, y, 100, 100)
+    # data Hess from a second seed, likelihood on both sides
+    _, _, obs2 = si.small_case(seed=2)
+    g2 = pu.gpu_simulate(ctx, lam, f32, obs2, want_flux=False)
+    ora2 = op.simulate(lam, f32, obs2)
+    hm_g, mm_g = pu.gpu_hess(ctx, g["mags"], hgrid)
+    hd_g, md_g = pu.gpu_hess(ctx, g2["mags"], hgrid)
+    hm_o, mm_o = oh.hess(ora["mags64"], hgrid)
+    hd_o, md_o = oh.hess(ora2["mags64"], hgrid)
+    for mode in (ol.POISSON, ol.GAUSS_PAPER, ol.GAUSS_LITERAL):
+        lg = pu.gpu_loglike(ctx, hm_g, hd_g, mm_g, md_g, mode)
+        lo = ol.loglike(hm_o, hd_o, mm_o, md_o, mode)
+        assert abs(lg - lo) <= pu.LOGL_ATOL, (mode, lg, lo)
+
+
+def test_hess_bit_exact_on_identical_magnitudes(ctx):
+    """Given the same FP32 magnitudes both sides bin in FP64: Hess and counts are identical."""
+    r = np.random.default_rng(3)
+    n = 70001
+    mags = np.stack([r.normal(21, 0.7, n), r.normal(20.5, 0.6, n), r.normal(20, 0.6, n)]).astype(np.float32)
+    mags[0, :50] = np.inf
+    mags[1, 25:75] = np.inf
+    mags[2, 100:110] = -np.inf
+    mags[0, 200:210] = np.nan
+    for grid, bands in ((dict(x0=-1.0, dx=0.05, nx=60, y0=19.0, dy=0.05, ny=50), (0, 1, 1)),
+                        (dict(x0=-0.5, dx=0.02, nx=200, y0=18.5, dy=0.02, ny=200), (1, 2, 2)),
+                        (dict(x0=-3.0, dx=0.05, nx=256, y0=15.0, dy=0.05, ny=256), (0, 2, 1))):
+        _print_case("hess_identical", nx=grid["nx"], ny=grid["ny"], bands=bands)
+        hg, mg = pu.gpu_hess(ctx, mags, grid, bands)
+        ho, mo = oh.hess(mags, grid, *bands)
+        assert np.array_equal(hg, ho)
+        assert mg[2] == mo[2] and mg[0] == pytest.approx(mo[0], rel=1e-12) and mg[1] == pytest.approx(mo[1], rel=1e-12)
+
+
+def test_hess_hand_example(ctx):
+    from tests.test_oracle_pipeline import load_hess_example
+    rows, Hx = load_hess_example()
+    mags = np.array([[r[0] for r in rows], [r[1] for r in rows]], dtype=np.float32)
+    hg, _ = pu.gpu_hess(ctx, mags, dict(x0=0.0, dx=0.05, nx=4, y0=20.0, dy=0.05, ny=3))
+    assert np.array_equal(hg, Hx)
+
+
+def test_loglike_modes_against_oracle(ctx):
+    r = np.random.default_rng(4)
+    for nb in (1, 7, 10000, 40000):
+        hm = r.poisson(3.0, nb)
+        hd = r.poisson(3.0, nb)
+        if nb > 1:
+            hm[:: max(nb // 5, 1)] = 0        # empty model bins
+        hm[-1] += 1                           # a non-empty model Hess
+        mom_m = np.array([40.0 * hm.sum(), 2e3 * hm.sum(), float(hm.sum())])
+        mom_d = np.array([41.0 * hd.sum(), 2.01e3 * hd.sum(), float(hd.sum())])
+        for mode in (0, 1, 2):
+            _print_case("loglike", nbins=nb, mode=mode)
+            lg = pu.gpu_loglike(ctx, hm, hd, mom_m, mom_d, mode)
+            lo = ol.loglike(hm, hd, mom_m, mom_d, mode)
+            assert abs(lg - lo) <= max(1e-9 * abs(lo), 1e-9)
+    # an empty model Hess stays finite under the Poisson pseudo-count
+    hm = np.zeros(100, np.int64)
+    hd = r.poisson(2.0, 100)
+    lg = pu.gpu_loglike(ctx, hm, hd, [0, 0, 0], [1, 1, 1], ol.POISSON)
+    assert np.isfinite(lg) and abs(lg - ol.loglike(hm, hd, None, None, ol.POISSON)) <= 1e-9 * abs(lg)
+
+
+def test_entries_against_oracle(ctx):
+    import torch
+    import paper_1904_00011_amd as P
+    G = si.headline_grid()
+    for seed in (1000, 1001, 7):
+        model, obs = si.draw_headline_params(seed)
+        ev = P.Evaluator(ctx, G, 64, None, dict(x0=0, dx=0.05, y0=0, dy=0.05, nx=10, ny=10))
+        lam_g = ev.entries(model).cpu().numpy()
+        lam_o, _, f32 = oe.build_entries(model, G)
+        _print_case("entries", seed=seed)
+        assert np.max(pu.rel_err(lam_g, lam_o, 1e-300)[lam_o > 0]) <= 1e-12
+        assert np.all(lam_g[lam_o == 0] == 0)
+        assert np.array_equal(ev.flux_d.cpu().numpy(), f32)
+    for sfh in ("ssp", "const", "dtau", "nonparam"):
+        m = si.Model(sfh=sfh, log_npix=3.0, tau_gyr=1.5, ssp_age_index=3, mdf="single", feh_index=2,
+                     log_sfh=(1.0, 0.3, 0.5, 1.5, 2.0, 2.2, 1.0))
+        ev = P.Evaluator(ctx, G, 64, None, dict(x0=0, dx=0.05, y0=0, dy=0.05, nx=10, ny=10))
+        lam_g = ev.entries(m).cpu().numpy()
+        lam_o, _, _ = oe.build_entries(m, G)
+        _print_case("entries", sfh=sfh)
+        assert np.max(pu.rel_err(lam_g, lam_o)[lam_o > 0]) <= 1e-12
+        assert lam_g.sum() == pytest.approx(oe.npix_of(m), rel=1e-12)
+
+
+def _headline_lam(log_npix, seed=1000, stride=1):
+    G = si.headline_grid()
+    if stride > 1:
+        G = G.subsample(stride)
+    model, obs = si.draw_headline_params(seed, log_npix=log_npix)
+    lam, _, f32 = oe.build_entries(model, G)
+    return G, lam, f32, obs
+
+
+def test_headline_grid_dust_ptrs_fft_sized_psf(ctx):
+    """Headline grid (52,500 entries, 26 chunks, ragged last chunk) at Npix=1e5 (PTRS entries), log-normal dust
+    with F=1/2, shot noise, 31x31 PSF, on a 40x40 image (ragged pixel blocks)."""
+    G, lam, f32, obs = _headline_lam(5.0)
+    obs.nim = 40
+    _print_case("headline_dust_ptrs", nim=40, E=len(lam), ptrs=int((lam >= 10).sum()))
+    assert (lam >= 10).sum() > 100
+    npx = 40 * 40
+    g = pu.gpu_simulate(ctx, lam, f32, obs, window=(0, npx))
+    Fo, s = osamp.simulate_flux(lam, f32, obs, 0, npx, want_counts=True)
+    bad = pu.explain_count_mismatches(lam, obs.seed, 0, g["counts"], s["counts"])
+    assert not bad, bad[:5]
+    assert np.array_equal(g["red"], s["red"])
+    assert np.max(pu.rel_err(g["flux_pre"], Fo)) <= pu.FLUX_RTOL
+    Go = ops.convolve_periodic(Fo.reshape(3, 40, 40), obs.psf).reshape(3, npx)
+    assert np.max(pu.rel_err(g["flux_psf"], Go)) <= pu.FLUX_RTOL
+    mo = on.magnitudes(Go, obs)
+    assert pu.mags_close(g["mags"], mo).all()
+
+
+@pytest.mark.parametrize("log_npix,dust_model,frac,noise,K", [
+    (5.0, 1, 0.3, 1, 5),      # fixed screen, general split fraction (one word per star)
+    (6.0, 2, 0.5, 1, 5),      # rejection-heavy (mean lambda ~190), log-normal screen
+    (4.0, 2, 1.0, 0, 1),      # all stars reddened, no PSF, no noise
+    (3.0, 2, 0.0, 2, 3),      # dust with F = 0 (no star reddened)
+    (2.0, 0, 0.5, 1, 7),      # no dust at all
+])
+def test_dust_and_noise_variants(ctx, log_npix, dust_model, frac, noise, K):
+    G, lam, f32, obs = _headline_lam(log_npix, seed=1003, stride=10)
+    obs.nim = 24
+    obs.dust_model = dust_model
+    obs.dust_frac = frac
+    obs.noise_model = noise
+    obs.noise_sigma_mag = (0.02, 0.03, 0.04)
+    obs.psf = None if K == 1 else si.psf_stack(K, (1.0, 1.2, 1.4))
+    _print_case("variant", log_npix=log_npix, dust=dust_model, frac=frac, noise=noise, K=K, E=len(lam))
+    _full_compare(ctx, lam, f32, obs)
+
+
+def test_edge_cases(ctx):
+    # one entry, one pixel, no PSF
+    obs = si.Obs(nim=1, seed=5, dmod=20.0, psf=None, noise_model=0)
+    lam = np.array([3.0])
+    f32 = np.array([[1.0], [0.5]], dtype=np.float32)
+    _print_case("edge_one_entry_one_pixel")
+    _full_compare(ctx, lam, f32, obs)
+    # ragged group of entries, odd image, PSF as wide as the image, zero-lambda entries
+    r = np.random.default_rng(6)
+    lam = r.uniform(0, 2, 7)
+    lam[2] = 0.0
+    lam[5] = 12.5
+    f32 = r.uniform(0.1, 1, (2, 7)).astype(np.float32)
+    obs = si.Obs(nim=17, seed=9, dmod=22.0, psf=si.psf_stack(17, (3.0, 4.0)), noise_model=1,
+                 noise_sigma_mag=(0.02, 0.02), dust_model=2, dust_frac=0.5, dust_R=(3.0, 2.0))
+    _print_case("edge_ragged", nim=17, E=7)
+    _full_compare(ctx, lam, f32, obs)
+    # all entries zero: every pixel empty -> +inf magnitudes, NaN colours in bin 0
+    lam0 = np.zeros(9)
+    obs0 = si.Obs(nim=8, seed=1, dmod=25.0, psf=si.psf_stack(3, (1.0, 1.0)), noise_model=1, noise_sigma_mag=(0.02, 0.02))
+    _print_case("edge_empty_pixels")
+    g = pu.gpu_simulate(ctx, lam0, f32[:, :1].repeat(9, axis=1), obs0, window=(0, 64))
+    assert (g["counts"] == 0).all() and np.isinf(g["mags"]).all()
+    hg, mg = pu.gpu_hess(ctx, g["mags"], dict(x0=0.0, dx=0.05, nx=5, y0=20.0, dy=0.05, ny=4))
+    assert hg[3, 0] == 64 and mg[2] == 0
+    # one band
+    lam1 = np.array([0.5, 2.0, 11.0])
+    f1 = np.array([[1.0, 0.2, 0.05]], dtype=np.float32)
+    obs1 = si.Obs(nim=9, seed=2, dmod=24.0, psf=si.psf_stack(3, (1.0,)), noise_model=1, noise_sigma_mag=(0.05,))
+    _print_case("edge_one_band")
+    _full_compare(ctx, lam1, f1, obs1)
+
+
+def test_determinism_and_streams(ctx):
+    import torch
+    G, lam, f32, obs = _headline_lam(4.0, seed=1004, stride=5)
+    obs.nim = 48
+    a = pu.gpu_simulate(ctx, lam, f32, obs, window=(100, 300))
+    b = pu.gpu_simulate(ctx, lam, f32, obs, window=(100, 300))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        c = pu.gpu_simulate(ctx, lam, f32, obs, window=(100, 300), stream=s)
+    for k in ("counts", "red", "flux_pre", "flux_psf", "mags"):
+        assert np.array_equal(a[k], b[k]) and np.array_equal(a[k], c[k]), k
+    # the counts do not depend on the debug window
+    d = pu.gpu_simulate(ctx, lam, f32, obs, window=(200, 260))
+    assert np.array_equal(d["counts"], a["counts"][100:160])
+
+
+def test_device_side_validation(ctx):
+    import paper_1904_00011_amd as P
+    obs = si.Obs(nim=8, seed=1, dmod=25.0, psf=None, noise_model=0)
+    f32 = np.ones((2, 3), np.float32)
+    for bad in (np.array([1.0, np.nan, 0.1]), np.array([1.0, -0.5, 0.1]), np.array([1.0, 5e6, 0.1])):
+        with pytest.raises(P.PcmdError) as ei:
+            pu.gpu_simulate(ctx, bad, f32, obs, want_flux=False)
+        assert ei.value.code == P._lib.E_INVAL
+    obs.psf = (si.psf_stack(3, (1.0, 1.0)) * 1.1).astype(np.float32)
+    with pytest.raises(P.PcmdError):
+        pu.gpu_simulate(ctx, np.array([1.0, 0.5, 0.1]), f32, obs, want_flux=False)
+    ctx.sync()
+
+
+def test_host_side_validation(ctx):
+    import torch
+    import paper_1904_00011_amd as P
+    dev = torch.device("cuda")
+    lam = torch.ones(3, dtype=torch.float64, device=dev)
+    flux = torch.ones((2, 3), dtype=torch.float32, device=dev)
+    mags = torch.empty((2, 64), dtype=torch.float32, device=dev)
+    for kw in (dict(nim=0), dict(nim=8, psf_k=4), dict(nim=8, dust_frac=1.5, dust_model=2), dict(nim=8, noise_model=5)):
+        o = si.Obs(nim=kw.get("nim", 8), seed=1, dmod=25.0, psf=None, noise_model=kw.get("noise_model", 0),
+                   dust_model=kw.get("dust_model", 0), dust_frac=kw.get("dust_frac", 0.5))
+        psf = None
+        if "psf_k" in kw:
+            psf = torch.ones((2, 4, 4), dtype=torch.float32, device=dev) / 16
+        with pytest.raises(P.PcmdError) as ei:
+            ctx.simulate(lam, flux, o, mags, psf=psf)
+        assert ei.value.code == P._lib.E_INVAL
+    h = torch.empty(10, dtype=torch.int32, device=dev)
+    mom = torch.empty(3, dtype=torch.float64, device=dev)
+    with pytest.raises(P.PcmdError):
+        ctx.hess(mags, 2, 64, dict(x0=0, dx=0.0, y0=0, dy=0.05, nx=5, ny=2), h, mom)
+    with pytest.raises(P.PcmdError):
+        ctx.hess(mags, 2, 64, dict(x0=0, dx=0.05, y0=0, dy=0.05, nx=5, ny=2), h, mom, bands=(0, 2, 1))
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    with pytest.raises(P.PcmdError):
+        ctx.loglike(h, h, mom, mom, out, mode=0, eps=0.0)
+
+
+def test_headline_full_size_sampled(ctx):
+    """256x256 image with the full 52,500-entry grid, in the benchmark's configuration: counts and fluxes
+    on sampled pixels, post-PSF flux and magnitude of one pixel from its oracle-computed neighbourhood,
+    flux conservation and the Hess total over the whole image."""
+    import torch
+    import paper_1904_00011_amd as P
+    G = si.headline_grid()
+    model, obs = si.draw_headline_params(1000)
+    lam, _, f32 = oe.build_entries(model, G)
+    N = obs.nim
+    npx = N * N
+    _print_case("headline_full_size", nim=N, E=len(lam), log_npix=round(model.log_npix, 3))
+    for px0 in (0, 33333):
+        g = pu.gpu_simulate(ctx, lam, f32, obs, window=(px0, px0 + 48))
+        Fo, s = osamp.simulate_flux(lam, f32, obs, px0, px0 + 48, want_counts=True)
+        assert not pu.explain_count_mismatches(lam, obs.seed, px0, g["counts"], s["counts"])
+        assert np.array_equal(g["red"], s["red"])
+        assert np.max(pu.rel_err(g["flux_pre"][:, px0:px0 + 48], Fo)) <= pu.FLUX_RTOL
+    # total flux is conserved by the normalised periodic PSF
+    for b in range(3):
+        assert g["flux_psf"][b].astype(np.float64).sum() == pytest.approx(g["flux_pre"][b].astype(np.float64).sum(), rel=1e-5)
+    # one pixel after the PSF: the oracle builds its 31x31 neighbourhood
+    y0, x0 = 100, 200
+    K, h = 31, 15
+    nb = np.array([((y0 + dy) % N) * N + (x0 + dx) % N for dy in range(-h, h + 1) for dx in range(-h, h + 1)])
+    Fr, _ = osamp.simulate_flux(lam, f32, obs, px=nb)
+    Fn = Fr.reshape(3, K, K)
+    Gp = np.einsum("buv,buv->b", obs.psf.astype(np.float64)[:, ::-1, ::-1], Fn)
+    p = y0 * N + x0
+    assert np.max(pu.rel_err(g["flux_psf"][:, p], Gp)) <= pu.FLUX_RTOL
+    mo = on.magnitudes(Gp[:, None], obs, px=np.array([p]))
+    assert pu.mags_close(g["mags"][:, p:p + 1], mo).all()
+    hg, mg = pu.gpu_hess(ctx, g["mags"], si.hess_grid_from_median(0.5, 30.0, 100, 100))
+    assert hg.sum() == npx

@@ -1,0 +1,87 @@
+"""CPU-only checks of the C ABI: the library loads, exports every declared entry point, its
+host-side helpers agree with the oracle, and argument validation needs no GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import entries as oe
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pcmd.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1904_00011_amd import _lib, build
+    if not os.path.exists(_lib.LIB_PATH):
+        build.build()
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pcmd_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version_string(lib):
+    assert lib.pcmd_version().decode().startswith("pcmd gfx950")
+
+
+def test_grid_prepare_matches_oracle():
+    from paper_1904_00011_amd import _lib
+    for g in (si.small_case()[0], si.headline_grid()):
+        w, f = _lib.grid_prepare(g.iso_of_entry, g.mass, g.absmag, 2.35)
+        wo = oe.imf_weights(g, 2.35)
+        assert np.max(np.abs(w / wo - 1)) < 1e-12
+        _, f64, f32 = oe.build_entries(si.Model(sfh="const", mdf="gauss" if g.n_iso > 1 else "single"), g)
+        assert np.max(np.abs(f.astype(np.float64) / f32.astype(np.float64) - 1)) <= 6e-8
+
+
+def test_iso_weights_match_oracle():
+    from paper_1904_00011_amd import _lib
+    G = si.headline_grid()
+    models = [si.draw_headline_params(s)[0] for s in range(5)]
+    models += [si.Model(sfh=k, log_npix=3.1, tau_gyr=0.7, ssp_age_index=2, mdf=m, feh_index=1, feh_mu=0.1,
+                        log_sfh=(0.1, 0.2, 0.3, 1.0, 2.0, 1.5, 0.5)) for k in ("ssp", "const", "tau", "dtau", "nonparam")
+               for m in ("single", "gauss")]
+    for m in models:
+        w, npix = _lib.iso_weights(m, G)
+        wo = oe.iso_weights(m, G)
+        # the library normalises the MDF and leaves the age weights unnormalised, like the oracle
+        nz = wo > 0
+        assert np.array_equal(nz, w > 0)
+        assert np.max(np.abs(w[nz] / wo[nz] - 1)) < 1e-12
+        assert npix == pytest.approx(oe.npix_of(m), rel=1e-14)
+
+
+def test_host_helper_validation():
+    from paper_1904_00011_amd import _lib
+    g = si.small_case()[0]
+    with pytest.raises(_lib.PcmdError):
+        _lib.grid_prepare(g.iso_of_entry, g.mass, g.absmag, 0.5)
+    bad_mass = g.mass.copy()
+    bad_mass[10] = bad_mass[9]
+    with pytest.raises(_lib.PcmdError):
+        _lib.grid_prepare(g.iso_of_entry, bad_mass, g.absmag, 2.35)
+    with pytest.raises(_lib.PcmdError):
+        _lib.iso_weights(si.Model(sfh="tau", tau_gyr=-1.0, mdf="single"), si.headline_grid())
+
+
+def test_null_context_is_rejected_without_a_gpu(lib):
+    assert lib.pcmd_simulate(None, None, None, None, None, None) == -1
+    assert lib.pcmd_hess(None, None, 2, 10, None, None, None, None) == -1
+    assert lib.pcmd_loglike(None, None, None, 1, None, None, 0, 0.01, None, None) == -1
+    assert lib.pcmd_entries(None, None, None, 1.0, None, None) == -1
+    assert lib.pcmd_last_error(None) == b"null context"
