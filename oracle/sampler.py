@@ -21,14 +21,18 @@ How a Poisson count is drawn is not fixed by the paper.  The rule here:
   Stirling series.  Both sides of the parity test take the same FP32 steps.
 * C3, dust split -- each of the n stars is reddened independently with
   probability F_dust (reading of "fraction of stars that are reddened").  For
-  F_dust = 1/2 one random bit per star, otherwise one 32-bit word per star
-  compared with floor(F * 2^32).
+  F_dust = 1/2 one random bit per star: the first 8 stars of entry i use byte
+  (i mod 16) of Philox(pixel, i // 16, TAG_SPLIT, 0) (word (i mod 16) // 4, bits
+  8 (i mod 4) upward), star 8 + t uses bit t mod 32 of word (t mod 128) // 32 of
+  Philox(pixel, i, TAG_SPLIT_X, t // 128).  For any other fraction star s uses
+  word s mod 4 of Philox(pixel, i, TAG_SPLIT_X, s // 4), reddened iff the word is
+  below floor(F * 2^32).
 
 Random words come from Philox4x32-10 keyed by the seed with counters
 (pixel, entry // 4, TAG_MAIN, 0) word entry % 4 (inversion),
 (pixel, entry, TAG_PTRS, j) (rejection attempts 2j and 2j+1),
-(pixel, entry // 4, TAG_SPLIT, 0) word entry % 4 and (pixel, entry, TAG_SPLIT_X, j)
-(dust split), and (pixel, 0, TAG_DUST, 0) (per-pixel dust).
+(pixel, entry // 16, TAG_SPLIT, 0) and (pixel, entry, TAG_SPLIT_X, j) (dust split),
+and (pixel, 0, TAG_DUST, 0) (per-pixel dust).
 
 Pins: threshold tables against the Poisson pmf to 2^-32; the PTRS sampler by
 chi-square and moment tests; the project logarithm against np.log; the split
@@ -207,42 +211,21 @@ def popcount32(w: np.ndarray) -> np.ndarray:
     return np.bitwise_count(np.asarray(w, dtype=np.uint64)).astype(np.int64)
 
 
-def split_reddened(n: np.ndarray, first_word: np.ndarray, frac: float, seed: int,
+SPLIT_FIRST_BITS = 8     # stars covered by the entry's byte of the 16-entry split block
+
+
+def split_first_byte(px: np.ndarray, entry: int, seed: int) -> np.ndarray:
+    """Byte (entry mod 16) of Philox(pixel, entry // 16, TAG_SPLIT, 0), as uint32."""
+    w = philox4x32_10(px, entry // 16, TAG_SPLIT, 0, seed)[(entry % 16) // 4]
+    return (np.asarray(w, dtype=np.uint32) >> np.uint32(8 * (entry % 4))) & np.uint32(0xFF)
+
+
+def split_reddened(n: np.ndarray, first_byte: np.ndarray, frac: float, seed: int,
                    px: np.ndarray, entry: int) -> np.ndarray:
-    """Number of the n stars that sit behind the dust screen (C3)."""
-    n = np.asarray(n, dtype=np.int64)
-    if frac <= 0.0:
-        return np.zeros_like(n)
-    if frac >= 1.0:
-        return n.copy()
-    r = np.zeros_like(n)
-    if frac == 0.5:
-        m = np.minimum(n, 32)
-        mask = np.where(m >= 32, np.uint64(0xFFFFFFFF),
-                        (np.uint64(1) << m.astype(np.uint64)) - np.uint64(1))
-        r += popcount32(np.asarray(first_word, dtype=np.uint64) & mask)
-        extra = n - 32
-        j = 0
-        while np.any(extra > 128 * j):
-            w = philox4x32_10(px, entry, TAG_SPLIT_X, j, seed)
-            for q in range(4):
-                base = 128 * j + 32 * q
-                cnt = np.clip(extra - base, 0, 32)
-                mk = np.where(cnt >= 32, np.uint64(0xFFFFFFFF),
-                              (np.uint64(1) << cnt.astype(np.uint64)) - np.uint64(1))
-                r += popcount32(np.asarray(w[q], dtype=np.uint64) & mk)
-            j += 1
-        return r
-    fq = np.uint64(int(math.floor(frac * 4294967296.0)))
-    r += ((n >= 1) & (np.asarray(first_word, dtype=np.uint64) < fq)).astype(np.int64)
-    j = 0
-    while np.any(n - 1 > 4 * j):
-        w = philox4x32_10(px, entry, TAG_SPLIT_X, j, seed)
-        for q in range(4):
-            s = 1 + 4 * j + q
-            r += ((n > s) & (np.asarray(w[q], dtype=np.uint64) < fq)).astype(np.int64)
-        j += 1
-    return r
+    """Number of the n stars that sit behind the dust screen (C3), one entry."""
+    r = split_block(np.asarray(n, dtype=np.int64)[:, None], np.asarray(first_byte, dtype=np.uint64)[:, None],
+                    frac, seed, np.asarray(px, dtype=np.int64), np.array([entry]))
+    return r[:, 0]
 
 
 # ---------------------------------------------------------------------------
@@ -312,8 +295,13 @@ def sample_pixels(lam: np.ndarray, flux32: np.ndarray, seed: int, px: np.ndarray
         for j in np.nonzero(lb >= LAM_SWITCH)[0]:
             n[:, j], _ = ptrs_draw(ptrs_constants(lb[j]), seed, px, e0 + j)
         if split and 0.0 < frac < 1.0:
-            sw = philox4x32_10(px[:, None], g[None, :], TAG_SPLIT, 0, seed)
-            W = np.stack(sw, axis=-1).reshape(npx, 4 * len(g))[:, : e1 - e0].astype(np.uint64)
+            W = None
+            if frac == 0.5:
+                g16 = np.arange(e0 // 16, (e1 + 15) // 16)
+                sw = philox4x32_10(px[:, None], g16[None, :], TAG_SPLIT, 0, seed)
+                words = np.stack(sw, axis=-1).reshape(npx, 4 * len(g16)).astype(np.uint64)
+                q = ents - 16 * g16[0]                       # entry's position from the first block
+                W = (words[:, q // 4] >> (np.uint64(8) * (q % 4).astype(np.uint64))) & np.uint64(0xFF)
             r = split_block(n, W, frac, seed, px, ents)
         elif split and frac >= 1.0:
             r = n.copy()
@@ -328,12 +316,17 @@ def sample_pixels(lam: np.ndarray, flux32: np.ndarray, seed: int, px: np.ndarray
     return dict(F_clr=F_clr, F_red=F_red, counts=counts, red=red)
 
 
-def split_block(n: np.ndarray, W: np.ndarray, frac: float, seed: int, px: np.ndarray, ents: np.ndarray):
-    """C3 for a block: n [npx][nent] counts, W [npx][nent] first split words."""
+def split_block(n: np.ndarray, W, frac: float, seed: int, px: np.ndarray, ents: np.ndarray):
+    """C3 for a block: n [npx][nent] counts; W [npx][nent] the entries' split bytes (F = 1/2)."""
+    n = np.asarray(n, dtype=np.int64)
     r = np.zeros_like(n)
+    if frac <= 0.0:
+        return r
+    if frac >= 1.0:
+        return n.copy()
     if frac == 0.5:
-        r += _popcount_masked(W, np.minimum(n, 32))
-        extra = n - 32
+        r += _popcount_masked(W, np.minimum(n, SPLIT_FIRST_BITS))
+        extra = n - SPLIT_FIRST_BITS
         j = 0
         while np.any(extra > 128 * j):
             cols = np.nonzero(np.any(extra > 128 * j, axis=0))[0]
@@ -344,14 +337,13 @@ def split_block(n: np.ndarray, W: np.ndarray, frac: float, seed: int, px: np.nda
             j += 1
         return r
     fq = np.uint64(int(math.floor(frac * 4294967296.0)))
-    r += ((n >= 1) & (W < fq)).astype(np.int64)
     j = 0
-    while np.any(n - 1 > 4 * j):
-        cols = np.nonzero(np.any(n - 1 > 4 * j, axis=0))[0]
+    while np.any(n > 4 * j):
+        cols = np.nonzero(np.any(n > 4 * j, axis=0))[0]
         x = philox4x32_10(px[:, None], ents[cols][None, :], TAG_SPLIT_X, j, seed)
         for q in range(4):
-            s = 1 + 4 * j + q
-            r[:, cols] += ((n[:, cols] > s) & (np.asarray(x[q], dtype=np.uint64) < fq)).astype(np.int64)
+            s_ = 4 * j + q
+            r[:, cols] += ((n[:, cols] > s_) & (np.asarray(x[q], dtype=np.uint64) < fq)).astype(np.int64)
         j += 1
     return r
 

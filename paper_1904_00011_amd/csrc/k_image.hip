@@ -50,50 +50,64 @@ hipError_t launch_copy_f32(const float *src, float *dst, int64_t n, hipStream_t 
 
 // ---------------------------------------------------------------------------------------
 // Direct periodic convolution.  G[y][x] = sum_{u,v} P[u][v] F[(y-u+h) mod N][(x-v+h) mod N].
-// A 64 x 32 output tile per 256-thread block; each thread owns a column strip of RY = 8
-// outputs so that every value read from LDS feeds up to RY accumulators.  The input tile
-// (with its K-1 halo, wrapped periodically) is staged in LDS as FP32; the PSF is read as
-// wave-uniform FP64 through the scalar cache; accumulation is FP64.
+// A 64 x 32 output tile per 256-thread block; each thread owns a column strip of CRY = 8
+// outputs.  The input tile (with its K-1 halo, wrapped periodically) and the PSF are staged in
+// LDS as FP32.  For every input row the thread forms, for each of its outputs that the row
+// touches, the K-term dot product with the matching PSF row in FP32 (all terms positive), and
+// adds it to an FP64 accumulator.
 // ---------------------------------------------------------------------------------------
 constexpr int CT_X = 64, CT_Y = 32, CRY = 8;
 
-__global__ void __launch_bounds__(256) k_conv_direct(const float *__restrict__ F, const double *__restrict__ psf64,
+size_t conv_direct_lds_bytes(int K) {
+  return ((size_t)(CT_Y + K - 1) * (CT_X + K - 1) + (size_t)K * K) * sizeof(float);
+}
+
+__global__ void __launch_bounds__(256) k_conv_direct(const float *__restrict__ F, const float *__restrict__ psf,
                                                      int N, int K, float *__restrict__ G) {
-  extern __shared__ float tile[];  // [(CT_Y + K - 1)][(CT_X + K - 1)]
+  extern __shared__ float lds[];
   const int b = blockIdx.z;
   const int h = (K - 1) >> 1;
   const int TW = CT_X + K - 1, TH = CT_Y + K - 1;
+  float *tile = lds;
+  float *P = lds + TW * TH;
   const int ox = blockIdx.x * CT_X, oy = blockIdx.y * CT_Y;
   const float *Fb = F + (size_t)b * N * N;
-  // Output (y, x) reads input rows y - u + h for u in [0, K): tile row ty holds input row oy - h + ty ... the
-  // tile origin is (oy - (K-1-h), ox - (K-1-h)) = (oy - h, ox - h) since K - 1 - h = h.
+  // tile row ty holds input row oy - h + ty (outputs [oy, oy + CT_Y) read rows y - h .. y + h)
   for (int idx = threadIdx.x; idx < TW * TH; idx += 256) {
     const int ty = idx / TW, tx = idx - ty * TW;
-    int gy = oy - h + ty, gx = ox - h + tx;
-    gy %= N; if (gy < 0) gy += N;
-    gx %= N; if (gx < 0) gx += N;
+    int gy = (oy - h + ty) % N;
+    if (gy < 0) gy += N;
+    int gx = (ox - h + tx) % N;
+    if (gx < 0) gx += N;
     tile[idx] = Fb[(size_t)gy * N + gx];
   }
+  // PSF stored flipped: Pf[a][c] = P[K-1-a][K-1-c], so output row j reads tile row ly0 + j + a
+  for (int idx = threadIdx.x; idx < K * K; idx += 256) {
+    const int a = idx / K, c = idx - a * K;
+    P[idx] = psf[(size_t)b * K * K + (size_t)(K - 1 - a) * K + (K - 1 - c)];
+  }
   __syncthreads();
-  const int lx = threadIdx.x & (CT_X - 1);     // 0..63
-  const int ly0 = (threadIdx.x >> 6) * CRY;    // 0, 8, 16, 24
+  const int lx = threadIdx.x & (CT_X - 1);
+  const int ly0 = (threadIdx.x >> 6) * CRY;
   double acc[CRY];
 #pragma unroll
   for (int j = 0; j < CRY; ++j) acc[j] = 0.0;
-  const double *Pb = psf64 + (size_t)b * K * K;
-  // output (ly0 + j, lx): sum over u, v of P[u][v] * tile[ly0 + j + (K-1) - u][lx + (K-1) - v]
-  // let rr = j + (K-1) - u  (tile row offset from ly0), cc = (K-1) - v
-  for (int rr = 0; rr < CRY + K - 1; ++rr) {
-    const float *trow = tile + (ly0 + rr) * TW + lx;
-    for (int cc = 0; cc < K; ++cc) {
-      const double val = (double)trow[cc];
-      const int v = K - 1 - cc;
+  // output (ly0 + j, lx) = sum_{a,c} Pf[a][c] tile[ly0 + j + a][lx + c]; tile row r = j + a
+  for (int r = 0; r < CRY + K - 1; ++r) {
+    const float *trow = tile + (ly0 + r) * TW + lx;
+    float dot[CRY];
+#pragma unroll
+    for (int j = 0; j < CRY; ++j) dot[j] = 0.0f;
+    for (int c = 0; c < K; ++c) {
+      const float val = trow[c];
 #pragma unroll
       for (int j = 0; j < CRY; ++j) {
-        const int u = j + (K - 1) - rr;
-        if (u >= 0 && u < K) acc[j] = fma(Pb[u * K + v], val, acc[j]);
+        const int a = r - j;
+        if (a >= 0 && a < K) dot[j] = fmaf(P[a * K + c], val, dot[j]);
       }
     }
+#pragma unroll
+    for (int j = 0; j < CRY; ++j) acc[j] += (double)dot[j];
   }
   const int x = ox + lx;
   if (x < N) {
@@ -105,11 +119,11 @@ __global__ void __launch_bounds__(256) k_conv_direct(const float *__restrict__ F
   }
 }
 
-hipError_t launch_conv_direct(const float *F, const double *psf64, int B, int N, int K, float *G, hipStream_t s) {
-  const size_t lds = (size_t)(CT_Y + K - 1) * (CT_X + K - 1) * sizeof(float);
+hipError_t launch_conv_direct(const float *F, const float *psf, int B, int N, int K, float *G, hipStream_t s) {
+  const size_t lds = conv_direct_lds_bytes(K);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   dim3 grid((N + CT_X - 1) / CT_X, (N + CT_Y - 1) / CT_Y, B);
-  hipLaunchKernelGGL(k_conv_direct, grid, dim3(256), lds, s, F, psf64, N, K, G);
+  hipLaunchKernelGGL(k_conv_direct, grid, dim3(256), lds, s, F, psf, N, K, G);
   return hipGetLastError();
 }
 
@@ -143,20 +157,6 @@ __global__ void __launch_bounds__(256) k_noise_mag(NoiseArgs a) {
 hipError_t launch_noise_mag(const NoiseArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_noise_mag, dim3((a.npx + 255) / 256), dim3(256), 0, s, a);
   return hipGetLastError();
-}
-
-// FFT convolution: not built yet.
-int fft_supported(int N) {
-  (void)N;
-  return 0;
-}
-size_t fft_scratch_bytes(int B, int N) {
-  (void)B;
-  (void)N;
-  return 0;
-}
-hipError_t launch_conv_fft(const float *, const float *, int, int, int, float *, void *, hipStream_t) {
-  return hipErrorNotSupported;
 }
 
 }  // namespace pcmd

@@ -61,7 +61,7 @@ __global__ void __launch_bounds__(256) k_prep(int E, int B, int BP, const double
     atomicOr(status, STATUS_BAD_LAMBDA);
     l = 0.0;
   }
-  EntryRec r{0u, 0u, KIND_ZERO, 0u};
+  EntryRec r{{0u, 0u, 0u}, KIND_ZERO};
   if (l >= 10.0) {
     const double slam = sqrt(l);
     const double b = 0.931 + 2.53 * slam;
@@ -78,7 +78,7 @@ __global__ void __launch_bounds__(256) k_prep(int E, int B, int BP, const double
     c.vr = (float)vr;
     c.pad = 0.0f;
     pc[i] = c;
-    r.kind = KIND_PTRS;
+    r.kk = KIND_PTRS;
   } else if (l > 0.0) {
     double p = exp(-l);
     double F = p;
@@ -95,9 +95,8 @@ __global__ void __launch_bounds__(256) k_prep(int E, int B, int BP, const double
       K = (uint32_t)(k + 1);
     }
     if (K > 0) {
-      r.kind = KIND_INV;
-      r.T0 = t[0];
-      r.K = K;
+      for (uint32_t k = 0; k < 3 && k < K; ++k) r.T[k] = t[k];
+      r.kk = (K << 8) | KIND_INV;
     }
   }
   rec[i] = r;
@@ -118,7 +117,7 @@ __device__ __forceinline__ uint32_t low_mask(uint32_t cnt) { return cnt >= 32u ?
 
 // Transformed-rejection draw for entry i at pixel p (attempts 2j, 2j+1 share one Philox call).
 __device__ __forceinline__ uint32_t ptrs_draw(const PtrsConst &c, uint32_t p, uint32_t i, uint32_t k0, uint32_t k1,
-                                              const float *__restrict__ lnfact, uint32_t *status) {
+                                              const float *__restrict__ lnfact, bool &failed) {
   int k = 0;
   bool done = false;
   for (uint32_t j = 0; j < (uint32_t)(PTRS_MAX_ATTEMPTS / 2); ++j) {
@@ -134,21 +133,25 @@ __device__ __forceinline__ uint32_t ptrs_draw(const PtrsConst &c, uint32_t p, ui
     }
     if (!wave_any(!done)) break;
   }
-  if (!done) {
-    atomicOr(status, STATUS_PTRS_RETRY);
+  if (!done) {  // reported once per wave at the end of the kernel (no stores inside the entry loop)
+    failed = true;
     k = 0;
   }
   return (uint32_t)k;
 }
 
-// Reddened stars among n (dust split), first word W from the group split block.
-__device__ __forceinline__ uint32_t split_count(uint32_t n, uint32_t W, int mode, uint32_t fq, uint32_t p,
+// Reddened stars among n (dust split).  F = 1/2: one bit per star, the first 8 from the
+// entry's byte of its 16-entry split block, the rest from (p, i, TAG_SPLIT_X, j) blocks.
+// Other fractions: star s compares word s mod 4 of (p, i, TAG_SPLIT_X, s / 4) with fq.
+constexpr uint32_t SPLIT_FIRST_BITS = 8;
+
+__device__ __forceinline__ uint32_t split_count(uint32_t n, uint32_t byte, int mode, uint32_t fq, uint32_t p,
                                                 uint32_t i, uint32_t k0, uint32_t k1) {
   if (mode == SPLIT_ALL) return n;
   uint32_t red = 0;
   if (mode == SPLIT_HALF) {
-    red = __popc(W & low_mask(n));
-    const uint32_t extra = n > 32u ? n - 32u : 0u;
+    red = __popc(byte & low_mask(min(n, SPLIT_FIRST_BITS)));
+    const uint32_t extra = n > SPLIT_FIRST_BITS ? n - SPLIT_FIRST_BITS : 0u;
     for (uint32_t j = 0; wave_any(extra > 128u * j); ++j) {
       const u4 x = philox10(p, i, TAG_SPLIT_X, j, k0, k1);
 #pragma unroll
@@ -160,21 +163,18 @@ __device__ __forceinline__ uint32_t split_count(uint32_t n, uint32_t W, int mode
     }
     return red;
   }
-  // general fraction: one word per star
-  red = (n >= 1u && W < fq) ? 1u : 0u;
-  const uint32_t rest = n > 1u ? n - 1u : 0u;  // stars 1..n-1
-  for (uint32_t j = 0; wave_any(rest > 4u * j); ++j) {
+  for (uint32_t j = 0; wave_any(n > 4u * j); ++j) {
     const u4 x = philox10(p, i, TAG_SPLIT_X, j, k0, k1);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const uint32_t s = 4u * j + (uint32_t)q;  // star index minus one
-      red += (rest > s && word_of(x, q) < fq) ? 1u : 0u;
+      const uint32_t st = 4u * j + (uint32_t)q;
+      red += (n > st && word_of(x, q) < fq) ? 1u : 0u;
     }
   }
   return red;
 }
 
-template <int B, int S>
+template <int B, int S, bool DBG>
 __global__ void __launch_bounds__(256) k_sample(SampleArgs a, const EntryRec *__restrict__ rec,
                                                 const uint32_t *__restrict__ thr, const PtrsConst *__restrict__ pc,
                                                 const double *__restrict__ fl64) {
@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a, const EntryRec *__
   const bool live = p < (uint32_t)a.npx;
   const int e0 = chunk * CHUNK;
   const int e1 = min(a.E, e0 + CHUNK);
-  const bool dbg = a.dbg_counts != nullptr && live && (int64_t)p >= a.px0 && (int64_t)p < a.px1;
+  const bool dbg = DBG && live && (int64_t)p >= a.px0 && (int64_t)p < a.px1;
 
   double acc_c[B], acc_r[B];
 #pragma unroll
@@ -195,47 +195,80 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a, const EntryRec *__
     acc_r[b] = 0.0;
   }
 
+  u4 sw{0u, 0u, 0u, 0u};
+  bool have_split = false;
+  bool ptrs_failed = false;
   for (int g0 = e0; g0 < e1; g0 += 4) {
     const uint32_t g = (uint32_t)(g0 >> 2);
+    // records and fluxes of the group: uniform scalar loads issued before the Philox work
     EntryRec r[4];
     bool need_main = false;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      r[q] = (g0 + q < e1) ? rec[g0 + q] : EntryRec{0u, 0u, KIND_ZERO, 0u};
-      need_main |= r[q].kind == KIND_INV;
+      r[q] = g0 + q < e1 ? rec[g0 + q] : EntryRec{{0u, 0u, 0u}, KIND_ZERO};
+      need_main |= (r[q].kk & 0xFFu) == KIND_INV;
     }
     u4 w{0u, 0u, 0u, 0u};
     if (need_main) w = philox10(p, g, TAG_MAIN, 0u, a.k0, a.k1);
-    u4 sw{0u, 0u, 0u, 0u};
-    bool have_split = false;
+    if ((g0 & 15) == 0) have_split = false;  // new 16-entry split block
+    // first threshold of all four entries at once; at small lambda most groups end here
+    uint32_t n0[4];
+    bool any_ptrs = false;
+    uint32_t hit = 0u;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint32_t kind = r[q].kk & 0xFFu;
+      n0[q] = (kind == KIND_INV && word_of(w, q) >= r[q].T[0]) ? 1u : 0u;
+      hit |= n0[q];
+      any_ptrs |= kind == KIND_PTRS;
+    }
+    if (!any_ptrs && !wave_any(hit != 0u)) continue;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint32_t i = (uint32_t)(g0 + q);
       uint32_t n = 0;
-      if (r[q].kind == KIND_INV) {
+      const uint32_t kind = r[q].kk & 0xFFu;
+      if (kind == KIND_INV) {
+        // n = #{k < K : T_k <= u}, walking up while any lane of the wave is still above
         const uint32_t u = word_of(w, q);
-        n = u >= r[q].T0 ? 1u : 0u;
-        if (wave_any(n != 0u)) {
-          const uint32_t *t = thr + (size_t)i * THR_STRIDE;
-          for (uint32_t k = 1; k < r[q].K; ++k) {
-            const uint32_t c = u >= t[k] ? 1u : 0u;
-            if (!wave_any(c != 0u)) break;
+        const uint32_t K = r[q].kk >> 8;
+        n = n0[q];
+        if (!wave_any(n != 0u)) continue;
+        if (K > 1) {
+          uint32_t c = u >= r[q].T[1] ? 1u : 0u;
+          if (wave_any(c != 0u)) {
             n += c;
+            if (K > 2) {
+              c = u >= r[q].T[2] ? 1u : 0u;
+              if (wave_any(c != 0u)) {
+                n += c;
+                const uint32_t *t = thr + (size_t)i * THR_STRIDE;
+                for (uint32_t k = 3; k < K; ++k) {
+                  c = u >= t[k] ? 1u : 0u;
+                  if (!wave_any(c != 0u)) break;
+                  n += c;
+                }
+              }
+            }
           }
         }
-      } else if (r[q].kind == KIND_PTRS) {
-        n = ptrs_draw(pc[i], p, i, a.k0, a.k1, a.lnfact, a.status);
+      } else if (kind == KIND_PTRS) {
+        n = ptrs_draw(pc[i], p, i, a.k0, a.k1, a.lnfact, ptrs_failed);
       } else {
         continue;
       }
       if (!wave_any(n != 0u)) continue;
       uint32_t red = 0u;
       if (S == 2) {
-        if (a.split_mode != SPLIT_ALL && !have_split) {
-          sw = philox10(p, g, TAG_SPLIT, 0u, a.k0, a.k1);
-          have_split = true;
+        uint32_t byte = 0u;
+        if (a.split_mode == SPLIT_HALF) {
+          if (!have_split) {
+            sw = philox10(p, (uint32_t)(g0 >> 4), TAG_SPLIT, 0u, a.k0, a.k1);
+            have_split = true;
+          }
+          byte = (word_of(sw, (g0 & 15) >> 2) >> (8 * q)) & 0xFFu;
         }
-        red = split_count(n, word_of(sw, q), a.split_mode, a.split_q, p, i, a.k0, a.k1);
+        red = split_count(n, byte, a.split_mode, a.split_q, p, i, a.k0, a.k1);
       }
       const double *f = fl64 + (size_t)i * BP;
       const double dc = (double)(n - red);
@@ -246,13 +279,14 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a, const EntryRec *__
 #pragma unroll
         for (int b = 0; b < B; ++b) acc_r[b] = fma(dr, f[b], acc_r[b]);
       }
-      if (dbg) {
+      if (DBG && dbg) {
         const size_t o = (size_t)((int64_t)p - a.px0) * (size_t)a.E + i;
         a.dbg_counts[o] = n;
         if (a.dbg_red) a.dbg_red[o] = red;
       }
     }
   }
+  if (wave_any(ptrs_failed) && (threadIdx.x & 63) == 0) atomicOr(a.status, STATUS_PTRS_RETRY);
   if (!live) return;
   const size_t plane = (size_t)a.npx;
 #pragma unroll
@@ -266,10 +300,15 @@ template <int B>
 static hipError_t launch_sample_b(const EntryTables &t, const SampleArgs &a, hipStream_t s) {
   const int nblk_px = (a.npx + 255) / 256;
   dim3 grid((unsigned)(nblk_px * a.nchunks));
-  if (a.S == 2)
-    hipLaunchKernelGGL((k_sample<B, 2>), grid, dim3(256), 0, s, a, t.rec, t.thr, (const PtrsConst *)t.pc, t.fl64);
+  const bool dbg = a.dbg_counts != nullptr;
+  if (a.S == 2 && dbg)
+    hipLaunchKernelGGL((k_sample<B, 2, true>), grid, dim3(256), 0, s, a, t.rec, t.thr, (const PtrsConst *)t.pc, t.fl64);
+  else if (a.S == 2)
+    hipLaunchKernelGGL((k_sample<B, 2, false>), grid, dim3(256), 0, s, a, t.rec, t.thr, (const PtrsConst *)t.pc, t.fl64);
+  else if (dbg)
+    hipLaunchKernelGGL((k_sample<B, 1, true>), grid, dim3(256), 0, s, a, t.rec, t.thr, (const PtrsConst *)t.pc, t.fl64);
   else
-    hipLaunchKernelGGL((k_sample<B, 1>), grid, dim3(256), 0, s, a, t.rec, t.thr, (const PtrsConst *)t.pc, t.fl64);
+    hipLaunchKernelGGL((k_sample<B, 1, false>), grid, dim3(256), 0, s, a, t.rec, t.thr, (const PtrsConst *)t.pc, t.fl64);
   return hipGetLastError();
 }
 

@@ -380,6 +380,8 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   const bool use_fft = o->conv_path == PCMD_CONV_FFT || (o->conv_path == PCMD_CONV_AUTO && K >= 31 && fft_supported(N));
   if (K > 1 && use_fft && !fft_supported(N))
     return fail(c, PCMD_E_UNSUPPORTED, "pcmd_simulate: FFT path needs nim a power of two in [8, 4096]");
+  if (K > 1 && !use_fft && conv_direct_lds_bytes(K) > 160 * 1024)
+    return fail(c, PCMD_E_UNSUPPORTED, "pcmd_simulate: psf_k %d too large for the direct path; use the FFT path", K);
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(c->device);
   const int BP = B <= 2 ? 2 : 4;
@@ -467,7 +469,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
       e = launch_conv_fft((const float *)c->F.p, o->psf, B, N, K, (float *)c->G.p, c->fft.p, s);
       if (e != hipSuccess) return hip_fail(c, e, "fft convolution");
     } else {
-      e = launch_conv_direct((const float *)c->F.p, (const double *)c->psf64.p, B, N, K, (float *)c->G.p, s);
+      e = launch_conv_direct((const float *)c->F.p, o->psf, B, N, K, (float *)c->G.p, s);
       if (e != hipSuccess) return hip_fail(c, e, "direct convolution");
     }
     Gp = (const float *)c->G.p;

@@ -8,11 +8,11 @@
 
 namespace pcmd {
 
+// One entry's sampler record (16 bytes, read with scalar loads): the first three inversion
+// thresholds inline (the rest in the threshold table) and K << 8 | kind.
 struct EntryRec {
-  uint32_t T0;    // first inversion threshold
-  uint32_t K;     // number of thresholds (inversion) / unused
-  uint32_t kind;  // KIND_ZERO, KIND_INV, KIND_PTRS
-  uint32_t pad;
+  uint32_t T[3];  // T_0..T_2 (valid below K)
+  uint32_t kk;    // (number of thresholds K) << 8 | kind (KIND_ZERO, KIND_INV, KIND_PTRS)
 };
 
 // Device-side tables built from lambda and the star fluxes for one simulation.
@@ -69,7 +69,8 @@ hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s);
 
 // k_image.hip
 hipError_t launch_psf64(const float *psf, int B, int K, double *psf64, uint32_t *status, hipStream_t s);
-hipError_t launch_conv_direct(const float *F, const double *psf64, int B, int N, int K, float *G, hipStream_t s);
+size_t conv_direct_lds_bytes(int K);
+hipError_t launch_conv_direct(const float *F, const float *psf, int B, int N, int K, float *G, hipStream_t s);
 hipError_t launch_noise_mag(const NoiseArgs &a, hipStream_t s);
 hipError_t launch_copy_f32(const float *src, float *dst, int64_t n, hipStream_t s);
 int fft_supported(int N);

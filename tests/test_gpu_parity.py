@@ -318,3 +318,37 @@ def test_headline_full_size_sampled(ctx):
     assert pu.mags_close(g["mags"][:, p:p + 1], mo).all()
     hg, mg = pu.gpu_hess(ctx, g["mags"], si.hess_grid_from_median(0.5, 30.0, 100, 100))
     assert hg.sum() == npx
+
+
+@pytest.mark.parametrize("N,K", [(64, 5), (64, 31), (64, 63), (128, 31), (32, 1)])
+def test_fft_path_against_oracle(ctx, N, K):
+    """FFT convolution (power-of-two sides) against the oracle's direct periodic sum."""
+    G, lam, f32, obs = _headline_lam(3.5, seed=1005, stride=25)
+    obs.nim = N
+    obs.psf = None if K == 1 else si.psf_stack(K, (1.6, 1.8, 2.0))
+    _print_case("fft_path", N=N, K=K)
+    g = pu.gpu_simulate(ctx, lam, f32, obs, conv_path=2 if K > 1 else 0)
+    Fo, _ = osamp.simulate_flux(lam, f32, obs)
+    assert np.max(pu.rel_err(g["flux_pre"], Fo)) <= pu.FLUX_RTOL
+    Go = Fo if K == 1 else ops.convolve_periodic(Fo.reshape(3, N, N), obs.psf).reshape(3, N * N)
+    assert np.max(pu.rel_err(g["flux_psf"], Go)) <= pu.FLUX_RTOL
+    assert pu.mags_close(g["mags"], on.magnitudes(Go, obs)).all()
+
+
+def test_fft_and_direct_agree_full_size(ctx):
+    G, lam, f32, obs = _headline_lam(3.0, seed=1006, stride=5)
+    a = pu.gpu_simulate(ctx, lam, f32, obs, conv_path=1)
+    b = pu.gpu_simulate(ctx, lam, f32, obs, conv_path=2)
+    _print_case("fft_vs_direct", N=obs.nim, K=obs.psf.shape[-1])
+    assert np.array_equal(a["flux_pre"], b["flux_pre"])
+    assert np.max(pu.rel_err(a["flux_psf"], b["flux_psf"])) <= 1e-6
+    assert np.max(np.abs(a["mags"] - b["mags"])) <= 1e-5
+
+
+def test_fft_needs_power_of_two(ctx):
+    import paper_1904_00011_amd as P
+    G, lam, f32, obs = _headline_lam(2.0, seed=1, stride=50)
+    obs.nim = 48
+    with pytest.raises(P.PcmdError) as ei:
+        pu.gpu_simulate(ctx, lam, f32, obs, conv_path=2, want_flux=False)
+    assert ei.value.code == P._lib.E_UNSUPPORTED

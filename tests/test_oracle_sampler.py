@@ -74,20 +74,25 @@ def test_ptrs_chi_square(lam):
 
 
 def test_split_half_enumeration():
-    # for n <= 16 stars, over all 2^16 values of the low word bits, r ~ Binomial(n, 1/2) exactly
-    W = np.arange(65536, dtype=np.uint32)
-    px = np.zeros(65536, dtype=np.int64)
-    for n in range(0, 17):
-        r = S.split_reddened(np.full(65536, n), W, 0.5, 1, px, 0)
+    # for n <= 8 stars, over all 256 values of the entry's split byte, r ~ Binomial(n, 1/2) exactly
+    W = np.arange(256, dtype=np.uint32)
+    px = np.zeros(256, dtype=np.int64)
+    for n in range(0, 9):
+        r = S.split_reddened(np.full(256, n), W, 0.5, 1, px, 0)
         cnt = np.bincount(r, minlength=n + 1)
-        expect = np.array([math.comb(n, k) * 2 ** (16 - n) for k in range(n + 1)])
+        expect = np.array([math.comb(n, k) * 2 ** (8 - n) for k in range(n + 1)])
         assert np.array_equal(cnt[:n + 1], expect)
+    # the byte of entry i is byte i mod 16 of its 16-entry block
+    px = np.arange(1000)
+    for i in (0, 5, 16, 31):
+        w = rng.philox4x32_10(px, i // 16, rng.TAG_SPLIT, 0, 3)[(i % 16) // 4]
+        assert np.array_equal(S.split_first_byte(px, i, 3), (w >> np.uint32(8 * (i % 4))) & np.uint32(255))
 
 
 def test_split_large_n_and_general_fraction():
     px = np.arange(100000)
-    w = rng.philox4x32_10(px, 0, rng.TAG_SPLIT, 0, 3)[0]
-    for n in (40, 300):
+    w = S.split_first_byte(px, 7, 3)
+    for n in (12, 40, 300):
         r = S.split_reddened(np.full(len(px), n), w, 0.5, 3, px, 7)
         assert abs(r.mean() - n / 2) < 5 * math.sqrt(n / 4 / len(px))
         assert abs(r.var() - n / 4) < 5 * (n / 4) * math.sqrt(2 / len(px))
