@@ -221,17 +221,61 @@ int pcmd_loglike(pcmd_ctx *ctx, const uint32_t *hess_model, const uint32_t *hess
                  double *out, pcmd_stream stream);
 
 /* ---------------------------------------------------------------------------------------
+ * a7: many parameter points in one launch (the paper's fits evaluate the stochastic likelihood
+ * at many points and re-simulate the best fit 100 times, Sec. 2.5 and Appendix A).
+ * ------------------------------------------------------------------------------------- */
+
+/* One job: the weighted points and observation of one simulation. */
+typedef struct {
+  pcmd_iso iso;
+  pcmd_obs obs;
+} pcmd_job;
+
+/* Simulate, bin and score n_jobs independent simulations, each bit-identical to pcmd_simulate +
+ * pcmd_hess + pcmd_loglike on the same inputs.  The sampler runs as one persistent launch whose
+ * (job, 256-pixel block, entry chunk) tiles are drawn from a shared counter, so jobs of uneven
+ * image size and entry count load-balance; the other steps run per job.  All jobs share n_bands;
+ * a job's convolution must resolve to the direct path (PCMD_E_UNSUPPORTED otherwise).
+ * use_graph != 0: the first call with a given shape signature (n_jobs, each job's nim, n_entries,
+ * psf_k and whether dust splits its stars, the Hess size, the tuning) captures the launch
+ * sequence into a HIP graph; later calls with that signature replay it with this call's
+ * parameters, seeds and input pointers.  Scratch for all jobs stays allocated in the context.
+ * jobs [host][n_jobs]; hess_data [dev][nx*ny]; mom_data [dev][3] (Gaussian modes);
+ * logl_out [dev][n_jobs]; hess_out [dev][n_jobs][nx*ny] or NULL. */
+int pcmd_batch_run(pcmd_ctx *ctx, int32_t n_jobs, const pcmd_job *jobs, const pcmd_hess_grid *grid,
+                   const uint32_t *hess_data, const double *mom_data, int32_t mode, double eps,
+                   double *logl_out, uint32_t *hess_out, int32_t use_graph, pcmd_stream stream);
+
+/* Schedule of the persistent sampler: workgroups per compute unit (1..8) and tile order (0: the
+ * most expensive job first, 1: submission order).  It changes speed only, never results. */
+typedef struct {
+  int32_t wg_per_cu;
+  int32_t order;
+} pcmd_batch_tuning;
+
+int pcmd_batch_set_tuning(pcmd_ctx *ctx, const pcmd_batch_tuning *tuning);
+int pcmd_batch_get_tuning(pcmd_ctx *ctx, pcmd_batch_tuning *tuning);
+/* Run the batch once per candidate schedule (eagerly, timed with HIP events), keep the fastest
+ * as the context's schedule and return it; ms_out [host][8] (or NULL) receives each candidate's
+ * time and *n_candidates their number.  Waits for the stream. */
+int pcmd_batch_autotune(pcmd_ctx *ctx, int32_t n_jobs, const pcmd_job *jobs, const pcmd_hess_grid *grid,
+                        const uint32_t *hess_data, const double *mom_data, int32_t mode, double eps,
+                        double *logl_out, pcmd_batch_tuning *best, double *ms_out, int32_t *n_candidates,
+                        pcmd_stream stream);
+
+/* ---------------------------------------------------------------------------------------
  * Kernel timing for benchmarks: HIP events recorded on the launch stream around each
  * launch of the timed kernels while enabled.
  * ------------------------------------------------------------------------------------- */
 
-enum { PCMD_TIMER_SAMPLE = 0, PCMD_TIMER_CONV = 1, PCMD_TIMER_HESS = 2, PCMD_TIMER_KINDS = 3 };
+enum { PCMD_TIMER_SAMPLE = 0, PCMD_TIMER_CONV = 1, PCMD_TIMER_HESS = 2, PCMD_TIMER_BATCH = 3, PCMD_TIMER_KINDS = 4 };
 
 /* Start (on != 0) or stop recording.  Starting discards earlier records. */
 int pcmd_timer_enable(pcmd_ctx *ctx, int on);
 /* Wait for the recorded launches of kernel `which` and return their summed duration (ms),
  * their number and the algorithmic units they processed (SAMPLE: pixel x entry draws;
- * CONV: image values read and written; HESS: pixels binned).  Consumes those records. */
+ * CONV: image values read and written; HESS: pixels binned; BATCH: a whole pcmd_batch_run,
+ * pixel x entry draws of all its jobs).  Consumes those records. */
 int pcmd_timer_read(pcmd_ctx *ctx, int which, double *total_ms, int64_t *launches, double *units);
 
 #ifdef __cplusplus

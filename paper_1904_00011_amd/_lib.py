@@ -24,7 +24,7 @@ DUST_NONE, DUST_SCREEN, DUST_LOGNORMAL = 0, 1, 2
 CONV_AUTO, CONV_DIRECT, CONV_FFT = 0, 1, 2
 NOISE_NONE, NOISE_GAUSS_MAG, NOISE_SHOT = 0, 1, 2
 LL_POISSON, LL_GAUSS_PAPER, LL_GAUSS_LITERAL = 0, 1, 2
-TIMER_SAMPLE, TIMER_CONV, TIMER_HESS = 0, 1, 2
+TIMER_SAMPLE, TIMER_CONV, TIMER_HESS, TIMER_BATCH = 0, 1, 2, 3
 
 D4 = C.c_double * MAX_BANDS
 
@@ -70,6 +70,14 @@ class DebugS(C.Structure):
                 ("flux_pre", C.c_void_p), ("flux_psf", C.c_void_p)]
 
 
+class JobS(C.Structure):
+    _fields_ = [("iso", IsoS), ("obs", ObsS)]
+
+
+class TuningS(C.Structure):
+    _fields_ = [("wg_per_cu", C.c_int32), ("order", C.c_int32)]
+
+
 class HessGridS(C.Structure):
     _fields_ = [("x0", C.c_double), ("dx", C.c_double), ("y0", C.c_double), ("dy", C.c_double),
                 ("nx", C.c_int32), ("ny", C.c_int32), ("b_blue", C.c_int32), ("b_red", C.c_int32),
@@ -100,6 +108,11 @@ def load(path: str = LIB_PATH):
         "pcmd_simulate": (C.c_int, [vp, C.POINTER(IsoS), C.POINTER(ObsS), vp, C.POINTER(DebugS), vp]),
         "pcmd_hess": (C.c_int, [vp, vp, i32, i64, C.POINTER(HessGridS), vp, vp, vp]),
         "pcmd_loglike": (C.c_int, [vp, vp, vp, i32, vp, vp, i32, dbl, vp, vp]),
+        "pcmd_batch_run": (C.c_int, [vp, i32, C.POINTER(JobS), C.POINTER(HessGridS), vp, vp, i32, dbl, vp, vp, i32, vp]),
+        "pcmd_batch_set_tuning": (C.c_int, [vp, C.POINTER(TuningS)]),
+        "pcmd_batch_get_tuning": (C.c_int, [vp, C.POINTER(TuningS)]),
+        "pcmd_batch_autotune": (C.c_int, [vp, i32, C.POINTER(JobS), C.POINTER(HessGridS), vp, vp, i32, dbl, vp,
+                                          C.POINTER(TuningS), vp, C.POINTER(i32), vp]),
         "pcmd_timer_enable": (C.c_int, [vp, C.c_int]),
         "pcmd_timer_read": (C.c_int, [vp, C.c_int, C.POINTER(dbl), C.POINTER(i64), C.POINTER(dbl)]),
     }
@@ -269,3 +282,49 @@ class Context:
         n = int(h_model.numel())
         self._check(self.lib.pcmd_loglike(self.h, _ptr(h_model), _ptr(h_data), n, _ptr(mom_model), _ptr(mom_data),
                                           int(mode), float(eps), _ptr(out), _stream(stream)), "pcmd_loglike")
+
+    # -------------------------------------------------------------------------------------
+    # batched evaluation
+    # -------------------------------------------------------------------------------------
+    @staticmethod
+    def _jobs_array(jobs):
+        """jobs: sequence of dicts with lam, flux (device tensors), obs, psf (device tensor or None),
+        conv_path."""
+        arr = (JobS * len(jobs))()
+        for k, j in enumerate(jobs):
+            flux = j["flux"]
+            B, E = int(flux.shape[0]), int(flux.shape[1])
+            arr[k].iso = IsoS(E, B, _ptr(j["lam"]), _ptr(flux))
+            arr[k].obs = obs_struct(j["obs"], B, j.get("psf"), j.get("conv_path", CONV_DIRECT))
+        return arr
+
+    def batch_run(self, jobs, grid: dict, hess_data, mom_data, logl_out, mode: int = LL_POISSON, eps: float = 0.01,
+                  hess_out=None, use_graph: bool = False, bands=(0, 1, 1), stream=None):
+        arr = self._jobs_array(jobs)
+        g = hess_grid_struct(grid, bands)
+        self._check(self.lib.pcmd_batch_run(self.h, len(jobs), arr, C.byref(g), _ptr(hess_data), _ptr(mom_data),
+                                            int(mode), float(eps), _ptr(logl_out), _ptr(hess_out), int(bool(use_graph)),
+                                            _stream(stream)), "pcmd_batch_run")
+
+    def batch_set_tuning(self, wg_per_cu: int, order: int):
+        t = TuningS(int(wg_per_cu), int(order))
+        self._check(self.lib.pcmd_batch_set_tuning(self.h, C.byref(t)), "pcmd_batch_set_tuning")
+
+    def batch_get_tuning(self):
+        t = TuningS()
+        self._check(self.lib.pcmd_batch_get_tuning(self.h, C.byref(t)), "pcmd_batch_get_tuning")
+        return t.wg_per_cu, t.order
+
+    def batch_autotune(self, jobs, grid: dict, hess_data, mom_data, logl_out, mode: int = LL_POISSON,
+                       eps: float = 0.01, bands=(0, 1, 1), stream=None):
+        """Returns ((wg_per_cu, order), [ms per candidate])."""
+        arr = self._jobs_array(jobs)
+        g = hess_grid_struct(grid, bands)
+        best = TuningS()
+        ms = (C.c_double * 8)()
+        n = C.c_int32(0)
+        self._check(self.lib.pcmd_batch_autotune(self.h, len(jobs), arr, C.byref(g), _ptr(hess_data), _ptr(mom_data),
+                                                 int(mode), float(eps), _ptr(logl_out), C.byref(best), ms, C.byref(n),
+                                                 _stream(stream)), "pcmd_batch_autotune")
+        return (best.wg_per_cu, best.order), [ms[i] for i in range(n.value)]
+

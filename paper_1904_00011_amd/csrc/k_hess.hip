@@ -32,18 +32,6 @@ __device__ __forceinline__ int bin_of(double t, int n) {
   return (int)t;
 }
 
-struct HessArgs {
-  const float *mags;
-  int64_t npx;
-  double x0, dx, y0, dy;
-  int nx, ny, bb, br, bm;
-  uint32_t *hess;
-  double *mom_part;  // [gridDim.x][3]
-  uint32_t *counter;
-  double *moments;
-  int use_lds;
-};
-
 __device__ __forceinline__ double block_sum(double v, double *red) {
   // fixed-order tree: within each wave by shuffles, then over the waves in order (deterministic)
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -56,7 +44,16 @@ __device__ __forceinline__ double block_sum(double v, double *red) {
   return r;
 }
 
-__global__ void __launch_bounds__(HESS_THREADS) k_hess(HessArgs a) {
+int hess_blocks(int64_t npx) {
+  // enough pixels per block to amortise clearing and merging the private histogram
+  int64_t blocks = (npx + 4095) / 4096;
+  if (blocks < 1) blocks = 1;
+  if (blocks > HESS_MAX_BLOCKS) blocks = HESS_MAX_BLOCKS;
+  return (int)blocks;
+}
+bool hess_use_lds(int nbins) { return nbins <= HESS_LDS_MAX_BINS; }
+
+__device__ __forceinline__ void hess_body(const HessArgs &a) {
   extern __shared__ uint32_t lh[];
   __shared__ double red[HESS_THREADS / 64];
   __shared__ bool last;
@@ -123,35 +120,35 @@ __global__ void __launch_bounds__(HESS_THREADS) k_hess(HessArgs a) {
   }
 }
 
-hipError_t launch_hess(const float *mags, int B, int64_t npx, const pcmd_hess_grid &g, uint32_t *hess,
-                       double *moments, double *mom_part, uint32_t *counter, hipStream_t s) {
-  (void)B;
-  const int nb = g.nx * g.ny;
-  hipError_t e = launch_fill_u32(hess, 0u, nb, s);
+__global__ void __launch_bounds__(HESS_THREADS) k_hess(HessArgs a) { hess_body(a); }
+__global__ void __launch_bounds__(HESS_THREADS) k_hess_job(const HessArgs *__restrict__ t, int j) {
+  const HessArgs a = t[j];
+  hess_body(a);
+}
+
+hipError_t launch_hess(const HessArgs &a, hipStream_t s) {
+  const int nb = a.nx * a.ny;
+  hipError_t e = launch_fill_u32(a.hess, 0u, nb, s);
   if (e != hipSuccess) return e;
-  HessArgs a;
-  a.mags = mags;
-  a.npx = npx;
-  a.x0 = g.x0;
-  a.dx = g.dx;
-  a.y0 = g.y0;
-  a.dy = g.dy;
-  a.nx = g.nx;
-  a.ny = g.ny;
-  a.bb = g.b_blue;
-  a.br = g.b_red;
-  a.bm = g.b_mag;
-  a.hess = hess;
-  a.mom_part = mom_part;
-  a.counter = counter;
-  a.moments = moments;
-  a.use_lds = nb <= HESS_LDS_MAX_BINS;
-  // enough pixels per block to amortise clearing and merging the private histogram
-  int64_t blocks = (npx + 4095) / 4096;
-  if (blocks < 1) blocks = 1;
-  if (blocks > HESS_MAX_BLOCKS) blocks = HESS_MAX_BLOCKS;
   const size_t lds = a.use_lds ? (size_t)nb * sizeof(uint32_t) : 0;
-  hipLaunchKernelGGL(k_hess, dim3((unsigned)blocks), dim3(HESS_THREADS), lds, s, a);
+  hipLaunchKernelGGL(k_hess, dim3((unsigned)hess_blocks(a.npx)), dim3(HESS_THREADS), lds, s, a);
+  return hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_hess_clear_job(const HessArgs *__restrict__ t, int j, int nbins) {
+  uint32_t *h = t[j].hess;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nbins; i += gridDim.x * blockDim.x) h[i] = 0u;
+}
+
+hipError_t launch_hess_clear_job(const HessArgs *table, int j, int nbins, hipStream_t s) {
+  hipLaunchKernelGGL(k_hess_clear_job, dim3((nbins + 255) / 256), dim3(256), 0, s, table, j, nbins);
+  return hipGetLastError();
+}
+
+// The job variant expects the histogram already cleared (k_hess_clear_job).
+hipError_t launch_hess_job(const HessArgs *table, int j, int64_t npx, int nbins, hipStream_t s) {
+  const size_t lds = hess_use_lds(nbins) ? (size_t)nbins * sizeof(uint32_t) : 0;
+  hipLaunchKernelGGL(k_hess_job, dim3((unsigned)hess_blocks(npx)), dim3(HESS_THREADS), lds, s, table, j);
   return hipGetLastError();
 }
 
@@ -160,10 +157,11 @@ hipError_t launch_hess(const float *mags, int B, int64_t npx, const pcmd_hess_gr
 // ---------------------------------------------------------------------------------------
 constexpr int LL_THREADS = 1024;
 
-__global__ void __launch_bounds__(LL_THREADS) k_loglike(const uint32_t *__restrict__ hm, const uint32_t *__restrict__ hd,
-                                                        int nbins, const double *__restrict__ mom_m,
-                                                        const double *__restrict__ mom_d, int mode, double eps,
-                                                        double *__restrict__ out) {
+__device__ __forceinline__ void loglike_body(const LoglikeArgs &a) {
+  const uint32_t *__restrict__ hm = a.hm;
+  const uint32_t *__restrict__ hd = a.hd;
+  const int nbins = a.nbins, mode = a.mode;
+  const double eps = a.eps;
   __shared__ double red[LL_THREADS];
   __shared__ unsigned long long tot[2];
   const int t = threadIdx.x;
@@ -204,17 +202,26 @@ __global__ void __launch_bounds__(LL_THREADS) k_loglike(const uint32_t *__restri
   if (t == 0) {
     double r = red[0];
     if (mode != PCMD_LL_POISSON) {
-      const double Cm = mom_m[0] / mom_m[2], Mm = mom_m[1] / mom_m[2];
-      const double Cd = mom_d[0] / mom_d[2], Md = mom_d[1] / mom_d[2];
+      const double Cm = a.mom_m[0] / a.mom_m[2], Mm = a.mom_m[1] / a.mom_m[2];
+      const double Cd = a.mom_d[0] / a.mom_d[2], Md = a.mom_d[1] / a.mom_d[2];
       r += -(Cd - Cm) * (Cd - Cm) / (2.0 * 0.05 * 0.05) - (Md - Mm) * (Md - Mm) / (2.0 * 0.05 * 0.05);
     }
-    out[0] = r;
+    a.out[0] = r;
   }
 }
 
-hipError_t launch_loglike(const uint32_t *hm, const uint32_t *hd, int nbins, const double *mom_m, const double *mom_d,
-                          int mode, double eps, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_loglike, dim3(1), dim3(LL_THREADS), 0, s, hm, hd, nbins, mom_m, mom_d, mode, eps, out);
+__global__ void __launch_bounds__(LL_THREADS) k_loglike(LoglikeArgs a) { loglike_body(a); }
+__global__ void __launch_bounds__(LL_THREADS) k_loglike_job(const LoglikeArgs *__restrict__ t, int j) {
+  const LoglikeArgs a = t[j];
+  loglike_body(a);
+}
+
+hipError_t launch_loglike(const LoglikeArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_loglike, dim3(1), dim3(LL_THREADS), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_loglike_job(const LoglikeArgs *table, int j, hipStream_t s) {
+  hipLaunchKernelGGL(k_loglike_job, dim3(1), dim3(LL_THREADS), 0, s, table, j);
   return hipGetLastError();
 }
 

@@ -8,20 +8,19 @@
 
 namespace pcmd {
 
-// One block per band: FP64 copy of the PSF and a check that it is finite, non-negative and sums
-// to one within 1e-3 (a failure sets a status bit reported by pcmd_sync).
-__global__ void __launch_bounds__(256) k_psf64(const float *__restrict__ psf, int KK, double *__restrict__ out,
-                                               uint32_t *__restrict__ status) {
+// One block per band: check that the PSF is finite, non-negative and sums to one within 1e-3
+// (a failure sets a status bit reported by pcmd_sync).
+__device__ __forceinline__ void psf_check_body(const ConvArgs &a) {
   __shared__ double red[256];
   __shared__ int bad;
   const int b = blockIdx.x;
+  const int KK = a.K * a.K;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
   double s = 0.0;
   for (int i = threadIdx.x; i < KK; i += 256) {
-    const float v = psf[(size_t)b * KK + i];
+    const float v = a.psf[(size_t)b * KK + i];
     if (!(v >= 0.0f) || !isfinite(v)) bad = 1;
-    out[(size_t)b * KK + i] = (double)v;
     s += (double)v;
   }
   red[threadIdx.x] = s;
@@ -30,11 +29,21 @@ __global__ void __launch_bounds__(256) k_psf64(const float *__restrict__ psf, in
     if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && (bad || !(fabs(red[0] - 1.0) <= 1e-3))) atomicOr(status, STATUS_BAD_PSF);
+  if (threadIdx.x == 0 && (bad || !(fabs(red[0] - 1.0) <= 1e-3))) atomicOr(a.status, STATUS_BAD_PSF);
 }
 
-hipError_t launch_psf64(const float *psf, int B, int K, double *psf64, uint32_t *status, hipStream_t s) {
-  hipLaunchKernelGGL(k_psf64, dim3(B), dim3(256), 0, s, psf, K * K, psf64, status);
+__global__ void __launch_bounds__(256) k_psf_check(ConvArgs a) { psf_check_body(a); }
+__global__ void __launch_bounds__(256) k_psf_check_job(const ConvArgs *__restrict__ t, int j) {
+  const ConvArgs a = t[j];
+  psf_check_body(a);
+}
+
+hipError_t launch_psf_check(const ConvArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_psf_check, dim3(a.B), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_psf_check_job(const ConvArgs *table, int j, int B, hipStream_t s) {
+  hipLaunchKernelGGL(k_psf_check_job, dim3(B), dim3(256), 0, s, table, j);
   return hipGetLastError();
 }
 
@@ -62,9 +71,12 @@ size_t conv_direct_lds_bytes(int K) {
   return ((size_t)(CT_Y + K - 1) * (CT_X + K - 1) + (size_t)K * K) * sizeof(float);
 }
 
-__global__ void __launch_bounds__(256) k_conv_direct(const float *__restrict__ F, const float *__restrict__ psf,
-                                                     int N, int K, float *__restrict__ G) {
+__device__ __forceinline__ void conv_direct_body(const ConvArgs &ca) {
   extern __shared__ float lds[];
+  const float *__restrict__ F = ca.F;
+  const float *__restrict__ psf = ca.psf;
+  float *__restrict__ G = ca.G;
+  const int N = ca.N, K = ca.K;
   const int b = blockIdx.z;
   const int h = (K - 1) >> 1;
   const int TW = CT_X + K - 1, TH = CT_Y + K - 1;
@@ -119,19 +131,31 @@ __global__ void __launch_bounds__(256) k_conv_direct(const float *__restrict__ F
   }
 }
 
-hipError_t launch_conv_direct(const float *F, const float *psf, int B, int N, int K, float *G, hipStream_t s) {
+__global__ void __launch_bounds__(256) k_conv_direct(ConvArgs a) { conv_direct_body(a); }
+__global__ void __launch_bounds__(256) k_conv_direct_job(const ConvArgs *__restrict__ t, int j) {
+  const ConvArgs a = t[j];
+  conv_direct_body(a);
+}
+
+hipError_t launch_conv_direct(const ConvArgs &a, hipStream_t s) {
+  const size_t lds = conv_direct_lds_bytes(a.K);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  dim3 grid((a.N + CT_X - 1) / CT_X, (a.N + CT_Y - 1) / CT_Y, a.B);
+  hipLaunchKernelGGL(k_conv_direct, grid, dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_conv_direct_job(const ConvArgs *table, int j, int B, int N, int K, hipStream_t s) {
   const size_t lds = conv_direct_lds_bytes(K);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   dim3 grid((N + CT_X - 1) / CT_X, (N + CT_Y - 1) / CT_Y, B);
-  hipLaunchKernelGGL(k_conv_direct, grid, dim3(256), lds, s, F, psf, N, K, G);
+  hipLaunchKernelGGL(k_conv_direct_job, grid, dim3(256), lds, s, table, j);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------------------
 // Noise and magnitudes (FP64 arithmetic per pixel, FP32 storage).
 // ---------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_noise_mag(NoiseArgs a) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void noise_mag_body(const NoiseArgs &a, int p) {
   if (p >= a.npx) return;
   for (int b = 0; b < a.B; ++b) {
     const double G = (double)a.G[(size_t)b * a.npx + p];
@@ -152,6 +176,17 @@ __global__ void __launch_bounds__(256) k_noise_mag(NoiseArgs a) {
     }
     a.mags[(size_t)b * a.npx + p] = (float)m;
   }
+}
+
+__global__ void __launch_bounds__(256) k_noise_mag(NoiseArgs a) { noise_mag_body(a, blockIdx.x * blockDim.x + threadIdx.x); }
+__global__ void __launch_bounds__(256) k_noise_mag_job(const NoiseArgs *__restrict__ t, int j) {
+  const NoiseArgs a = t[j];
+  noise_mag_body(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+hipError_t launch_noise_mag_job(const NoiseArgs *table, int j, int npx, hipStream_t s) {
+  hipLaunchKernelGGL(k_noise_mag_job, dim3((npx + 255) / 256), dim3(256), 0, s, table, j);
+  return hipGetLastError();
 }
 
 hipError_t launch_noise_mag(const NoiseArgs &a, hipStream_t s) {

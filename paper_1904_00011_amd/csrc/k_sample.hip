@@ -49,41 +49,38 @@ hipError_t launch_entries(const pcmd_grid *g, const double *scale, double *lam, 
 // Per-entry tables: inversion thresholds (lambda < 10) or rejection constants (lambda >= 10)
 // and FP64 star fluxes laid out [E][BP] for scalar loads.
 // ---------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_prep(int E, int B, int BP, const double *__restrict__ lam,
-                                              const float *__restrict__ flux, EntryRec *__restrict__ rec,
-                                              uint32_t *__restrict__ thr, PtrsConst *__restrict__ pc,
-                                              double *__restrict__ fl64, uint32_t *__restrict__ status) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= E) return;
-  for (int b = 0; b < BP; ++b) fl64[(size_t)i * BP + b] = b < B ? (double)flux[(size_t)b * E + i] : 0.0;
-  double l = lam[i];
+__device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
+  if (i >= a.E) return;
+  const int E = a.E, B = a.B, BP = a.BP;
+  for (int b = 0; b < BP; ++b) a.fl64[(size_t)i * BP + b] = b < B ? (double)a.flux[(size_t)b * E + i] : 0.0;
+  double l = a.lam[i];
   if (!(l >= 0.0 && l < 4194304.0)) {  // NaN, negative or too large: drawn as zero, reported
-    atomicOr(status, STATUS_BAD_LAMBDA);
+    atomicOr(a.status, STATUS_BAD_LAMBDA);
     l = 0.0;
   }
   EntryRec r{{0u, 0u, 0u}, KIND_ZERO};
   if (l >= 10.0) {
     const double slam = sqrt(l);
-    const double b = 0.931 + 2.53 * slam;
-    const double a = -0.059 + 0.02483 * b;
-    const double inv_alpha = 1.1239 + 1.1328 / (b - 3.4);
-    const double vr = 0.9277 - 3.6224 / (b - 2.0);
+    const double bb = 0.931 + 2.53 * slam;
+    const double aa = -0.059 + 0.02483 * bb;
+    const double inv_alpha = 1.1239 + 1.1328 / (bb - 3.4);
+    const double vr = 0.9277 - 3.6224 / (bb - 2.0);
     PtrsConst c;
     c.mu = (float)l;
     c.lnmu = (float)log(l);
-    c.b = (float)b;
-    c.a = (float)a;
-    c.twoa = (float)(2.0 * a);
+    c.b = (float)bb;
+    c.a = (float)aa;
+    c.twoa = (float)(2.0 * aa);
     c.lninva = (float)log(inv_alpha);
     c.vr = (float)vr;
     c.pad = 0.0f;
-    pc[i] = c;
+    ((PtrsConst *)a.pc)[i] = c;
     r.kk = KIND_PTRS;
   } else if (l > 0.0) {
     double p = exp(-l);
     double F = p;
     uint32_t K = 0;
-    uint32_t *t = thr + (size_t)i * THR_STRIDE;
+    uint32_t *t = a.thr + (size_t)i * THR_STRIDE;
     for (int k = 0; k < THR_STRIDE - 1; ++k) {
       if (k > 0) {
         p = p * l / (double)k;
@@ -99,12 +96,21 @@ __global__ void __launch_bounds__(256) k_prep(int E, int B, int BP, const double
       r.kk = (K << 8) | KIND_INV;
     }
   }
-  rec[i] = r;
+  a.rec[i] = r;
 }
 
-hipError_t launch_prep(const double *lam, const float *flux, EntryTables &t, uint32_t *status, hipStream_t s) {
-  hipLaunchKernelGGL(k_prep, dim3((t.E + 255) / 256), dim3(256), 0, s, t.E, t.B, t.BP, lam, flux, t.rec, t.thr,
-                     (PtrsConst *)t.pc, t.fl64, status);
+__global__ void __launch_bounds__(256) k_prep(PrepArgs a) { prep_body(a, blockIdx.x * blockDim.x + threadIdx.x); }
+__global__ void __launch_bounds__(256) k_prep_job(const PrepArgs *__restrict__ t, int j) {
+  const PrepArgs a = t[j];
+  prep_body(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+hipError_t launch_prep(const PrepArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep, dim3((a.E + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_prep_job(const PrepArgs *table, int j, int E, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep_job, dim3((E + 255) / 256), dim3(256), 0, s, table, j);
   return hipGetLastError();
 }
 
@@ -174,14 +180,29 @@ __device__ __forceinline__ uint32_t split_count(uint32_t n, uint32_t byte, int m
   return red;
 }
 
+// The entry tables are only read while sampling: reading them through the constant address
+// space lets the wave-uniform loads go through the scalar cache.
+#define PCMD_CONST __attribute__((address_space(4)))
+
+// Copy a struct out of constant-address-space memory word by word (scalar loads).
+template <typename T>
+__device__ __forceinline__ T ld_const(const PCMD_CONST T *p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized structs only");
+  T v;
+  uint32_t *d = reinterpret_cast<uint32_t *>(&v);
+  const PCMD_CONST uint32_t *s = reinterpret_cast<const PCMD_CONST uint32_t *>(p);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) d[k] = s[k];
+  return v;
+}
+
 template <int B, int S, bool DBG>
-__global__ void __launch_bounds__(256) k_sample(SampleArgs a, const EntryRec *__restrict__ rec,
-                                                const uint32_t *__restrict__ thr, const PtrsConst *__restrict__ pc,
-                                                const double *__restrict__ fl64) {
+__device__ __forceinline__ void sample_tile(const SampleArgs &a, int pblk, int chunk) {
   constexpr int BP = B <= 2 ? 2 : 4;
-  const int nblk_px = (a.npx + 255) >> 8;
-  const int chunk = blockIdx.x / nblk_px;
-  const int pblk = blockIdx.x - chunk * nblk_px;
+  const PCMD_CONST EntryRec *rec = (const PCMD_CONST EntryRec *)a.rec;
+  const PCMD_CONST uint32_t *thr = (const PCMD_CONST uint32_t *)a.thr;
+  const PCMD_CONST PtrsConst *pc = (const PCMD_CONST PtrsConst *)a.pc;
+  const PCMD_CONST double *fl64 = (const PCMD_CONST double *)a.fl64;
   const uint32_t p = (uint32_t)(pblk * 256 + threadIdx.x);
   const bool live = p < (uint32_t)a.npx;
   const int e0 = chunk * CHUNK;
@@ -205,7 +226,8 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a, const EntryRec *__
     bool need_main = false;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      r[q] = g0 + q < e1 ? rec[g0 + q] : EntryRec{{0u, 0u, 0u}, KIND_ZERO};
+      r[q] = EntryRec{{0u, 0u, 0u}, KIND_ZERO};
+      if (g0 + q < e1) r[q] = ld_const(rec + g0 + q);
       need_main |= (r[q].kk & 0xFFu) == KIND_INV;
     }
     u4 w{0u, 0u, 0u, 0u};
@@ -242,7 +264,7 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a, const EntryRec *__
               c = u >= r[q].T[2] ? 1u : 0u;
               if (wave_any(c != 0u)) {
                 n += c;
-                const uint32_t *t = thr + (size_t)i * THR_STRIDE;
+                const PCMD_CONST uint32_t *t = thr + (size_t)i * THR_STRIDE;
                 for (uint32_t k = 3; k < K; ++k) {
                   c = u >= t[k] ? 1u : 0u;
                   if (!wave_any(c != 0u)) break;
@@ -253,7 +275,8 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a, const EntryRec *__
           }
         }
       } else if (kind == KIND_PTRS) {
-        n = ptrs_draw(pc[i], p, i, a.k0, a.k1, a.lnfact, ptrs_failed);
+        const PtrsConst c = ld_const(pc + i);
+        n = ptrs_draw(c, p, i, a.k0, a.k1, a.lnfact, ptrs_failed);
       } else {
         continue;
       }
@@ -270,7 +293,7 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a, const EntryRec *__
         }
         red = split_count(n, byte, a.split_mode, a.split_q, p, i, a.k0, a.k1);
       }
-      const double *f = fl64 + (size_t)i * BP;
+      const PCMD_CONST double *f = fl64 + (size_t)i * BP;
       const double dc = (double)(n - red);
 #pragma unroll
       for (int b = 0; b < B; ++b) acc_c[b] = fma(dc, f[b], acc_c[b]);
@@ -296,37 +319,102 @@ __global__ void __launch_bounds__(256) k_sample(SampleArgs a, const EntryRec *__
   }
 }
 
+template <int B, int S, bool DBG>
+__global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
+  const int nblk_px = (a.npx + 255) >> 8;
+  const int chunk = blockIdx.x / nblk_px;
+  sample_tile<B, S, DBG>(a, blockIdx.x - chunk * nblk_px, chunk);
+}
+
 template <int B>
-static hipError_t launch_sample_b(const EntryTables &t, const SampleArgs &a, hipStream_t s) {
+static hipError_t launch_sample_b(const SampleArgs &a, hipStream_t s) {
   const int nblk_px = (a.npx + 255) / 256;
   dim3 grid((unsigned)(nblk_px * a.nchunks));
   const bool dbg = a.dbg_counts != nullptr;
   if (a.S == 2 && dbg)
-    hipLaunchKernelGGL((k_sample<B, 2, true>), grid, dim3(256), 0, s, a, t.rec, t.thr, (const PtrsConst *)t.pc, t.fl64);
+    hipLaunchKernelGGL((k_sample<B, 2, true>), grid, dim3(256), 0, s, a);
   else if (a.S == 2)
-    hipLaunchKernelGGL((k_sample<B, 2, false>), grid, dim3(256), 0, s, a, t.rec, t.thr, (const PtrsConst *)t.pc, t.fl64);
+    hipLaunchKernelGGL((k_sample<B, 2, false>), grid, dim3(256), 0, s, a);
   else if (dbg)
-    hipLaunchKernelGGL((k_sample<B, 1, true>), grid, dim3(256), 0, s, a, t.rec, t.thr, (const PtrsConst *)t.pc, t.fl64);
+    hipLaunchKernelGGL((k_sample<B, 1, true>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((k_sample<B, 1, false>), grid, dim3(256), 0, s, a, t.rec, t.thr, (const PtrsConst *)t.pc, t.fl64);
+    hipLaunchKernelGGL((k_sample<B, 1, false>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
-hipError_t launch_sample(const EntryTables &t, const SampleArgs &a, hipStream_t s) {
+hipError_t launch_sample(const SampleArgs &a, hipStream_t s) {
   switch (a.B) {
-    case 1: return launch_sample_b<1>(t, a, s);
-    case 2: return launch_sample_b<2>(t, a, s);
-    case 3: return launch_sample_b<3>(t, a, s);
-    case 4: return launch_sample_b<4>(t, a, s);
+    case 1: return launch_sample_b<1>(a, s);
+    case 2: return launch_sample_b<2>(a, s);
+    case 3: return launch_sample_b<3>(a, s);
+    case 4: return launch_sample_b<4>(a, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 // ---------------------------------------------------------------------------------------
+// Persistent batched sampler.  Workgroups take tiles (job, pixel block, chunk) from one atomic
+// counter until none is left; jobs appear in the table in execution order (the host puts the
+// most expensive first) and each job's tiles are contiguous items, pixel block fastest.  Every
+// tile is computed exactly as by k_sample, so the schedule never changes a result.
+// ---------------------------------------------------------------------------------------
+__global__ void k_reset_counter(uint32_t *c) { *c = 0u; }
+
+hipError_t launch_reset_counter(uint32_t *counter, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, counter);
+  return hipGetLastError();
+}
+
+template <int B>
+__global__ void __launch_bounds__(256) k_sample_persistent(const BatchSampleJob *__restrict__ jobs, int n_jobs,
+                                                           int total_items, uint32_t *__restrict__ counter) {
+  __shared__ int item_s;
+  const PCMD_CONST BatchSampleJob *cj = (const PCMD_CONST BatchSampleJob *)jobs;
+  for (;;) {
+    if (threadIdx.x == 0) item_s = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    const int item = __builtin_amdgcn_readfirstlane(item_s);
+    __syncthreads();
+    if (item >= total_items) break;
+    // job owning the item: last job with item0 <= item (binary search over the table)
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (cj[mid].item0 <= item)
+        lo = mid;
+      else
+        hi = mid - 1;
+    }
+    const int j = __builtin_amdgcn_readfirstlane(lo);
+    const int local = item - cj[j].item0;
+    const int pblocks = cj[j].pblocks;
+    const int chunk = local / pblocks;
+    const int pblk = local - chunk * pblocks;
+    const SampleArgs a = ld_const(&cj[j].a);
+    if (a.S == 2)
+      sample_tile<B, 2, false>(a, pblk, chunk);
+    else
+      sample_tile<B, 1, false>(a, pblk, chunk);
+  }
+}
+
+hipError_t launch_sample_persistent(const BatchSampleJob *jobs, int n_jobs, int total_items, int B, uint32_t *counter,
+                                    int n_workgroups, hipStream_t s) {
+  dim3 grid((unsigned)n_workgroups);
+  switch (B) {
+    case 1: hipLaunchKernelGGL(k_sample_persistent<1>, grid, dim3(256), 0, s, jobs, n_jobs, total_items, counter); break;
+    case 2: hipLaunchKernelGGL(k_sample_persistent<2>, grid, dim3(256), 0, s, jobs, n_jobs, total_items, counter); break;
+    case 3: hipLaunchKernelGGL(k_sample_persistent<3>, grid, dim3(256), 0, s, jobs, n_jobs, total_items, counter); break;
+    case 4: hipLaunchKernelGGL(k_sample_persistent<4>, grid, dim3(256), 0, s, jobs, n_jobs, total_items, counter); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------
 // Chunk reduction + epilogue: F_b = 10^(-0.4 mu_d) (F_clr_b + F_red_b 10^(-0.4 R_b E_p)).
 // ---------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void reduce_body(const ReduceArgs &a, int p) {
   if (p >= a.npx) return;
   double ebv = 0.0;
   if (a.dust_model == PCMD_DUST_SCREEN) {
@@ -351,8 +439,18 @@ __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) { reduce_body(a, blockIdx.x * blockDim.x + threadIdx.x); }
+__global__ void __launch_bounds__(256) k_reduce_job(const ReduceArgs *__restrict__ t, int j) {
+  const ReduceArgs a = t[j];
+  reduce_body(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_reduce, dim3((a.npx + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_reduce_job(const ReduceArgs *table, int j, int npx, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_job, dim3((npx + 255) / 256), dim3(256), 0, s, table, j);
   return hipGetLastError();
 }
 

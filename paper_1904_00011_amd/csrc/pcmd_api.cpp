@@ -9,113 +9,57 @@
 #include <string>
 #include <vector>
 
+#include "pcmd_ctx.h"
 #include "pcmd_device.h"
 #include "pcmd_internal.h"
 
 using namespace pcmd;
 
-struct Buf {
-  void *p = nullptr;
-  size_t n = 0;
-};
+namespace pcmd {
 
-struct TimerRec {
-  int which;
-  hipEvent_t start, stop;
-  double units;
-};
-
-struct pcmd_ctx {
-  int device = 0;
-  std::string err;
-  bool timing = false;
-  std::vector<TimerRec> timers;
-  Buf rec, thr, pc, fl64, part, F, G, psf64, mom_part, fft;
-  float *lnfact = nullptr;     // [256]
-  uint32_t *status = nullptr;  // [1]
-  uint32_t *counter = nullptr; // [1]
-};
-
-namespace {
-
-int fail(pcmd_ctx *c, int code, const char *fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  if (c) c->err = buf;
-  return code;
+bool uses_fft(const pcmd_obs *o) {
+  return o->psf_k > 1 && (o->conv_path == PCMD_CONV_FFT ||
+                          (o->conv_path == PCMD_CONV_AUTO && o->psf_k >= 31 && fft_supported(o->nim)));
 }
 
-int hip_fail(pcmd_ctx *c, hipError_t e, const char *what) {
-  return fail(c, PCMD_E_HIP, "%s: %s", what, hipGetErrorString(e));
-}
-
-// Grow-only device buffer.
-int ensure(pcmd_ctx *c, Buf &b, size_t bytes, const char *what) {
-  if (bytes <= b.n) return PCMD_OK;
-  if (b.p) {
-    hipError_t e = hipFree(b.p);
-    if (e != hipSuccess) return hip_fail(c, e, "hipFree");
-    b.p = nullptr;
-    b.n = 0;
+int validate_sim(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, const char *who) {
+  if (!iso || !o) return fail(c, PCMD_E_INVAL, "%s: null argument", who);
+  const int E = iso->n_entries, B = iso->n_bands;
+  if (E <= 0 || E > (1 << 26)) return fail(c, PCMD_E_INVAL, "%s: n_entries %d out of range", who, E);
+  if (B < 1 || B > PCMD_MAX_BANDS) return fail(c, PCMD_E_INVAL, "%s: n_bands %d out of range", who, B);
+  if (!iso->lam || !iso->flux) return fail(c, PCMD_E_INVAL, "%s: null lam/flux", who);
+  const int N = o->nim;
+  if (N < 1 || N > 8192) return fail(c, PCMD_E_INVAL, "%s: nim %d out of range", who, N);
+  if (!isfinite(o->dmod)) return fail(c, PCMD_E_INVAL, "%s: dmod not finite", who);
+  if (o->dust_model < 0 || o->dust_model > 2) return fail(c, PCMD_E_INVAL, "%s: bad dust_model", who);
+  if (o->dust_model != PCMD_DUST_NONE) {
+    if (!(o->dust_frac >= 0.0 && o->dust_frac <= 1.0)) return fail(c, PCMD_E_INVAL, "%s: dust_frac outside [0,1]", who);
+    if (!isfinite(o->dust_mu) || !(o->dust_sigma >= 0.0) || !isfinite(o->dust_sigma))
+      return fail(c, PCMD_E_INVAL, "%s: bad dust parameters", who);
+    for (int b = 0; b < B; ++b)
+      if (!isfinite(o->dust_R[b])) return fail(c, PCMD_E_INVAL, "%s: dust_R not finite", who);
   }
-  size_t want = bytes + bytes / 8 + 256;
-  hipError_t e = hipMalloc(&b.p, want);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    b.p = nullptr;
-    return fail(c, PCMD_E_NOMEM, "cannot allocate %zu bytes of scratch for %s", want, what);
+  const int K = o->psf_k;
+  if (K < 1 || (K & 1) == 0 || K > N || K > PCMD_MAX_PSF_K)
+    return fail(c, PCMD_E_INVAL, "%s: psf_k %d must be odd, <= nim and <= %d", who, K, PCMD_MAX_PSF_K);
+  if (K > 1 && !o->psf) return fail(c, PCMD_E_INVAL, "%s: psf is NULL", who);
+  if (o->conv_path < 0 || o->conv_path > 2) return fail(c, PCMD_E_INVAL, "%s: bad conv_path", who);
+  if (o->noise_model < 0 || o->noise_model > 2) return fail(c, PCMD_E_INVAL, "%s: bad noise_model", who);
+  for (int b = 0; b < B; ++b) {
+    if (o->noise_model == PCMD_NOISE_GAUSS_MAG && !(o->noise_sigma_mag[b] >= 0.0 && isfinite(o->noise_sigma_mag[b])))
+      return fail(c, PCMD_E_INVAL, "%s: bad noise_sigma_mag", who);
+    if (o->noise_model == PCMD_NOISE_SHOT &&
+        (!(o->exptime[b] > 0.0) || !isfinite(o->exptime[b]) || !isfinite(o->zp[b]) || !(o->sky[b] >= 0.0)))
+      return fail(c, PCMD_E_INVAL, "%s: bad exptime/zp/sky", who);
   }
-  b.n = want;
+  if (uses_fft(o) && !fft_supported(N))
+    return fail(c, PCMD_E_UNSUPPORTED, "%s: FFT path needs nim a power of two in [8, 4096]", who);
+  if (K > 1 && !uses_fft(o) && conv_direct_lds_bytes(K) > 160 * 1024)
+    return fail(c, PCMD_E_UNSUPPORTED, "%s: psf_k %d too large for the direct path; use the FFT path", who, K);
   return PCMD_OK;
 }
 
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-    if (prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    if (prev >= 0) (void)hipSetDevice(prev);
-  }
-};
-
-
-// Event pair around one launch when timing is enabled.
-struct ScopedTimer {
-  pcmd_ctx *c;
-  hipStream_t s;
-  TimerRec r{};
-  bool on;
-  ScopedTimer(pcmd_ctx *c_, int which, double units, hipStream_t s_) : c(c_), s(s_), on(c_->timing) {
-    if (!on) return;
-    r.which = which;
-    r.units = units;
-    if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) {
-      on = false;
-      return;
-    }
-    (void)hipEventRecord(r.start, s);
-  }
-  ~ScopedTimer() {
-    if (!on) return;
-    (void)hipEventRecord(r.stop, s);
-    c->timers.push_back(r);
-  }
-};
-
-void clear_timers(pcmd_ctx *c) {
-  for (auto &t : c->timers) {
-    (void)hipEventDestroy(t.start);
-    (void)hipEventDestroy(t.stop);
-  }
-  c->timers.clear();
-}
-
-}  // namespace
+}  // namespace pcmd
 
 extern "C" {
 
@@ -131,6 +75,9 @@ int pcmd_create(pcmd_ctx **out, int hip_device) {
   pcmd_ctx *c = new pcmd_ctx();
   c->device = hip_device;
   DeviceGuard g(hip_device);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, hip_device) == hipSuccess && prop.multiProcessorCount > 0)
+    c->n_cu = prop.multiProcessorCount;
   // ln k! for k < 256: FP64 running sum of ln j, rounded to FP32.
   float tab[256];
   double acc = 0.0;
@@ -161,9 +108,9 @@ void pcmd_destroy(pcmd_ctx *c) {
   DeviceGuard g(c->device);
   (void)hipDeviceSynchronize();
   clear_timers(c);
-  Buf *bufs[] = {&c->rec, &c->thr, &c->pc, &c->fl64, &c->part, &c->F, &c->G, &c->psf64, &c->mom_part, &c->fft};
-  for (Buf *b : bufs)
-    if (b->p) (void)hipFree(b->p);
+  batch_destroy(c);
+  Buf *bufs[] = {&c->rec, &c->thr, &c->pc, &c->fl64, &c->part, &c->F, &c->G, &c->mom_part, &c->fft};
+  for (Buf *b : bufs) release(*b);
   if (c->lnfact) (void)hipFree(c->lnfact);
   if (c->status) (void)hipFree(c->status);
   if (c->counter) (void)hipFree(c->counter);
@@ -340,36 +287,11 @@ int pcmd_entries(pcmd_ctx *c, const pcmd_grid *g, const double *iso_w, double np
 int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *mags, const pcmd_debug *dbg,
                   pcmd_stream stream) {
   if (!c) return PCMD_E_INVAL;
-  if (!iso || !o || !mags) return fail(c, PCMD_E_INVAL, "pcmd_simulate: null argument");
-  const int E = iso->n_entries, B = iso->n_bands;
-  if (E <= 0 || E > (1 << 26)) return fail(c, PCMD_E_INVAL, "pcmd_simulate: n_entries %d out of range", E);
-  if (B < 1 || B > PCMD_MAX_BANDS) return fail(c, PCMD_E_INVAL, "pcmd_simulate: n_bands %d out of range", B);
-  if (!iso->lam || !iso->flux) return fail(c, PCMD_E_INVAL, "pcmd_simulate: null lam/flux");
-  const int N = o->nim;
-  if (N < 1 || N > 8192) return fail(c, PCMD_E_INVAL, "pcmd_simulate: nim %d out of range", N);
+  if (!mags) return fail(c, PCMD_E_INVAL, "pcmd_simulate: null mags_out");
+  int r = validate_sim(c, iso, o, "pcmd_simulate");
+  if (r) return r;
+  const int E = iso->n_entries, B = iso->n_bands, N = o->nim, K = o->psf_k;
   const int64_t npx = (int64_t)N * N;
-  if (!isfinite(o->dmod)) return fail(c, PCMD_E_INVAL, "pcmd_simulate: dmod not finite");
-  if (o->dust_model < 0 || o->dust_model > 2) return fail(c, PCMD_E_INVAL, "pcmd_simulate: bad dust_model");
-  if (o->dust_model != PCMD_DUST_NONE) {
-    if (!(o->dust_frac >= 0.0 && o->dust_frac <= 1.0)) return fail(c, PCMD_E_INVAL, "pcmd_simulate: dust_frac outside [0,1]");
-    if (!isfinite(o->dust_mu) || !(o->dust_sigma >= 0.0) || !isfinite(o->dust_sigma))
-      return fail(c, PCMD_E_INVAL, "pcmd_simulate: bad dust parameters");
-    for (int b = 0; b < B; ++b)
-      if (!isfinite(o->dust_R[b])) return fail(c, PCMD_E_INVAL, "pcmd_simulate: dust_R not finite");
-  }
-  const int K = o->psf_k;
-  if (K < 1 || (K & 1) == 0 || K > N || K > PCMD_MAX_PSF_K)
-    return fail(c, PCMD_E_INVAL, "pcmd_simulate: psf_k %d must be odd, <= nim and <= %d", K, PCMD_MAX_PSF_K);
-  if (K > 1 && !o->psf) return fail(c, PCMD_E_INVAL, "pcmd_simulate: psf is NULL");
-  if (o->conv_path < 0 || o->conv_path > 2) return fail(c, PCMD_E_INVAL, "pcmd_simulate: bad conv_path");
-  if (o->noise_model < 0 || o->noise_model > 2) return fail(c, PCMD_E_INVAL, "pcmd_simulate: bad noise_model");
-  for (int b = 0; b < B; ++b) {
-    if (o->noise_model == PCMD_NOISE_GAUSS_MAG && !(o->noise_sigma_mag[b] >= 0.0 && isfinite(o->noise_sigma_mag[b])))
-      return fail(c, PCMD_E_INVAL, "pcmd_simulate: bad noise_sigma_mag");
-    if (o->noise_model == PCMD_NOISE_SHOT &&
-        (!(o->exptime[b] > 0.0) || !isfinite(o->exptime[b]) || !isfinite(o->zp[b]) || !(o->sky[b] >= 0.0)))
-      return fail(c, PCMD_E_INVAL, "pcmd_simulate: bad exptime/zp/sky");
-  }
   int64_t px0 = 0, px1 = 0;
   if (dbg && (dbg->counts || dbg->reddened)) {
     px0 = dbg->px0;
@@ -377,18 +299,13 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
     if (!dbg->counts || px0 < 0 || px1 <= px0 || px1 > npx)
       return fail(c, PCMD_E_INVAL, "pcmd_simulate: bad debug window [%lld, %lld)", (long long)px0, (long long)px1);
   }
-  const bool use_fft = o->conv_path == PCMD_CONV_FFT || (o->conv_path == PCMD_CONV_AUTO && K >= 31 && fft_supported(N));
-  if (K > 1 && use_fft && !fft_supported(N))
-    return fail(c, PCMD_E_UNSUPPORTED, "pcmd_simulate: FFT path needs nim a power of two in [8, 4096]");
-  if (K > 1 && !use_fft && conv_direct_lds_bytes(K) > 160 * 1024)
-    return fail(c, PCMD_E_UNSUPPORTED, "pcmd_simulate: psf_k %d too large for the direct path; use the FFT path", K);
+  const bool use_fft = uses_fft(o);
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(c->device);
   const int BP = B <= 2 ? 2 : 4;
   const int nchunks = (E + CHUNK - 1) / CHUNK;
-  const bool split = o->dust_model != PCMD_DUST_NONE && o->dust_frac > 0.0;
-  const int S = split ? 2 : 1;
-  int r;
+  const int split_mode = split_mode_of(o);
+  const int S = split_mode == SPLIT_NONE ? 1 : 2;
   if ((r = ensure(c, c->rec, (size_t)E * sizeof(EntryRec), "entry records"))) return r;
   if ((r = ensure(c, c->thr, (size_t)E * THR_STRIDE * 4, "thresholds"))) return r;
   if ((r = ensure(c, c->pc, (size_t)E * sizeof(PtrsConst), "rejection constants"))) return r;
@@ -396,18 +313,11 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   if ((r = ensure(c, c->part, (size_t)nchunks * S * B * npx * 8, "partial sums"))) return r;
   if ((r = ensure(c, c->F, (size_t)B * npx * 4, "image"))) return r;
   if ((r = ensure(c, c->G, (size_t)B * npx * 4, "convolved image"))) return r;
-  if (K > 1 && (r = ensure(c, c->psf64, (size_t)B * K * K * 8, "psf"))) return r;
   if (K > 1 && use_fft && (r = ensure(c, c->fft, fft_scratch_bytes(B, N), "fft"))) return r;
 
-  EntryTables t;
-  t.E = E;
-  t.B = B;
-  t.BP = BP;
-  t.rec = (EntryRec *)c->rec.p;
-  t.thr = (uint32_t *)c->thr.p;
-  t.pc = c->pc.p;
-  t.fl64 = (double *)c->fl64.p;
-  hipError_t e = launch_prep(iso->lam, iso->flux, t, c->status, s);
+  PrepArgs pa{E, B, BP, iso->lam, iso->flux, (EntryRec *)c->rec.p, (uint32_t *)c->thr.p, c->pc.p, (double *)c->fl64.p,
+              c->status};
+  hipError_t e = launch_prep(pa, s);
   if (e != hipSuccess) return hip_fail(c, e, "k_prep");
 
   const uint32_t k0 = (uint32_t)(o->seed & 0xFFFFFFFFu), k1 = (uint32_t)(o->seed >> 32);
@@ -425,8 +335,12 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   a.S = S;
   a.k0 = k0;
   a.k1 = k1;
-  a.split_mode = !split ? SPLIT_NONE : (o->dust_frac >= 1.0 ? SPLIT_ALL : (o->dust_frac == 0.5 ? SPLIT_HALF : SPLIT_GENERAL));
-  a.split_q = (uint32_t)fmin(floor(o->dust_frac * 4294967296.0), 4294967295.0);
+  a.split_mode = split_mode;
+  a.split_q = split_q_of(o);
+  a.rec = pa.rec;
+  a.thr = pa.thr;
+  a.pc = pa.pc;
+  a.fl64 = pa.fl64;
   a.part = (double *)c->part.p;
   a.dbg_counts = dbg ? dbg->counts : nullptr;
   a.dbg_red = dbg ? dbg->reddened : nullptr;
@@ -436,7 +350,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   a.lnfact = c->lnfact;
   {
     ScopedTimer tm(c, PCMD_TIMER_SAMPLE, (double)npx * (double)E, s);
-    e = launch_sample(t, a, s);
+    e = launch_sample(a, s);
   }
   if (e != hipSuccess) return hip_fail(c, e, "k_sample");
 
@@ -462,16 +376,15 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   }
   const float *Gp = (const float *)c->F.p;
   if (K > 1) {
-    e = launch_psf64(o->psf, B, K, (double *)c->psf64.p, c->status, s);
+    ConvArgs ca{B, N, K, (const float *)c->F.p, o->psf, (float *)c->G.p, c->status};
+    e = launch_psf_check(ca, s);
     if (e != hipSuccess) return hip_fail(c, e, "psf check");
     ScopedTimer tm(c, PCMD_TIMER_CONV, 2.0 * (double)B * (double)npx, s);
-    if (use_fft) {
+    if (use_fft)
       e = launch_conv_fft((const float *)c->F.p, o->psf, B, N, K, (float *)c->G.p, c->fft.p, s);
-      if (e != hipSuccess) return hip_fail(c, e, "fft convolution");
-    } else {
-      e = launch_conv_direct((const float *)c->F.p, o->psf, B, N, K, (float *)c->G.p, s);
-      if (e != hipSuccess) return hip_fail(c, e, "direct convolution");
-    }
+    else
+      e = launch_conv_direct(ca, s);
+    if (e != hipSuccess) return hip_fail(c, e, "convolution");
     Gp = (const float *)c->G.p;
   }
   if (dbg && dbg->flux_psf) {
@@ -517,10 +430,27 @@ int pcmd_hess(pcmd_ctx *c, const float *mags, int32_t B, int64_t npx, const pcmd
   DeviceGuard dg(c->device);
   int r = ensure(c, c->mom_part, (size_t)hess_max_blocks() * 3 * 8, "moment partials");
   if (r) return r;
+  HessArgs a;
+  a.mags = mags;
+  a.npx = npx;
+  a.x0 = g->x0;
+  a.dx = g->dx;
+  a.y0 = g->y0;
+  a.dy = g->dy;
+  a.nx = g->nx;
+  a.ny = g->ny;
+  a.bb = g->b_blue;
+  a.br = g->b_red;
+  a.bm = g->b_mag;
+  a.hess = hess;
+  a.mom_part = (double *)c->mom_part.p;
+  a.counter = c->counter;
+  a.moments = moments;
+  a.use_lds = hess_use_lds(g->nx * g->ny);
   hipError_t e;
   {
     ScopedTimer tm(c, PCMD_TIMER_HESS, (double)npx, (hipStream_t)stream);
-    e = launch_hess(mags, B, npx, *g, hess, moments, (double *)c->mom_part.p, c->counter, (hipStream_t)stream);
+    e = launch_hess(a, (hipStream_t)stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "k_hess");
   c->err.clear();
@@ -536,7 +466,8 @@ int pcmd_loglike(pcmd_ctx *c, const uint32_t *hm, const uint32_t *hd, int32_t nb
   if (mode == PCMD_LL_POISSON && !(eps > 0.0 && isfinite(eps))) return fail(c, PCMD_E_INVAL, "pcmd_loglike: eps must be > 0");
   if (mode != PCMD_LL_POISSON && (!mom_m || !mom_d)) return fail(c, PCMD_E_INVAL, "pcmd_loglike: moments needed");
   DeviceGuard dg(c->device);
-  hipError_t e = launch_loglike(hm, hd, nbins, mom_m, mom_d, mode, eps, out, (hipStream_t)stream);
+  LoglikeArgs a{hm, hd, nbins, mode, mom_m, mom_d, eps, out};
+  hipError_t e = launch_loglike(a, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(c, e, "k_loglike");
   c->err.clear();
   return PCMD_OK;

@@ -1,4 +1,9 @@
 // Internal launch interface between the C ABI layer and the gfx950 kernels.
+//
+// Every kernel's arguments form one plain struct.  A single simulation passes it by value; the
+// batched path keeps one struct per job in a device table and launches the `_job` variant with
+// (table, job index), so that a captured graph can be replayed with new parameters by
+// rewriting the table.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -15,25 +20,33 @@ struct EntryRec {
   uint32_t kk;    // (number of thresholds K) << 8 | kind (KIND_ZERO, KIND_INV, KIND_PTRS)
 };
 
-// Device-side tables built from lambda and the star fluxes for one simulation.
-struct EntryTables {
-  int E = 0, B = 0, BP = 0;
-  EntryRec *rec = nullptr;   // [E]
-  uint32_t *thr = nullptr;   // [E][THR_STRIDE]
-  void *pc = nullptr;        // [E] PtrsConst
-  double *fl64 = nullptr;    // [E][BP]
-};
-
 // Device status bits, reported by pcmd_sync.
 constexpr uint32_t STATUS_PTRS_RETRY = 1u, STATUS_BAD_LAMBDA = 2u, STATUS_BAD_PSF = 4u;
 
 enum SplitMode { SPLIT_NONE = 0, SPLIT_HALF = 1, SPLIT_GENERAL = 2, SPLIT_ALL = 3 };
 
+// Per-entry tables built from lambda and the star fluxes (k_prep).
+struct PrepArgs {
+  int E, B, BP;
+  const double *lam;   // [E]
+  const float *flux;   // [B][E]
+  EntryRec *rec;       // [E]
+  uint32_t *thr;       // [E][THR_STRIDE]
+  void *pc;            // [E] PtrsConst
+  double *fl64;        // [E][BP]
+  uint32_t *status;
+};
+
+// Sampler over (pixel block of 256, chunk of CHUNK entries) tiles (k_sample).
 struct SampleArgs {
   int E, B, BP, npx, nchunks, S;
   uint32_t k0, k1;
   int split_mode;
   uint32_t split_q;
+  const EntryRec *rec;
+  const uint32_t *thr;
+  const void *pc;
+  const double *fl64;
   double *part;  // [nchunks][S][B][npx]
   uint32_t *dbg_counts, *dbg_red;
   int64_t px0, px1;
@@ -41,6 +54,7 @@ struct SampleArgs {
   const float *lnfact;
 };
 
+// Chunk reduction and dust / distance epilogue (k_reduce).
 struct ReduceArgs {
   int B, npx, nchunks, S;
   const double *part;
@@ -52,6 +66,16 @@ struct ReduceArgs {
   uint32_t k0, k1;
 };
 
+// PSF check (k_psf_check) and direct periodic convolution (k_conv_direct).
+struct ConvArgs {
+  int B, N, K;
+  const float *F;    // [B][N][N]
+  const float *psf;  // [B][K][K]
+  float *G;          // [B][N][N]
+  uint32_t *status;
+};
+
+// Sky, noise and magnitudes (k_noise_mag).
 struct NoiseArgs {
   int B, npx;
   const float *G;  // [B][npx]
@@ -61,18 +85,56 @@ struct NoiseArgs {
   uint32_t k0, k1;
 };
 
+// Hess diagram (k_hess).
+struct HessArgs {
+  const float *mags;
+  int64_t npx;
+  double x0, dx, y0, dy;
+  int nx, ny, bb, br, bm;
+  uint32_t *hess;
+  double *mom_part;  // [blocks][3]
+  uint32_t *counter;
+  double *moments;
+  int use_lds;
+};
+
+// Log-likelihood (k_loglike).
+struct LoglikeArgs {
+  const uint32_t *hm, *hd;
+  int nbins, mode;
+  const double *mom_m, *mom_d;
+  double eps;
+  double *out;
+};
+
+// Sampler job of the persistent batched kernel: its tiles are items [item0, item0 + items).
+struct BatchSampleJob {
+  SampleArgs a;
+  int item0, items, pblocks, pad;
+};
+
 // k_sample.hip
 hipError_t launch_entries(const pcmd_grid *g, const double *scale, double *lam, uint32_t *status, hipStream_t s);
-hipError_t launch_prep(const double *lam, const float *flux, EntryTables &t, uint32_t *status, hipStream_t s);
-hipError_t launch_sample(const EntryTables &t, const SampleArgs &a, hipStream_t s);
+hipError_t launch_prep(const PrepArgs &a, hipStream_t s);
+hipError_t launch_prep_job(const PrepArgs *table, int j, int E, hipStream_t s);
+hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
+hipError_t launch_sample_persistent(const BatchSampleJob *jobs, int n_jobs, int total_items, int B, uint32_t *counter,
+                                    int n_workgroups, hipStream_t s);
+hipError_t launch_reset_counter(uint32_t *counter, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s);
+hipError_t launch_reduce_job(const ReduceArgs *table, int j, int npx, hipStream_t s);
 
 // k_image.hip
-hipError_t launch_psf64(const float *psf, int B, int K, double *psf64, uint32_t *status, hipStream_t s);
+hipError_t launch_psf_check(const ConvArgs &a, hipStream_t s);
+hipError_t launch_psf_check_job(const ConvArgs *table, int j, int B, hipStream_t s);
 size_t conv_direct_lds_bytes(int K);
-hipError_t launch_conv_direct(const float *F, const float *psf, int B, int N, int K, float *G, hipStream_t s);
+hipError_t launch_conv_direct(const ConvArgs &a, hipStream_t s);
+hipError_t launch_conv_direct_job(const ConvArgs *table, int j, int B, int N, int K, hipStream_t s);
 hipError_t launch_noise_mag(const NoiseArgs &a, hipStream_t s);
+hipError_t launch_noise_mag_job(const NoiseArgs *table, int j, int npx, hipStream_t s);
 hipError_t launch_copy_f32(const float *src, float *dst, int64_t n, hipStream_t s);
+
+// k_fft.hip
 int fft_supported(int N);
 size_t fft_scratch_bytes(int B, int N);
 hipError_t launch_conv_fft(const float *F, const float *psf, int B, int N, int K, float *G, void *scratch,
@@ -80,10 +142,13 @@ hipError_t launch_conv_fft(const float *F, const float *psf, int B, int N, int K
 
 // k_hess.hip
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);
-hipError_t launch_hess(const float *mags, int B, int64_t npx, const pcmd_hess_grid &g, uint32_t *hess,
-                       double *moments, double *mom_part, uint32_t *counter, hipStream_t s);
-hipError_t launch_loglike(const uint32_t *hm, const uint32_t *hd, int nbins, const double *mom_m,
-                          const double *mom_d, int mode, double eps, double *out, hipStream_t s);
 int hess_max_blocks();
+int hess_blocks(int64_t npx);
+bool hess_use_lds(int nbins);
+hipError_t launch_hess(const HessArgs &a, hipStream_t s);
+hipError_t launch_hess_job(const HessArgs *table, int j, int64_t npx, int nbins, hipStream_t s);
+hipError_t launch_hess_clear_job(const HessArgs *table, int j, int nbins, hipStream_t s);
+hipError_t launch_loglike(const LoglikeArgs &a, hipStream_t s);
+hipError_t launch_loglike_job(const LoglikeArgs *table, int j, hipStream_t s);
 
 }  // namespace pcmd

@@ -257,3 +257,28 @@ def hess_grid_from_median(mx: float, my: float, nx: int = 100, ny: int = 100, d:
     x0 = math.floor(mx / d) * d - (nx // 2) * d
     y0 = math.floor(my / d) * d - (ny // 2) * d
     return dict(x0=x0, dx=d, y0=y0, dy=d, nx=nx, ny=ny)
+
+
+def batch_workload(n_jobs: int = 256, seed0: int = 0, nim_log2=(6.0, 9.0), entries=(5000, 52500), psf_k: int = 31,
+                   grid: IsoGrid | None = None):
+    """Uneven batch of parameter points: per job an image side 2^U[6, 9] rounded to a multiple of
+    16, an isochrone set of U[5k, 52.5k] entries (mass points of the headline grid subsampled),
+    and parameters drawn from the mock-test priors with seed `seed0 + j`.  Returns a list of
+    (grid, model, obs) tuples; grids are shared between jobs with the same subsampling."""
+    base = headline_grid() if grid is None else grid
+    cache = {}
+    out = []
+    for j in range(n_jobs):
+        r = np.random.default_rng(np.random.SeedSequence([4242, seed0 + j]))
+        nim = int(round(2.0 ** r.uniform(*nim_log2) / 16.0)) * 16
+        nim = max(nim, 16)
+        e_target = r.uniform(*entries)
+        stride = max(1, int(round(base.n_entries / e_target)))
+        if stride not in cache:
+            cache[stride] = base.subsample(stride)
+        model, obs = draw_headline_params(seed0 + j)
+        obs.nim = nim
+        if psf_k != 31:
+            obs.psf = psf_stack(psf_k, (1.6, 1.8, 2.0))
+        out.append((cache[stride], model, obs))
+    return out
