@@ -32,6 +32,10 @@ VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
 # threshold compare.  Data-dependent work (accumulation, extra thresholds, rejection, dust
 # split) is not counted, so the fraction is a lower bound.
 OPS_PER_DRAW = 60 / 4 + 1
+# HBM bytes per k_sample launch of the first headline step, from FETCH_SIZE and WRITE_SIZE
+# calibrated against a copy of known size (profiles/k_sample_headline_256x256_52500_counters.md).
+# Set to None whenever k_sample changes until the counters are taken again.
+SAMPLE_TRAFFIC_BYTES = 114.1e6
 
 
 def parse():
@@ -42,7 +46,148 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=256, help="pixels in the oracle's timed sampler window")
     ap.add_argument("--conv", type=int, default=0, help="0 auto, 1 direct, 2 fft")
+    ap.add_argument("--workload", default="headline", choices=["headline", "batch", "counters"],
+                    help="headline: 256x256 single evaluations; batch: 256 uneven jobs per step; counters: one "
+                         "headline simulation plus a copy of known size, for hardware-counter runs")
+    ap.add_argument("--jobs", type=int, default=256)
+    ap.add_argument("--no-graph", action="store_true")
     return ap.parse_args()
+
+
+def run_batch(args):
+    """256 uneven parameter points per step (image sides 2^U[6,9] rounded to 16, 5k-52.5k entries,
+    parameters from the mock-test priors, 31x31 PSF on the direct path) through the persistent
+    batched launch replayed from a HIP graph, against the same jobs as sequential single calls."""
+    import torch
+
+    import paper_1904_00011_amd as P
+    import synth_inputs as si
+
+    dev = torch.device("cuda:0")
+    ctx = P.Context(0)
+    work = si.batch_workload(args.jobs, 0)
+    evs = {}
+    jobs = []
+    for grid, model, obs in work:
+        key = id(grid)
+        if key not in evs:
+            evs[key] = P.Evaluator(ctx, grid, 64, None, dict(x0=0, dx=0.05, y0=0, dy=0.05, nx=100, ny=100))
+        ev = evs[key]
+        lam = torch.empty(grid.n_entries, dtype=torch.float64, device=dev)
+        jobs.append(dict(ev=ev, model=model, lam=lam, flux=ev.flux_d, obs=obs,
+                         psf=torch.from_numpy(obs.psf).to(dev), conv_path=P.CONV_DIRECT))
+    # data Hess: the 256x256 headline data image (seed 2), direct convolution
+    model_d, obs_d = si.draw_headline_params(2)
+    hd = P.Evaluator(ctx, si.headline_grid(), obs_d.nim, obs_d.psf, dict(x0=0.0, dx=0.05, y0=0.0, dy=0.05, nx=100, ny=100))
+    mags_d = hd.simulate(model_d, obs_d, P.CONV_DIRECT).clone()
+    ctx.sync()
+    md = mags_d.cpu().numpy().astype(np.float64)
+    fin = np.isfinite(md).all(axis=0)
+    hgrid = si.hess_grid_from_median(float(np.median((md[0] - md[1])[fin])), float(np.median(md[1][fin])), 100, 100)
+    hd.hess_grid = hgrid
+    data_hess = torch.empty(10000, dtype=torch.int32, device=dev)
+    data_mom = torch.empty(3, dtype=torch.float64, device=dev)
+    hd.hess_of(mags_d, data_hess, data_mom)
+    n = len(jobs)
+    ll = torch.empty(n, dtype=torch.float64, device=dev)
+
+    def entries_all():
+        for j in jobs:
+            w, npix = P.iso_weights(j["model"], j["ev"].grid)
+            ctx.entries(j["ev"].E, j["ev"].iso_d, j["ev"].imf_d, j["ev"].iso_imf_sum, w, npix, j["lam"])
+
+    entries_all()
+    best, cand_ms = ctx.batch_autotune(jobs, hgrid, data_hess, data_mom, ll)
+    use_graph = not args.no_graph
+    for _ in range(max(args.warmup, 1)):
+        entries_all()
+        ctx.batch_run(jobs, hgrid, data_hess, data_mom, ll, use_graph=use_graph)
+    torch.cuda.synchronize()
+    ctx.timer_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        entries_all()
+        ctx.batch_run(jobs, hgrid, data_hess, data_mom, ll, use_graph=use_graph)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    b_ms, b_n, b_units = ctx.timer_read(P._lib.TIMER_BATCH)
+    ctx.timer_enable(False)
+    ll_batch = ll.cpu().numpy().copy()
+    # the same jobs as sequential single calls
+    ll_seq = torch.empty(n, dtype=torch.float64, device=dev)
+    mags = {}
+    hs = torch.empty(10000, dtype=torch.int32, device=dev)
+    mom = torch.empty(3, dtype=torch.float64, device=dev)
+
+    def sequential():
+        for k, j in enumerate(jobs):
+            N = j["obs"].nim
+            if N not in mags:
+                mags[N] = torch.empty((3, N * N), dtype=torch.float32, device=dev)
+            w, npix = P.iso_weights(j["model"], j["ev"].grid)
+            ctx.entries(j["ev"].E, j["ev"].iso_d, j["ev"].imf_d, j["ev"].iso_imf_sum, w, npix, j["lam"])
+            ctx.simulate(j["lam"], j["flux"], j["obs"], mags[N], psf=j["psf"], conv_path=P.CONV_DIRECT)
+            ctx.hess(mags[N], 3, N * N, hgrid, hs, mom)
+            ctx.loglike(hs, data_hess, mom, data_mom, ll_seq[k:k + 1])
+
+    sequential()
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    sequential()
+    torch.cuda.synchronize()
+    s1 = time.perf_counter()
+    identical = bool(np.array_equal(ll_seq.cpu().numpy(), ll_batch))
+    elapsed = t1 - t0
+    res = {
+        "metric": "batched likelihood evals/sec (256 uneven parameter points per launch)",
+        "value": n * args.steps / elapsed,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32 counts / f64 sums / f32 images",
+        "data": "synthetic",
+        "config": {"workload": f"{n} jobs: sides 2^U[6,9] rounded to 16, 5k-52.5k entries, mock-test priors, "
+                               "31x31 PSF (direct), shot noise, 100x100 Hess, Poisson logL",
+                   "graph": use_graph, "tuning": {"wg_per_cu": best[0], "order": best[1]},
+                   "autotune_ms": cand_ms, "draws_per_step": b_units / max(b_n, 1)},
+        "sequential_evals_per_s": n / (s1 - s0),
+        "speedup_vs_sequential": (n * args.steps / elapsed) / (n / (s1 - s0)),
+        "batch_draws_per_s": b_units / (b_ms / 1e3) if b_ms > 0 else None,
+        "identical_to_sequential": identical,
+    }
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
+def run_counters():
+    """One headline simulation (the parameters of step 0) and a 2048x2048x3 FP32 image copy of
+    known size (50,331,648 bytes read and written) that calibrates FETCH_SIZE / WRITE_SIZE."""
+    import torch
+
+    import paper_1904_00011_amd as P
+    import synth_inputs as si
+
+    ctx = P.Context(0)
+    grid = si.headline_grid()
+    model, obs = si.draw_headline_params(1000)
+    ev = P.Evaluator(ctx, grid, obs.nim, obs.psf, dict(x0=0.0, dx=0.05, y0=0.0, dy=0.05, nx=100, ny=100))
+    ev.simulate(model, obs)
+    ctx.sync()
+    dev = torch.device("cuda:0")
+    o2 = si.Obs(nim=2048, seed=1, dmod=25.0, psf=None, noise_model=0)
+    lam = torch.tensor([0.5], dtype=torch.float64, device=dev)
+    flux = torch.ones((3, 1), dtype=torch.float32, device=dev)
+    mags = torch.empty((3, 2048 * 2048), dtype=torch.float32, device=dev)
+    pre = torch.empty_like(mags)
+    ctx.simulate(lam, flux, o2, mags, flux_pre=pre)
+    ctx.sync()
+    ctx.close()
+    print(json.dumps({"counters_run": "done", "copy_bytes_each_way": 3 * 2048 * 2048 * 4}), flush=True)
 
 
 def cpu_baseline(grid, model, obs, hgrid, n_px_sample):
@@ -86,6 +231,12 @@ def main():
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is "
               "described in DESIGN.md but not built", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        run_batch(args)
+        return
+    if args.workload == "counters":
+        run_counters()
+        return
     import torch
 
     import paper_1904_00011_amd as P
@@ -156,7 +307,7 @@ def main():
         "kernel_ms_per_eval": {"sample": s_ms / max(s_n, 1), "conv": c_ms / max(c_n, 1), "hess": h_ms / max(h_n, 1)},
         "roofline": {"bound": "alu", "kernel": "k_sample", "achieved": achieved / 1e12,
                      "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "TOP/s (VALU lane-ops)",
-                     "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": None,
+                     "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": SAMPLE_TRAFFIC_BYTES,
                      "ops_per_draw": OPS_PER_DRAW, "avg_launch_ms": avg_sample_s * 1e3},
         "mean_logL": float(ll.mean()),
     }

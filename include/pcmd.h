@@ -264,18 +264,66 @@ int pcmd_batch_autotune(pcmd_ctx *ctx, int32_t n_jobs, const pcmd_job *jobs, con
                         pcmd_stream stream);
 
 /* ---------------------------------------------------------------------------------------
+ * a8: surrogate network of the log-Hess diagram, used to screen sampler proposals before the
+ * simulator judges them.  A multilayer perceptron with GELU hidden layers whose matrix products
+ * run on BF16 MFMA with FP32 accumulation:
+ *   x_0 = bf16(theta); z_l = x_l W_l^T + b_l; x_{l+1} = bf16(GELU(z_l)); y = z_last.
+ * Training minimises the mean squared error to log-Hess targets with Adam (beta1 0.9, beta2
+ * 0.999, eps 1e-8) on FP32 master weights; BF16 copies of W and W^T feed the products.
+ * ------------------------------------------------------------------------------------- */
+
+#define PCMD_MLP_MAX_LAYERS 8
+
+/* A network.  Parameters are packed per layer: W_l [dims[l+1]][dims[l]] then b_l [dims[l+1]]
+ * (FP32).  w_bf16 / wt_bf16 hold, per layer and packed the same way without biases, W_l and
+ * W_l^T ([dims[l]][dims[l+1]]) in BF16.  All pointers [dev], caller-owned. */
+typedef struct {
+  int32_t n_layers;
+  int32_t dims[PCMD_MLP_MAX_LAYERS + 1];
+  float *master;
+  float *adam_m, *adam_v;
+  uint16_t *w_bf16;
+  uint16_t *wt_bf16;
+} pcmd_mlp;
+
+/* Number of FP32 parameters (weights and biases) and of weights. */
+int64_t pcmd_mlp_param_count(const int32_t *dims, int32_t n_layers);
+int64_t pcmd_mlp_weight_count(const int32_t *dims, int32_t n_layers);
+/* Refresh the BF16 weight copies from the master weights (after initialisation or loading). */
+int pcmd_mlp_refresh(pcmd_ctx *ctx, const pcmd_mlp *net, pcmd_stream stream);
+/* Inference: x [dev][n][dims[0]] FP32 -> y [dev][n][dims[n_layers]] FP32. */
+int pcmd_mlp_forward(pcmd_ctx *ctx, const pcmd_mlp *net, int32_t n, const float *x, float *y, pcmd_stream stream);
+/* One training step on a batch: forward, loss = mean((y - t)^2), backward, and (if apply_update)
+ * one Adam step number `step` (>= 1) with learning rate lr.  loss_out [dev][1] or NULL;
+ * grad_out [dev][param_count] or NULL receives the packed FP32 gradient of the loss. */
+int pcmd_mlp_train_step(pcmd_ctx *ctx, const pcmd_mlp *net, int32_t n, const float *x, const float *t, float lr,
+                        int32_t step, float *loss_out, float *grad_out, int32_t apply_update, pcmd_stream stream);
+/* Surrogate Poisson log-likelihood of a data Hess under predicted log-Hess diagrams:
+ * lam_j = N_d exp(y_j) / sum_k exp(y_k), logL = sum_j d_j ln lam_j - lam_j - ln d_j!.
+ * y [dev][n][nbins] FP32; hess_data [dev][nbins]; out [dev][n] FP64. */
+int pcmd_surrogate_loglike(pcmd_ctx *ctx, const float *y, int32_t n, int32_t nbins, const uint32_t *hess_data,
+                           double *out, pcmd_stream stream);
+/* General BF16 product for callers that build their own layers: C[M][N] = sum_k A(m,k) B(n,k),
+ * A(m,k) = a_trans ? A[k*lda + m] : A[m*lda + k], B(n,k) = b_trans ? B[k*ldb + n] : B[n*ldb + k],
+ * FP32 C with leading dimension ldc.  Supported (a_trans, b_trans): any. */
+int pcmd_gemm_bf16(pcmd_ctx *ctx, int32_t M, int32_t N, int32_t K, const uint16_t *A, int32_t lda, int32_t a_trans,
+                   const uint16_t *B, int32_t ldb, int32_t b_trans, float *C, int32_t ldc, pcmd_stream stream);
+
+/* ---------------------------------------------------------------------------------------
  * Kernel timing for benchmarks: HIP events recorded on the launch stream around each
  * launch of the timed kernels while enabled.
  * ------------------------------------------------------------------------------------- */
 
-enum { PCMD_TIMER_SAMPLE = 0, PCMD_TIMER_CONV = 1, PCMD_TIMER_HESS = 2, PCMD_TIMER_BATCH = 3, PCMD_TIMER_KINDS = 4 };
+enum { PCMD_TIMER_SAMPLE = 0, PCMD_TIMER_CONV = 1, PCMD_TIMER_HESS = 2, PCMD_TIMER_BATCH = 3, PCMD_TIMER_GEMM = 4,
+       PCMD_TIMER_KINDS = 5 };
 
 /* Start (on != 0) or stop recording.  Starting discards earlier records. */
 int pcmd_timer_enable(pcmd_ctx *ctx, int on);
 /* Wait for the recorded launches of kernel `which` and return their summed duration (ms),
  * their number and the algorithmic units they processed (SAMPLE: pixel x entry draws;
  * CONV: image values read and written; HESS: pixels binned; BATCH: a whole pcmd_batch_run,
- * pixel x entry draws of all its jobs).  Consumes those records. */
+ * pixel x entry draws of all its jobs; GEMM: floating-point operations of the surrogate's
+ * matrix products).  Consumes those records. */
 int pcmd_timer_read(pcmd_ctx *ctx, int which, double *total_ms, int64_t *launches, double *units);
 
 #ifdef __cplusplus

@@ -24,7 +24,7 @@ DUST_NONE, DUST_SCREEN, DUST_LOGNORMAL = 0, 1, 2
 CONV_AUTO, CONV_DIRECT, CONV_FFT = 0, 1, 2
 NOISE_NONE, NOISE_GAUSS_MAG, NOISE_SHOT = 0, 1, 2
 LL_POISSON, LL_GAUSS_PAPER, LL_GAUSS_LITERAL = 0, 1, 2
-TIMER_SAMPLE, TIMER_CONV, TIMER_HESS, TIMER_BATCH = 0, 1, 2, 3
+TIMER_SAMPLE, TIMER_CONV, TIMER_HESS, TIMER_BATCH, TIMER_GEMM = 0, 1, 2, 3, 4
 
 D4 = C.c_double * MAX_BANDS
 
@@ -78,6 +78,14 @@ class TuningS(C.Structure):
     _fields_ = [("wg_per_cu", C.c_int32), ("order", C.c_int32)]
 
 
+MLP_MAX_LAYERS = 8
+
+
+class MlpS(C.Structure):
+    _fields_ = [("n_layers", C.c_int32), ("dims", C.c_int32 * (MLP_MAX_LAYERS + 1)), ("master", C.c_void_p),
+                ("adam_m", C.c_void_p), ("adam_v", C.c_void_p), ("w_bf16", C.c_void_p), ("wt_bf16", C.c_void_p)]
+
+
 class HessGridS(C.Structure):
     _fields_ = [("x0", C.c_double), ("dx", C.c_double), ("y0", C.c_double), ("dy", C.c_double),
                 ("nx", C.c_int32), ("ny", C.c_int32), ("b_blue", C.c_int32), ("b_red", C.c_int32),
@@ -113,6 +121,13 @@ def load(path: str = LIB_PATH):
         "pcmd_batch_get_tuning": (C.c_int, [vp, C.POINTER(TuningS)]),
         "pcmd_batch_autotune": (C.c_int, [vp, i32, C.POINTER(JobS), C.POINTER(HessGridS), vp, vp, i32, dbl, vp,
                                           C.POINTER(TuningS), vp, C.POINTER(i32), vp]),
+        "pcmd_mlp_param_count": (C.c_int64, [C.POINTER(i32), i32]),
+        "pcmd_mlp_weight_count": (C.c_int64, [C.POINTER(i32), i32]),
+        "pcmd_mlp_refresh": (C.c_int, [vp, C.POINTER(MlpS), vp]),
+        "pcmd_mlp_forward": (C.c_int, [vp, C.POINTER(MlpS), i32, vp, vp, vp]),
+        "pcmd_mlp_train_step": (C.c_int, [vp, C.POINTER(MlpS), i32, vp, vp, C.c_float, i32, vp, vp, i32, vp]),
+        "pcmd_surrogate_loglike": (C.c_int, [vp, vp, i32, i32, vp, vp, vp]),
+        "pcmd_gemm_bf16": (C.c_int, [vp, i32, i32, i32, vp, i32, i32, vp, i32, i32, vp, i32, vp]),
         "pcmd_timer_enable": (C.c_int, [vp, C.c_int]),
         "pcmd_timer_read": (C.c_int, [vp, C.c_int, C.POINTER(dbl), C.POINTER(i64), C.POINTER(dbl)]),
     }
@@ -327,4 +342,44 @@ class Context:
                                                  int(mode), float(eps), _ptr(logl_out), C.byref(best), ms, C.byref(n),
                                                  _stream(stream)), "pcmd_batch_autotune")
         return (best.wg_per_cu, best.order), [ms[i] for i in range(n.value)]
+
+    # -------------------------------------------------------------------------------------
+    # surrogate network
+    # -------------------------------------------------------------------------------------
+    def mlp_refresh(self, net, stream=None):
+        self._check(self.lib.pcmd_mlp_refresh(self.h, C.byref(net), _stream(stream)), "pcmd_mlp_refresh")
+
+    def mlp_forward(self, net, x, y, stream=None):
+        self._check(self.lib.pcmd_mlp_forward(self.h, C.byref(net), int(x.shape[0]), _ptr(x), _ptr(y), _stream(stream)),
+                    "pcmd_mlp_forward")
+
+    def mlp_train_step(self, net, x, t, lr: float, step: int, loss_out=None, grad_out=None, apply_update=True,
+                       stream=None):
+        self._check(self.lib.pcmd_mlp_train_step(self.h, C.byref(net), int(x.shape[0]), _ptr(x), _ptr(t), float(lr),
+                                                 int(step), _ptr(loss_out), _ptr(grad_out), int(bool(apply_update)),
+                                                 _stream(stream)), "pcmd_mlp_train_step")
+
+    def surrogate_loglike(self, y, hess_data, out, stream=None):
+        n, nb = int(y.shape[0]), int(y.shape[1])
+        self._check(self.lib.pcmd_surrogate_loglike(self.h, _ptr(y), n, nb, _ptr(hess_data), _ptr(out), _stream(stream)),
+                    "pcmd_surrogate_loglike")
+
+    def gemm_bf16(self, A, B, C_out, a_trans=False, b_trans=False, stream=None):
+        """C[M][N] = sum_k A(m,k) B(n,k) with A, B torch bfloat16 tensors (2-D, contiguous)."""
+        M = int(A.shape[1] if a_trans else A.shape[0])
+        K = int(A.shape[0] if a_trans else A.shape[1])
+        N = int(B.shape[1] if b_trans else B.shape[0])
+        self._check(self.lib.pcmd_gemm_bf16(self.h, M, N, K, _ptr(A), int(A.shape[1]), int(bool(a_trans)), _ptr(B),
+                                            int(B.shape[1]), int(bool(b_trans)), _ptr(C_out), int(C_out.shape[1]),
+                                            _stream(stream)), "pcmd_gemm_bf16")
+
+
+def mlp_param_count(dims) -> int:
+    arr = (C.c_int32 * len(dims))(*dims)
+    return int(load().pcmd_mlp_param_count(arr, len(dims) - 1))
+
+
+def mlp_weight_count(dims) -> int:
+    arr = (C.c_int32 * len(dims))(*dims)
+    return int(load().pcmd_mlp_weight_count(arr, len(dims) - 1))
 

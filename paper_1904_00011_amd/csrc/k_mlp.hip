@@ -1,0 +1,270 @@
+// Surrogate network kernels (gfx950): BF16 MFMA matrix products with FP32 accumulation and fused
+// epilogues (bias, GELU, GELU derivative), MSE gradient, bias gradients, Adam with BF16 shadow
+// weights, and the surrogate Poisson log-likelihood.
+#include <math.h>
+
+#include "pcmd_device.h"
+#include "pcmd_mlp.h"
+
+namespace pcmd {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * expf(-0.5f * z * z) * 0.3989422804014327f;
+}
+
+// ---------------------------------------------------------------------------------------
+// C[M][N] = sum_k A(m, k) B(n, k) on v_mfma_f32_32x32x16_bf16.
+// A(m, k) = AT ? A[k lda + m] : A[m lda + k];  B(n, k) = BT ? B[k ldb + n] : B[n ldb + k].
+// 64 x 64 block tile, 4 waves of 32 x 32, K step 32 staged in LDS as [row][k].
+// ---------------------------------------------------------------------------------------
+constexpr int GBM = 64, GBN = 64, GBK = 32, GLDS = GBK + 8;  // row stride padded to 40 halves
+
+template <bool T>
+__device__ __forceinline__ void load_tile(__bf16 *lds, const __bf16 *__restrict__ src, int ld, int rows, int K, int r0,
+                                          int k0) {
+  const int t = threadIdx.x;
+  if (!T) {
+    // rows x K row-major: thread -> (row t/4, 8 consecutive k)
+    const int r = t >> 2, kc = (t & 3) * 8;
+    const int gr = r0 + r, gk = k0 + kc;
+    __bf16 v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = (gr < rows && gk + i < K) ? src[(size_t)gr * ld + gk + i] : (__bf16)0.0f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lds[r * GLDS + kc + i] = v[i];
+  } else {
+    // K x rows row-major: thread -> (k t/8, 8 consecutive rows), transposed into LDS
+    const int kk = t >> 3, rc = (t & 7) * 8;
+    const int gk = k0 + kk, gr = r0 + rc;
+    __bf16 v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = (gk < K && gr + i < rows) ? src[(size_t)gk * ld + gr + i] : (__bf16)0.0f;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) lds[(rc + i) * GLDS + kk] = v[i];
+  }
+}
+
+template <bool AT, bool BT, int EPI>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+  __shared__ __bf16 As[GBM * GLDS];
+  __shared__ __bf16 Bs[GBN * GLDS];
+  const int bm = blockIdx.y * GBM, bn = blockIdx.x * GBN;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f32x16 acc;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+  for (int k0 = 0; k0 < g.K; k0 += GBK) {
+    load_tile<AT>(As, g.A, g.lda, g.M, g.K, bm, k0);
+    load_tile<BT>(Bs, g.B, g.ldb, g.N, g.K, bn, k0);
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < GBK; ks += 16) {
+      const int r = lane & 31, kh = (lane >> 5) * 8;
+      bf16x8 a, b;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        a[i] = As[(wm + r) * GLDS + ks + kh + i];
+        b[i] = Bs[(wn + r) * GLDS + ks + kh + i];
+      }
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // accumulator element e: row 8 (e / 4) + 4 (lane / 32) + e % 4, column lane % 32
+  const int col = bn + wn + (lane & 31);
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    const int row = bm + wm + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+    if (row >= g.M || col >= g.N) continue;
+    float v = acc[e];
+    if (EPI == EPI_STORE) {
+      g.C[(size_t)row * g.ldc + col] = v;
+    } else if (EPI == EPI_BIAS) {
+      g.C[(size_t)row * g.ldc + col] = v + g.bias[col];
+    } else if (EPI == EPI_BIAS_GELU) {
+      v += g.bias[col];
+      g.C[(size_t)row * g.ldc + col] = v;
+      g.Cb[(size_t)row * g.ldcb + col] = (__bf16)gelu_f(v);
+    } else {  // EPI_GELU_GRAD: dz_prev = bf16(dx * GELU'(z_prev))
+      g.Cb[(size_t)row * g.ldcb + col] = (__bf16)(v * gelu_grad_f(g.Z[(size_t)row * g.ldz + col]));
+    }
+  }
+}
+
+hipError_t launch_gemm(const GemmArgs &g, bool at, bool bt, int epi, hipStream_t s) {
+  dim3 grid((g.N + GBN - 1) / GBN, (g.M + GBM - 1) / GBM);
+#define PCMD_GEMM_CASE(A_, B_, E_)                                                \
+  if (at == A_ && bt == B_ && epi == E_) {                                        \
+    hipLaunchKernelGGL((k_gemm<A_, B_, E_>), grid, dim3(256), 0, s, g);           \
+    return hipGetLastError();                                                     \
+  }
+  PCMD_GEMM_CASE(false, false, EPI_STORE)
+  PCMD_GEMM_CASE(false, false, EPI_BIAS)
+  PCMD_GEMM_CASE(false, false, EPI_BIAS_GELU)
+  PCMD_GEMM_CASE(false, false, EPI_GELU_GRAD)
+  PCMD_GEMM_CASE(true, true, EPI_STORE)
+  PCMD_GEMM_CASE(true, false, EPI_STORE)
+  PCMD_GEMM_CASE(false, true, EPI_STORE)
+#undef PCMD_GEMM_CASE
+  return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------------------
+// Elementwise and reduction kernels.
+// ---------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_f32_to_bf16(const float *__restrict__ x, __bf16 *__restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = (__bf16)x[i];
+}
+
+hipError_t launch_f32_to_bf16(const float *x, void *y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_f32_to_bf16, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, (__bf16 *)y, n);
+  return hipGetLastError();
+}
+
+// dy = 2 (y - t) / (n M) stored in BF16; per-block partial sums of (y - t)^2 in FP64.
+__global__ void __launch_bounds__(256) k_mse_grad(const float *__restrict__ y, const float *__restrict__ t, int64_t n,
+                                                  double scale, __bf16 *__restrict__ dy, double *__restrict__ part) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float d = y[i] - t[i];
+    dy[i] = (__bf16)((float)(2.0 * scale) * d);
+    s += (double)d * (double)d;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_loss_final(const double *__restrict__ part, int nb, double scale, float *__restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int k = 0; k < nb; ++k) s += part[k];
+    out[0] = (float)(s * scale);
+  }
+}
+
+constexpr int MSE_BLOCKS = 256;
+
+hipError_t launch_mse_grad(const float *y, const float *t, int64_t n, double scale, void *dy, double *part,
+                           float *loss_out, hipStream_t s) {
+  hipLaunchKernelGGL(k_mse_grad, dim3(MSE_BLOCKS), dim3(256), 0, s, y, t, n, scale, (__bf16 *)dy, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !loss_out) return e;
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, part, MSE_BLOCKS, scale, loss_out);
+  return hipGetLastError();
+}
+
+// db[m] = sum_n dz[n][m] (FP32, fixed order over n)
+__global__ void __launch_bounds__(256) k_colsum(const __bf16 *__restrict__ dz, int n, int m, float *__restrict__ db) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= m) return;
+  float s = 0.0f;
+  for (int r = 0; r < n; ++r) s += (float)dz[(size_t)r * m + c];
+  db[c] = s;
+}
+
+hipError_t launch_colsum(const void *dz, int n, int m, float *db, hipStream_t s) {
+  hipLaunchKernelGGL(k_colsum, dim3((m + 255) / 256), dim3(256), 0, s, (const __bf16 *)dz, n, m, db);
+  return hipGetLastError();
+}
+
+// Adam on one layer's FP32 master weights [out][in] and biases, refreshing the BF16 copies
+// W [out][in] and W^T [in][out].  With update == 0 only the BF16 copies are refreshed.
+__global__ void __launch_bounds__(256) k_adam_layer(AdamArgs a) {
+  const int64_t nw = (int64_t)a.n_out * a.n_in;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nw + a.n_out) return;
+  float w = a.master[i];
+  if (a.update) {
+    const float g = a.grad[i];
+    const float m = a.beta1 * a.m[i] + (1.0f - a.beta1) * g;
+    const float v = a.beta2 * a.v[i] + (1.0f - a.beta2) * g * g;
+    a.m[i] = m;
+    a.v[i] = v;
+    const float mh = m / a.bc1, vh = v / a.bc2;
+    w = w - a.lr * mh / (sqrtf(vh) + a.eps);
+    a.master[i] = w;
+  }
+  if (i < nw) {
+    const int o = (int)(i / a.n_in), k = (int)(i - (int64_t)o * a.n_in);
+    const __bf16 wb = (__bf16)w;
+    ((__bf16 *)a.w_bf16)[i] = wb;
+    ((__bf16 *)a.wt_bf16)[(size_t)k * a.n_out + o] = wb;
+  }
+}
+
+hipError_t launch_adam_layer(const AdamArgs &a, hipStream_t s) {
+  const int64_t n = (int64_t)a.n_out * a.n_in + a.n_out;
+  hipLaunchKernelGGL(k_adam_layer, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// Surrogate log-likelihood: one block per sample, lam_j = N_d exp(y_j - max) / sum exp(y - max).
+__global__ void __launch_bounds__(256) k_surrogate_loglike(const float *__restrict__ y, int nbins,
+                                                           const uint32_t *__restrict__ d, double *__restrict__ out) {
+  __shared__ double red[256];
+  const float *ys = y + (size_t)blockIdx.x * nbins;
+  const int t = threadIdx.x;
+  double mx = -INFINITY, nd = 0.0;
+  for (int j = t; j < nbins; j += 256) {
+    mx = fmax(mx, (double)ys[j]);
+    nd += (double)d[j];
+  }
+  red[t] = mx;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (t < k) red[t] = fmax(red[t], red[t + k]);
+    __syncthreads();
+  }
+  mx = red[0];
+  __syncthreads();
+  double se = 0.0;
+  for (int j = t; j < nbins; j += 256) se += exp((double)ys[j] - mx);
+  red[t] = se;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (t < k) red[t] += red[t + k];
+    __syncthreads();
+  }
+  se = red[0];
+  __syncthreads();
+  red[t] = nd;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (t < k) red[t] += red[t + k];
+    __syncthreads();
+  }
+  nd = red[0];
+  __syncthreads();
+  double acc = 0.0;
+  for (int j = t; j < nbins; j += 256) {
+    const double lam = nd * exp((double)ys[j] - mx) / se;
+    const double dj = (double)d[j];
+    acc += dj * log(lam) - lam - lgamma(dj + 1.0);
+  }
+  red[t] = acc;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (t < k) red[t] += red[t + k];
+    __syncthreads();
+  }
+  if (t == 0) out[blockIdx.x] = red[0];
+}
+
+hipError_t launch_surrogate_loglike(const float *y, int n, int nbins, const uint32_t *d, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_surrogate_loglike, dim3(n), dim3(256), 0, s, y, nbins, d, out);
+  return hipGetLastError();
+}
+
+}  // namespace pcmd

@@ -282,3 +282,59 @@ def batch_workload(n_jobs: int = 256, seed0: int = 0, nim_log2=(6.0, 9.0), entri
             obs.psf = psf_stack(psf_k, (1.6, 1.8, 2.0))
         out.append((cache[stride], model, obs))
     return out
+
+
+def mlp_init(dims, seed: int = 0) -> np.ndarray:
+    """Initial surrogate weights (packed per layer: W [out][in] then b [out]): uniform He-style
+    weights, zero biases, FP32."""
+    r = np.random.default_rng(seed)
+    parts = []
+    for l in range(len(dims) - 1):
+        lim = math.sqrt(6.0 / dims[l])
+        parts.append(r.uniform(-lim, lim, dims[l + 1] * dims[l]))
+        parts.append(np.zeros(dims[l + 1]))
+    return np.concatenate(parts).astype(np.float32)
+
+
+SURROGATE_PARAM_NAMES = ("logSFH0", "logSFH1", "logSFH2", "logSFH3", "logSFH4", "logSFH5", "logSFH6",
+                         "feh_mu", "feh_sigma", "dust_mu", "dust_sigma", "dmod")
+
+
+def surrogate_theta_draws(n: int, seed: int = 0, nim: int = 128):
+    """n parameter vectors of the 12-parameter model (non-parametric 7-bin SFH, Gaussian MDF with
+    free width, log-normal dust with free width, distance modulus): a tau-model SFH with
+    log Npix ~ U[2, 5] and tau ~ U[0.1, 8] Gyr, each bin then perturbed by U[-1, 1] dex (the mock
+    tests' +-1 dex prior), mu_[Fe/H] ~ U[-0.5, 0.25], sigma_[Fe/H] ~ U[0.1, 0.4],
+    mu_dust ~ U[-1, 0], sigma_dust ~ U[0.1, 0.4], mu_d ~ U[24, 30].
+    Returns theta [n][12] (float64) and the matching (Model, Obs) pairs."""
+    r = np.random.default_rng(np.random.SeedSequence([777, seed]))
+    grid = headline_grid()
+    edges = grid.age_edges
+    T = 10.0 ** 10.2
+    thetas, pairs = [], []
+    for k in range(n):
+        lnp = r.uniform(2.0, 5.0)
+        tau = r.uniform(0.1, 8.0) * 1e9
+        t1 = T - 10.0 ** edges[1:]
+        t2 = T - 10.0 ** edges[:-1]
+        w = np.exp(-t1 / tau) - np.exp(-t2 / tau)
+        w = np.maximum(w / w.sum(), 1e-12) * 10.0 ** lnp
+        log_sfh = np.log10(w) + r.uniform(-1.0, 1.0, 7)
+        log_sfh = np.maximum(log_sfh, -3.0)
+        th = np.concatenate([log_sfh, [r.uniform(-0.5, 0.25), r.uniform(0.1, 0.4), r.uniform(-1.0, 0.0),
+                                       r.uniform(0.1, 0.4), r.uniform(24.0, 30.0)]])
+        thetas.append(th)
+        pairs.append(theta_to_model(th, seed=100000 * (seed + 1) + k, nim=nim))
+    return np.array(thetas), pairs
+
+
+def theta_to_model(th, seed: int, nim: int = 128):
+    """(Model, Obs) of one 12-parameter vector on the headline grid and observation set-up."""
+    th = np.asarray(th, dtype=np.float64)
+    model = Model(sfh="nonparam", log_sfh=tuple(th[:7]), mdf="gauss", feh_mu=float(th[7]),
+                  feh_sigma=float(th[8]), mdf_prune=0.01)
+    obs = Obs(nim=nim, seed=seed, dmod=float(th[11]), dust_model=2, dust_mu=float(th[9]),
+              dust_sigma=float(th[10]), dust_frac=0.5, dust_R=(3.6, 1.9, 1.3),
+              psf=psf_stack(31, (1.6, 1.8, 2.0)), noise_model=2, exptime=(3620.0, 3235.0, 3000.0),
+              zp=(26.0, 25.5, 25.0), sky=(0.0, 0.0, 0.0))
+    return model, obs

@@ -1,0 +1,144 @@
+"""Surrogate network on BF16 MFMA against the oracle network (FP64 with the same BF16 roundings)."""
+import numpy as np
+import pytest
+
+import synth_inputs as si
+from oracle import mlp as om
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1904_00011_amd as P
+    c = P.Context(0)
+    yield c
+    c.close()
+
+
+def _bf16_tensor(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(torch.device("cuda")).to(torch.bfloat16)
+
+
+@pytest.mark.parametrize("M,N,K", [(70, 45, 37), (128, 64, 512), (1, 1, 1), (200, 130, 12)])
+@pytest.mark.parametrize("at,bt", [(False, False), (True, True), (True, False), (False, True)])
+def test_gemm_layouts_against_fp64(ctx, M, N, K, at, bt):
+    import torch
+    r = np.random.default_rng(M * 7 + N + K)
+    A = om.bf16_round(r.normal(size=(M, K)).astype(np.float32)).astype(np.float64)
+    B = om.bf16_round(r.normal(size=(N, K)).astype(np.float32)).astype(np.float64)
+    Ad = _bf16_tensor(A.T.copy() if at else A)
+    Bd = _bf16_tensor(B.T.copy() if bt else B)
+    Cd = torch.full((M, N), float("nan"), dtype=torch.float32, device=torch.device("cuda"))
+    print(f"[case] gemm M={M} N={N} K={K} at={at} bt={bt}", flush=True)
+    ctx.gemm_bf16(Ad, Bd, Cd, a_trans=at, b_trans=bt)
+    ctx.sync()
+    ref = A @ B.T
+    got = Cd.cpu().numpy().astype(np.float64)
+    scale = np.sqrt(K) * 1.0
+    assert np.max(np.abs(got - ref)) <= 1e-5 * scale + 1e-6
+
+
+def _net(ctx, dims, seed):
+    from paper_1904_00011_amd.surrogate import SurrogateNet
+    master = si.mlp_init(dims, seed)
+    return SurrogateNet(ctx, dims, master), master.astype(np.float64)
+
+
+def test_forward_against_oracle(ctx):
+    import torch
+    dims = (12, 64, 96, 100)
+    net, master = _net(ctx, dims, 3)
+    r = np.random.default_rng(4)
+    x = r.uniform(-1, 1, (37, 12)).astype(np.float32)
+    y = net.forward(torch.from_numpy(x).cuda())
+    ctx.sync()
+    yo, _ = om.forward(master.astype(np.float32).astype(np.float64), dims, x)
+    got = y.cpu().numpy()
+    assert np.max(np.abs(got - yo)) <= 2e-3 * np.max(np.abs(yo))
+
+
+def test_gradients_against_oracle(ctx):
+    import torch
+    dims = (12, 64, 96, 100)
+    net, master = _net(ctx, dims, 5)
+    r = np.random.default_rng(6)
+    x = r.uniform(-1, 1, (53, 12)).astype(np.float32)
+    t = r.normal(0, 1, (53, 100)).astype(np.float32)
+    dev = torch.device("cuda")
+    grad = torch.empty(net.n_params, dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    net.train_step(torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev), 0.0, loss_out=loss, grad_out=grad,
+                   apply_update=False)
+    ctx.sync()
+    lo, go = om.loss_and_grad(master.astype(np.float32).astype(np.float64), dims, x, t)
+    assert float(loss.item()) == pytest.approx(lo, rel=1e-4)
+    g = grad.cpu().numpy().astype(np.float64)
+    o = 0
+    for l in range(len(dims) - 1):
+        n = dims[l + 1] * dims[l] + dims[l + 1]
+        gl, ol_ = g[o:o + n], go[o:o + n]
+        print(f"[case] grad layer {l} max|g|={np.max(np.abs(ol_)):.3e} maxdiff={np.max(np.abs(gl - ol_)):.3e}", flush=True)
+        assert np.max(np.abs(gl - ol_)) <= 1e-2 * np.max(np.abs(ol_))
+        assert np.corrcoef(gl, ol_)[0, 1] > 0.9999
+        o += n
+
+
+def test_adam_step_against_oracle(ctx):
+    import torch
+    dims = (12, 32, 40)
+    net, master = _net(ctx, dims, 7)
+    r = np.random.default_rng(8)
+    x = r.uniform(-1, 1, (16, 12)).astype(np.float32)
+    t = r.normal(0, 1, (16, 40)).astype(np.float32)
+    dev = torch.device("cuda")
+    lr = 1e-3
+    net.train_step(torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev), lr)
+    ctx.sync()
+    m32 = master.astype(np.float32).astype(np.float64)
+    _, go = om.loss_and_grad(m32, dims, x, t)
+    new, _, _ = om.adam_update(m32, go, np.zeros_like(go), np.zeros_like(go), 1, lr)
+    got = net.master.cpu().numpy().astype(np.float64)
+    big = np.abs(go) > 1e-5          # the first Adam step is lr * sign(g) wherever |g| >> eps
+    assert np.max(np.abs(got - new)[big]) <= 1e-3 * lr + 1e-7
+    assert np.max(np.abs(got - m32)) <= lr * (1 + 1e-3)
+    # BF16 shadows follow the master weights
+    w = net.w.float().cpu().numpy()
+    assert np.array_equal(w[:32 * 12], om.bf16_round(got[:32 * 12].astype(np.float32)))
+
+
+def test_training_reduces_loss(ctx):
+    import torch
+    dims = (12, 128, 128, 64)
+    net, _ = _net(ctx, dims, 9)
+    r = np.random.default_rng(10)
+    P = r.normal(size=(12, 64))
+    x = r.uniform(-1, 1, (512, 12)).astype(np.float32)
+    t = np.sin(x @ P).astype(np.float32)
+    dev = torch.device("cuda")
+    xd, td = torch.from_numpy(x).to(dev), torch.from_numpy(t).to(dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    first = None
+    for k in range(400):
+        net.train_step(xd, td, 3e-3, loss_out=loss)
+        if k == 0:
+            ctx.sync()
+            first = float(loss.item())
+    ctx.sync()
+    last = float(loss.item())
+    print(f"[case] training loss {first:.4f} -> {last:.4f}", flush=True)
+    assert last < 0.1 * first
+
+
+def test_surrogate_loglike_against_oracle(ctx):
+    import torch
+    r = np.random.default_rng(11)
+    y = r.normal(-9, 1, (5, 10000)).astype(np.float32)
+    d = r.poisson(2.0, 10000)
+    dev = torch.device("cuda")
+    out = torch.empty(5, dtype=torch.float64, device=dev)
+    ctx.surrogate_loglike(torch.from_numpy(y).to(dev), torch.from_numpy(d.astype(np.int32)).to(dev), out)
+    ctx.sync()
+    for k in range(5):
+        assert out[k].item() == pytest.approx(om.surrogate_loglike(y[k], d), rel=1e-9)
