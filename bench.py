@@ -46,11 +46,14 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=256, help="pixels in the oracle's timed sampler window")
     ap.add_argument("--conv", type=int, default=0, help="0 auto, 1 direct, 2 fft")
-    ap.add_argument("--workload", default="headline", choices=["headline", "batch", "counters"],
+    ap.add_argument("--workload", default="headline", choices=["headline", "batch", "counters", "surrogate"],
                     help="headline: 256x256 single evaluations; batch: 256 uneven jobs per step; counters: one "
                          "headline simulation plus a copy of known size, for hardware-counter runs")
     ap.add_argument("--jobs", type=int, default=256)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--train-pairs", type=int, default=16384)
+    ap.add_argument("--train-steps", type=int, default=1500)
+    ap.add_argument("--mcmc-steps", type=int, default=300)
     return ap.parse_args()
 
 
@@ -164,6 +167,118 @@ def run_batch(args):
     print(json.dumps(res), flush=True)
 
 
+def run_surrogate(args):
+    """The log-Hess surrogate: simulator-generated training pairs (batched launches), BF16 MFMA
+    training, its likelihood error against the simulator, and delayed-acceptance MCMC with the
+    surrogate as a screen against plain Metropolis-Hastings (both on the likelihood tempered to
+    its own stochastic scatter)."""
+    import torch
+    from scipy import stats
+
+    import paper_1904_00011_amd as P
+    import synth_inputs as si
+    from paper_1904_00011_amd.surrogate_pipeline import SurrogateWorkflow
+
+    dims = (12, 512, 512, 512, 512, 10000)
+    ctx = P.Context(0)
+    dev = torch.device("cuda:0")
+    G = si.headline_grid()
+    th_true, box = si.surrogate_truth(), si.surrogate_box()
+    model, obs = si.theta_to_model(th_true, seed=2, nim=256)
+    ev = P.Evaluator(ctx, G, 256, obs.psf, dict(x0=0, dx=0.05, y0=0, dy=0.05, nx=100, ny=100))
+    md = ev.simulate(model, obs).cpu().numpy().astype(np.float64)
+    fin = np.isfinite(md).all(axis=0)
+    hg = si.hess_grid_from_median(float(np.median((md[0] - md[1])[fin])), float(np.median(md[1][fin])), 100, 100)
+    ev.hess_grid = hg
+    dh = torch.empty(10000, dtype=torch.int32, device=dev)
+    dm = torch.empty(3, dtype=torch.float64, device=dev)
+    ev.hess_of(ev.mags, dh, dm)
+    ctx.sync()
+    wf = SurrogateWorkflow(ctx, G, si.theta_to_model, hg, dh, dm, box, train_nim=128, dims=dims,
+                           init_master=si.mlp_init(dims, 0))
+    th = si.surrogate_theta_draws(args.train_pairs, seed=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    H = wf.simulate_hess(th, seed0=10 ** 6)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    X, T = wf.inputs(th), wf.targets(H)
+    thv = si.surrogate_theta_draws(512, seed=2)
+    Xv, Tv = wf.inputs(thv), wf.targets(wf.simulate_hess(thv, seed0=2 * 10 ** 6))
+    mse0 = wf.mse(Xv, Tv)
+    ctx.timer_enable(True)
+    t0 = time.perf_counter()
+    wf.fit(X, T, args.train_steps, batch=1024)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    g_ms, g_n, g_flops = ctx.timer_read(P._lib.TIMER_GEMM)
+    ctx.timer_enable(False)
+    mse1 = wf.mse(Xv, Tv)
+    # likelihood error on held-out points and the simulator's own seed-to-seed scatter
+    ths = si.surrogate_theta_draws(128, seed=3)
+    L1 = np.array([wf.simulator_loglike(t, 5000 + k) for k, t in enumerate(ths)])
+    L2 = np.array([wf.simulator_loglike(t, 9000 + k) for k, t in enumerate(ths)])
+    S = wf.surrogate_loglike_batch(ths)
+    # throughput: surrogate likelihoods (4096 points per call) vs one simulator likelihood at a time
+    xs = si.surrogate_theta_draws(4096, seed=4)
+    wf.surrogate_loglike_batch(xs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        wf.surrogate_loglike_batch(xs)
+    torch.cuda.synchronize()
+    sur_rate = 5 * 4096 / (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    for k in range(20):
+        wf.simulator_loglike(ths[k], 7000 + k)
+    sim_rate = 20 / (time.perf_counter() - t0)
+    # the dominant product of training and inference alone: 8192 x 10000 x 512
+    A = torch.randn((8192, 512), device=dev).to(torch.bfloat16)
+    Bw = torch.randn((10000, 512), device=dev).to(torch.bfloat16)
+    Cm = torch.empty((8192, 10000), dtype=torch.float32, device=dev)
+    ctx.gemm_bf16(A, Bw, Cm)
+    ctx.timer_enable(True)
+    for _ in range(10):
+        ctx.gemm_bf16(A, Bw, Cm)
+    torch.cuda.synchronize()
+    b_ms, b_n, b_flops = ctx.timer_read(P._lib.TIMER_GEMM)
+    ctx.timer_enable(False)
+    scale = 0.1 * (box[1] - box[0])
+    mc = {}
+    for screen in (False, True):
+        _, _, info = wf.run_mcmc(th_true, args.mcmc_steps, scale, np.random.default_rng(1), screen=screen,
+                                 temperature=3000.0)
+        mc["screened" if screen else "plain"] = info
+    res = {
+        "metric": "surrogate-screened MCMC steps/sec (256^2 simulator judge, 12-parameter model)",
+        "value": args.mcmc_steps / mc["screened"]["seconds"],
+        "unit": "MCMC steps/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "bf16 MFMA, fp32 accumulate",
+        "data": "synthetic",
+        "config": {"workload": f"MLP {dims}, {args.train_pairs} simulator pairs at 128x128, {args.train_steps} Adam "
+                               "steps of 256, data Hess 256x256 at the fiducial parameters",
+                   "temperature": 3000.0, "step": "10% of the prior box"},
+        "plain_mcmc_steps_per_s": args.mcmc_steps / mc["plain"]["seconds"],
+        "mcmc": mc,
+        "train_pairs_per_s": args.train_pairs / t_gen,
+        "train_seconds": t_fit,
+        "gemm_tflops": g_flops / (g_ms / 1e3) / 1e12 if g_ms > 0 else None,
+        "gemm_frac_of_bf16_peak": (g_flops / (g_ms / 1e3)) / 2.5e15 if g_ms > 0 else None,
+        "roofline": {"bound": "mfma", "kernel": "k_gemm 8192x10000x512 bf16", "achieved": b_flops / (b_ms / 1e3) / 1e12,
+                     "peak": 2500.0, "unit": "TFLOP/s", "frac": b_flops / (b_ms / 1e3) / 2.5e15, "traffic": None},
+        "val_mse": [mse0, mse1],
+        "spearman_surrogate_simulator": float(stats.spearmanr(S, L1)[0]),
+        "median_abs_logL_error": float(np.median(np.abs(S - L1))),
+        "median_abs_simulator_seed_scatter": float(np.median(np.abs(L1 - L2))),
+        "surrogate_loglikes_per_s": sur_rate,
+        "simulator_loglikes_per_s": sim_rate,
+    }
+    ctx.close()
+    print(json.dumps(res), flush=True)
+
+
 def run_counters():
     """One headline simulation (the parameters of step 0) and a 2048x2048x3 FP32 image copy of
     known size (50,331,648 bytes read and written) that calibrates FETCH_SIZE / WRITE_SIZE."""
@@ -236,6 +351,9 @@ def main():
         return
     if args.workload == "counters":
         run_counters()
+        return
+    if args.workload == "surrogate":
+        run_surrogate(args)
         return
     import torch
 

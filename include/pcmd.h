@@ -322,8 +322,8 @@ int pcmd_timer_enable(pcmd_ctx *ctx, int on);
 /* Wait for the recorded launches of kernel `which` and return their summed duration (ms),
  * their number and the algorithmic units they processed (SAMPLE: pixel x entry draws;
  * CONV: image values read and written; HESS: pixels binned; BATCH: a whole pcmd_batch_run,
- * pixel x entry draws of all its jobs; GEMM: floating-point operations of the surrogate's
- * matrix products).  Consumes those records. */
+ * pixel x entry draws of all its jobs; GEMM: each BF16 matrix product of the surrogate,
+ * 2 M N K floating-point operations).  Consumes those records. */
 int pcmd_timer_read(pcmd_ctx *ctx, int which, double *total_ms, int64_t *launches, double *units);
 
 #ifdef __cplusplus

@@ -19,81 +19,104 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 // ---------------------------------------------------------------------------------------
 // C[M][N] = sum_k A(m, k) B(n, k) on v_mfma_f32_32x32x16_bf16.
 // A(m, k) = AT ? A[k lda + m] : A[m lda + k];  B(n, k) = BT ? B[k ldb + n] : B[n ldb + k].
-// 64 x 64 block tile, 4 waves of 32 x 32, K step 32 staged in LDS as [row][k].
+// 128 x 128 block tile, 4 waves of 64 x 64 (2 x 2 MFMA tiles of 32 x 32), K step 32 staged in
+// LDS as [row][k] (row stride 40 halves = 80 bytes, so every 8-element run is 16-byte aligned).
 // ---------------------------------------------------------------------------------------
-constexpr int GBM = 64, GBN = 64, GBK = 32, GLDS = GBK + 8;  // row stride padded to 40 halves
+constexpr int GBM = 128, GBN = 128, GBK = 32, GLDS = GBK + 8;
 
 template <bool T>
 __device__ __forceinline__ void load_tile(__bf16 *lds, const __bf16 *__restrict__ src, int ld, int rows, int K, int r0,
-                                          int k0) {
-  const int t = threadIdx.x;
-  if (!T) {
-    // rows x K row-major: thread -> (row t/4, 8 consecutive k)
-    const int r = t >> 2, kc = (t & 3) * 8;
-    const int gr = r0 + r, gk = k0 + kc;
-    __bf16 v[8];
+                                          int k0, bool vec_ok) {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = (gr < rows && gk + i < K) ? src[(size_t)gr * ld + gk + i] : (__bf16)0.0f;
+  for (int it = 0; it < 2; ++it) {
+    const int idx = threadIdx.x + 256 * it;
+    if (!T) {
+      // rows x K row-major: (row idx/4, 8 consecutive k)
+      const int r = idx >> 2, kc = (idx & 3) * 8;
+      const int gr = r0 + r, gk = k0 + kc;
+      __bf16 *dst = lds + r * GLDS + kc;
+      if (vec_ok && gr < rows && gk + 8 <= K) {
+        *reinterpret_cast<bf16x8 *>(dst) = *reinterpret_cast<const bf16x8 *>(src + (size_t)gr * ld + gk);
+      } else {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) lds[r * GLDS + kc + i] = v[i];
-  } else {
-    // K x rows row-major: thread -> (k t/8, 8 consecutive rows), transposed into LDS
-    const int kk = t >> 3, rc = (t & 7) * 8;
-    const int gk = k0 + kk, gr = r0 + rc;
-    __bf16 v[8];
+        for (int i = 0; i < 8; ++i) dst[i] = (gr < rows && gk + i < K) ? src[(size_t)gr * ld + gk + i] : (__bf16)0.0f;
+      }
+    } else {
+      // K x rows row-major: (k idx/16, 8 consecutive rows), transposed into LDS
+      const int kk = idx >> 4, rc = (idx & 15) * 8;
+      const int gk = k0 + kk, gr = r0 + rc;
+      bf16x8 v;
+      if (vec_ok && gk < K && gr + 8 <= rows) {
+        v = *reinterpret_cast<const bf16x8 *>(src + (size_t)gk * ld + gr);
+      } else {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = (gk < K && gr + i < rows) ? src[(size_t)gk * ld + gr + i] : (__bf16)0.0f;
+        for (int i = 0; i < 8; ++i) v[i] = (gk < K && gr + i < rows) ? src[(size_t)gk * ld + gr + i] : (__bf16)0.0f;
+      }
 #pragma unroll
-    for (int i = 0; i < 8; ++i) lds[(rc + i) * GLDS + kk] = v[i];
+      for (int i = 0; i < 8; ++i) lds[(rc + i) * GLDS + kk] = v[i];
+    }
   }
 }
 
 template <bool AT, bool BT, int EPI>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
-  __shared__ __bf16 As[GBM * GLDS];
-  __shared__ __bf16 Bs[GBN * GLDS];
+  __shared__ __attribute__((aligned(16))) __bf16 As[GBM * GLDS];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[GBN * GLDS];
   const int bm = blockIdx.y * GBM, bn = blockIdx.x * GBN;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  f32x16 acc;
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const bool va = (g.lda % 8 == 0) && (((uintptr_t)g.A & 15) == 0);
+  const bool vb = (g.ldb % 8 == 0) && (((uintptr_t)g.B & 15) == 0);
+  f32x16 acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[mi][ni][i] = 0.0f;
+  const int r = lane & 31, kh = (lane >> 5) * 8;
   for (int k0 = 0; k0 < g.K; k0 += GBK) {
-    load_tile<AT>(As, g.A, g.lda, g.M, g.K, bm, k0);
-    load_tile<BT>(Bs, g.B, g.ldb, g.N, g.K, bn, k0);
+    load_tile<AT>(As, g.A, g.lda, g.M, g.K, bm, k0, va);
+    load_tile<BT>(Bs, g.B, g.ldb, g.N, g.K, bn, k0, vb);
     __syncthreads();
 #pragma unroll
     for (int ks = 0; ks < GBK; ks += 16) {
-      const int r = lane & 31, kh = (lane >> 5) * 8;
-      bf16x8 a, b;
+      bf16x8 a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        a[i] = As[(wm + r) * GLDS + ks + kh + i];
-        b[i] = Bs[(wn + r) * GLDS + ks + kh + i];
-      }
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+      for (int mi = 0; mi < 2; ++mi) a[mi] = *reinterpret_cast<const bf16x8 *>(&As[(wm + mi * 32 + r) * GLDS + ks + kh]);
+#pragma unroll
+      for (int ni = 0; ni < 2; ++ni) b[ni] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn + ni * 32 + r) * GLDS + ks + kh]);
+#pragma unroll
+      for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
     }
     __syncthreads();
   }
-  // accumulator element e: row 8 (e / 4) + 4 (lane / 32) + e % 4, column lane % 32
-  const int col = bn + wn + (lane & 31);
+  // accumulator element e of a 32 x 32 tile: row 8 (e / 4) + 4 (lane / 32) + e % 4, column lane % 32
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
-    const int row = bm + wm + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-    if (row >= g.M || col >= g.N) continue;
-    float v = acc[e];
-    if (EPI == EPI_STORE) {
-      g.C[(size_t)row * g.ldc + col] = v;
-    } else if (EPI == EPI_BIAS) {
-      g.C[(size_t)row * g.ldc + col] = v + g.bias[col];
-    } else if (EPI == EPI_BIAS_GELU) {
-      v += g.bias[col];
-      g.C[(size_t)row * g.ldc + col] = v;
-      g.Cb[(size_t)row * g.ldcb + col] = (__bf16)gelu_f(v);
-    } else {  // EPI_GELU_GRAD: dz_prev = bf16(dx * GELU'(z_prev))
-      g.Cb[(size_t)row * g.ldcb + col] = (__bf16)(v * gelu_grad_f(g.Z[(size_t)row * g.ldz + col]));
+  for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+    for (int ni = 0; ni < 2; ++ni) {
+      const int col = bn + wn + ni * 32 + (lane & 31);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = bm + wm + mi * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        if (row >= g.M || col >= g.N) continue;
+        float v = acc[mi][ni][e];
+        if (EPI == EPI_STORE) {
+          g.C[(size_t)row * g.ldc + col] = v;
+        } else if (EPI == EPI_BIAS) {
+          g.C[(size_t)row * g.ldc + col] = v + g.bias[col];
+        } else if (EPI == EPI_BIAS_GELU) {
+          v += g.bias[col];
+          g.C[(size_t)row * g.ldc + col] = v;
+          g.Cb[(size_t)row * g.ldcb + col] = (__bf16)gelu_f(v);
+        } else {  // EPI_GELU_GRAD: dz_prev = bf16(dx * GELU'(z_prev))
+          g.Cb[(size_t)row * g.ldcb + col] = (__bf16)(v * gelu_grad_f(g.Z[(size_t)row * g.ldz + col]));
+        }
+      }
     }
-  }
 }
 
 hipError_t launch_gemm(const GemmArgs &g, bool at, bool bt, int epi, hipStream_t s) {

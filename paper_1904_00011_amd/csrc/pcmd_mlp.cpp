@@ -75,7 +75,10 @@ hipError_t forward_impl(pcmd_ctx *c, const pcmd_mlp *net, const Layout &lay, int
       g.Cb = act + aoff + (int64_t)n * din;
       g.ldcb = dout;
     }
-    e = launch_gemm(g, false, false, last ? EPI_BIAS : EPI_BIAS_GELU, s);
+    {
+      ScopedTimer tm(c, PCMD_TIMER_GEMM, 2.0 * (double)n * (double)din * (double)dout, s);
+      e = launch_gemm(g, false, false, last ? EPI_BIAS : EPI_BIAS_GELU, s);
+    }
     aoff += (int64_t)n * din;
     poff += (int64_t)n * dout;
   }
@@ -141,11 +144,7 @@ int pcmd_mlp_forward(pcmd_ctx *c, const pcmd_mlp *net, int32_t n, const float *x
   if (n < 1 || !x || !y) return fail(c, PCMD_E_INVAL, "pcmd_mlp_forward: bad batch or null pointer");
   DeviceGuard dg(c->device);
   if ((r = ensure_mlp_scratch(c, lay, n))) return r;
-  hipError_t e;
-  {
-    ScopedTimer tm(c, PCMD_TIMER_GEMM, (double)n * (double)lay.flops_per_sample, (hipStream_t)stream);
-    e = forward_impl(c, net, lay, n, x, y, (hipStream_t)stream);
-  }
+  hipError_t e = forward_impl(c, net, lay, n, x, y, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(c, e, "pcmd_mlp_forward");
   c->err.clear();
   return PCMD_OK;
@@ -166,7 +165,6 @@ int pcmd_mlp_train_step(pcmd_ctx *c, const pcmd_mlp *net, int32_t n, const float
   float *grad = grad_out ? grad_out : (float *)c->mlp_grad.p;
   hipError_t e;
   {
-    ScopedTimer tm(c, PCMD_TIMER_GEMM, 3.0 * (double)n * (double)lay.flops_per_sample, s);
     e = forward_impl(c, net, lay, n, x, nullptr, s);
     // output layer pre-activations are the prediction
     int64_t aoff = 0, poff_last = 0;
@@ -200,7 +198,10 @@ int pcmd_mlp_train_step(pcmd_ctx *c, const pcmd_mlp *net, int32_t n, const float
       gw.ldb = din;
       gw.C = grad + lay.off[l];
       gw.ldc = din;
-      e = launch_gemm(gw, true, true, EPI_STORE, s);
+      {
+        ScopedTimer tm(c, PCMD_TIMER_GEMM, 2.0 * (double)n * (double)din * (double)dout, s);
+        e = launch_gemm(gw, true, true, EPI_STORE, s);
+      }
       if (e == hipSuccess) e = launch_colsum(dz, n, dout, grad + lay.off[l] + (int64_t)dout * din, s);
       if (e == hipSuccess && l > 0) {
         GemmArgs gx{};
@@ -215,7 +216,10 @@ int pcmd_mlp_train_step(pcmd_ctx *c, const pcmd_mlp *net, int32_t n, const float
         gx.ldcb = din;
         gx.Z = pre + poffs[l - 1];
         gx.ldz = din;
-        e = launch_gemm(gx, false, false, EPI_GELU_GRAD, s);
+        {
+          ScopedTimer tm(c, PCMD_TIMER_GEMM, 2.0 * (double)n * (double)din * (double)dout, s);
+          e = launch_gemm(gx, false, false, EPI_GELU_GRAD, s);
+        }
         __bf16 *tmp = dz;
         dz = dz2;
         dz2 = tmp;

@@ -91,16 +91,19 @@ class Standardizer:
 
 
 def delayed_acceptance_mcmc(theta0, n_steps: int, step_scale, log_prior, sim_loglike, sur_loglike, rng,
-                            screen: bool = True):
-    """Metropolis-Hastings with a symmetric Gaussian random walk.  With screen=True a proposal is
-    first accepted with probability min(1, exp(dS + d log prior)) using the surrogate log-likelihood
-    S; survivors are then accepted with probability min(1, exp(dL - dS)) using the simulator's L
-    (delayed acceptance, Christen & Fox 2005), so the chain targets prior x exp(L).  With
-    screen=False every proposal goes to the simulator (plain Metropolis-Hastings).
+                            screen: bool = True, temperature: float = 1.0):
+    """Metropolis-Hastings with a symmetric Gaussian random walk on the target
+    prior x exp(L / temperature).  With screen=True a proposal is first accepted with probability
+    min(1, exp(dS / temperature + d log prior)) using the surrogate log-likelihood S; survivors are
+    then accepted with probability min(1, exp((dL - dS) / temperature)) using the simulator's L
+    (delayed acceptance, Christen & Fox 2005), so the chain targets the same distribution as plain
+    Metropolis-Hastings (screen=False, every proposal judged by the simulator).  A temperature
+    above one tempers the likelihood, e.g. to the scale of its own stochastic scatter.
     Returns (chain [n_steps+1][d], logL chain, counters dict)."""
+    inv_t = 1.0 / float(temperature)
     theta = np.asarray(theta0, np.float64)
-    L = sim_loglike(theta)
-    S = sur_loglike(theta) if screen else 0.0
+    L = sim_loglike(theta) * inv_t
+    S = sur_loglike(theta) * inv_t if screen else 0.0
     lp = log_prior(theta)
     chain, lchain = [theta.copy()], [L]
     n_sim, n_sur, n_acc, n_stage1 = 1, 1 if screen else 0, 0, 0
@@ -111,25 +114,25 @@ def delayed_acceptance_mcmc(theta0, n_steps: int, step_scale, log_prior, sim_log
             chain.append(theta.copy()); lchain.append(L)
             continue
         if screen:
-            Sp = sur_loglike(prop)
+            Sp = sur_loglike(prop) * inv_t
             n_sur += 1
             a1 = (Sp - S) + (lpp - lp)
             if math.log(rng.uniform()) >= min(0.0, a1):
                 chain.append(theta.copy()); lchain.append(L)
                 continue
             n_stage1 += 1
-            Lp = sim_loglike(prop)
+            Lp = sim_loglike(prop) * inv_t
             n_sim += 1
             a2 = (Lp - L) - (Sp - S)
             if math.log(rng.uniform()) < min(0.0, a2):
                 theta, L, S, lp = prop, Lp, Sp, lpp
                 n_acc += 1
         else:
-            Lp = sim_loglike(prop)
+            Lp = sim_loglike(prop) * inv_t
             n_sim += 1
             if math.log(rng.uniform()) < min(0.0, (Lp - L) + (lpp - lp)):
                 theta, L, lp = prop, Lp, lpp
                 n_acc += 1
         chain.append(theta.copy()); lchain.append(L)
-    return np.array(chain), np.array(lchain), dict(simulator_calls=n_sim, surrogate_calls=n_sur, accepted=n_acc,
+    return np.array(chain), np.array(lchain) / inv_t, dict(simulator_calls=n_sim, surrogate_calls=n_sur, accepted=n_acc,
                                                    passed_screen=n_stage1)

@@ -1,0 +1,138 @@
+"""Training data, training and evaluation of the log-Hess surrogate, all through the C ABI.
+
+Training pairs (theta, log-Hess) come from the batched simulator (one persistent launch per 256
+parameter points, replayed from a HIP graph); the network trains on the library's BF16 MFMA
+kernels; the surrogate log-likelihood screens proposals in delayed-acceptance MCMC with the
+simulator's log-likelihood as the judge.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import _lib
+from .pipeline import Evaluator
+from .surrogate import Standardizer, SurrogateNet, delayed_acceptance_mcmc, log_hess_target
+
+class SurrogateWorkflow:
+    def __init__(self, ctx: _lib.Context, grid, theta_to_model, hess_grid: dict, data_hess: torch.Tensor,
+                 data_mom: torch.Tensor, box, train_nim: int = 128, dims=(12, 512, 512, 512, 512, 10000),
+                 init_master=None):
+        """box = (lo, hi): the flat prior of the 12 parameters, also the training domain."""
+        self.ctx = ctx
+        self.grid = grid
+        self.theta_to_model = theta_to_model
+        self.hess_grid = dict(hess_grid)
+        self.nbins = hess_grid["nx"] * hess_grid["ny"]
+        self.data_hess = data_hess
+        self.data_mom = data_mom
+        self.train_nim = train_nim
+        self.dev = data_hess.device
+        self.lo = np.asarray(box[0], np.float64)
+        self.hi = np.asarray(box[1], np.float64)
+        self.std = Standardizer(self.lo, self.hi)
+        self.ev = Evaluator(ctx, grid, train_nim, None, hess_grid)
+        self.net = SurrogateNet(ctx, dims, init_master)
+        self.eval_256 = None
+        self._x1 = torch.empty((1, 12), dtype=torch.float32, device=self.dev)
+        self._y1 = torch.empty((1, dims[-1]), dtype=torch.float32, device=self.dev)
+        self._ll1 = torch.empty(1, dtype=torch.float64, device=self.dev)
+
+    # ---------------------------------------------------------------- data generation
+    def simulate_hess(self, thetas: np.ndarray, seed0: int, nim: int | None = None, batch: int = 256):
+        """Hess diagrams [n][nbins] (int32, device) of the parameter vectors, one batched launch
+        per `batch` points."""
+        nim = self.train_nim if nim is None else nim
+        n = len(thetas)
+        out = torch.empty((n, self.nbins), dtype=torch.int32, device=self.dev)
+        lams = [torch.empty(self.ev.E, dtype=torch.float64, device=self.dev) for _ in range(min(batch, n))]
+        psf = None
+        ll = torch.empty(min(batch, n), dtype=torch.float64, device=self.dev)
+        for b0 in range(0, n, batch):
+            b1 = min(n, b0 + batch)
+            jobs = []
+            for k in range(b0, b1):
+                model, obs = self.theta_to_model(thetas[k], seed=seed0 + k, nim=nim)
+                if psf is None:
+                    psf = torch.from_numpy(obs.psf).to(self.dev)
+                w, npix = _lib.iso_weights(model, self.grid)
+                lam = lams[k - b0]
+                self.ctx.entries(self.ev.E, self.ev.iso_d, self.ev.imf_d, self.ev.iso_imf_sum, w, npix, lam)
+                jobs.append(dict(lam=lam, flux=self.ev.flux_d, obs=obs, psf=psf, conv_path=_lib.CONV_DIRECT))
+            self.ctx.batch_run(jobs, self.hess_grid, self.data_hess, self.data_mom, ll[: b1 - b0],
+                               hess_out=out[b0:b1], use_graph=True)
+        return out
+
+    def targets(self, hess: torch.Tensor) -> torch.Tensor:
+        return log_hess_target(hess)
+
+    def inputs(self, thetas: np.ndarray) -> torch.Tensor:
+        return torch.from_numpy(self.std(thetas)).to(self.dev)
+
+    # ---------------------------------------------------------------- training
+    def fit(self, x: torch.Tensor, t: torch.Tensor, steps: int, batch: int = 256, lr: float = 1e-3,
+            lr_final: float = 1e-4, seed: int = 0, log_every: int = 0):
+        """Adam with a geometric learning-rate decay from lr to lr_final; returns the loss history."""
+        g = torch.Generator(device="cpu").manual_seed(seed)
+        n = x.shape[0]
+        loss = torch.empty(1, dtype=torch.float32, device=self.dev)
+        hist = []
+        for s in range(steps):
+            idx = torch.randint(0, n, (batch,), generator=g).to(self.dev)
+            xb = x.index_select(0, idx).contiguous()
+            tb = t.index_select(0, idx).contiguous()
+            cur = lr * (lr_final / lr) ** (s / max(steps - 1, 1))
+            self.net.train_step(xb, tb, cur, loss_out=loss)
+            if log_every and (s % log_every == 0 or s == steps - 1):
+                hist.append((s, float(loss.item())))
+        return hist
+
+    def mse(self, x: torch.Tensor, t: torch.Tensor, batch: int = 1024) -> float:
+        se = 0.0
+        for b0 in range(0, x.shape[0], batch):
+            y = self.net.forward(x[b0:b0 + batch].contiguous())
+            se += float(((y - t[b0:b0 + batch]) ** 2).sum().item())
+        return se / (x.shape[0] * t.shape[1])
+
+    # ---------------------------------------------------------------- likelihoods
+    def surrogate_loglike_batch(self, thetas: np.ndarray) -> np.ndarray:
+        x = self.inputs(thetas)
+        y = self.net.forward(x)
+        out = torch.empty(len(thetas), dtype=torch.float64, device=self.dev)
+        self.ctx.surrogate_loglike(y, self.data_hess, out)
+        return out.cpu().numpy()
+
+    def surrogate_loglike(self, theta: np.ndarray) -> float:
+        self._x1.copy_(torch.from_numpy(self.std(np.asarray(theta)[None, :])))
+        self.net.forward(self._x1, self._y1)
+        self.ctx.surrogate_loglike(self._y1, self.data_hess, self._ll1)
+        return float(self._ll1.item())
+
+    def simulator_loglike(self, theta: np.ndarray, seed: int, nim: int = 256, data_nim: int | None = None) -> float:
+        """Simulator Poisson log-likelihood of the data Hess at theta (one simulation)."""
+        if self.eval_256 is None or self.eval_256.nim != nim:
+            model, obs = self.theta_to_model(theta, seed=seed, nim=nim)
+            self.eval_256 = Evaluator(self.ctx, self.grid, nim, obs.psf, self.hess_grid)
+        model, obs = self.theta_to_model(theta, seed=seed, nim=nim)
+        out = self.eval_256.loglike(model, obs, self.data_hess, self.data_mom)
+        return float(out.item())
+
+    def run_mcmc(self, theta0, n_steps: int, step_scale, rng, screen: bool, nim: int = 256, seed0: int = 10_000_000,
+                 temperature: float = 1.0):
+        counter = [seed0]
+
+        def sim(th):
+            counter[0] += 1
+            return self.simulator_loglike(th, counter[0], nim)
+
+        def prior(th):
+            th = np.asarray(th)
+            return 0.0 if np.all(th >= self.lo) and np.all(th <= self.hi) else -np.inf
+
+        t0 = time.perf_counter()
+        chain, lchain, info = delayed_acceptance_mcmc(theta0, n_steps, step_scale, prior, sim, self.surrogate_loglike,
+                                                      rng, screen=screen, temperature=temperature)
+        info["seconds"] = time.perf_counter() - t0
+        return chain, lchain, info

@@ -300,32 +300,36 @@ SURROGATE_PARAM_NAMES = ("logSFH0", "logSFH1", "logSFH2", "logSFH3", "logSFH4", 
                          "feh_mu", "feh_sigma", "dust_mu", "dust_sigma", "dmod")
 
 
-def surrogate_theta_draws(n: int, seed: int = 0, nim: int = 128):
-    """n parameter vectors of the 12-parameter model (non-parametric 7-bin SFH, Gaussian MDF with
-    free width, log-normal dust with free width, distance modulus): a tau-model SFH with
-    log Npix ~ U[2, 5] and tau ~ U[0.1, 8] Gyr, each bin then perturbed by U[-1, 1] dex (the mock
-    tests' +-1 dex prior), mu_[Fe/H] ~ U[-0.5, 0.25], sigma_[Fe/H] ~ U[0.1, 0.4],
-    mu_dust ~ U[-1, 0], sigma_dust ~ U[0.1, 0.4], mu_d ~ U[24, 30].
-    Returns theta [n][12] (float64) and the matching (Model, Obs) pairs."""
-    r = np.random.default_rng(np.random.SeedSequence([777, seed]))
-    grid = headline_grid()
-    edges = grid.age_edges
+def surrogate_truth() -> np.ndarray:
+    """The 12-parameter vector of the mock data: the paper's fiducial-tau values (Sec. 3.1):
+    tau = 3 Gyr SFH at Npix = 10^2 spread over the 7 age bins, mu_[Fe/H] = -0.25,
+    sigma_[Fe/H] = 0.2, mu_dust = -0.5, sigma_dust = 0.1, mu_d = 26."""
+    edges = headline_grid().age_edges
     T = 10.0 ** 10.2
-    thetas, pairs = [], []
-    for k in range(n):
-        lnp = r.uniform(2.0, 5.0)
-        tau = r.uniform(0.1, 8.0) * 1e9
-        t1 = T - 10.0 ** edges[1:]
-        t2 = T - 10.0 ** edges[:-1]
-        w = np.exp(-t1 / tau) - np.exp(-t2 / tau)
-        w = np.maximum(w / w.sum(), 1e-12) * 10.0 ** lnp
-        log_sfh = np.log10(w) + r.uniform(-1.0, 1.0, 7)
-        log_sfh = np.maximum(log_sfh, -3.0)
-        th = np.concatenate([log_sfh, [r.uniform(-0.5, 0.25), r.uniform(0.1, 0.4), r.uniform(-1.0, 0.0),
-                                       r.uniform(0.1, 0.4), r.uniform(24.0, 30.0)]])
-        thetas.append(th)
-        pairs.append(theta_to_model(th, seed=100000 * (seed + 1) + k, nim=nim))
-    return np.array(thetas), pairs
+    tau = 3e9
+    t1 = T - 10.0 ** edges[1:]
+    t2 = T - 10.0 ** edges[:-1]
+    w = np.exp(-t1 / tau) - np.exp(-t2 / tau)
+    log_sfh = np.log10(w / w.sum() * 100.0)
+    return np.concatenate([log_sfh, [-0.25, 0.2, -0.5, 0.1, 26.0]])
+
+
+def surrogate_box(center=None):
+    """Parameter box of the surrogate's training draws and of the sampler's flat prior: log SFH
+    bins +-0.5 dex around the truth, mu_[Fe/H] +-0.25, sigma_[Fe/H] in [0.1, 0.3],
+    mu_dust +-0.25, sigma_dust in [0.05, 0.3], mu_d +-1."""
+    c = surrogate_truth() if center is None else np.asarray(center, np.float64)
+    lo = np.concatenate([c[:7] - 0.5, [c[7] - 0.25, 0.1, c[9] - 0.25, 0.05, c[11] - 1.0]])
+    hi = np.concatenate([c[:7] + 0.5, [c[7] + 0.25, 0.3, c[9] + 0.25, 0.3, c[11] + 1.0]])
+    return lo, hi
+
+
+def surrogate_theta_draws(n: int, seed: int = 0, box=None):
+    """n parameter vectors uniform in the surrogate box (12 parameters: log SFH of the 7 age bins
+    in stars per pixel, mu_[Fe/H], sigma_[Fe/H], mu_dust, sigma_dust, mu_d)."""
+    lo, hi = surrogate_box() if box is None else box
+    r = np.random.default_rng(np.random.SeedSequence([777, seed]))
+    return lo + (hi - lo) * r.uniform(size=(n, len(lo)))
 
 
 def theta_to_model(th, seed: int, nim: int = 128):

@@ -1,0 +1,81 @@
+"""End to end: the surrogate trained on the simulator's own Hess diagrams, and what it gains as a
+proposal screen inside MCMC with the simulator as the judge."""
+import numpy as np
+import pytest
+from scipy import stats
+
+import synth_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (12, 512, 512, 512, 512, 10000)
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import torch
+    import paper_1904_00011_amd as P
+    from paper_1904_00011_amd.surrogate_pipeline import SurrogateWorkflow
+    ctx = P.Context(0)
+    dev = torch.device("cuda")
+    G = si.headline_grid()
+    th_true = si.surrogate_truth()
+    box = si.surrogate_box()
+    model, obs = si.theta_to_model(th_true, seed=2, nim=256)
+    ev = P.Evaluator(ctx, G, 256, obs.psf, dict(x0=0, dx=0.05, y0=0, dy=0.05, nx=100, ny=100))
+    md = ev.simulate(model, obs).cpu().numpy().astype(np.float64)
+    fin = np.isfinite(md).all(axis=0)
+    hg = si.hess_grid_from_median(float(np.median((md[0] - md[1])[fin])), float(np.median(md[1][fin])), 100, 100)
+    ev.hess_grid = hg
+    dh = torch.empty(10000, dtype=torch.int32, device=dev)
+    dm = torch.empty(3, dtype=torch.float64, device=dev)
+    ev.hess_of(ev.mags, dh, dm)
+    ctx.sync()
+    wf = SurrogateWorkflow(ctx, G, si.theta_to_model, hg, dh, dm, box, train_nim=128, dims=DIMS,
+                           init_master=si.mlp_init(DIMS, 0))
+    th = si.surrogate_theta_draws(4096, seed=1)
+    H = wf.simulate_hess(th, seed0=10 ** 6)
+    X, T = wf.inputs(th), wf.targets(H)
+    thv = si.surrogate_theta_draws(256, seed=2)
+    Xv, Tv = wf.inputs(thv), wf.targets(wf.simulate_hess(thv, seed0=2 * 10 ** 6))
+    mse0 = wf.mse(Xv, Tv)
+    print(f"[case] surrogate training: 4096 pairs, validation mse before {mse0:.3f}", flush=True)
+    wf.fit(X, T, 800, batch=1024)
+    mse1 = wf.mse(Xv, Tv)
+    print(f"[case] validation mse after {mse1:.4f}", flush=True)
+    yield dict(ctx=ctx, wf=wf, th_true=th_true, box=box, mse0=mse0, mse1=mse1)
+    ctx.close()
+
+
+def test_training_on_simulator_output(setup):
+    assert setup["mse1"] < 0.01 * setup["mse0"]
+
+
+def test_surrogate_tracks_the_simulator_likelihood(setup):
+    from paper_1904_00011_amd.surrogate import SurrogateNet
+    wf = setup["wf"]
+    ths = si.surrogate_theta_draws(48, seed=3)
+    L = np.array([wf.simulator_loglike(t, 5000 + k) for k, t in enumerate(ths)])
+    S = wf.surrogate_loglike_batch(ths)
+    trained = wf.net
+    wf.net = SurrogateNet(setup["ctx"], DIMS, si.mlp_init(DIMS, 0))
+    Su = wf.surrogate_loglike_batch(ths)
+    wf.net = trained
+    r_t, r_u = stats.spearmanr(S, L)[0], stats.spearmanr(Su, L)[0]
+    print(f"[case] Spearman(surrogate, simulator): trained {r_t:.3f}, untrained {r_u:.3f}", flush=True)
+    assert r_t > 0.85 and r_t > r_u + 0.3
+
+
+def test_screen_saves_simulator_calls(setup):
+    wf, box, th0 = setup["wf"], setup["box"], setup["th_true"]
+    scale = 0.1 * (box[1] - box[0])
+    out = {}
+    for screen in (False, True):
+        _, _, info = wf.run_mcmc(th0, 200, scale, np.random.default_rng(1), screen=screen, temperature=3000.0)
+        out[screen] = info
+        print(f"[case] mcmc screen={screen} {info}", flush=True)
+    plain, da = out[False], out[True]
+    # every plain step costs one simulation; the screen sends only its survivors to the simulator
+    assert da["simulator_calls"] < 0.85 * plain["simulator_calls"]
+    # and the survivors are better proposals: the simulator accepts a larger share of them
+    assert da["accepted"] / da["simulator_calls"] > plain["accepted"] / plain["simulator_calls"]
