@@ -25,17 +25,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X published figures: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 VALU lane-ops/s.
+# MI355X published figures: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 VALU lane-instructions/s.
 VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
-# Algorithmic lane-ops of one pixel x entry draw: a quarter of one Philox4x32-10 evaluation
-# (10 rounds x (2 32x32->64-bit products + 4 XORs) = 60 lane-ops for 4 words) plus the
-# threshold compare.  Data-dependent work (accumulation, extra thresholds, rejection, dust
+# Minimum VALU lane-instructions of one pixel x entry draw on gfx950: a quarter of one
+# Philox4x32-10 evaluation (10 rounds x (2 v_mad_u64_u32, each giving both halves of a 32x32
+# product, + 2 three-input XORs) = 40 for 4 words) plus the threshold compare.  Only entries
+# with lambda > 0 draw; data-dependent work (accumulation, further thresholds, rejection, dust
 # split) is not counted, so the fraction is a lower bound.
-OPS_PER_DRAW = 60 / 4 + 1
+OPS_PER_DRAW = 40 / 4 + 1
 # HBM bytes per k_sample launch of the first headline step, from FETCH_SIZE and WRITE_SIZE
 # calibrated against a copy of known size (profiles/k_sample_headline_256x256_52500_counters.md).
 # Set to None whenever k_sample changes until the counters are taken again.
-SAMPLE_TRAFFIC_BYTES = 114.1e6
+SAMPLE_TRAFFIC_BYTES = None
 
 
 def parse():
@@ -377,6 +378,8 @@ def main():
     data_mom = torch.empty(3, dtype=torch.float64, device=dev)
     ev.hess_of(mags_d, data_hess, data_mom)
     params = [si.draw_headline_params(1000 + k) for k in range(args.steps + args.warmup)]
+    # share of entries with lambda > 0 (the rest, e.g. pruned metallicities, draw nothing)
+    active = [float(np.mean(P.iso_weights(m, grid)[0][grid.iso_of_entry] > 0.0)) for m, _ in params[args.warmup:]]
     logls = torch.empty(args.steps + args.warmup, dtype=torch.float64, device=dev)
     for k in range(args.warmup):
         m, o = params[k]
@@ -399,7 +402,7 @@ def main():
     assert np.all(np.isfinite(ll)), "non-finite log-likelihood"
     elapsed = t1 - t0
     evals_per_s = args.steps / elapsed
-    draws_per_launch = s_units / max(s_n, 1)
+    draws_per_launch = s_units / max(s_n, 1) * float(np.mean(active))
     avg_sample_s = s_ms / max(s_n, 1) / 1e3
     achieved = OPS_PER_DRAW * draws_per_launch / avg_sample_s
     res = {
@@ -424,7 +427,7 @@ def main():
         "draws_per_eval": draws_per_launch,
         "kernel_ms_per_eval": {"sample": s_ms / max(s_n, 1), "conv": c_ms / max(c_n, 1), "hess": h_ms / max(h_n, 1)},
         "roofline": {"bound": "alu", "kernel": "k_sample", "achieved": achieved / 1e12,
-                     "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "TOP/s (VALU lane-ops)",
+                     "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "T lane-instr/s (VALU)",
                      "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": SAMPLE_TRAFFIC_BYTES,
                      "ops_per_draw": OPS_PER_DRAW, "avg_launch_ms": avg_sample_s * 1e3},
         "mean_logL": float(ll.mean()),

@@ -50,53 +50,70 @@ hipError_t launch_entries(const pcmd_grid *g, const double *scale, double *lam, 
 // and FP64 star fluxes laid out [E][BP] for scalar loads.
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
-  if (i >= a.E) return;
+  // every lane of the block takes part in the group summary below (no early return)
   const int E = a.E, B = a.B, BP = a.BP;
-  for (int b = 0; b < BP; ++b) a.fl64[(size_t)i * BP + b] = b < B ? (double)a.flux[(size_t)b * E + i] : 0.0;
-  double l = a.lam[i];
-  if (!(l >= 0.0 && l < 4194304.0)) {  // NaN, negative or too large: drawn as zero, reported
-    atomicOr(a.status, STATUS_BAD_LAMBDA);
-    l = 0.0;
-  }
   EntryRec r{{0u, 0u, 0u}, KIND_ZERO};
-  if (l >= 10.0) {
-    const double slam = sqrt(l);
-    const double bb = 0.931 + 2.53 * slam;
-    const double aa = -0.059 + 0.02483 * bb;
-    const double inv_alpha = 1.1239 + 1.1328 / (bb - 3.4);
-    const double vr = 0.9277 - 3.6224 / (bb - 2.0);
-    PtrsConst c;
-    c.mu = (float)l;
-    c.lnmu = (float)log(l);
-    c.b = (float)bb;
-    c.a = (float)aa;
-    c.twoa = (float)(2.0 * aa);
-    c.lninva = (float)log(inv_alpha);
-    c.vr = (float)vr;
-    c.pad = 0.0f;
-    ((PtrsConst *)a.pc)[i] = c;
-    r.kk = KIND_PTRS;
-  } else if (l > 0.0) {
-    double p = exp(-l);
-    double F = p;
-    uint32_t K = 0;
-    uint32_t *t = a.thr + (size_t)i * THR_STRIDE;
-    for (int k = 0; k < THR_STRIDE - 1; ++k) {
-      if (k > 0) {
-        p = p * l / (double)k;
-        F = F + p;
-      }
-      const double tk = floor(F * 4294967296.0);
-      if (tk >= 4294967296.0) break;
-      t[k] = (uint32_t)tk;
-      K = (uint32_t)(k + 1);
+  if (i < E) {
+    for (int b = 0; b < BP; ++b) a.fl64[(size_t)i * BP + b] = b < B ? (double)a.flux[(size_t)b * E + i] : 0.0;
+    double l = a.lam[i];
+    if (!(l >= 0.0 && l < 4194304.0)) {  // NaN, negative or too large: drawn as zero, reported
+      atomicOr(a.status, STATUS_BAD_LAMBDA);
+      l = 0.0;
     }
-    if (K > 0) {
-      for (uint32_t k = 0; k < 3 && k < K; ++k) r.T[k] = t[k];
-      r.kk = (K << 8) | KIND_INV;
+    if (l >= 10.0) {
+      const double slam = sqrt(l);
+      const double bb = 0.931 + 2.53 * slam;
+      const double aa = -0.059 + 0.02483 * bb;
+      const double inv_alpha = 1.1239 + 1.1328 / (bb - 3.4);
+      const double vr = 0.9277 - 3.6224 / (bb - 2.0);
+      PtrsConst c;
+      c.mu = (float)l;
+      c.lnmu = (float)log(l);
+      c.b = (float)bb;
+      c.a = (float)aa;
+      c.twoa = (float)(2.0 * aa);
+      c.lninva = (float)log(inv_alpha);
+      c.vr = (float)vr;
+      c.pad = 0.0f;
+      ((PtrsConst *)a.pc)[i] = c;
+      r.kk = KIND_PTRS;
+    } else if (l > 0.0) {
+      double p = exp(-l);
+      double F = p;
+      uint32_t K = 0;
+      uint32_t *t = a.thr + (size_t)i * THR_STRIDE;
+      for (int k = 0; k < THR_STRIDE - 1; ++k) {
+        if (k > 0) {
+          p = p * l / (double)k;
+          F = F + p;
+        }
+        const double tk = floor(F * 4294967296.0);
+        if (tk >= 4294967296.0) break;
+        t[k] = (uint32_t)tk;
+        K = (uint32_t)(k + 1);
+      }
+      if (K > 0) {
+        for (uint32_t k = 0; k < 3 && k < K; ++k) r.T[k] = t[k];
+        r.kk = (K << 8) | KIND_INV;
+      }
     }
   }
-  a.rec[i] = r;
+  const int E4 = entries_padded(E);
+  if (i < E4) a.rec[i] = r;
+  // group of entries 4g..4g+3 = four neighbouring lanes of one wave (blocks of 256 threads)
+  const uint32_t kind = r.kk & 0xFFu;
+  const uint32_t t0m1 = kind == KIND_INV ? r.T[0] - 1u : 0xFFFFFFFFu;
+  const uint32_t fl = kind == KIND_INV ? GRP_INV : (kind == KIND_PTRS ? GRP_PTRS : 0u);
+  const int first = (int)(threadIdx.x & 63u) & ~3;
+  GroupRec gr;
+  gr.flags = 0u;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    gr.t0m1[q] = (uint32_t)__shfl((int)t0m1, first + q, 64);
+    gr.flags |= (uint32_t)__shfl((int)fl, first + q, 64);
+  }
+  gr.pad[0] = gr.pad[1] = gr.pad[2] = 0u;
+  if ((i & 3) == 0 && i < E4) a.grp[i >> 2] = gr;
 }
 
 __global__ void __launch_bounds__(256) k_prep(PrepArgs a) { prep_body(a, blockIdx.x * blockDim.x + threadIdx.x); }
@@ -219,32 +236,27 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, int pblk, int c
   u4 sw{0u, 0u, 0u, 0u};
   bool have_split = false;
   bool ptrs_failed = false;
+  const PCMD_CONST GroupRec *grp = (const PCMD_CONST GroupRec *)a.grp;
+  // the next group's summary is loaded one iteration ahead (the table has one spare record)
+  GroupRec nxt = ld_const(grp + (e0 >> 2));
   for (int g0 = e0; g0 < e1; g0 += 4) {
     const uint32_t g = (uint32_t)(g0 >> 2);
-    // records and fluxes of the group: uniform scalar loads issued before the Philox work
-    EntryRec r[4];
-    bool need_main = false;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      r[q] = EntryRec{{0u, 0u, 0u}, KIND_ZERO};
-      if (g0 + q < e1) r[q] = ld_const(rec + g0 + q);
-      need_main |= (r[q].kk & 0xFFu) == KIND_INV;
-    }
-    u4 w{0u, 0u, 0u, 0u};
-    if (need_main) w = philox10(p, g, TAG_MAIN, 0u, a.k0, a.k1);
+    const GroupRec gr = nxt;
+    nxt = ld_const(grp + g + 1);
     if ((g0 & 15) == 0) have_split = false;  // new 16-entry split block
-    // first threshold of all four entries at once; at small lambda most groups end here
+    // at small lambda most groups end after one Philox block and four compares, without
+    // touching the entry records
+    if (gr.flags == 0u) continue;  // no entry of the group has stars
+    const u4 w = philox10(p, g, TAG_MAIN, 0u, a.k0, a.k1);  // unused by groups of PTRS entries only
+    if (!(gr.flags & GRP_PTRS) && (__ballot(w.x > gr.t0m1[0]) | __ballot(w.y > gr.t0m1[1]) |
+                                   __ballot(w.z > gr.t0m1[2]) | __ballot(w.w > gr.t0m1[3])) == 0ull)
+      continue;
     uint32_t n0[4];
-    bool any_ptrs = false;
-    uint32_t hit = 0u;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t kind = r[q].kk & 0xFFu;
-      n0[q] = (kind == KIND_INV && word_of(w, q) >= r[q].T[0]) ? 1u : 0u;
-      hit |= n0[q];
-      any_ptrs |= kind == KIND_PTRS;
-    }
-    if (!any_ptrs && !wave_any(hit != 0u)) continue;
+    for (int q = 0; q < 4; ++q) n0[q] = word_of(w, q) > gr.t0m1[q] ? 1u : 0u;
+    EntryRec r[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) r[q] = ld_const(rec + g0 + q);  // padded to a multiple of 4
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint32_t i = (uint32_t)(g0 + q);

@@ -308,7 +308,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   const int nchunks = (E + CHUNK - 1) / CHUNK;
   const int split_mode = split_mode_of(o);
   const int S = split_mode == SPLIT_NONE ? 1 : 2;
-  if ((r = ensure(c, c->rec, (size_t)E * sizeof(EntryRec), "entry records"))) return r;
+  if ((r = ensure(c, c->rec, rec_bytes(E), "entry records"))) return r;
   if ((r = ensure(c, c->thr, (size_t)E * THR_STRIDE * 4, "thresholds"))) return r;
   if ((r = ensure(c, c->pc, (size_t)E * sizeof(PtrsConst), "rejection constants"))) return r;
   if ((r = ensure(c, c->fl64, (size_t)E * BP * 8, "fluxes"))) return r;
@@ -317,7 +317,16 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   if ((r = ensure(c, c->G, (size_t)B * npx * 4, "convolved image"))) return r;
   if (K > 1 && use_fft && (r = ensure(c, c->fft, fft_scratch_bytes(B, N), "fft"))) return r;
 
-  PrepArgs pa{E, B, BP, iso->lam, iso->flux, (EntryRec *)c->rec.p, (uint32_t *)c->thr.p, c->pc.p, (double *)c->fl64.p,
+  PrepArgs pa{E,
+              B,
+              BP,
+              iso->lam,
+              iso->flux,
+              (EntryRec *)c->rec.p,
+              (GroupRec *)((EntryRec *)c->rec.p + entries_padded(E)),
+              (uint32_t *)c->thr.p,
+              c->pc.p,
+              (double *)c->fl64.p,
               c->status};
   hipError_t e = launch_prep(pa, s);
   if (e != hipSuccess) return hip_fail(c, e, "k_prep");
@@ -340,6 +349,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   a.split_mode = split_mode;
   a.split_q = split_q_of(o);
   a.rec = pa.rec;
+  a.grp = pa.grp;
   a.thr = pa.thr;
   a.pc = pa.pc;
   a.fl64 = pa.fl64;

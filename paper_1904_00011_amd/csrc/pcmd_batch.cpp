@@ -136,7 +136,7 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
     ji.o_fl = n_fl;
     ji.o_part = n_part;
     ji.o_img = n_img;
-    n_rec += (size_t)ji.E;
+    n_rec += rec_bytes(ji.E) / sizeof(EntryRec);
     n_thr += (size_t)ji.E * THR_STRIDE;
     n_pc += (size_t)ji.E;
     n_fl += (size_t)ji.E * BP;
@@ -223,7 +223,8 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
     float *G = (float *)p->G.p + ji.o_img;
     float *mags = (float *)p->mags.p + ji.o_img;
     const uint32_t k0 = (uint32_t)(o->seed & 0xFFFFFFFFu), k1 = (uint32_t)(o->seed >> 32);
-    pa[j] = PrepArgs{ji.E, B, BP, jobs[j].iso.lam, jobs[j].iso.flux, rec, thr, pc, fl, c->status};
+    GroupRec *grp = (GroupRec *)(rec + entries_padded(ji.E));
+    pa[j] = PrepArgs{ji.E, B, BP, jobs[j].iso.lam, jobs[j].iso.flux, rec, grp, thr, pc, fl, c->status};
     ReduceArgs rr;
     memset(&rr, 0, sizeof rr);
     rr.B = B;
@@ -296,6 +297,7 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
     s.split_mode = split_mode_of(o);
     s.split_q = split_q_of(o);
     s.rec = (EntryRec *)p->rec.p + ji.o_rec;
+    s.grp = (const GroupRec *)(s.rec + entries_padded(ji.E));
     s.thr = (uint32_t *)p->thr.p + ji.o_thr;
     s.pc = (PtrsConst *)p->pc.p + ji.o_pc;
     s.fl64 = (double *)p->fl.p + ji.o_fl;

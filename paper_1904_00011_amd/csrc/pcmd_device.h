@@ -24,14 +24,28 @@ constexpr int PTRS_MAX_ATTEMPTS = 64;
 
 struct u4 { uint32_t x, y, z, w; };
 
+// Every counter used here is (lane-varying word, uniform, uniform, uniform), so the first two
+// rounds still mix uniform words (their XORs go to the scalar unit); from the third round on all
+// three XOR inputs are per lane and one v_bitop3_b32 (truth table 0x96 = a ^ b ^ c) replaces two
+// v_xor_b32.
+__device__ __forceinline__ uint32_t xor3_lane(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96u);
+}
+
 __device__ __forceinline__ u4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                        uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     const uint64_t p0 = (uint64_t)PH_M0 * c0;
     const uint64_t p1 = (uint64_t)PH_M1 * c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    uint32_t n0, n2;
+    if (r < 2) {
+      n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+      n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    } else {
+      n0 = xor3_lane((uint32_t)(p1 >> 32), c1, k0);
+      n2 = xor3_lane((uint32_t)(p0 >> 32), c3, k1);
+    }
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;

@@ -20,6 +20,25 @@ struct EntryRec {
   uint32_t kk;    // (number of thresholds K) << 8 | kind (KIND_ZERO, KIND_INV, KIND_PTRS)
 };
 
+// Summary of four consecutive entries (32 bytes, one scalar load), enough to finish a group in
+// which no pixel of the wave draws a star: T_0 - 1 of each entry drawn by inversion
+// (0xFFFFFFFF otherwise, so u > t0m1 never holds) and the kinds present.  For inversion
+// entries T_0 >= 1 (lambda < 10), so u >= T_0 is exactly u > T_0 - 1.
+struct GroupRec {
+  uint32_t t0m1[4];
+  uint32_t flags;  // GRP_INV | GRP_PTRS
+  uint32_t pad[3];
+};
+constexpr uint32_t GRP_INV = 1u, GRP_PTRS = 2u;
+
+// The record table holds E rounded up to a multiple of 4 entry records (the padding records
+// have KIND_ZERO), then one group record per four entries and one spare group record (the
+// sampler reads the next group's record one iteration ahead; the spare's value is never used).
+__host__ __device__ inline int entries_padded(int E) { return (E + 3) & ~3; }
+inline size_t rec_bytes(int E) {
+  return (size_t)entries_padded(E) * sizeof(EntryRec) + (size_t)(entries_padded(E) / 4 + 1) * sizeof(GroupRec);
+}
+
 // Device status bits, reported by pcmd_sync.
 constexpr uint32_t STATUS_PTRS_RETRY = 1u, STATUS_BAD_LAMBDA = 2u, STATUS_BAD_PSF = 4u;
 
@@ -30,7 +49,8 @@ struct PrepArgs {
   int E, B, BP;
   const double *lam;   // [E]
   const float *flux;   // [B][E]
-  EntryRec *rec;       // [E]
+  EntryRec *rec;       // [entries_padded(E)]
+  GroupRec *grp;       // [entries_padded(E) / 4]
   uint32_t *thr;       // [E][THR_STRIDE]
   void *pc;            // [E] PtrsConst
   double *fl64;        // [E][BP]
@@ -44,6 +64,7 @@ struct SampleArgs {
   int split_mode;
   uint32_t split_q;
   const EntryRec *rec;
+  const GroupRec *grp;
   const uint32_t *thr;
   const void *pc;
   const double *fl64;
