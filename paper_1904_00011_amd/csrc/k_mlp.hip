@@ -21,47 +21,78 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 // A(m, k) = AT ? A[k lda + m] : A[m lda + k];  B(n, k) = BT ? B[k ldb + n] : B[n ldb + k].
 // 128 x 128 block tile, 4 waves of 64 x 64 (2 x 2 MFMA tiles of 32 x 32), K step 32 staged in
 // LDS as [row][k] (row stride 40 halves = 80 bytes, so every 8-element run is 16-byte aligned).
+// Two LDS buffers: the next K step's global loads are issued into registers before the MFMAs of
+// the current one and written to the other buffer after them, one barrier per K step.
 // ---------------------------------------------------------------------------------------
 constexpr int GBM = 128, GBN = 128, GBK = 32, GLDS = GBK + 8;
 
+// One thread's share of a 128 x 32 operand tile: two runs of 8 elements.
+struct TileRegs {
+  bf16x8 v[2];
+};
+
 template <bool T>
-__device__ __forceinline__ void load_tile(__bf16 *lds, const __bf16 *__restrict__ src, int ld, int rows, int K, int r0,
-                                          int k0, bool vec_ok) {
+__device__ __forceinline__ void load_regs(TileRegs &t, const __bf16 *__restrict__ src, int ld, int rows, int K,
+                                          int r0, int k0, bool vec_ok) {
 #pragma unroll
   for (int it = 0; it < 2; ++it) {
     const int idx = threadIdx.x + 256 * it;
     if (!T) {
       // rows x K row-major: (row idx/4, 8 consecutive k)
-      const int r = idx >> 2, kc = (idx & 3) * 8;
-      const int gr = r0 + r, gk = k0 + kc;
-      __bf16 *dst = lds + r * GLDS + kc;
+      const int gr = r0 + (idx >> 2), gk = k0 + (idx & 3) * 8;
       if (vec_ok && gr < rows && gk + 8 <= K) {
-        *reinterpret_cast<bf16x8 *>(dst) = *reinterpret_cast<const bf16x8 *>(src + (size_t)gr * ld + gk);
+        t.v[it] = *reinterpret_cast<const bf16x8 *>(src + (size_t)gr * ld + gk);
       } else {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) dst[i] = (gr < rows && gk + i < K) ? src[(size_t)gr * ld + gk + i] : (__bf16)0.0f;
+        for (int i = 0; i < 8; ++i) t.v[it][i] = (gr < rows && gk + i < K) ? src[(size_t)gr * ld + gk + i] : (__bf16)0.0f;
       }
     } else {
-      // K x rows row-major: (k idx/16, 8 consecutive rows), transposed into LDS
-      const int kk = idx >> 4, rc = (idx & 15) * 8;
-      const int gk = k0 + kk, gr = r0 + rc;
-      bf16x8 v;
+      // K x rows row-major: (k idx/16, 8 consecutive rows)
+      const int gk = k0 + (idx >> 4), gr = r0 + (idx & 15) * 8;
       if (vec_ok && gk < K && gr + 8 <= rows) {
-        v = *reinterpret_cast<const bf16x8 *>(src + (size_t)gk * ld + gr);
+        t.v[it] = *reinterpret_cast<const bf16x8 *>(src + (size_t)gk * ld + gr);
       } else {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = (gk < K && gr + i < rows) ? src[(size_t)gk * ld + gr + i] : (__bf16)0.0f;
+        for (int i = 0; i < 8; ++i) t.v[it][i] = (gk < K && gr + i < rows) ? src[(size_t)gk * ld + gr + i] : (__bf16)0.0f;
       }
-#pragma unroll
-      for (int i = 0; i < 8; ++i) lds[(rc + i) * GLDS + kk] = v[i];
     }
+  }
+}
+
+template <bool T>
+__device__ __forceinline__ void store_lds(__bf16 *lds, const TileRegs &t) {
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int idx = threadIdx.x + 256 * it;
+    if (!T) {
+      *reinterpret_cast<bf16x8 *>(lds + (idx >> 2) * GLDS + (idx & 3) * 8) = t.v[it];
+    } else {  // transposed into [row][k]
+      const int kk = idx >> 4, rc = (idx & 15) * 8;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) lds[(rc + i) * GLDS + kk] = t.v[it][i];
+    }
+  }
+}
+
+template <int EPI>
+__device__ __forceinline__ void gemm_epilogue(const GemmArgs &g, int row, int col, float v) {
+  if (EPI == EPI_STORE) {
+    g.C[(size_t)row * g.ldc + col] = v;
+  } else if (EPI == EPI_BIAS) {
+    g.C[(size_t)row * g.ldc + col] = v + g.bias[col];
+  } else if (EPI == EPI_BIAS_GELU) {
+    v += g.bias[col];
+    g.C[(size_t)row * g.ldc + col] = v;
+    g.Cb[(size_t)row * g.ldcb + col] = (__bf16)gelu_f(v);
+  } else {  // EPI_GELU_GRAD: dz_prev = bf16(dx * GELU'(z_prev))
+    g.Cb[(size_t)row * g.ldcb + col] = (__bf16)(v * gelu_grad_f(g.Z[(size_t)row * g.ldz + col]));
   }
 }
 
 template <bool AT, bool BT, int EPI>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) __bf16 As[GBM * GLDS];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[GBN * GLDS];
+  __shared__ __attribute__((aligned(16))) __bf16 As[2][GBM * GLDS];
+  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][GBN * GLDS];
   const int bm = blockIdx.y * GBM, bn = blockIdx.x * GBN;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
@@ -75,25 +106,45 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[mi][ni][i] = 0.0f;
   const int r = lane & 31, kh = (lane >> 5) * 8;
-  for (int k0 = 0; k0 < g.K; k0 += GBK) {
-    load_tile<AT>(As, g.A, g.lda, g.M, g.K, bm, k0, va);
-    load_tile<BT>(Bs, g.B, g.ldb, g.N, g.K, bn, k0, vb);
-    __syncthreads();
+  // split over K: block z of a split product covers [z kchunk, (z + 1) kchunk)
+  const int kb = g.part ? (int)blockIdx.z * g.kchunk : 0;
+  const int ke = g.part ? min(g.K, kb + g.kchunk) : g.K;
+  const int nk = (ke - kb + GBK - 1) / GBK;
+  TileRegs ra, rb;
+  load_regs<AT>(ra, g.A, g.lda, g.M, ke, bm, kb, va);
+  load_regs<BT>(rb, g.B, g.ldb, g.N, ke, bn, kb, vb);
+  store_lds<AT>(As[0], ra);
+  store_lds<BT>(Bs[0], rb);
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    const bool more = kt + 1 < nk;
+    if (more) {
+      load_regs<AT>(ra, g.A, g.lda, g.M, ke, bm, kb + (kt + 1) * GBK, va);
+      load_regs<BT>(rb, g.B, g.ldb, g.N, ke, bn, kb + (kt + 1) * GBK, vb);
+    }
+    const __bf16 *as = As[cur];
+    const __bf16 *bs = Bs[cur];
 #pragma unroll
     for (int ks = 0; ks < GBK; ks += 16) {
       bf16x8 a[2], b[2];
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi) a[mi] = *reinterpret_cast<const bf16x8 *>(&As[(wm + mi * 32 + r) * GLDS + ks + kh]);
+      for (int mi = 0; mi < 2; ++mi) a[mi] = *reinterpret_cast<const bf16x8 *>(&as[(wm + mi * 32 + r) * GLDS + ks + kh]);
 #pragma unroll
-      for (int ni = 0; ni < 2; ++ni) b[ni] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn + ni * 32 + r) * GLDS + ks + kh]);
+      for (int ni = 0; ni < 2; ++ni) b[ni] = *reinterpret_cast<const bf16x8 *>(&bs[(wn + ni * 32 + r) * GLDS + ks + kh]);
 #pragma unroll
       for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
     }
+    if (more) {
+      store_lds<AT>(As[cur ^ 1], ra);
+      store_lds<BT>(Bs[cur ^ 1], rb);
+    }
     __syncthreads();
   }
   // accumulator element e of a 32 x 32 tile: row 8 (e / 4) + 4 (lane / 32) + e % 4, column lane % 32
+  float *part = g.part ? g.part + (size_t)blockIdx.z * g.M * g.N : nullptr;
 #pragma unroll
   for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -103,28 +154,57 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       for (int e = 0; e < 16; ++e) {
         const int row = bm + wm + mi * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
         if (row >= g.M || col >= g.N) continue;
-        float v = acc[mi][ni][e];
-        if (EPI == EPI_STORE) {
-          g.C[(size_t)row * g.ldc + col] = v;
-        } else if (EPI == EPI_BIAS) {
-          g.C[(size_t)row * g.ldc + col] = v + g.bias[col];
-        } else if (EPI == EPI_BIAS_GELU) {
-          v += g.bias[col];
-          g.C[(size_t)row * g.ldc + col] = v;
-          g.Cb[(size_t)row * g.ldcb + col] = (__bf16)gelu_f(v);
-        } else {  // EPI_GELU_GRAD: dz_prev = bf16(dx * GELU'(z_prev))
-          g.Cb[(size_t)row * g.ldcb + col] = (__bf16)(v * gelu_grad_f(g.Z[(size_t)row * g.ldz + col]));
-        }
+        if (part)
+          part[(size_t)row * g.N + col] = acc[mi][ni][e];
+        else
+          gemm_epilogue<EPI>(g, row, col, acc[mi][ni][e]);
       }
     }
 }
 
-hipError_t launch_gemm(const GemmArgs &g, bool at, bool bt, int epi, hipStream_t s) {
-  dim3 grid((g.N + GBN - 1) / GBN, (g.M + GBM - 1) / GBM);
-#define PCMD_GEMM_CASE(A_, B_, E_)                                                \
-  if (at == A_ && bt == B_ && epi == E_) {                                        \
-    hipLaunchKernelGGL((k_gemm<A_, B_, E_>), grid, dim3(256), 0, s, g);           \
-    return hipGetLastError();                                                     \
+// Sum of the split-K partial products in split order, then the epilogue.
+template <int EPI>
+__global__ void __launch_bounds__(256) k_gemm_splitk_reduce(GemmArgs g, int splits) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t mn = (int64_t)g.M * g.N;
+  if (idx >= mn) return;
+  float v = 0.0f;
+  for (int z = 0; z < splits; ++z) v += g.part[(size_t)z * mn + idx];
+  gemm_epilogue<EPI>(g, (int)(idx / g.N), (int)(idx % g.N), v);
+}
+
+// Split over K when the output tile grid cannot fill the chip and K is long enough: about two
+// blocks per CU, at least 256 K elements per split.
+static int gemm_splits(int M, int N, int K, int &kchunk) {
+  const int blocks = ((M + GBM - 1) / GBM) * ((N + GBN - 1) / GBN);
+  kchunk = K;
+  if (blocks >= 128 || K < 512) return 1;
+  int splits = min((512 + blocks - 1) / blocks, K / 256);
+  if (splits < 2) return 1;
+  kchunk = ((K + splits - 1) / splits + GBK - 1) / GBK * GBK;
+  return (K + kchunk - 1) / kchunk;
+}
+
+size_t gemm_workspace_elems(int M, int N, int K) {
+  int kchunk;
+  const int splits = gemm_splits(M, N, K, kchunk);
+  return splits > 1 ? (size_t)splits * M * N : 0;
+}
+
+hipError_t launch_gemm(const GemmArgs &g0, bool at, bool bt, int epi, float *ws, size_t ws_elems, hipStream_t s) {
+  GemmArgs g = g0;
+  int kchunk;
+  const int splits = gemm_splits(g.M, g.N, g.K, kchunk);
+  const bool split = splits > 1 && ws && ws_elems >= (size_t)splits * g.M * g.N;
+  g.part = split ? ws : nullptr;
+  g.kchunk = split ? kchunk : g.K;
+  dim3 grid((g.N + GBN - 1) / GBN, (g.M + GBM - 1) / GBM, split ? splits : 1);
+  const unsigned rblocks = (unsigned)(((int64_t)g.M * g.N + 255) / 256);
+#define PCMD_GEMM_CASE(A_, B_, E_)                                                                   \
+  if (at == A_ && bt == B_ && epi == E_) {                                                           \
+    hipLaunchKernelGGL((k_gemm<A_, B_, E_>), grid, dim3(256), 0, s, g);                              \
+    if (split) hipLaunchKernelGGL((k_gemm_splitk_reduce<E_>), dim3(rblocks), dim3(256), 0, s, g, splits); \
+    return hipGetLastError();                                                                        \
   }
   PCMD_GEMM_CASE(false, false, EPI_STORE)
   PCMD_GEMM_CASE(false, false, EPI_BIAS)

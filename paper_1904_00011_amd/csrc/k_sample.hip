@@ -222,8 +222,6 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, int pblk, int c
   const PCMD_CONST double *fl64 = (const PCMD_CONST double *)a.fl64;
   const uint32_t p = (uint32_t)(pblk * 256 + threadIdx.x);
   const bool live = p < (uint32_t)a.npx;
-  const int e0 = chunk * CHUNK;
-  const int e1 = min(a.E, e0 + CHUNK);
   const bool dbg = DBG && live && (int64_t)p >= a.px0 && (int64_t)p < a.px1;
 
   double acc_c[B], acc_r[B];
@@ -237,12 +235,20 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, int pblk, int c
   bool have_split = false;
   bool ptrs_failed = false;
   const PCMD_CONST GroupRec *grp = (const PCMD_CONST GroupRec *)a.grp;
+  // Slice `chunk` of nchunks takes the 16-entry blocks chunk, chunk + nchunks, chunk + 2 nchunks,
+  // ...: every slice then spans all isochrones and masses, so slices cost about the same (runs
+  // of consecutive entries differ in cost several-fold: high-lambda low-mass stars cluster at the
+  // start of each isochrone).  The j-th group of the slice is group slice_group(j) of the table.
+  const int ngrp = entries_padded(a.E) >> 2;
+  const int stride = a.nchunks * 4;
+  auto slice_group = [&](int j) { return chunk * 4 + (j >> 2) * stride + (j & 3); };
   // the next group's summary is loaded one iteration ahead (the table has one spare record)
-  GroupRec nxt = ld_const(grp + (e0 >> 2));
-  for (int g0 = e0; g0 < e1; g0 += 4) {
-    const uint32_t g = (uint32_t)(g0 >> 2);
+  GroupRec nxt = ld_const(grp + min(slice_group(0), ngrp));
+  for (int j = 0, gi = slice_group(0); gi < ngrp; ++j, gi = slice_group(j)) {
+    const uint32_t g = (uint32_t)gi;
+    const int g0 = gi * 4;
     const GroupRec gr = nxt;
-    nxt = ld_const(grp + g + 1);
+    nxt = ld_const(grp + min(slice_group(j + 1), ngrp));
     if ((g0 & 15) == 0) have_split = false;  // new 16-entry split block
     // at small lambda most groups end after one Philox block and four compares, without
     // touching the entry records

@@ -111,7 +111,7 @@ void pcmd_destroy(pcmd_ctx *c) {
   batch_destroy(c);
   Buf *bufs[] = {&c->rec,     &c->thr,     &c->pc,      &c->fl64,    &c->part,     &c->F,       &c->G,
                  &c->mom_part, &c->fft,    &c->mlp_act, &c->mlp_pre, &c->mlp_dza, &c->mlp_dzb, &c->mlp_grad,
-                 &c->mlp_part};
+                 &c->mlp_part, &c->mlp_ws};
   for (Buf *b : bufs) release(*b);
   if (c->lnfact) (void)hipFree(c->lnfact);
   if (c->status) (void)hipFree(c->status);

@@ -22,6 +22,8 @@ struct GemmArgs {
   const float *bias;  // [N]
   const float *Z;     // FP32 pre-activations for GELU' (EPI_GELU_GRAD)
   int ldz;
+  float *part;        // split-K partial products [splits][M][N] (set by launch_gemm)
+  int kchunk;         // K elements per split (a multiple of the K step)
 };
 
 struct AdamArgs {
@@ -32,7 +34,9 @@ struct AdamArgs {
   float lr, beta1, beta2, eps, bc1, bc2;
 };
 
-hipError_t launch_gemm(const GemmArgs &g, bool at, bool bt, int epi, hipStream_t s);
+// Workspace (FP32 elements) launch_gemm needs for an M x N x K product (0: no split over K).
+size_t gemm_workspace_elems(int M, int N, int K);
+hipError_t launch_gemm(const GemmArgs &g, bool at, bool bt, int epi, float *ws, size_t ws_elems, hipStream_t s);
 hipError_t launch_f32_to_bf16(const float *x, void *y, int64_t n, hipStream_t s);
 hipError_t launch_mse_grad(const float *y, const float *t, int64_t n, double scale, void *dy, double *part,
                            float *loss_out, hipStream_t s);

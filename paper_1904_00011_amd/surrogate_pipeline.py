@@ -89,6 +89,24 @@ class SurrogateWorkflow:
                 hist.append((s, float(loss.item())))
         return hist
 
+    def local_draws(self, center, frac: float, n: int, seed: int) -> np.ndarray:
+        """n parameter vectors uniform in center +- frac x (prior width), clipped to the prior box."""
+        r = np.random.default_rng(np.random.SeedSequence([31337, seed]))
+        w = self.hi - self.lo
+        u = r.uniform(-1.0, 1.0, size=(n, len(self.lo)))
+        return np.clip(np.asarray(center, np.float64) + u * frac * w, self.lo, self.hi)
+
+    def refine(self, x: torch.Tensor, t: torch.Tensor, center, frac: float, n: int, steps: int, seed0: int,
+               batch: int = 1024, lr: float = 3e-4, lr_final: float = 3e-5, seed: int = 1):
+        """Sequential design: simulate n extra pairs around `center` (e.g. the chain's start),
+        then continue training on the union of the old and new pairs.  Returns the union."""
+        th = self.local_draws(center, frac, n, seed)
+        xl = self.inputs(th)
+        tl = self.targets(self.simulate_hess(th, seed0=seed0))
+        xu, tu = torch.cat([x, xl]), torch.cat([t, tl])
+        self.fit(xu, tu, steps, batch=batch, lr=lr, lr_final=lr_final, seed=seed)
+        return xu, tu
+
     def mse(self, x: torch.Tensor, t: torch.Tensor, batch: int = 1024) -> float:
         se = 0.0
         for b0 in range(0, x.shape[0], batch):

@@ -21,7 +21,9 @@ def _bf16_tensor(a):
     return torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(torch.device("cuda")).to(torch.bfloat16)
 
 
-@pytest.mark.parametrize("M,N,K", [(70, 45, 37), (128, 64, 512), (1, 1, 1), (200, 130, 12)])
+# the last two split K over several blocks (ragged final split) and sum the parts in order
+@pytest.mark.parametrize("M,N,K", [(70, 45, 37), (128, 64, 512), (1, 1, 1), (200, 130, 12), (256, 200, 3000),
+                                   (130, 70, 1000)])
 @pytest.mark.parametrize("at,bt", [(False, False), (True, True), (True, False), (False, True)])
 def test_gemm_layouts_against_fp64(ctx, M, N, K, at, bt):
     import torch
@@ -59,13 +61,14 @@ def test_forward_against_oracle(ctx):
     assert np.max(np.abs(got - yo)) <= 2e-3 * np.max(np.abs(yo))
 
 
-def test_gradients_against_oracle(ctx):
+@pytest.mark.parametrize("n", [53, 600])  # 600: the weight gradients split the batch over two blocks
+def test_gradients_against_oracle(ctx, n):
     import torch
     dims = (12, 64, 96, 100)
     net, master = _net(ctx, dims, 5)
     r = np.random.default_rng(6)
-    x = r.uniform(-1, 1, (53, 12)).astype(np.float32)
-    t = r.normal(0, 1, (53, 100)).astype(np.float32)
+    x = r.uniform(-1, 1, (n, 12)).astype(np.float32)
+    t = r.normal(0, 1, (n, 100)).astype(np.float32)
     dev = torch.device("cuda")
     grad = torch.empty(net.n_params, dtype=torch.float32, device=dev)
     loss = torch.empty(1, dtype=torch.float32, device=dev)

@@ -43,7 +43,7 @@ def setup():
     wf.fit(X, T, 800, batch=1024)
     mse1 = wf.mse(Xv, Tv)
     print(f"[case] validation mse after {mse1:.4f}", flush=True)
-    yield dict(ctx=ctx, wf=wf, th_true=th_true, box=box, mse0=mse0, mse1=mse1)
+    yield dict(ctx=ctx, wf=wf, th_true=th_true, box=box, mse0=mse0, mse1=mse1, X=X, T=T)
     ctx.close()
 
 
@@ -67,15 +67,19 @@ def test_surrogate_tracks_the_simulator_likelihood(setup):
 
 
 def test_screen_saves_simulator_calls(setup):
+    """Delayed acceptance against plain Metropolis-Hastings from the same start, both on the
+    simulator's likelihood tempered to the scale of its seed-to-seed scatter (T = 3000), with
+    the surrogate refined around the start (4096 extra pairs within 15% of the prior width)."""
     wf, box, th0 = setup["wf"], setup["box"], setup["th_true"]
+    wf.refine(setup["X"], setup["T"], th0, 0.15, 4096, 800, seed0=3 * 10 ** 6)
     scale = 0.1 * (box[1] - box[0])
     out = {}
     for screen in (False, True):
-        _, _, info = wf.run_mcmc(th0, 200, scale, np.random.default_rng(1), screen=screen, temperature=3000.0)
+        _, _, info = wf.run_mcmc(th0, 300, scale, np.random.default_rng(1), screen=screen, temperature=3000.0)
         out[screen] = info
         print(f"[case] mcmc screen={screen} {info}", flush=True)
     plain, da = out[False], out[True]
     # every plain step costs one simulation; the screen sends only its survivors to the simulator
-    assert da["simulator_calls"] < 0.85 * plain["simulator_calls"]
+    assert da["simulator_calls"] < 0.6 * plain["simulator_calls"]
     # and the survivors are better proposals: the simulator accepts a larger share of them
-    assert da["accepted"] / da["simulator_calls"] > plain["accepted"] / plain["simulator_calls"]
+    assert da["accepted"] / da["simulator_calls"] > 1.5 * plain["accepted"] / plain["simulator_calls"]
