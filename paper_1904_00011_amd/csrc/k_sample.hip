@@ -98,22 +98,23 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
       }
     }
   }
-  const int E4 = entries_padded(E);
-  if (i < E4) a.rec[i] = r;
-  // group of entries 4g..4g+3 = four neighbouring lanes of one wave (blocks of 256 threads)
+  const int EP = entries_padded(E);
+  if (i < EP) a.rec[i] = r;
+  // group of entries GRP g .. GRP g + GRP - 1 = neighbouring lanes of one wave (256-thread blocks)
   const uint32_t kind = r.kk & 0xFFu;
   const uint32_t t0m1 = kind == KIND_INV ? r.T[0] - 1u : 0xFFFFFFFFu;
   const uint32_t fl = kind == KIND_INV ? GRP_INV : (kind == KIND_PTRS ? GRP_PTRS : 0u);
-  const int first = (int)(threadIdx.x & 63u) & ~3;
+  const int first = (int)(threadIdx.x & 63u) & ~(GRP - 1);
   GroupRec gr;
   gr.flags = 0u;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < GRP; ++q) {
     gr.t0m1[q] = (uint32_t)__shfl((int)t0m1, first + q, 64);
     gr.flags |= (uint32_t)__shfl((int)fl, first + q, 64);
   }
-  gr.pad[0] = gr.pad[1] = gr.pad[2] = 0u;
-  if ((i & 3) == 0 && i < E4) a.grp[i >> 2] = gr;
+#pragma unroll
+  for (int q = 0; q < 7; ++q) gr.pad[q] = 0u;
+  if ((i & (GRP - 1)) == 0 && i < EP) a.grp[i / GRP] = gr;
 }
 
 __global__ void __launch_bounds__(256) k_prep(PrepArgs a) { prep_body(a, blockIdx.x * blockDim.x + threadIdx.x); }
@@ -140,7 +141,7 @@ __device__ __forceinline__ uint32_t low_mask(uint32_t cnt) { return cnt >= 32u ?
 
 // Transformed-rejection draw for entry i at pixel p (attempts 2j, 2j+1 share one Philox call).
 __device__ __forceinline__ uint32_t ptrs_draw(const PtrsConst &c, uint32_t p, uint32_t i, uint32_t k0, uint32_t k1,
-                                              const float *__restrict__ lnfact, bool &failed) {
+                                              const float *__restrict__ lnfact, uint32_t &failed) {
   int k = 0;
   bool done = false;
   for (uint32_t j = 0; j < (uint32_t)(PTRS_MAX_ATTEMPTS / 2); ++j) {
@@ -157,7 +158,7 @@ __device__ __forceinline__ uint32_t ptrs_draw(const PtrsConst &c, uint32_t p, ui
     if (!wave_any(!done)) break;
   }
   if (!done) {  // reported once per wave at the end of the kernel (no stores inside the entry loop)
-    failed = true;
+    failed = 1u;
     k = 0;
   }
   return (uint32_t)k;
@@ -232,102 +233,108 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, int pblk, int c
   }
 
   u4 sw{0u, 0u, 0u, 0u};
-  bool have_split = false;
-  bool ptrs_failed = false;
+  int split_blk = -1;         // the 16-entry block whose split bits sw holds
+  uint32_t ptrs_failed = 0u;  // per lane, kept in a vector register
   const PCMD_CONST GroupRec *grp = (const PCMD_CONST GroupRec *)a.grp;
   // Slice `chunk` of nchunks takes the 16-entry blocks chunk, chunk + nchunks, chunk + 2 nchunks,
   // ...: every slice then spans all isochrones and masses, so slices cost about the same (runs
   // of consecutive entries differ in cost several-fold: high-lambda low-mass stars cluster at the
-  // start of each isochrone).  The j-th group of the slice is group slice_group(j) of the table.
-  const int ngrp = entries_padded(a.E) >> 2;
-  const int stride = a.nchunks * 4;
-  auto slice_group = [&](int j) { return chunk * 4 + (j >> 2) * stride + (j & 3); };
-  // the next group's summary is loaded one iteration ahead (the table has one spare record)
-  GroupRec nxt = ld_const(grp + min(slice_group(0), ngrp));
+  // start of each isochrone).  The j-th group of GRP entries of the slice is group
+  // slice_group(j) of the table.
+  const int ngrp = entries_padded(a.E) / GRP;
+  const int stride = a.nchunks * (16 / GRP);
+  auto slice_group = [&](int j) { return chunk * (16 / GRP) + (j >> 1) * stride + (j & 1); };
+  static_assert(GRP == 8, "two groups per 16-entry block");
   for (int j = 0, gi = slice_group(0); gi < ngrp; ++j, gi = slice_group(j)) {
-    const uint32_t g = (uint32_t)gi;
-    const int g0 = gi * 4;
-    const GroupRec gr = nxt;
-    nxt = ld_const(grp + min(slice_group(j + 1), ngrp));
-    if ((g0 & 15) == 0) have_split = false;  // new 16-entry split block
-    // at small lambda most groups end after one Philox block and four compares, without
+    const int g0 = gi * GRP;
+    const GroupRec gr = ld_const(grp + gi);
+    // at small lambda most groups end after two Philox blocks and eight compares, without
     // touching the entry records
     if (gr.flags == 0u) continue;  // no entry of the group has stars
-    const u4 w = philox10(p, g, TAG_MAIN, 0u, a.k0, a.k1);  // unused by groups of PTRS entries only
-    if (!(gr.flags & GRP_PTRS) && (__ballot(w.x > gr.t0m1[0]) | __ballot(w.y > gr.t0m1[1]) |
-                                   __ballot(w.z > gr.t0m1[2]) | __ballot(w.w > gr.t0m1[3])) == 0ull)
+    // inversion words of the group's two quads: counters (p, i / 4, TAG_MAIN, 0)
+    const u4 wa = philox10(p, (uint32_t)(2 * gi), TAG_MAIN, 0u, a.k0, a.k1);
+    const u4 wb = philox10(p, (uint32_t)(2 * gi + 1), TAG_MAIN, 0u, a.k0, a.k1);
+    if (!(gr.flags & GRP_PTRS) &&
+        (__ballot(wa.x > gr.t0m1[0]) | __ballot(wa.y > gr.t0m1[1]) | __ballot(wa.z > gr.t0m1[2]) |
+         __ballot(wa.w > gr.t0m1[3]) | __ballot(wb.x > gr.t0m1[4]) | __ballot(wb.y > gr.t0m1[5]) |
+         __ballot(wb.z > gr.t0m1[6]) | __ballot(wb.w > gr.t0m1[7])) == 0ull)
       continue;
-    uint32_t n0[4];
+#pragma unroll 1
+    for (int h = 0; h < 2; ++h) {
+      const int q0 = g0 + 4 * h;  // first entry of the quad
+      const u4 w = h ? wb : wa;
+      uint32_t n0[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) n0[q] = word_of(w, q) > gr.t0m1[q] ? 1u : 0u;
-    EntryRec r[4];
+      for (int q = 0; q < 4; ++q) n0[q] = word_of(w, q) > (h ? gr.t0m1[4 + q] : gr.t0m1[q]) ? 1u : 0u;
+      EntryRec r[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) r[q] = ld_const(rec + g0 + q);  // padded to a multiple of 4
+      for (int q = 0; q < 4; ++q) r[q] = ld_const(rec + q0 + q);  // padded to a multiple of GRP
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const uint32_t i = (uint32_t)(g0 + q);
-      uint32_t n = 0;
-      const uint32_t kind = r[q].kk & 0xFFu;
-      if (kind == KIND_INV) {
-        // n = #{k < K : T_k <= u}, walking up while any lane of the wave is still above
-        const uint32_t u = word_of(w, q);
-        const uint32_t K = r[q].kk >> 8;
-        n = n0[q];
-        if (!wave_any(n != 0u)) continue;
-        if (K > 1) {
-          uint32_t c = u >= r[q].T[1] ? 1u : 0u;
-          if (wave_any(c != 0u)) {
-            n += c;
-            if (K > 2) {
-              c = u >= r[q].T[2] ? 1u : 0u;
-              if (wave_any(c != 0u)) {
-                n += c;
-                const PCMD_CONST uint32_t *t = thr + (size_t)i * THR_STRIDE;
-                for (uint32_t k = 3; k < K; ++k) {
-                  c = u >= t[k] ? 1u : 0u;
-                  if (!wave_any(c != 0u)) break;
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t i = (uint32_t)(q0 + q);
+        uint32_t n = 0;
+        const uint32_t kind = r[q].kk & 0xFFu;
+        if (kind == KIND_INV) {
+          // n = #{k < K : T_k <= u}, walking up while any lane of the wave is still above
+          const uint32_t u = word_of(w, q);
+          const uint32_t K = r[q].kk >> 8;
+          n = n0[q];
+          if (!wave_any(n != 0u)) continue;
+          if (K > 1) {
+            uint32_t c = u >= r[q].T[1] ? 1u : 0u;
+            if (wave_any(c != 0u)) {
+              n += c;
+              if (K > 2) {
+                c = u >= r[q].T[2] ? 1u : 0u;
+                if (wave_any(c != 0u)) {
                   n += c;
+                  const PCMD_CONST uint32_t *t = thr + (size_t)i * THR_STRIDE;
+                  for (uint32_t k = 3; k < K; ++k) {
+                    c = u >= t[k] ? 1u : 0u;
+                    if (!wave_any(c != 0u)) break;
+                    n += c;
+                  }
                 }
               }
             }
           }
+        } else if (kind == KIND_PTRS) {
+          const PtrsConst c = ld_const(pc + i);
+          n = ptrs_draw(c, p, i, a.k0, a.k1, a.lnfact, ptrs_failed);
+        } else {
+          continue;
         }
-      } else if (kind == KIND_PTRS) {
-        const PtrsConst c = ld_const(pc + i);
-        n = ptrs_draw(c, p, i, a.k0, a.k1, a.lnfact, ptrs_failed);
-      } else {
-        continue;
-      }
-      if (!wave_any(n != 0u)) continue;
-      uint32_t red = 0u;
-      if (S == 2) {
-        uint32_t byte = 0u;
-        if (a.split_mode == SPLIT_HALF) {
-          if (!have_split) {
-            sw = philox10(p, (uint32_t)(g0 >> 4), TAG_SPLIT, 0u, a.k0, a.k1);
-            have_split = true;
+        if (!wave_any(n != 0u)) continue;
+        uint32_t red = 0u;
+        if (S == 2) {
+          uint32_t byte = 0u;
+          if (a.split_mode == SPLIT_HALF) {
+            if (split_blk != (q0 >> 4)) {
+              sw = philox10(p, (uint32_t)(q0 >> 4), TAG_SPLIT, 0u, a.k0, a.k1);
+              split_blk = q0 >> 4;
+            }
+            byte = (word_of(sw, (q0 & 15) >> 2) >> (8 * q)) & 0xFFu;
           }
-          byte = (word_of(sw, (g0 & 15) >> 2) >> (8 * q)) & 0xFFu;
+          red = split_count(n, byte, a.split_mode, a.split_q, p, i, a.k0, a.k1);
         }
-        red = split_count(n, byte, a.split_mode, a.split_q, p, i, a.k0, a.k1);
-      }
-      const PCMD_CONST double *f = fl64 + (size_t)i * BP;
-      const double dc = (double)(n - red);
+        const PCMD_CONST double *f = fl64 + (size_t)i * BP;
+        const double dc = (double)(n - red);
 #pragma unroll
-      for (int b = 0; b < B; ++b) acc_c[b] = fma(dc, f[b], acc_c[b]);
-      if (S == 2) {
-        const double dr = (double)red;
+        for (int b = 0; b < B; ++b) acc_c[b] = fma(dc, f[b], acc_c[b]);
+        if (S == 2) {
+          const double dr = (double)red;
 #pragma unroll
-        for (int b = 0; b < B; ++b) acc_r[b] = fma(dr, f[b], acc_r[b]);
-      }
-      if (DBG && dbg) {
-        const size_t o = (size_t)((int64_t)p - a.px0) * (size_t)a.E + i;
-        a.dbg_counts[o] = n;
-        if (a.dbg_red) a.dbg_red[o] = red;
+          for (int b = 0; b < B; ++b) acc_r[b] = fma(dr, f[b], acc_r[b]);
+        }
+        if (DBG && dbg) {
+          const size_t o = (size_t)((int64_t)p - a.px0) * (size_t)a.E + i;
+          a.dbg_counts[o] = n;
+          if (a.dbg_red) a.dbg_red[o] = red;
+        }
       }
     }
   }
-  if (wave_any(ptrs_failed) && (threadIdx.x & 63) == 0) atomicOr(a.status, STATUS_PTRS_RETRY);
+  if (wave_any(ptrs_failed != 0u) && (threadIdx.x & 63) == 0) atomicOr(a.status, STATUS_PTRS_RETRY);
   if (!live) return;
   const size_t plane = (size_t)a.npx;
 #pragma unroll

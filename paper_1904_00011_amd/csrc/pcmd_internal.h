@@ -20,23 +20,24 @@ struct EntryRec {
   uint32_t kk;    // (number of thresholds K) << 8 | kind (KIND_ZERO, KIND_INV, KIND_PTRS)
 };
 
-// Summary of four consecutive entries (32 bytes, one scalar load), enough to finish a group in
+// Summary of eight consecutive entries (64 bytes, scalar loads), enough to finish a group in
 // which no pixel of the wave draws a star: T_0 - 1 of each entry drawn by inversion
 // (0xFFFFFFFF otherwise, so u > t0m1 never holds) and the kinds present.  For inversion
 // entries T_0 >= 1 (lambda < 10), so u >= T_0 is exactly u > T_0 - 1.
+constexpr int GRP = 8;  // entries per group record (two Philox blocks)
 struct GroupRec {
-  uint32_t t0m1[4];
+  uint32_t t0m1[GRP];
   uint32_t flags;  // GRP_INV | GRP_PTRS
-  uint32_t pad[3];
+  uint32_t pad[7];
 };
 constexpr uint32_t GRP_INV = 1u, GRP_PTRS = 2u;
 
-// The record table holds E rounded up to a multiple of 4 entry records (the padding records
-// have KIND_ZERO), then one group record per four entries and one spare group record (the
+// The record table holds E rounded up to a multiple of GRP entry records (the padding records
+// have KIND_ZERO), then one group record per GRP entries and one spare group record (the
 // sampler reads the next group's record one iteration ahead; the spare's value is never used).
-__host__ __device__ inline int entries_padded(int E) { return (E + 3) & ~3; }
+__host__ __device__ inline int entries_padded(int E) { return (E + GRP - 1) / GRP * GRP; }
 inline size_t rec_bytes(int E) {
-  return (size_t)entries_padded(E) * sizeof(EntryRec) + (size_t)(entries_padded(E) / 4 + 1) * sizeof(GroupRec);
+  return (size_t)entries_padded(E) * sizeof(EntryRec) + (size_t)(entries_padded(E) / GRP + 1) * sizeof(GroupRec);
 }
 
 // Device status bits, reported by pcmd_sync.
@@ -50,7 +51,7 @@ struct PrepArgs {
   const double *lam;   // [E]
   const float *flux;   // [B][E]
   EntryRec *rec;       // [entries_padded(E)]
-  GroupRec *grp;       // [entries_padded(E) / 4]
+  GroupRec *grp;       // [entries_padded(E) / GRP + 1]
   uint32_t *thr;       // [E][THR_STRIDE]
   void *pc;            // [E] PtrsConst
   double *fl64;        // [E][BP]
