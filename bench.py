@@ -36,7 +36,7 @@ OPS_PER_DRAW = 40 / 4 + 1
 # HBM bytes per k_sample launch of the first headline step, from FETCH_SIZE and WRITE_SIZE
 # calibrated against a copy of known size (profiles/k_sample_headline_256x256_52500_counters.md).
 # Set to None whenever k_sample changes until the counters are taken again.
-SAMPLE_TRAFFIC_BYTES = None
+SAMPLE_TRAFFIC_BYTES = 115.7e6
 
 
 def parse():
@@ -45,7 +45,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=256, help="pixels in the oracle's timed sampler window")
+    ap.add_argument("--cpu-pixels", type=int, default=3072, help="pixels in the oracle's timed sampler window")
     ap.add_argument("--conv", type=int, default=0, help="0 auto, 1 direct, 2 fft")
     ap.add_argument("--workload", default="headline", choices=["headline", "batch", "counters", "surrogate"],
                     help="headline: 256x256 single evaluations; batch: 256 uneven jobs per step; counters: one "
