@@ -45,11 +45,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=3072, help="pixels in the oracle's timed sampler window")
+    ap.add_argument("--cpu-pixels", type=int, default=None,
+                    help="pixels in the oracle's timed sampler window (default 3072 headline, 192 large)")
     ap.add_argument("--conv", type=int, default=0, help="0 auto, 1 direct, 2 fft")
-    ap.add_argument("--workload", default="headline", choices=["headline", "batch", "counters", "surrogate"],
-                    help="headline: 256x256 single evaluations; batch: 256 uneven jobs per step; counters: one "
-                         "headline simulation plus a copy of known size, for hardware-counter runs")
+    ap.add_argument("--workload", default="headline", choices=["headline", "large", "batch", "counters", "surrogate"],
+                    help="headline: 256x256 single evaluations; large: 512x512 at Npix = 1e6 with a 63x63 PSF and "
+                         "200x200 Hess; batch: 256 uneven jobs per step; counters: one headline simulation plus a "
+                         "copy of known size, for hardware-counter runs; surrogate: the learned screen")
     ap.add_argument("--jobs", type=int, default=256)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--train-pairs", type=int, default=16384)
@@ -138,10 +140,13 @@ def run_batch(args):
 
     sequential()
     torch.cuda.synchronize()
+    ctx.timer_enable(True)
     s0 = time.perf_counter()
     sequential()
     torch.cuda.synchronize()
     s1 = time.perf_counter()
+    seq_sample_ms, _, seq_draws = ctx.timer_read(P._lib.TIMER_SAMPLE)
+    ctx.timer_enable(False)
     identical = bool(np.array_equal(ll_seq.cpu().numpy(), ll_batch))
     elapsed = t1 - t0
     res = {
@@ -164,6 +169,9 @@ def run_batch(args):
         "sequential_evals_per_s": n / (s1 - s0),
         "speedup_vs_sequential": (n * args.steps / elapsed) / (n / (s1 - s0)),
         "batch_draws_per_s": b_units / (b_ms / 1e3) if b_ms > 0 else None,
+        "sequential_sampler_draws_per_s": seq_draws / (seq_sample_ms / 1e3) if seq_sample_ms > 0 else None,
+        "batch_sampler_ms_per_step": b_ms / max(b_n, 1),
+        "sequential_sampler_ms_per_step": seq_sample_ms,
         "identical_to_sequential": identical,
     }
     ctx.close()
@@ -381,19 +389,23 @@ def main():
     dev = torch.device("cuda:0")
     ctx = P.Context(0)
     grid = si.headline_grid()
-    model_d, obs_d = si.draw_headline_params(2)
+    large = args.workload == "large"
+    draw = si.draw_large_params if large else si.draw_headline_params
+    nh = 200 if large else 100
+    cpu_pixels = args.cpu_pixels if args.cpu_pixels else (192 if large else 3072)
+    model_d, obs_d = draw(2)
     # data image and Hess grid (untimed set-up)
-    ev = P.Evaluator(ctx, grid, obs_d.nim, obs_d.psf, dict(x0=0.0, dx=0.05, y0=0.0, dy=0.05, nx=100, ny=100))
+    ev = P.Evaluator(ctx, grid, obs_d.nim, obs_d.psf, dict(x0=0.0, dx=0.05, y0=0.0, dy=0.05, nx=nh, ny=nh))
     mags_d = ev.simulate(model_d, obs_d, args.conv).clone()
     ctx.sync()
     md = mags_d.cpu().numpy().astype(np.float64)
     fin = np.isfinite(md).all(axis=0)
-    hgrid = si.hess_grid_from_median(float(np.median((md[0] - md[1])[fin])), float(np.median(md[1][fin])), 100, 100)
+    hgrid = si.hess_grid_from_median(float(np.median((md[0] - md[1])[fin])), float(np.median(md[1][fin])), nh, nh)
     ev.hess_grid = hgrid
-    data_hess = torch.empty(100 * 100, dtype=torch.int32, device=dev)
+    data_hess = torch.empty(nh * nh, dtype=torch.int32, device=dev)
     data_mom = torch.empty(3, dtype=torch.float64, device=dev)
     ev.hess_of(mags_d, data_hess, data_mom)
-    params = [si.draw_headline_params(1000 + k) for k in range(args.steps + args.warmup)]
+    params = [draw(1000 + k) for k in range(args.steps + args.warmup)]
     # share of entries with lambda > 0 (the rest, e.g. pruned metallicities, draw nothing)
     active = [float(np.mean(P.iso_weights(m, grid)[0][grid.iso_of_entry] > 0.0)) for m, _ in params[args.warmup:]]
     logls = torch.empty(args.steps + args.warmup, dtype=torch.float64, device=dev)
@@ -421,8 +433,17 @@ def main():
     draws_per_launch = s_units / max(s_n, 1) * float(np.mean(active))
     avg_sample_s = s_ms / max(s_n, 1) / 1e3
     achieved = OPS_PER_DRAW * draws_per_launch / avg_sample_s
+    if large:
+        metric = "likelihood evals/sec (512^2 image, 52,500 isochrone points, Npix = 1e6)"
+        workload = ("512x512 px, 3 bands, 52,500 entries (7 ages x 5 [Fe/H] x 1500 masses), Npix = 1e6 (1 entry in 8 "
+                    "above the rejection threshold), log-normal dust F=0.5, 63x63 PSF (FFT), shot noise, 200x200 Hess, "
+                    "Poisson logL")
+    else:
+        metric = "likelihood evals/sec (256^2 image, 52,500 isochrone points)"
+        workload = ("256x256 px, 3 bands, 52,500 entries (7 ages x 5 [Fe/H] x 1500 masses), log Npix ~ U[2,5], "
+                    "log-normal dust F=0.5, 31x31 PSF, shot noise, 100x100 Hess, Poisson logL")
     res = {
-        "metric": "likelihood evals/sec (256^2 image, 52,500 isochrone points)",
+        "metric": metric,
         "value": evals_per_s,
         "unit": "evals/s",
         "n_gpus": 1,
@@ -434,23 +455,20 @@ def main():
         "vs_baseline": None,
         "dtype": "u32 counts / f64 sums / f32 images",
         "data": "synthetic",
-        "config": {"workload": "256x256 px, 3 bands, 52,500 entries (7 ages x 5 [Fe/H] x 1500 masses), "
-                               "log Npix ~ U[2,5], log-normal dust F=0.5, 31x31 PSF, shot noise, 100x100 Hess, "
-                               "Poisson logL",
-                   "nim": 256, "entries": 52500, "bands": 3, "psf_k": 31, "hess": [100, 100],
-                   "parallelism": "1 GPU"},
+        "config": {"workload": workload, "nim": obs_d.nim, "entries": grid.n_entries, "bands": 3,
+                   "psf_k": int(obs_d.psf.shape[-1]), "hess": [nh, nh], "parallelism": "1 GPU"},
         "poisson_draws_per_s": s_units / (s_ms / 1e3) if s_ms > 0 else None,
         "draws_per_eval": draws_per_launch,
         "kernel_ms_per_eval": {"sample": s_ms / max(s_n, 1), "conv": c_ms / max(c_n, 1), "hess": h_ms / max(h_n, 1)},
         "roofline": {"bound": "alu", "kernel": "k_sample", "achieved": achieved / 1e12,
                      "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "T lane-instr/s (VALU)",
-                     "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": SAMPLE_TRAFFIC_BYTES,
+                     "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": None if large else SAMPLE_TRAFFIC_BYTES,
                      "ops_per_draw": OPS_PER_DRAW, "avg_launch_ms": avg_sample_s * 1e3},
         "mean_logL": float(ll.mean()),
     }
     if not args.no_cpu_baseline:
         m, o = params[args.warmup]
-        res["cpu_baseline"] = cpu_baseline(grid, m, o, hgrid, args.cpu_pixels)
+        res["cpu_baseline"] = cpu_baseline(grid, m, o, hgrid, cpu_pixels)
     ctx.close()
     print(json.dumps(res), flush=True)
 

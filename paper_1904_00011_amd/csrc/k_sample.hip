@@ -172,6 +172,7 @@ constexpr uint32_t SPLIT_FIRST_BITS = 8;
 __device__ __forceinline__ uint32_t split_count(uint32_t n, uint32_t byte, int mode, uint32_t fq, uint32_t p,
                                                 uint32_t i, uint32_t k0, uint32_t k1) {
   if (mode == SPLIT_ALL) return n;
+  if (mode == SPLIT_NONE) return 0u;
   uint32_t red = 0;
   if (mode == SPLIT_HALF) {
     red = __popc(byte & low_mask(min(n, SPLIT_FIRST_BITS)));
@@ -215,13 +216,12 @@ __device__ __forceinline__ T ld_const(const PCMD_CONST T *p) {
 }
 
 template <int B, int S, bool DBG>
-__device__ __forceinline__ void sample_tile(const SampleArgs &a, int pblk, int chunk) {
+__device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int chunk) {
   constexpr int BP = B <= 2 ? 2 : 4;
   const PCMD_CONST EntryRec *rec = (const PCMD_CONST EntryRec *)a.rec;
   const PCMD_CONST uint32_t *thr = (const PCMD_CONST uint32_t *)a.thr;
   const PCMD_CONST PtrsConst *pc = (const PCMD_CONST PtrsConst *)a.pc;
   const PCMD_CONST double *fl64 = (const PCMD_CONST double *)a.fl64;
-  const uint32_t p = (uint32_t)(pblk * 256 + threadIdx.x);
   const bool live = p < (uint32_t)a.npx;
   const bool dbg = DBG && live && (int64_t)p >= a.px0 && (int64_t)p < a.px1;
 
@@ -348,7 +348,7 @@ template <int B, int S, bool DBG>
 __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
   const int nblk_px = (a.npx + 255) >> 8;
   const int chunk = blockIdx.x / nblk_px;
-  sample_tile<B, S, DBG>(a, blockIdx.x - chunk * nblk_px, chunk);
+  sample_tile<B, S, DBG>(a, (uint32_t)((blockIdx.x - chunk * nblk_px) * 256 + threadIdx.x), chunk);
 }
 
 template <int B>
@@ -390,16 +390,18 @@ hipError_t launch_reset_counter(uint32_t *counter, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Persistent batched sampler: every wave takes (job, 64-pixel block, slice) items from one
+// atomic counter until none is left, so no wave waits for another (items of one job are
+// consecutive; jobs come in the host's order).
 template <int B>
 __global__ void __launch_bounds__(256) k_sample_persistent(const BatchSampleJob *__restrict__ jobs, int n_jobs,
                                                            int total_items, uint32_t *__restrict__ counter) {
-  __shared__ int item_s;
   const PCMD_CONST BatchSampleJob *cj = (const PCMD_CONST BatchSampleJob *)jobs;
+  const uint32_t lane = threadIdx.x & 63u;
   for (;;) {
-    if (threadIdx.x == 0) item_s = (int)atomicAdd(counter, 1u);
-    __syncthreads();
-    const int item = __builtin_amdgcn_readfirstlane(item_s);
-    __syncthreads();
+    uint32_t got = 0u;
+    if (lane == 0) got = atomicAdd(counter, 1u);
+    const int item = (int)__builtin_amdgcn_readfirstlane(got);
     if (item >= total_items) break;
     // job owning the item: last job with item0 <= item (binary search over the table)
     int lo = 0, hi = n_jobs - 1;
@@ -412,14 +414,11 @@ __global__ void __launch_bounds__(256) k_sample_persistent(const BatchSampleJob 
     }
     const int j = __builtin_amdgcn_readfirstlane(lo);
     const int local = item - cj[j].item0;
-    const int pblocks = cj[j].pblocks;
+    const int pblocks = cj[j].pblocks;  // 64-pixel blocks of the job
     const int chunk = local / pblocks;
     const int pblk = local - chunk * pblocks;
     const SampleArgs a = ld_const(&cj[j].a);
-    if (a.S == 2)
-      sample_tile<B, 2, false>(a, pblk, chunk);
-    else
-      sample_tile<B, 1, false>(a, pblk, chunk);
+    sample_tile<B, 2, false>(a, (uint32_t)(pblk * 64) + lane, chunk);  // batch jobs always carry two streams
   }
 }
 

@@ -125,11 +125,14 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
     ji.N = jobs[j].obs.nim;
     ji.npx = ji.N * ji.N;
     ji.K = jobs[j].obs.psf_k;
-    ji.S = split_mode_of(&jobs[j].obs) == SPLIT_NONE ? 1 : 2;
+    // Every batch job keeps both partial streams (unreddened, reddened), so the persistent
+    // sampler has one instantiation; a job without a split draws no reddened stars, its second
+    // stream holds zeros and the reduction's sums are unchanged (c + 0 = c).
+    ji.S = 2;
     ji.nchunks = (ji.E + CHUNK - 1) / CHUNK;
-    ji.pblocks = (ji.npx + 255) / 256;
+    ji.pblocks = (ji.npx + 63) / 64;  // one persistent-sampler item = one wave's 64 pixels x one slice
     ji.items = ji.nchunks * ji.pblocks;
-    ji.cost = (double)ji.npx * (double)ji.E * (ji.S == 2 ? 1.3 : 1.0);
+    ji.cost = (double)ji.npx * (double)ji.E * (split_mode_of(&jobs[j].obs) == SPLIT_NONE ? 1.0 : 1.3);
     ji.o_rec = n_rec;
     ji.o_thr = n_thr;
     ji.o_pc = n_pc;

@@ -251,6 +251,16 @@ def draw_headline_params(seed: int, log_npix=None):
     return model, obs
 
 
+def draw_large_params(seed: int):
+    """Parameters of one 512x512 evaluation at Npix = 1e6 (most bright entries above the
+    rejection threshold): the headline priors for SFH shape, metallicity, dust and distance,
+    with 63x63 Gaussian PSFs (sigma = 3.2, 3.6, 4.0 px); used with a 200 x 200 Hess."""
+    model, obs = draw_headline_params(seed, log_npix=6.0)
+    obs.nim = 512
+    obs.psf = psf_stack(63, (3.2, 3.6, 4.0))
+    return model, obs
+
+
 def hess_grid_from_median(mx: float, my: float, nx: int = 100, ny: int = 100, d: float = 0.05):
     """Hess origin: the data's median (colour, magnitude) floored to a multiple
     of the bin width, minus half the grid extent."""

@@ -320,6 +320,38 @@ def test_headline_full_size_sampled(ctx):
     assert hg.sum() == npx
 
 
+def test_large_config_sampled(ctx):
+    """512x512 image, 52,500 entries at Npix = 1e6 (one entry in eight above the rejection
+    threshold), 63x63 PSF on the FFT path, 200x200 Hess: counts, splits and fluxes on sampled
+    pixels against the oracle, the FFT and direct paths against each other over the whole image,
+    flux conservation and the Hess total."""
+    G = si.headline_grid()
+    model, obs = si.draw_large_params(3000)
+    lam, _, f32 = oe.build_entries(model, G)
+    N = obs.nim
+    npx = N * N
+    _print_case("large_full_size", nim=N, E=len(lam), ptrs=int((lam >= 10).sum()), K=obs.psf.shape[-1])
+    assert (lam >= 10).sum() > 5000
+    for px0 in (0, 200000):
+        g = pu.gpu_simulate(ctx, lam, f32, obs, conv_path=2, window=(px0, px0 + 12))
+        Fo, s = osamp.simulate_flux(lam, f32, obs, px0, px0 + 12, want_counts=True)
+        assert not pu.explain_count_mismatches(lam, obs.seed, px0, g["counts"], s["counts"])
+        assert np.array_equal(g["red"], s["red"])
+        assert np.max(pu.rel_err(g["flux_pre"][:, px0:px0 + 12], Fo)) <= pu.FLUX_RTOL
+    for b in range(3):
+        assert g["flux_psf"][b].astype(np.float64).sum() == pytest.approx(g["flux_pre"][b].astype(np.float64).sum(), rel=1e-5)
+    d = pu.gpu_simulate(ctx, lam, f32, obs, conv_path=1)
+    assert np.array_equal(d["flux_pre"], g["flux_pre"])
+    assert np.max(pu.rel_err(d["flux_psf"], g["flux_psf"])) <= 1e-6
+    m = g["mags"].astype(np.float64)
+    fin = np.isfinite(m).all(axis=0)
+    hgrid = si.hess_grid_from_median(float(np.median((m[0] - m[1])[fin])), float(np.median(m[1][fin])), 200, 200)
+    hg, mg = pu.gpu_hess(ctx, g["mags"], hgrid)
+    assert hg.sum() == npx
+    ho, mo = oh.hess(m, hgrid)
+    assert np.array_equal(hg, ho)  # identical magnitudes bin identically
+
+
 @pytest.mark.parametrize("N,K", [(64, 5), (64, 31), (64, 63), (128, 31), (32, 1)])
 def test_fft_path_against_oracle(ctx, N, K):
     """FFT convolution (power-of-two sides) against the oracle's direct periodic sum."""
