@@ -36,7 +36,7 @@ OPS_PER_DRAW = 40 / 4 + 1
 # HBM bytes per k_sample launch of the first headline step, from FETCH_SIZE and WRITE_SIZE
 # calibrated against a copy of known size (profiles/k_sample_headline_256x256_52500_counters.md).
 # Set to None whenever k_sample changes until the counters are taken again.
-SAMPLE_TRAFFIC_BYTES = 115.7e6
+SAMPLE_TRAFFIC_BYTES = None
 
 
 def parse():
@@ -168,9 +168,9 @@ def run_batch(args):
                    "autotune_ms": cand_ms, "draws_per_step": b_units / max(b_n, 1)},
         "sequential_evals_per_s": n / (s1 - s0),
         "speedup_vs_sequential": (n * args.steps / elapsed) / (n / (s1 - s0)),
-        "batch_draws_per_s": b_units / (b_ms / 1e3) if b_ms > 0 else None,
-        "sequential_sampler_draws_per_s": seq_draws / (seq_sample_ms / 1e3) if seq_sample_ms > 0 else None,
-        "batch_sampler_ms_per_step": b_ms / max(b_n, 1),
+        # GPU time of one batched run (prep, persistent sampler, reduction, PSF, noise, Hess and
+        # likelihood of all jobs) and the sampler kernels alone of the sequential calls
+        "batch_gpu_ms_per_step": b_ms / max(b_n, 1),
         "sequential_sampler_ms_per_step": seq_sample_ms,
         "identical_to_sequential": identical,
     }

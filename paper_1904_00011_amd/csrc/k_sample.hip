@@ -247,17 +247,21 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
   static_assert(GRP == 8, "two groups per 16-entry block");
   for (int j = 0, gi = slice_group(0); gi < ngrp; ++j, gi = slice_group(j)) {
     const int g0 = gi * GRP;
-    const GroupRec gr = ld_const(grp + gi);
+    const PCMD_CONST GroupRec *gr = grp + gi;
     // at small lambda most groups end after two Philox blocks and eight compares, without
     // touching the entry records
-    if (gr.flags == 0u) continue;  // no entry of the group has stars
+    const uint32_t flags = gr->flags;
+    if (flags == 0u) continue;  // no entry of the group has stars
     // inversion words of the group's two quads: counters (p, i / 4, TAG_MAIN, 0)
     const u4 wa = philox10(p, (uint32_t)(2 * gi), TAG_MAIN, 0u, a.k0, a.k1);
     const u4 wb = philox10(p, (uint32_t)(2 * gi + 1), TAG_MAIN, 0u, a.k0, a.k1);
-    if (!(gr.flags & GRP_PTRS) &&
-        (__ballot(wa.x > gr.t0m1[0]) | __ballot(wa.y > gr.t0m1[1]) | __ballot(wa.z > gr.t0m1[2]) |
-         __ballot(wa.w > gr.t0m1[3]) | __ballot(wb.x > gr.t0m1[4]) | __ballot(wb.y > gr.t0m1[5]) |
-         __ballot(wb.z > gr.t0m1[6]) | __ballot(wb.w > gr.t0m1[7])) == 0ull)
+    // the first thresholds are loaded only now: held across the Philox rounds they pushed the
+    // scalar register file into spilling inside this loop
+    __builtin_amdgcn_sched_barrier(0);
+    if (!(flags & GRP_PTRS) &&
+        (__ballot(wa.x > gr->t0m1[0]) | __ballot(wa.y > gr->t0m1[1]) | __ballot(wa.z > gr->t0m1[2]) |
+         __ballot(wa.w > gr->t0m1[3]) | __ballot(wb.x > gr->t0m1[4]) | __ballot(wb.y > gr->t0m1[5]) |
+         __ballot(wb.z > gr->t0m1[6]) | __ballot(wb.w > gr->t0m1[7])) == 0ull)
       continue;
 #pragma unroll 1
     for (int h = 0; h < 2; ++h) {
@@ -265,27 +269,26 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
       const u4 w = h ? wb : wa;
       uint32_t n0[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) n0[q] = word_of(w, q) > (h ? gr.t0m1[4 + q] : gr.t0m1[q]) ? 1u : 0u;
-      EntryRec r[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) r[q] = ld_const(rec + q0 + q);  // padded to a multiple of GRP
+      for (int q = 0; q < 4; ++q) n0[q] = word_of(w, q) > gr->t0m1[4 * h + q] ? 1u : 0u;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const uint32_t i = (uint32_t)(q0 + q);
+        // one record at a time keeps the scalar registers of the loop below the spill point
+        const EntryRec rq = ld_const(rec + i);  // padded to a multiple of GRP
         uint32_t n = 0;
-        const uint32_t kind = r[q].kk & 0xFFu;
+        const uint32_t kind = rq.kk & 0xFFu;
         if (kind == KIND_INV) {
           // n = #{k < K : T_k <= u}, walking up while any lane of the wave is still above
           const uint32_t u = word_of(w, q);
-          const uint32_t K = r[q].kk >> 8;
+          const uint32_t K = rq.kk >> 8;
           n = n0[q];
           if (!wave_any(n != 0u)) continue;
           if (K > 1) {
-            uint32_t c = u >= r[q].T[1] ? 1u : 0u;
+            uint32_t c = u >= rq.T[1] ? 1u : 0u;
             if (wave_any(c != 0u)) {
               n += c;
               if (K > 2) {
-                c = u >= r[q].T[2] ? 1u : 0u;
+                c = u >= rq.T[2] ? 1u : 0u;
                 if (wave_any(c != 0u)) {
                   n += c;
                   const PCMD_CONST uint32_t *t = thr + (size_t)i * THR_STRIDE;
