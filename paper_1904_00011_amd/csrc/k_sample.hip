@@ -169,13 +169,14 @@ __device__ __forceinline__ uint32_t ptrs_draw(const PtrsConst &c, uint32_t p, ui
 // Other fractions: star s compares word s mod 4 of (p, i, TAG_SPLIT_X, s / 4) with fq.
 constexpr uint32_t SPLIT_FIRST_BITS = 8;
 
-__device__ __forceinline__ uint32_t split_count(uint32_t n, uint32_t byte, int mode, uint32_t fq, uint32_t p,
-                                                uint32_t i, uint32_t k0, uint32_t k1) {
+__device__ __forceinline__ uint32_t split_count(uint32_t n, uint32_t word, uint32_t shift, int mode, uint32_t fq,
+                                                uint32_t p, uint32_t i, uint32_t k0, uint32_t k1) {
   if (mode == SPLIT_ALL) return n;
   if (mode == SPLIT_NONE) return 0u;
   uint32_t red = 0;
   if (mode == SPLIT_HALF) {
-    red = __popc(byte & low_mask(min(n, SPLIT_FIRST_BITS)));
+    // the entry's byte sits at bit `shift` of `word`; its low min(n, 8) bits decide the first stars
+    red = __popc(__builtin_amdgcn_ubfe(word, shift, min(n, SPLIT_FIRST_BITS)));
     const uint32_t extra = n > SPLIT_FIRST_BITS ? n - SPLIT_FIRST_BITS : 0u;
     for (uint32_t j = 0; wave_any(extra > 128u * j); ++j) {
       const u4 x = philox10(p, i, TAG_SPLIT_X, j, k0, k1);
@@ -263,10 +264,17 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
          __ballot(wa.w > gr->t0m1[3]) | __ballot(wb.x > gr->t0m1[4]) | __ballot(wb.y > gr->t0m1[5]) |
          __ballot(wb.z > gr->t0m1[6]) | __ballot(wb.w > gr->t0m1[7])) == 0ull)
       continue;
-#pragma unroll 1
+    // the split bits of the group's 16-entry block: a slow group almost always has a star to
+    // split, and the two groups of a block share them
+    if (S == 2 && a.split_mode == SPLIT_HALF && split_blk != (gi >> 1)) {
+      sw = philox10(p, (uint32_t)(gi >> 1), TAG_SPLIT, 0u, a.k0, a.k1);
+      split_blk = gi >> 1;
+    }
+#pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int q0 = g0 + 4 * h;  // first entry of the quad
-      const u4 w = h ? wb : wa;
+      const u4 &w = h ? wb : wa;
+      const uint32_t sq = word_of(sw, 2 * (gi & 1) + h);  // the quad's word of the split block
       uint32_t n0[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) n0[q] = word_of(w, q) > gr->t0m1[4 * h + q] ? 1u : 0u;
@@ -310,15 +318,7 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
         if (!wave_any(n != 0u)) continue;
         uint32_t red = 0u;
         if (S == 2) {
-          uint32_t byte = 0u;
-          if (a.split_mode == SPLIT_HALF) {
-            if (split_blk != (q0 >> 4)) {
-              sw = philox10(p, (uint32_t)(q0 >> 4), TAG_SPLIT, 0u, a.k0, a.k1);
-              split_blk = q0 >> 4;
-            }
-            byte = (word_of(sw, (q0 & 15) >> 2) >> (8 * q)) & 0xFFu;
-          }
-          red = split_count(n, byte, a.split_mode, a.split_q, p, i, a.k0, a.k1);
+          red = split_count(n, sq, 8u * q, a.split_mode, a.split_q, p, i, a.k0, a.k1);
         }
         const PCMD_CONST double *f = fl64 + (size_t)i * BP;
         const double dc = (double)(n - red);
