@@ -285,7 +285,7 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
         const EntryRec rq = ld_const(rec + i);  // padded to a multiple of GRP
         uint32_t n = 0;
         const uint32_t kind = rq.kk & 0xFFu;
-        if (kind == KIND_INV) {
+        if (kind != KIND_PTRS) {  // inversion; a KIND_ZERO entry never passes its first threshold
           // n = #{k < K : T_k <= u}, walking up while any lane of the wave is still above
           const uint32_t u = word_of(w, q);
           const uint32_t K = rq.kk >> 8;
@@ -309,11 +309,9 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
               }
             }
           }
-        } else if (kind == KIND_PTRS) {
+        } else {
           const PtrsConst c = ld_const(pc + i);
           n = ptrs_draw(c, p, i, a.k0, a.k1, a.lnfact, ptrs_failed);
-        } else {
-          continue;
         }
         if (!wave_any(n != 0u)) continue;
         uint32_t red = 0u;
@@ -321,10 +319,14 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
           red = split_count(n, sq, 8u * q, a.split_mode, a.split_q, p, i, a.k0, a.k1);
         }
         const PCMD_CONST double *f = fl64 + (size_t)i * BP;
-        const double dc = (double)(n - red);
+        // a stream with no star in any lane adds exact zeros: skipped
+        const uint32_t nc = n - red;
+        if (S == 1 || wave_any(nc != 0u)) {
+          const double dc = (double)nc;
 #pragma unroll
-        for (int b = 0; b < B; ++b) acc_c[b] = fma(dc, f[b], acc_c[b]);
-        if (S == 2) {
+          for (int b = 0; b < B; ++b) acc_c[b] = fma(dc, f[b], acc_c[b]);
+        }
+        if (S == 2 && wave_any(red != 0u)) {
           const double dr = (double)red;
 #pragma unroll
           for (int b = 0; b < B; ++b) acc_r[b] = fma(dr, f[b], acc_r[b]);

@@ -63,7 +63,7 @@ int validate_sim(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, const char
 
 extern "C" {
 
-const char *pcmd_version(void) { return "pcmd gfx950 HIP 1.0 (philox4x32-10, chunk 2048)"; }
+const char *pcmd_version(void) { return "pcmd gfx950 HIP 1.1 (philox4x32-10, 1024-entry slices)"; }
 
 int pcmd_create(pcmd_ctx **out, int hip_device) {
   if (!out) return PCMD_E_INVAL;

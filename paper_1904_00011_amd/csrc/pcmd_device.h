@@ -19,7 +19,7 @@ constexpr uint32_t TAG_MAIN = 0, TAG_SPLIT = 1, TAG_SPLIT_X = 2, TAG_PTRS = 3, T
 // Entry kinds written by the preparation kernel.
 constexpr uint32_t KIND_ZERO = 0, KIND_INV = 1, KIND_PTRS = 2;
 constexpr int THR_STRIDE = 64;       // thresholds per entry slot (K <= 63)
-constexpr int CHUNK = 2048;          // canonical accumulation chunk (entries)
+constexpr int CHUNK = 1024;          // entries per slice (the number of slices is ceil(E / CHUNK))
 constexpr int PTRS_MAX_ATTEMPTS = 64;
 
 struct u4 { uint32_t x, y, z, w; };

@@ -156,7 +156,7 @@ def _headline_lam(log_npix, seed=1000, stride=1):
 
 
 def test_headline_grid_dust_ptrs_fft_sized_psf(ctx):
-    """Headline grid (52,500 entries, 26 chunks, ragged last chunk) at Npix=1e5 (PTRS entries), log-normal dust
+    """Headline grid (52,500 entries, 52 slices, ragged last block) at Npix=1e5 (PTRS entries), log-normal dust
     with F=1/2, shot noise, 31x31 PSF, on a 40x40 image (ragged pixel blocks)."""
     G, lam, f32, obs = _headline_lam(5.0)
     obs.nim = 40
