@@ -153,75 +153,97 @@ hipError_t launch_hess_job(const HessArgs *table, int j, int64_t npx, int nbins,
 }
 
 // ---------------------------------------------------------------------------------------
-// Log-likelihood: one block, fixed-order reduction in FP64.
+// Log-likelihood: one thread per bin over ceil(nbins / LL_THREADS) blocks, each block's sum
+// written to part[block]; a second one-block kernel adds the block sums in block order (fixed
+// order, so the result does not depend on scheduling) and the mean-colour / mean-magnitude term.
+// Every block recomputes the totals N_m, N_d itself: integer sums are exact, so they agree.
 // ---------------------------------------------------------------------------------------
-constexpr int LL_THREADS = 1024;
+// Fixed-order sum over the block (tree in LDS).
+template <typename T>
+__device__ __forceinline__ T block_sum_ordered(T v, T *sh) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int s = LL_THREADS / 2; s > 0; s >>= 1) {
+    if (t < s) sh[t] = sh[t] + sh[t + s];
+    __syncthreads();
+  }
+  const T r = sh[0];
+  __syncthreads();
+  return r;
+}
 
-__device__ __forceinline__ void loglike_body(const LoglikeArgs &a) {
+__device__ __forceinline__ void loglike_bins_body(const LoglikeArgs &a, int blk) {
   const uint32_t *__restrict__ hm = a.hm;
   const uint32_t *__restrict__ hd = a.hd;
   const int nbins = a.nbins, mode = a.mode;
   const double eps = a.eps;
-  __shared__ double red[LL_THREADS];
-  __shared__ unsigned long long tot[2];
+  __shared__ unsigned long long shu[LL_THREADS];
+  __shared__ double shd[LL_THREADS];
   const int t = threadIdx.x;
-  if (t < 2) tot[t] = 0ull;
-  __syncthreads();
   unsigned long long sm = 0, sd = 0;
   for (int j = t; j < nbins; j += LL_THREADS) {
     sm += hm[j];
     sd += hd[j];
   }
-  atomicAdd(&tot[0], sm);
-  atomicAdd(&tot[1], sd);
-  __syncthreads();
-  const double Nm = (double)tot[0], Nd = (double)tot[1];
+  const double Nm = (double)block_sum_ordered(sm, shu);
+  const double Nd = (double)block_sum_ordered(sd, shu);
   double acc = 0.0;
-  for (int j = t; j < nbins; j += LL_THREADS) {
+  const int j = blk * LL_THREADS + t;
+  if (j < nbins) {
     const double m = (double)hm[j], d = (double)hd[j];
     if (mode == PCMD_LL_POISSON) {
       const double lam = Nd * (m + eps) / (Nm + eps * (double)nbins);
-      acc += d * log(lam) - lam - lgamma(d + 1.0);
+      acc = d * log(lam) - lam - lgamma(d + 1.0);
     } else if (mode == PCMD_LL_GAUSS_PAPER) {
       const double mh = m * Nd / Nm;
       const double sig = fmax(sqrt(d + mh), 2.0);
       const double df = d - mh;
-      acc -= df * df / (2.0 * sig * sig);
+      acc = -df * df / (2.0 * sig * sig);
     } else {
       const double sig = fmax(sqrt(d * d + m * m), 2.0);
       const double df = d / Nd - m / Nm;
-      acc -= df * df / (2.0 * sig * sig);
+      acc = -df * df / (2.0 * sig * sig);
     }
   }
-  red[t] = acc;
-  __syncthreads();
-  for (int s = LL_THREADS / 2; s > 0; s >>= 1) {
-    if (t < s) red[t] = red[t] + red[t + s];
-    __syncthreads();
-  }
-  if (t == 0) {
-    double r = red[0];
-    if (mode != PCMD_LL_POISSON) {
-      const double Cm = a.mom_m[0] / a.mom_m[2], Mm = a.mom_m[1] / a.mom_m[2];
-      const double Cd = a.mom_d[0] / a.mom_d[2], Md = a.mom_d[1] / a.mom_d[2];
-      r += -(Cd - Cm) * (Cd - Cm) / (2.0 * 0.05 * 0.05) - (Md - Mm) * (Md - Mm) / (2.0 * 0.05 * 0.05);
-    }
-    a.out[0] = r;
-  }
+  const double bsum = block_sum_ordered(acc, shd);
+  if (t == 0) a.part[blk] = bsum;
 }
 
-__global__ void __launch_bounds__(LL_THREADS) k_loglike(LoglikeArgs a) { loglike_body(a); }
-__global__ void __launch_bounds__(LL_THREADS) k_loglike_job(const LoglikeArgs *__restrict__ t, int j) {
-  const LoglikeArgs a = t[j];
-  loglike_body(a);
+__device__ __forceinline__ void loglike_final_body(const LoglikeArgs &a) {
+  if (threadIdx.x != 0) return;
+  const int nb = loglike_blocks(a.nbins);
+  double r = 0.0;
+  for (int b = 0; b < nb; ++b) r += a.part[b];
+  if (a.mode != PCMD_LL_POISSON) {
+    const double Cm = a.mom_m[0] / a.mom_m[2], Mm = a.mom_m[1] / a.mom_m[2];
+    const double Cd = a.mom_d[0] / a.mom_d[2], Md = a.mom_d[1] / a.mom_d[2];
+    r += -(Cd - Cm) * (Cd - Cm) / (2.0 * 0.05 * 0.05) - (Md - Mm) * (Md - Mm) / (2.0 * 0.05 * 0.05);
+  }
+  a.out[0] = r;
+}
+
+__global__ void __launch_bounds__(LL_THREADS) k_loglike_bins(LoglikeArgs a) { loglike_bins_body(a, blockIdx.x); }
+__global__ void __launch_bounds__(64) k_loglike_final(LoglikeArgs a) { loglike_final_body(a); }
+// batched: grid.y (bins) / grid.x (final) runs over the jobs of a descriptor table
+__global__ void __launch_bounds__(LL_THREADS) k_loglike_bins_jobs(const LoglikeArgs *__restrict__ t) {
+  const LoglikeArgs a = t[blockIdx.y];
+  loglike_bins_body(a, blockIdx.x);
+}
+__global__ void __launch_bounds__(64) k_loglike_final_jobs(const LoglikeArgs *__restrict__ t) {
+  const LoglikeArgs a = t[blockIdx.x];
+  loglike_final_body(a);
 }
 
 hipError_t launch_loglike(const LoglikeArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_loglike, dim3(1), dim3(LL_THREADS), 0, s, a);
+  hipLaunchKernelGGL(k_loglike_bins, dim3((unsigned)loglike_blocks(a.nbins)), dim3(LL_THREADS), 0, s, a);
+  hipLaunchKernelGGL(k_loglike_final, dim3(1), dim3(64), 0, s, a);
   return hipGetLastError();
 }
-hipError_t launch_loglike_job(const LoglikeArgs *table, int j, hipStream_t s) {
-  hipLaunchKernelGGL(k_loglike_job, dim3(1), dim3(LL_THREADS), 0, s, table, j);
+hipError_t launch_loglike_jobs(const LoglikeArgs *table, int n_jobs, int nbins, hipStream_t s) {
+  hipLaunchKernelGGL(k_loglike_bins_jobs, dim3((unsigned)loglike_blocks(nbins), (unsigned)n_jobs), dim3(LL_THREADS), 0,
+                     s, table);
+  hipLaunchKernelGGL(k_loglike_final_jobs, dim3((unsigned)n_jobs), dim3(64), 0, s, table);
   return hipGetLastError();
 }
 

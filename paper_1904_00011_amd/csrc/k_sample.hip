@@ -441,31 +441,53 @@ hipError_t launch_sample_persistent(const BatchSampleJob *jobs, int n_jobs, int 
 }
 
 // ---------------------------------------------------------------------------------------
-// Chunk reduction + epilogue: F_b = 10^(-0.4 mu_d) (F_clr_b + F_red_b 10^(-0.4 R_b E_p)).
+// Slice reduction + epilogue: F_b = 10^(-0.4 mu_d) (F_clr_b + F_red_b 10^(-0.4 R_b E_p)).
+// One thread per (band, pixel); the partials of all slices are loaded in batches of eight
+// before they are added, in ascending slice order (the order fixes the rounding).
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ void reduce_body(const ReduceArgs &a, int p) {
-  if (p >= a.npx) return;
-  double ebv = 0.0;
-  if (a.dust_model == PCMD_DUST_SCREEN) {
-    ebv = exp10(a.dust_mu);
-  } else if (a.dust_model == PCMD_DUST_LOGNORMAL) {
-    const u4 w = philox10((uint32_t)p, 0u, TAG_DUST, 0u, a.k0, a.k1);
-    ebv = exp10(a.dust_mu + a.dust_sigma * box_muller(w.x, w.y));
-  }
-  const size_t plane = (size_t)a.npx;
-  for (int b = 0; b < a.B; ++b) {
-    double c = 0.0, r = 0.0;
-    for (int ch = 0; ch < a.nchunks; ++ch) {
-      c += a.part[((size_t)(ch * a.S + 0) * a.B + b) * plane + p];
-      if (a.S == 2) r += a.part[((size_t)(ch * a.S + 1) * a.B + b) * plane + p];
+constexpr int RED_BATCH = 8;
+
+__device__ __forceinline__ void reduce_body(const ReduceArgs &a, int idx) {
+  const int npx = a.npx;
+  if (idx >= a.B * npx) return;
+  const int b = idx / npx, p = idx - b * npx;
+  const size_t plane = (size_t)npx;
+  const size_t step = (size_t)a.S * a.B * plane;  // from one slice to the next
+  const double *pc = a.part + (size_t)b * plane + p;
+  const double *pr = pc + (size_t)a.B * plane;  // reddened stream (S == 2)
+  double c = 0.0, r = 0.0;
+  int ch = 0;
+  for (; ch + RED_BATCH <= a.nchunks; ch += RED_BATCH) {
+    double xc[RED_BATCH], xr[RED_BATCH];
+#pragma unroll
+    for (int k = 0; k < RED_BATCH; ++k) {
+      xc[k] = pc[(size_t)(ch + k) * step];
+      xr[k] = a.S == 2 ? pr[(size_t)(ch + k) * step] : 0.0;
     }
-    double F;
-    if (a.dust_model == PCMD_DUST_NONE)
-      F = a.dist * (c + r);
-    else
-      F = a.dist * (c + r * exp10(-0.4 * a.dust_R[b] * ebv));
-    a.F[(size_t)b * plane + p] = (float)F;
+#pragma unroll
+    for (int k = 0; k < RED_BATCH; ++k) {
+      c += xc[k];
+      r += xr[k];
+    }
   }
+  for (; ch < a.nchunks; ++ch) {
+    c += pc[(size_t)ch * step];
+    if (a.S == 2) r += pr[(size_t)ch * step];
+  }
+  double F;
+  if (a.dust_model == PCMD_DUST_NONE) {
+    F = a.dist * (c + r);
+  } else {
+    double ebv;
+    if (a.dust_model == PCMD_DUST_SCREEN) {
+      ebv = exp10(a.dust_mu);
+    } else {
+      const u4 w = philox10((uint32_t)p, 0u, TAG_DUST, 0u, a.k0, a.k1);
+      ebv = exp10(a.dust_mu + a.dust_sigma * box_muller(w.x, w.y));
+    }
+    F = a.dist * (c + r * exp10(-0.4 * a.dust_R[b] * ebv));
+  }
+  a.F[(size_t)b * plane + p] = (float)F;
 }
 
 __global__ void __launch_bounds__(256) k_reduce(ReduceArgs a) { reduce_body(a, blockIdx.x * blockDim.x + threadIdx.x); }
@@ -475,11 +497,11 @@ __global__ void __launch_bounds__(256) k_reduce_job(const ReduceArgs *__restrict
 }
 
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce, dim3((a.npx + 255) / 256), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_reduce, dim3((a.B * a.npx + 255) / 256), dim3(256), 0, s, a);
   return hipGetLastError();
 }
-hipError_t launch_reduce_job(const ReduceArgs *table, int j, int npx, hipStream_t s) {
-  hipLaunchKernelGGL(k_reduce_job, dim3((npx + 255) / 256), dim3(256), 0, s, table, j);
+hipError_t launch_reduce_job(const ReduceArgs *table, int j, int npx, int B, hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_job, dim3((B * npx + 255) / 256), dim3(256), 0, s, table, j);
   return hipGetLastError();
 }
 

@@ -111,7 +111,7 @@ void pcmd_destroy(pcmd_ctx *c) {
   batch_destroy(c);
   Buf *bufs[] = {&c->rec,     &c->thr,     &c->pc,      &c->fl64,    &c->part,     &c->F,       &c->G,
                  &c->mom_part, &c->fft,    &c->mlp_act, &c->mlp_pre, &c->mlp_dza, &c->mlp_dzb, &c->mlp_grad,
-                 &c->mlp_part, &c->mlp_ws};
+                 &c->mlp_part, &c->mlp_ws, &c->ll_part};
   for (Buf *b : bufs) release(*b);
   if (c->lnfact) (void)hipFree(c->lnfact);
   if (c->status) (void)hipFree(c->status);
@@ -478,7 +478,9 @@ int pcmd_loglike(pcmd_ctx *c, const uint32_t *hm, const uint32_t *hd, int32_t nb
   if (mode == PCMD_LL_POISSON && !(eps > 0.0 && isfinite(eps))) return fail(c, PCMD_E_INVAL, "pcmd_loglike: eps must be > 0");
   if (mode != PCMD_LL_POISSON && (!mom_m || !mom_d)) return fail(c, PCMD_E_INVAL, "pcmd_loglike: moments needed");
   DeviceGuard dg(c->device);
-  LoglikeArgs a{hm, hd, nbins, mode, mom_m, mom_d, eps, out};
+  int r;
+  if ((r = ensure(c, c->ll_part, (size_t)loglike_blocks(nbins) * 8, "likelihood partials"))) return r;
+  LoglikeArgs a{hm, hd, nbins, mode, mom_m, mom_d, eps, out, (double *)c->ll_part.p};
   hipError_t e = launch_loglike(a, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(c, e, "k_loglike");
   c->err.clear();

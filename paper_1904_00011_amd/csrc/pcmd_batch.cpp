@@ -33,7 +33,7 @@ struct pcmd_batch_plan {
   int n_jobs = 0, B = 0, nbins = 0, total_items = 0, wg = 0, order_mode = 0;
   std::vector<JobInfo> info;
   std::vector<int> order;  // sampler table position -> job
-  Buf rec, thr, pc, fl, part, F, G, mags, hess, mom, mom_part, counters, desc;
+  Buf rec, thr, pc, fl, part, F, G, mags, hess, mom, mom_part, ll_part, counters, desc;
   void *desc_host = nullptr;
   size_t desc_bytes = 0;
   size_t o_prep = 0, o_samp = 0, o_red = 0, o_conv = 0, o_noise = 0, o_hess = 0, o_ll = 0;
@@ -51,7 +51,7 @@ static void plan_free_device(pcmd_batch_plan *p) {
   if (p->graph) (void)hipGraphDestroy(p->graph);
   p->exec = nullptr;
   p->graph = nullptr;
-  Buf *bufs[] = {&p->rec, &p->thr, &p->pc, &p->fl, &p->part, &p->F, &p->G, &p->mags, &p->hess, &p->mom, &p->mom_part,
+  Buf *bufs[] = {&p->rec, &p->thr, &p->pc, &p->fl, &p->part, &p->F, &p->G, &p->mags, &p->hess, &p->mom, &p->mom_part, &p->ll_part,
                  &p->counters, &p->desc};
   for (Buf *b : bufs) release(*b);
   if (p->desc_host) (void)hipHostFree(p->desc_host);
@@ -165,6 +165,8 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
   if ((r = ensure(c, p->hess, (size_t)n_jobs * p->nbins * 4, "batch Hess"))) return r;
   if ((r = ensure(c, p->mom, (size_t)n_jobs * 3 * 8, "batch moments"))) return r;
   if ((r = ensure(c, p->mom_part, (size_t)n_jobs * hess_max_blocks() * 3 * 8, "batch moment partials"))) return r;
+  if ((r = ensure(c, p->ll_part, (size_t)n_jobs * loglike_blocks(g->nx * g->ny) * 8, "batch likelihood partials")))
+    return r;
   if ((r = ensure(c, p->counters, (size_t)(n_jobs + 1) * 4, "batch counters"))) return r;
   hipError_t e = hipMemsetAsync(p->counters.p, 0, (size_t)(n_jobs + 1) * 4, p->stream);  // outside any graph
   if (e != hipSuccess) return hip_fail(c, e, "clearing batch counters");
@@ -280,7 +282,8 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
     hh.moments = (double *)p->mom.p + (size_t)j * 3;
     hh.use_lds = hess_use_lds(p->nbins);
     ha[j] = hh;
-    la[j] = LoglikeArgs{hh.hess, hess_data, p->nbins, mode, hh.moments, mom_data, eps, logl_out + j};
+    la[j] = LoglikeArgs{hh.hess, hess_data,    p->nbins,    mode, hh.moments, mom_data, eps, logl_out + j,
+                        (double *)p->ll_part.p + (size_t)j * loglike_blocks(p->nbins)};
   }
   for (int t = 0; t < p->n_jobs; ++t) {
     const int j = p->order[t];
@@ -332,7 +335,7 @@ static hipError_t enqueue(pcmd_ctx *c, pcmd_batch_plan *p, hipStream_t s) {
     e = launch_sample_persistent(sa, p->n_jobs, p->total_items, p->B, persist, c->n_cu * p->wg, s);
   for (int j = 0; j < p->n_jobs && e == hipSuccess; ++j) {
     const JobInfo &ji = p->info[j];
-    e = launch_reduce_job(ra, j, ji.npx, s);
+    e = launch_reduce_job(ra, j, ji.npx, ji.B, s);
     if (e == hipSuccess && ji.K > 1) e = launch_psf_check_job(ca, j, ji.B, s);
     if (e == hipSuccess && ji.K > 1) e = launch_conv_direct_job(ca, j, ji.B, ji.N, ji.K, s);
     if (e == hipSuccess) e = launch_noise_mag_job(na, j, ji.npx, s);
@@ -340,8 +343,8 @@ static hipError_t enqueue(pcmd_ctx *c, pcmd_batch_plan *p, hipStream_t s) {
   for (int j = 0; j < p->n_jobs && e == hipSuccess; ++j) {
     e = launch_hess_clear_job(ha, j, p->nbins, s);
     if (e == hipSuccess) e = launch_hess_job(ha, j, p->info[j].npx, p->nbins, s);
-    if (e == hipSuccess) e = launch_loglike_job(la, j, s);
   }
+  if (e == hipSuccess) e = launch_loglike_jobs(la, p->n_jobs, p->nbins, s);
   return e;
 }
 

@@ -127,6 +127,7 @@ struct LoglikeArgs {
   const double *mom_m, *mom_d;
   double eps;
   double *out;
+  double *part;  // [loglike_blocks(nbins)] block sums
 };
 
 // Sampler job of the persistent batched kernel: its tiles are items [item0, item0 + items).
@@ -144,7 +145,7 @@ hipError_t launch_sample_persistent(const BatchSampleJob *jobs, int n_jobs, int 
                                     int n_workgroups, hipStream_t s);
 hipError_t launch_reset_counter(uint32_t *counter, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s);
-hipError_t launch_reduce_job(const ReduceArgs *table, int j, int npx, hipStream_t s);
+hipError_t launch_reduce_job(const ReduceArgs *table, int j, int npx, int B, hipStream_t s);
 
 // k_image.hip
 hipError_t launch_psf_check(const ConvArgs &a, hipStream_t s);
@@ -170,7 +171,9 @@ bool hess_use_lds(int nbins);
 hipError_t launch_hess(const HessArgs &a, hipStream_t s);
 hipError_t launch_hess_job(const HessArgs *table, int j, int64_t npx, int nbins, hipStream_t s);
 hipError_t launch_hess_clear_job(const HessArgs *table, int j, int nbins, hipStream_t s);
+constexpr int LL_THREADS = 256;  // bins per likelihood block
+__host__ __device__ inline int loglike_blocks(int nbins) { return (nbins + LL_THREADS - 1) / LL_THREADS; }
 hipError_t launch_loglike(const LoglikeArgs &a, hipStream_t s);
-hipError_t launch_loglike_job(const LoglikeArgs *table, int j, hipStream_t s);
+hipError_t launch_loglike_jobs(const LoglikeArgs *table, int n_jobs, int nbins, hipStream_t s);
 
 }  // namespace pcmd
