@@ -59,32 +59,35 @@ hipError_t launch_copy_f32(const float *src, float *dst, int64_t n, hipStream_t 
 
 // ---------------------------------------------------------------------------------------
 // Direct periodic convolution.  G[y][x] = sum_{u,v} P[u][v] F[(y-u+h) mod N][(x-v+h) mod N].
-// A 64 x 32 output tile per 256-thread block; each thread owns a column strip of CRY = 8
-// outputs.  The input tile (with its K-1 halo, wrapped periodically) and the PSF are staged in
-// LDS as FP32.  For every input row the thread forms, for each of its outputs that the row
-// touches, the K-term dot product with the matching PSF row in FP32 (all terms positive), and
-// adds it to an FP64 accumulator.
+// A 64 x 16 output tile per 256-thread block; each thread owns four neighbouring outputs of one
+// row.  The input tile with its K-1 halo (wrapped periodically) and the flipped PSF (rows
+// zero-padded to a multiple of 4) are staged in LDS as FP32 and read 16 bytes at a time: tile
+// values into a sliding register window, PSF values as broadcasts.  For every PSF row the thread
+// forms the four K-term dot products in FP32 (all terms positive, ascending column; the zero
+// padding adds exact zeros) and adds them to FP64 accumulators in ascending row order.
 // ---------------------------------------------------------------------------------------
-constexpr int CT_X = 64, CT_Y = 32, CRY = 8;
+constexpr int CT_X = 64, CT_Y = 16;
+
+__host__ __device__ inline int conv_kp(int K) { return (K + 3) & ~3; }
+__host__ __device__ inline int conv_tile_w(int K) { return CT_X + conv_kp(K) + 4; }
 
 size_t conv_direct_lds_bytes(int K) {
-  return ((size_t)(CT_Y + K - 1) * (CT_X + K - 1) + (size_t)K * K) * sizeof(float);
+  return ((size_t)(CT_Y + K - 1) * conv_tile_w(K) + (size_t)K * conv_kp(K)) * sizeof(float);
 }
 
 __device__ __forceinline__ void conv_direct_body(const ConvArgs &ca) {
-  extern __shared__ float lds[];
+  extern __shared__ float4 lds4[];
+  float *tile = reinterpret_cast<float *>(lds4);
   const float *__restrict__ F = ca.F;
-  const float *__restrict__ psf = ca.psf;
   float *__restrict__ G = ca.G;
-  const int N = ca.N, K = ca.K;
+  const int N = ca.N, K = ca.K, Kp = conv_kp(K);
   const int b = blockIdx.z;
   const int h = (K - 1) >> 1;
-  const int TW = CT_X + K - 1, TH = CT_Y + K - 1;
-  float *tile = lds;
-  float *P = lds + TW * TH;
+  const int TW = conv_tile_w(K), TH = CT_Y + K - 1;
+  float *Pf = tile + TW * TH;  // Pf[a][c] = P[K-1-a][K-1-c], 0 for c >= K
   const int ox = blockIdx.x * CT_X, oy = blockIdx.y * CT_Y;
   const float *Fb = F + (size_t)b * N * N;
-  // tile row ty holds input row oy - h + ty (outputs [oy, oy + CT_Y) read rows y - h .. y + h)
+  // tile[ty][tx] = F[(oy - h + ty) mod N][(ox - h + tx) mod N]; columns past the halo are padding
   for (int idx = threadIdx.x; idx < TW * TH; idx += 256) {
     const int ty = idx / TW, tx = idx - ty * TW;
     int gy = (oy - h + ty) % N;
@@ -93,40 +96,44 @@ __device__ __forceinline__ void conv_direct_body(const ConvArgs &ca) {
     if (gx < 0) gx += N;
     tile[idx] = Fb[(size_t)gy * N + gx];
   }
-  // PSF stored flipped: Pf[a][c] = P[K-1-a][K-1-c], so output row j reads tile row ly0 + j + a
-  for (int idx = threadIdx.x; idx < K * K; idx += 256) {
-    const int a = idx / K, c = idx - a * K;
-    P[idx] = psf[(size_t)b * K * K + (size_t)(K - 1 - a) * K + (K - 1 - c)];
+  for (int idx = threadIdx.x; idx < K * Kp; idx += 256) {
+    const int a = idx / Kp, c = idx - a * Kp;
+    Pf[idx] = c < K ? ca.psf[(size_t)b * K * K + (size_t)(K - 1 - a) * K + (K - 1 - c)] : 0.0f;
   }
   __syncthreads();
-  const int lx = threadIdx.x & (CT_X - 1);
-  const int ly0 = (threadIdx.x >> 6) * CRY;
-  double acc[CRY];
+  const int tx4 = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  // output (oy + ty, ox + 4 tx4 + i) = sum_{a,c} Pf[a][c] tile[ty + a][4 tx4 + i + c]
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int a = 0; a < K; ++a) {
+    const float *row = tile + (ty + a) * TW + 4 * tx4;
+    const float *prow = Pf + a * Kp;
+    float d0 = 0.0f, d1 = 0.0f, d2 = 0.0f, d3 = 0.0f;
+    float4 lo = *reinterpret_cast<const float4 *>(row);
+    for (int c = 0; c < Kp; c += 4) {
+      const float4 hi = *reinterpret_cast<const float4 *>(row + c + 4);
+      const float4 p4 = *reinterpret_cast<const float4 *>(prow + c);
+      const float w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+      const float pk[4] = {p4.x, p4.y, p4.z, p4.w};
 #pragma unroll
-  for (int j = 0; j < CRY; ++j) acc[j] = 0.0;
-  // output (ly0 + j, lx) = sum_{a,c} Pf[a][c] tile[ly0 + j + a][lx + c]; tile row r = j + a
-  for (int r = 0; r < CRY + K - 1; ++r) {
-    const float *trow = tile + (ly0 + r) * TW + lx;
-    float dot[CRY];
-#pragma unroll
-    for (int j = 0; j < CRY; ++j) dot[j] = 0.0f;
-    for (int c = 0; c < K; ++c) {
-      const float val = trow[c];
-#pragma unroll
-      for (int j = 0; j < CRY; ++j) {
-        const int a = r - j;
-        if (a >= 0 && a < K) dot[j] = fmaf(P[a * K + c], val, dot[j]);
+      for (int k = 0; k < 4; ++k) {
+        d0 = fmaf(pk[k], w[k], d0);
+        d1 = fmaf(pk[k], w[k + 1], d1);
+        d2 = fmaf(pk[k], w[k + 2], d2);
+        d3 = fmaf(pk[k], w[k + 3], d3);
       }
+      lo = hi;
     }
-#pragma unroll
-    for (int j = 0; j < CRY; ++j) acc[j] += (double)dot[j];
+    acc[0] += (double)d0;
+    acc[1] += (double)d1;
+    acc[2] += (double)d2;
+    acc[3] += (double)d3;
   }
-  const int x = ox + lx;
-  if (x < N) {
+  const int y = oy + ty;
+  if (y < N) {
 #pragma unroll
-    for (int j = 0; j < CRY; ++j) {
-      const int y = oy + ly0 + j;
-      if (y < N) G[(size_t)b * N * N + (size_t)y * N + x] = (float)acc[j];
+    for (int i = 0; i < 4; ++i) {
+      const int x = ox + 4 * tx4 + i;
+      if (x < N) G[(size_t)b * N * N + (size_t)y * N + x] = (float)acc[i];
     }
   }
 }
