@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # MI355X published figures: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 VALU lane-instructions/s.
 VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
 # Minimum VALU lane-instructions of one pixel x entry draw on gfx950: a quarter of one
@@ -46,7 +47,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=None,
-                    help="pixels in the oracle's timed sampler window (default 3072 headline, 192 large)")
+                    help="pixels in the oracle's timed sampler window (default 3072 headline, 512 large)")
     ap.add_argument("--conv", type=int, default=0, help="0 auto, 1 direct, 2 fft")
     ap.add_argument("--workload", default="headline", choices=["headline", "large", "batch", "counters", "surrogate"],
                     help="headline: 256x256 single evaluations; large: 512x512 at Npix = 1e6 with a 63x63 PSF and "
@@ -330,6 +331,49 @@ def run_counters():
     print(json.dumps({"counters_run": "done", "copy_bytes_each_way": 3 * 2048 * 2048 * 4}), flush=True)
 
 
+def image_plane_at_scale(ctx, P, si, hgrid, N: int = 4096, reps: int = 3) -> dict:
+    """PSF convolution (both paths) and Hess binning of a 4096x4096x3 image: at the benchmark's
+    256x256 the image-plane kernels are bound by launch latency, here by the memory system.  The
+    stars come from the headline grid thinned to 1,050 entries so that sampling stays short."""
+    import torch
+
+    G = si.headline_grid().subsample(50)
+    model, obs = si.draw_headline_params(1000)
+    obs.nim = N
+    ev = P.Evaluator(ctx, G, N, obs.psf, hgrid)
+    out = {"image": f"{N}x{N}x3, 31x31 PSF, {hgrid['nx']}x{hgrid['ny']} Hess"}
+    for path, name in ((P.CONV_FFT, "conv_fft"), (P.CONV_DIRECT, "conv_direct")):
+        ev.simulate(model, obs, path)
+        ctx.sync()
+        ctx.timer_enable(True)
+        for _ in range(reps):
+            ev.simulate(model, obs, path)
+        ctx.sync()
+        c_ms, c_n, _ = ctx.timer_read(P._lib.TIMER_CONV)
+        ctx.timer_enable(False)
+        out[name] = hbm_roofline(8.0 * 3 * N * N, c_ms / max(c_n, 1), name)
+    h = torch.empty(hgrid["nx"] * hgrid["ny"], dtype=torch.int32, device=ev.mags.device)
+    mom = torch.empty(3, dtype=torch.float64, device=ev.mags.device)
+    ev.hess_of(ev.mags, h, mom)
+    ctx.sync()
+    ctx.timer_enable(True)
+    for _ in range(reps):
+        ev.hess_of(ev.mags, h, mom)
+    ctx.sync()
+    h_ms, h_n, _ = ctx.timer_read(P._lib.TIMER_HESS)
+    ctx.timer_enable(False)
+    out["hess"] = hbm_roofline(8.0 * N * N + 4.0 * hgrid["nx"] * hgrid["ny"], h_ms / max(h_n, 1), "k_hess")
+    del ev
+    torch.cuda.empty_cache()
+    return out
+
+
+def hbm_roofline(nbytes: float, ms: float, kernel: str) -> dict:
+    gbs = nbytes / (ms / 1e3) / 1e9 if ms > 0 else None
+    return {"bound": "hbm", "kernel": kernel, "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS if gbs else None, "bytes": nbytes, "avg_launch_ms": ms}
+
+
 def cpu_baseline(grid, model, obs, hgrid, n_px_sample):
     """Time the oracle (single thread) on a bounded sample of one evaluation."""
     from threadpoolctl import threadpool_limits
@@ -392,7 +436,7 @@ def main():
     large = args.workload == "large"
     draw = si.draw_large_params if large else si.draw_headline_params
     nh = 200 if large else 100
-    cpu_pixels = args.cpu_pixels if args.cpu_pixels else (192 if large else 3072)
+    cpu_pixels = args.cpu_pixels if args.cpu_pixels else (512 if large else 3072)
     model_d, obs_d = draw(2)
     # data image and Hess grid (untimed set-up)
     ev = P.Evaluator(ctx, grid, obs_d.nim, obs_d.psf, dict(x0=0.0, dx=0.05, y0=0.0, dy=0.05, nx=nh, ny=nh))
@@ -460,12 +504,20 @@ def main():
         "poisson_draws_per_s": s_units / (s_ms / 1e3) if s_ms > 0 else None,
         "draws_per_eval": draws_per_launch,
         "kernel_ms_per_eval": {"sample": s_ms / max(s_n, 1), "conv": c_ms / max(c_n, 1), "hess": h_ms / max(h_n, 1)},
+        # HBM view of the image-plane steps: algorithmic bytes (convolution: read F, write G, 4 B
+        # each per pixel and band; Hess: read the two magnitude planes it bins, 4 B each per
+        # pixel, write the bins) over the timed launches' average duration, against 8 TB/s
+        "conv_roofline": hbm_roofline(8.0 * 3 * obs_d.nim ** 2, c_ms / max(c_n, 1),
+                                      "PSF convolution (FFT chain)" if obs_d.psf.shape[-1] >= 31 else "PSF convolution"),
+        "hess_roofline": hbm_roofline(8.0 * obs_d.nim ** 2 + 4.0 * nh * nh, h_ms / max(h_n, 1), "k_hess"),
         "roofline": {"bound": "alu", "kernel": "k_sample", "achieved": achieved / 1e12,
                      "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "T lane-instr/s (VALU)",
                      "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": None if large else SAMPLE_TRAFFIC_BYTES,
                      "ops_per_draw": OPS_PER_DRAW, "avg_launch_ms": avg_sample_s * 1e3},
         "mean_logL": float(ll.mean()),
     }
+    if not large:
+        res["image_plane_at_scale"] = image_plane_at_scale(ctx, P, si, hgrid)
     if not args.no_cpu_baseline:
         m, o = params[args.warmup]
         res["cpu_baseline"] = cpu_baseline(grid, m, o, hgrid, cpu_pixels)

@@ -21,7 +21,7 @@ hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s) {
 }
 
 constexpr int HESS_THREADS = 512;
-constexpr int HESS_MAX_BLOCKS = 256;
+constexpr int HESS_MAX_BLOCKS = 1024;  // four 40 KB private histograms per CU
 constexpr int HESS_LDS_MAX_BINS = 40000;  // 160,000 bytes of LDS (of 163,840 per workgroup)
 int hess_max_blocks() { return HESS_MAX_BLOCKS; }
 
@@ -103,15 +103,19 @@ __device__ __forceinline__ void hess_body(const HessArgs &a) {
   }
   __syncthreads();
   if (last) {
-    // every block's partial is visible: combine in block order
+    // every block's partial is visible: thread t adds blocks t, t + HESS_THREADS, ... in order,
+    // then the fixed-order block sum (the combination does not depend on which block is last)
+    __threadfence();
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    for (unsigned k = threadIdx.x; k < gridDim.x; k += HESS_THREADS) {
+      s0 += __builtin_nontemporal_load(&a.mom_part[k * 3 + 0]);
+      s1 += __builtin_nontemporal_load(&a.mom_part[k * 3 + 1]);
+      s2 += __builtin_nontemporal_load(&a.mom_part[k * 3 + 2]);
+    }
+    s0 = block_sum(s0, red);
+    s1 = block_sum(s1, red);
+    s2 = block_sum(s2, red);
     if (threadIdx.x == 0) {
-      __threadfence();
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-      for (unsigned k = 0; k < gridDim.x; ++k) {
-        s0 += __builtin_nontemporal_load(&a.mom_part[k * 3 + 0]);
-        s1 += __builtin_nontemporal_load(&a.mom_part[k * 3 + 1]);
-        s2 += __builtin_nontemporal_load(&a.mom_part[k * 3 + 2]);
-      }
       a.moments[0] = s0;
       a.moments[1] = s1;
       a.moments[2] = s2;
