@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--train-pairs", type=int, default=16384)
     ap.add_argument("--train-steps", type=int, default=3000)
+    ap.add_argument("--train-nim", type=int, default=128, help="image side of the surrogate's training simulations")
     ap.add_argument("--refine-pairs", type=int, default=8192)
     ap.add_argument("--refine-steps", type=int, default=2000)
     ap.add_argument("--mcmc-steps", type=int, default=300)
@@ -206,15 +207,23 @@ def run_surrogate(args):
     dm = torch.empty(3, dtype=torch.float64, device=dev)
     ev.hess_of(ev.mags, dh, dm)
     ctx.sync()
-    wf = SurrogateWorkflow(ctx, G, si.theta_to_model, hg, dh, dm, box, train_nim=128, dims=dims,
+    wf = SurrogateWorkflow(ctx, G, si.theta_to_model, hg, dh, dm, box, train_nim=args.train_nim, dims=dims,
                            init_master=si.mlp_init(dims, 0))
     th = si.surrogate_theta_draws(args.train_pairs, seed=1)
+    last = [time.perf_counter()]
+
+    def progress(done, n):
+        if time.perf_counter() - last[0] > 30.0 or done == n:
+            print(f"[surrogate] simulated {done}/{n} training pairs", file=sys.stderr, flush=True)
+            last[0] = time.perf_counter()
+
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    H = wf.simulate_hess(th, seed0=10 ** 6)
+    H = wf.simulate_hess(th, seed0=10 ** 6, progress=progress)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     X, T = wf.inputs(th), wf.targets(H)
+    del H
     thv = si.surrogate_theta_draws(512, seed=2)
     Xv, Tv = wf.inputs(thv), wf.targets(wf.simulate_hess(thv, seed0=2 * 10 ** 6))
     mse0 = wf.mse(Xv, Tv)
@@ -281,7 +290,7 @@ def run_surrogate(args):
         "vs_baseline": None,
         "dtype": "bf16 MFMA, fp32 accumulate",
         "data": "synthetic",
-        "config": {"workload": f"MLP {dims}, {args.train_pairs} simulator pairs at 128x128 over the prior box + "
+        "config": {"workload": f"MLP {dims}, {args.train_pairs} simulator pairs at {args.train_nim}x{args.train_nim} over the prior box + "
                                f"{args.refine_pairs} within 15% of its width around the start, {args.train_steps}+"
                                f"{args.refine_steps} Adam steps of 1024, data Hess 256x256 at the fiducial parameters",
                    "temperature": 3000.0, "step": "10% of the prior box"},

@@ -41,10 +41,15 @@ class SurrogateWorkflow:
         self._ll1 = torch.empty(1, dtype=torch.float64, device=self.dev)
 
     # ---------------------------------------------------------------- data generation
-    def simulate_hess(self, thetas: np.ndarray, seed0: int, nim: int | None = None, batch: int = 256):
+    def simulate_hess(self, thetas: np.ndarray, seed0: int, nim: int | None = None, batch: int | None = None,
+                      progress=None):
         """Hess diagrams [n][nbins] (int32, device) of the parameter vectors, one batched launch
-        per `batch` points."""
+        per `batch` points (default: 256 at 128x128 and below, fewer for larger images so that the
+        batch's partial sums stay within a few tens of GB).  `progress(done, n)` is called after
+        every launch."""
         nim = self.train_nim if nim is None else nim
+        if batch is None:
+            batch = max(16, min(256, 256 * 128 * 128 // (nim * nim)))
         n = len(thetas)
         out = torch.empty((n, self.nbins), dtype=torch.int32, device=self.dev)
         lams = [torch.empty(self.ev.E, dtype=torch.float64, device=self.dev) for _ in range(min(batch, n))]
@@ -63,6 +68,8 @@ class SurrogateWorkflow:
                 jobs.append(dict(lam=lam, flux=self.ev.flux_d, obs=obs, psf=psf, conv_path=_lib.CONV_DIRECT))
             self.ctx.batch_run(jobs, self.hess_grid, self.data_hess, self.data_mom, ll[: b1 - b0],
                                hess_out=out[b0:b1], use_graph=True)
+            if progress is not None:
+                progress(b1, n)
         return out
 
     def targets(self, hess: torch.Tensor) -> torch.Tensor:
