@@ -208,6 +208,10 @@ int pcmd_hess(pcmd_ctx *ctx, const float *mags, int32_t n_bands, int64_t n_px,
  * ------------------------------------------------------------------------------------- */
 
 enum { PCMD_LL_POISSON = 0, PCMD_LL_GAUSS_PAPER = 1, PCMD_LL_GAUSS_LITERAL = 2 };
+/* OR-ed into mode: add the result to *out instead of storing it.  Summing the calls of several
+ * colour-magnitude diagrams of one image (e.g. (b0 - b1, b1) and (b1 - b2, b2) for three bands)
+ * gives their joint log-likelihood, the extension of the paper's two-band pCMD (Sec. 2.1). */
+enum { PCMD_LL_ACCUMULATE = 0x100 };
 
 /* POISSON: lam_j = N_d (m_j + eps) / (N_m + eps n_bins), logL = sum d_j ln lam_j - lam_j - ln d_j!
  * GAUSS_PAPER: mh_j = m_j N_d / N_m, sigma_j = max(sqrt(d_j + mh_j), 2),

@@ -29,3 +29,14 @@ def evaluate(model, grid, obs, hgrid, data_hess, data_mom, mode=0, eps=0.01, ban
     out = simulate(lam, f32, obs)
     H, mom = hess_mod.hess(out["mags"], hgrid, *bands)
     return ll_mod.loglike(H, data_hess, mom, data_mom, mode, eps), H, mom, out
+
+
+def loglike_multi_cmd(mags, cmds, mode=0, eps=0.01):
+    """Joint log-likelihood of several colour-magnitude diagrams of one image: the sum over the
+    diagrams of the binned likelihood of each (extends the two-band pCMD of Sec. 2.1 to three
+    bands).  cmds: sequence of (bands, hess_grid, data_hess, data_mom)."""
+    total = 0.0
+    for bands, hgrid, dh, dm in cmds:
+        H, mom = hess_mod.hess(mags, hgrid, *bands)
+        total += ll_mod.loglike(H, dh, mom, dm, mode, eps)
+    return total

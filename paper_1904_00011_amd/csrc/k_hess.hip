@@ -224,7 +224,7 @@ __device__ __forceinline__ void loglike_final_body(const LoglikeArgs &a) {
     const double Cd = a.mom_d[0] / a.mom_d[2], Md = a.mom_d[1] / a.mom_d[2];
     r += -(Cd - Cm) * (Cd - Cm) / (2.0 * 0.05 * 0.05) - (Md - Mm) * (Md - Mm) / (2.0 * 0.05 * 0.05);
   }
-  a.out[0] = r;
+  a.out[0] = a.accumulate ? a.out[0] + r : r;
 }
 
 __global__ void __launch_bounds__(LL_THREADS) k_loglike_bins(LoglikeArgs a) { loglike_bins_body(a, blockIdx.x); }

@@ -474,13 +474,15 @@ int pcmd_loglike(pcmd_ctx *c, const uint32_t *hm, const uint32_t *hd, int32_t nb
   if (!c) return PCMD_E_INVAL;
   if (!hm || !hd || !out) return fail(c, PCMD_E_INVAL, "pcmd_loglike: null argument");
   if (nbins < 1 || nbins > 65536) return fail(c, PCMD_E_INVAL, "pcmd_loglike: n_bins %d out of range", nbins);
+  const bool accumulate = (mode & PCMD_LL_ACCUMULATE) != 0;
+  mode &= ~PCMD_LL_ACCUMULATE;
   if (mode < 0 || mode > 2) return fail(c, PCMD_E_INVAL, "pcmd_loglike: bad mode %d", mode);
   if (mode == PCMD_LL_POISSON && !(eps > 0.0 && isfinite(eps))) return fail(c, PCMD_E_INVAL, "pcmd_loglike: eps must be > 0");
   if (mode != PCMD_LL_POISSON && (!mom_m || !mom_d)) return fail(c, PCMD_E_INVAL, "pcmd_loglike: moments needed");
   DeviceGuard dg(c->device);
   int r;
   if ((r = ensure(c, c->ll_part, (size_t)loglike_blocks(nbins) * 8, "likelihood partials"))) return r;
-  LoglikeArgs a{hm, hd, nbins, mode, mom_m, mom_d, eps, out, (double *)c->ll_part.p};
+  LoglikeArgs a{hm, hd, nbins, mode, mom_m, mom_d, eps, out, (double *)c->ll_part.p, accumulate ? 1 : 0};
   hipError_t e = launch_loglike(a, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(c, e, "k_loglike");
   c->err.clear();

@@ -128,6 +128,7 @@ struct LoglikeArgs {
   double eps;
   double *out;
   double *part;  // [loglike_blocks(nbins)] block sums
+  int accumulate;  // add to *out instead of storing
 };
 
 // Sampler job of the persistent batched kernel: its tiles are items [item0, item0 + items).

@@ -57,3 +57,22 @@ class Evaluator:
         self.hess_of(self.mags, self.hess, self.mom, stream)
         self.ctx.loglike(self.hess, data_hess, self.mom, data_mom, self.out, mode, eps, stream)
         return self.out
+
+    def loglike_multi(self, model, obs, cmds, mode: int = _lib.LL_POISSON, eps: float = 0.01,
+                      conv_path: int = _lib.CONV_AUTO, stream=None):
+        """Joint log-likelihood of several colour-magnitude diagrams of one simulated image, e.g.
+        (b0 - b1, b1) and (b1 - b2, b2) for three bands: one simulation, then per diagram its Hess
+        and likelihood, the diagrams' likelihoods added on the device.  cmds: sequence of
+        (bands, hess_grid, data_hess, data_mom).  The result lands in self.out (device)."""
+        self.simulate(model, obs, conv_path, stream)
+        if not hasattr(self, "_multi_h") or len(self._multi_h) < len(cmds):
+            self._multi_h = [None] * len(cmds)
+        for k, (bands, hgrid, dh, dm) in enumerate(cmds):
+            nb = hgrid["nx"] * hgrid["ny"]
+            if self._multi_h[k] is None or self._multi_h[k].numel() != nb:
+                self._multi_h[k] = torch.empty(nb, dtype=torch.int32, device=self.dev)
+            self.ctx.hess(self.mags, self.B, self.mags.shape[1], hgrid, self._multi_h[k], self.mom, bands, stream)
+            self.ctx.loglike(self._multi_h[k], dh, self.mom, dm, self.out, mode | (_lib.LL_ACCUMULATE if k else 0), eps,
+                             stream)
+        return self.out
+

@@ -1,4 +1,5 @@
 """GPU parity: the HIP path through the C ABI against the oracle on the same seeded inputs."""
+import dataclasses
 import math
 
 import numpy as np
@@ -384,3 +385,65 @@ def test_fft_needs_power_of_two(ctx):
     with pytest.raises(P.PcmdError) as ei:
         pu.gpu_simulate(ctx, lam, f32, obs, conv_path=2, want_flux=False)
     assert ei.value.code == P._lib.E_UNSUPPORTED
+
+
+def test_multi_cmd_loglike(ctx):
+    """Three bands scored on two colour-magnitude diagrams, (b0 - b1, b1) and (b1 - b2, b2), their
+    log-likelihoods added on the device (PCMD_LL_ACCUMULATE): against the oracle's sum on the same
+    magnitudes, and the oracle's own simulation of the same image."""
+    import torch
+    import paper_1904_00011_amd as P
+    G, lam, f32, obs = _headline_lam(3.0, seed=1007, stride=25)
+    obs.nim = 48
+    obs.psf = si.psf_stack(5, (1.0, 1.2, 1.4))
+    dev = torch.device("cuda")
+    _print_case("multi_cmd", nim=48, E=len(lam))
+    ora = op.simulate(lam, f32, obs)
+    m64 = ora["mags64"]
+    cmd_bands = [(0, 1, 1), (1, 2, 2)]
+    grids = []
+    for bb, br, bm in cmd_bands:
+        fin = np.isfinite(m64).all(axis=0)
+        grids.append(si.hess_grid_from_median(float(np.median((m64[bb] - m64[br])[fin])),
+                                              float(np.median(m64[bm][fin])), 60, 60))
+    # data diagrams from a second seed (oracle side)
+    obs_d = dataclasses.replace(obs, seed=obs.seed + 1)
+    md = op.simulate(lam, f32, obs_d)["mags64"]
+    cmds_o, cmds_g = [], []
+    for bands, hg in zip(cmd_bands, grids):
+        hd, mom_d = oh.hess(md, hg, *bands)
+        cmds_o.append((bands, hg, hd, mom_d))
+        cmds_g.append((bands, hg, torch.from_numpy(hd.ravel().astype(np.int32)).to(dev),
+                       torch.from_numpy(mom_d.astype(np.float64)).to(dev)))
+    model = si.Model(sfh="tau", log_npix=3.0, tau_gyr=1.0, mdf="gauss", feh_mu=0.0, feh_sigma=0.2)
+    ev = P.Evaluator(ctx, G, obs.nim, obs.psf, grids[0])
+    ev.lam.copy_(torch.from_numpy(lam).to(dev))
+    for mode in (ol.POISSON, ol.GAUSS_PAPER):
+        # the simulation from the given lambda (the model only fixes the shapes here)
+        ctx.simulate(ev.lam, ev.flux_d, obs, ev.mags, psf=ev.psf_d)
+        for k, (bands, hg, hd, mom_d) in enumerate(cmds_g):
+            h = torch.empty(hg["nx"] * hg["ny"], dtype=torch.int32, device=dev)
+            ctx.hess(ev.mags, 3, obs.nim ** 2, hg, h, ev.mom, bands)
+            ctx.loglike(h, hd, ev.mom, mom_d, ev.out, mode | (P.LL_ACCUMULATE if k else 0))
+        ctx.sync()
+        lg = float(ev.out.item())
+        mg = ev.mags.cpu().numpy().astype(np.float64)
+        lo_same = op.loglike_multi_cmd(mg, cmds_o, mode)
+        assert abs(lg - lo_same) <= 1e-9 * abs(lo_same), (mode, lg, lo_same)
+        # end to end: each diagram of the GPU image equals the oracle's except for pixels within
+        # 1e-4 mag of a bin edge; with none of those the likelihoods agree to 1e-3
+        near = 0
+        for b, hg in zip(cmd_bands, grids):
+            hg_g, _ = oh.hess(mg, hg, *b)
+            hg_o, _ = oh.hess(m64, hg, *b)
+            nb_ = int(pu.near_edge_pixels(m64, hg, b).sum())
+            assert pu.hess_diff_explained(hg_g, hg_o, nb_), (b, np.abs(hg_g - hg_o).sum(), nb_)
+            near += nb_
+        _print_case("multi_cmd_e2e", mode=mode, near_edge_pixels=near)
+        if near == 0:
+            lo_e2e = op.loglike_multi_cmd(m64, cmds_o, mode)
+            assert abs(lg - lo_e2e) <= pu.LOGL_ATOL, (mode, lg, lo_e2e)
+    # the Evaluator's own path: one simulation, then both diagrams
+    ll = ev.loglike_multi(model, obs, cmds_g)
+    ctx.sync()
+    assert np.isfinite(float(ll.item()))

@@ -218,3 +218,29 @@ def test_poisson_loglike_scatter_shrinks_with_image_size():
             vals.append(L.loglike(Hm, Hd, mm, md, L.POISSON))
         spread[nim] = np.std(vals)
     assert spread[48] < spread[16]
+
+
+def test_multi_cmd_loglike_is_the_sum_over_diagrams():
+    """The joint likelihood of several colour-magnitude diagrams: one diagram reproduces the single
+    likelihood, the order of the diagrams does not matter, and a diagram whose data and model Hess
+    are both the full pixel count in one bin adds exactly the Poisson term of that bin."""
+    import math
+    from oracle import hess as oh, loglike as ol
+    from oracle import pipeline as op
+    r = np.random.default_rng(3)
+    mags = np.stack([r.normal(25.0, 1.0, 500), r.normal(24.5, 1.0, 500), r.normal(24.0, 1.0, 500)])
+    g1 = dict(x0=-3.0, dx=0.1, nx=60, y0=21.0, dy=0.1, ny=70)
+    g2 = dict(x0=-3.0, dx=0.2, nx=30, y0=20.0, dy=0.2, ny=40)
+    data = np.stack([r.normal(25.1, 1.0, 500), r.normal(24.5, 1.0, 500), r.normal(24.0, 1.0, 500)])
+    c1 = ((0, 1, 1), g1, *oh.hess(data, g1, 0, 1, 1))
+    c2 = ((1, 2, 2), g2, *oh.hess(data, g2, 1, 2, 2))
+    H1, m1 = oh.hess(mags, g1, 0, 1, 1)
+    assert op.loglike_multi_cmd(mags, [c1]) == ol.loglike(H1, c1[2], m1, c1[3])
+    a = op.loglike_multi_cmd(mags, [c1, c2])
+    b = op.loglike_multi_cmd(mags, [c2, c1])
+    assert a == pytest.approx(b, rel=1e-14)
+    # a one-bin diagram: d = m = 500 in the single bin, lambda = 500, term 500 ln 500 - 500 - ln 500!
+    g0 = dict(x0=-100.0, dx=200.0, nx=1, y0=-100.0, dy=200.0, ny=1)
+    c0 = ((0, 1, 1), g0, *oh.hess(data, g0, 0, 1, 1))
+    one = op.loglike_multi_cmd(mags, [c1, c0]) - op.loglike_multi_cmd(mags, [c1])
+    assert one == pytest.approx(500 * math.log(500.0) - 500.0 - math.lgamma(501.0), rel=1e-12)
