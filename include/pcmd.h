@@ -148,6 +148,11 @@ enum { PCMD_NOISE_NONE = 0, PCMD_NOISE_GAUSS_MAG = 1, PCMD_NOISE_SHOT = 2 };
  *  dust_R[b]      A_b / E(B-V)
  *  psf_k, psf     odd K <= nim and <= PCMD_MAX_PSF_K; psf [dev][B][K][K] FP32, each band sums to 1
  *                 (checked to 1e-3); the convolution is periodic.  psf_k = 1 with psf NULL = no PSF
+ *  psf_grid       0 or 1: one PSF per band.  4: the image is split into a 4 x 4 grid of regions,
+ *                 region (ry, rx) = (floor(4 y / nim), floor(4 x / nim)), and the pixels of region
+ *                 r = 4 ry + rx take the PSF psf[b][r] (psf is [dev][B][16][K][K]): the paper's
+ *                 sub-pixel model, each region with a PSF shifted by a fraction of a pixel
+ *                 (Sec. 2.2).  Direct path only (AUTO picks it; FFT is PCMD_E_UNSUPPORTED)
  *  conv_path      AUTO, DIRECT or FFT (FFT needs nim a power of two, 8..4096)
  *  noise_model    NONE, GAUSS_MAG (m += sigma_b z) or SHOT (c = G t_b 10^(0.4 zp_b) + sky_b,
  *                 c' = c + sqrt(c) z, m = -2.5 log10((c' - sky_b)/t_b) + zp_b; +inf if <= 0) */
@@ -160,7 +165,7 @@ typedef struct {
   double dust_R[PCMD_MAX_BANDS];
   int32_t psf_k, conv_path;
   const float *psf;
-  int32_t noise_model, pad_;
+  int32_t noise_model, psf_grid;
   double noise_sigma_mag[PCMD_MAX_BANDS];
   double exptime[PCMD_MAX_BANDS];
   double zp[PCMD_MAX_BANDS];

@@ -16,7 +16,9 @@ def simulate(lam, flux32, obs, want_counts=False):
     N = obs.nim
     B = flux32.shape[0]
     F, s = sampler.simulate_flux(lam, flux32, obs, 0, N * N, want_counts)
-    if obs.psf is not None:
+    if obs.psf is not None and np.asarray(obs.psf).ndim == 4:  # 4 x 4 sub-pixel PSF grid
+        G = psf.convolve_periodic_subpixel(F.reshape(B, N, N), obs.psf[:B]).reshape(B, N * N)
+    elif obs.psf is not None:
         G = psf.convolve_periodic(F.reshape(B, N, N), obs.psf[:B]).reshape(B, N * N)
     else:
         G = F.copy()

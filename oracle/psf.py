@@ -28,3 +28,24 @@ def convolve_periodic(F: np.ndarray, psf: np.ndarray) -> np.ndarray:
             for v in range(K):
                 G[b] += P[b, u, v] * np.roll(F[b], shift=(u - h, v - h), axis=(0, 1))
     return G
+
+
+def region_of(N: int, grid: int = 4) -> np.ndarray:
+    """[N][N] region index r = grid * floor(grid y / N) + floor(grid x / N) of every pixel."""
+    idx = (grid * np.arange(N)) // N
+    return idx[:, None] * grid + idx[None, :]
+
+
+def convolve_periodic_subpixel(F: np.ndarray, psf: np.ndarray) -> np.ndarray:
+    """The 4 x 4 sub-pixel model (Sec. 2.2): the image is split into a 4 x 4 grid of regions and
+    the pixels of region r take the periodic convolution of the whole image with PSF r.
+    F: [B][N][N], psf: [B][16][K][K] -> G: [B][N][N] (FP64)."""
+    F = np.asarray(F, dtype=np.float64)
+    B, N, _ = F.shape
+    reg = region_of(N, 4)
+    G = np.zeros_like(F)
+    for r in range(16):
+        Gr = convolve_periodic(F, np.asarray(psf)[:, r])
+        G[:, reg == r] = Gr[:, reg == r]
+    return G
+

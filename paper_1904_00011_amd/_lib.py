@@ -62,7 +62,7 @@ class ObsS(C.Structure):
     _fields_ = [("nim", C.c_int32), ("dust_model", C.c_int32), ("seed", C.c_uint64), ("dmod", C.c_double),
                 ("dust_mu", C.c_double), ("dust_sigma", C.c_double), ("dust_frac", C.c_double),
                 ("dust_R", D4), ("psf_k", C.c_int32), ("conv_path", C.c_int32), ("psf", C.c_void_p),
-                ("noise_model", C.c_int32), ("pad_", C.c_int32), ("noise_sigma_mag", D4), ("exptime", D4),
+                ("noise_model", C.c_int32), ("psf_grid", C.c_int32), ("noise_sigma_mag", D4), ("exptime", D4),
                 ("zp", D4), ("sky", D4)]
 
 
@@ -217,9 +217,11 @@ def obs_struct(obs, B: int, psf_tensor=None, conv_path: int = CONV_AUTO):
         vals = vals + [fill] * (MAX_BANDS - len(vals))
         return D4(*[float(x) for x in vals])
     K = 1 if psf_tensor is None else int(psf_tensor.shape[-1])
+    # [B][K][K]: one PSF per band; [B][16][K][K]: the 4 x 4 grid of sub-pixel PSFs
+    grid = 4 if psf_tensor is not None and psf_tensor.dim() == 4 else 1
     return ObsS(int(obs.nim), int(obs.dust_model), int(obs.seed) & 0xFFFFFFFFFFFFFFFF, float(obs.dmod),
                 float(obs.dust_mu), float(obs.dust_sigma), float(obs.dust_frac), arr(obs.dust_R, 0.0), K,
-                int(conv_path), _ptr(psf_tensor), int(obs.noise_model), 0, arr(obs.noise_sigma_mag, 0.0),
+                int(conv_path), _ptr(psf_tensor), int(obs.noise_model), grid, arr(obs.noise_sigma_mag, 0.0),
                 arr(obs.exptime, 1.0), arr(obs.zp, 0.0), arr(obs.sky, 0.0))
 
 

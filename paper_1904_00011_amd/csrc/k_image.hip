@@ -8,12 +8,12 @@
 
 namespace pcmd {
 
-// One block per band: check that the PSF is finite, non-negative and sums to one within 1e-3
-// (a failure sets a status bit reported by pcmd_sync).
+// One block per PSF (band, and region of the sub-pixel grid): check that it is finite,
+// non-negative and sums to one within 1e-3 (a failure sets a status bit reported by pcmd_sync).
 __device__ __forceinline__ void psf_check_body(const ConvArgs &a) {
   __shared__ double red[256];
   __shared__ int bad;
-  const int b = blockIdx.x;
+  const int b = blockIdx.x;  // PSF index b_band * grid^2 + region
   const int KK = a.K * a.K;
   if (threadIdx.x == 0) bad = 0;
   __syncthreads();
@@ -39,11 +39,11 @@ __global__ void __launch_bounds__(256) k_psf_check_job(const ConvArgs *__restric
 }
 
 hipError_t launch_psf_check(const ConvArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_psf_check, dim3(a.B), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_psf_check, dim3(a.B * a.grid * a.grid), dim3(256), 0, s, a);
   return hipGetLastError();
 }
-hipError_t launch_psf_check_job(const ConvArgs *table, int j, int B, hipStream_t s) {
-  hipLaunchKernelGGL(k_psf_check_job, dim3(B), dim3(256), 0, s, table, j);
+hipError_t launch_psf_check_job(const ConvArgs *table, int j, int B, int grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_psf_check_job, dim3(B * grid * grid), dim3(256), 0, s, table, j);
   return hipGetLastError();
 }
 
@@ -81,12 +81,20 @@ __device__ __forceinline__ void conv_direct_body(const ConvArgs &ca) {
   const float *__restrict__ F = ca.F;
   float *__restrict__ G = ca.G;
   const int N = ca.N, K = ca.K, Kp = conv_kp(K);
-  const int b = blockIdx.z;
+  // blockIdx.z = band * grid^2 + region; region (ry, rx) holds the pixels with
+  // floor(grid y / N) = ry and floor(grid x / N) = rx, i.e. y in [ceil(ry N / grid), ceil((ry+1) N / grid))
+  const int R = ca.grid * ca.grid;
+  const int b = blockIdx.z / R, r = blockIdx.z - b * R;
+  const int ry = r / ca.grid, rx = r - ry * ca.grid;
+  const int y0r = (ry * N + ca.grid - 1) / ca.grid, y1r = ((ry + 1) * N + ca.grid - 1) / ca.grid;
+  const int x0r = (rx * N + ca.grid - 1) / ca.grid, x1r = ((rx + 1) * N + ca.grid - 1) / ca.grid;
+  const int ox = x0r + blockIdx.x * CT_X, oy = y0r + blockIdx.y * CT_Y;
+  if (ox >= x1r || oy >= y1r) return;  // the grid is sized for the largest region
   const int h = (K - 1) >> 1;
   const int TW = conv_tile_w(K), TH = CT_Y + K - 1;
   float *Pf = tile + TW * TH;  // Pf[a][c] = P[K-1-a][K-1-c], 0 for c >= K
-  const int ox = blockIdx.x * CT_X, oy = blockIdx.y * CT_Y;
   const float *Fb = F + (size_t)b * N * N;
+  const float *psf = ca.psf + (size_t)blockIdx.z * K * K;
   // tile[ty][tx] = F[(oy - h + ty) mod N][(ox - h + tx) mod N]; columns past the halo are padding
   for (int idx = threadIdx.x; idx < TW * TH; idx += 256) {
     const int ty = idx / TW, tx = idx - ty * TW;
@@ -98,7 +106,7 @@ __device__ __forceinline__ void conv_direct_body(const ConvArgs &ca) {
   }
   for (int idx = threadIdx.x; idx < K * Kp; idx += 256) {
     const int a = idx / Kp, c = idx - a * Kp;
-    Pf[idx] = c < K ? ca.psf[(size_t)b * K * K + (size_t)(K - 1 - a) * K + (K - 1 - c)] : 0.0f;
+    Pf[idx] = c < K ? psf[(size_t)(K - 1 - a) * K + (K - 1 - c)] : 0.0f;
   }
   __syncthreads();
   const int tx4 = threadIdx.x & 15, ty = threadIdx.x >> 4;
@@ -129,11 +137,11 @@ __device__ __forceinline__ void conv_direct_body(const ConvArgs &ca) {
     acc[3] += (double)d3;
   }
   const int y = oy + ty;
-  if (y < N) {
+  if (y < y1r) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int x = ox + 4 * tx4 + i;
-      if (x < N) G[(size_t)b * N * N + (size_t)y * N + x] = (float)acc[i];
+      if (x < x1r) G[(size_t)b * N * N + (size_t)y * N + x] = (float)acc[i];
     }
   }
 }
@@ -144,18 +152,22 @@ __global__ void __launch_bounds__(256) k_conv_direct_job(const ConvArgs *__restr
   conv_direct_body(a);
 }
 
+// Blocks per region side: the largest region of a grid x grid split is ceil(N / grid) wide.
+static dim3 conv_grid(int B, int N, int grid) {
+  const int side = (N + grid - 1) / grid;
+  return dim3((side + CT_X - 1) / CT_X, (side + CT_Y - 1) / CT_Y, B * grid * grid);
+}
+
 hipError_t launch_conv_direct(const ConvArgs &a, hipStream_t s) {
   const size_t lds = conv_direct_lds_bytes(a.K);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  dim3 grid((a.N + CT_X - 1) / CT_X, (a.N + CT_Y - 1) / CT_Y, a.B);
-  hipLaunchKernelGGL(k_conv_direct, grid, dim3(256), lds, s, a);
+  hipLaunchKernelGGL(k_conv_direct, conv_grid(a.B, a.N, a.grid), dim3(256), lds, s, a);
   return hipGetLastError();
 }
-hipError_t launch_conv_direct_job(const ConvArgs *table, int j, int B, int N, int K, hipStream_t s) {
+hipError_t launch_conv_direct_job(const ConvArgs *table, int j, int B, int N, int K, int grid, hipStream_t s) {
   const size_t lds = conv_direct_lds_bytes(K);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  dim3 grid((N + CT_X - 1) / CT_X, (N + CT_Y - 1) / CT_Y, B);
-  hipLaunchKernelGGL(k_conv_direct_job, grid, dim3(256), lds, s, table, j);
+  hipLaunchKernelGGL(k_conv_direct_job, conv_grid(B, N, grid), dim3(256), lds, s, table, j);
   return hipGetLastError();
 }
 

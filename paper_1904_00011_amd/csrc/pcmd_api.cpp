@@ -17,9 +17,12 @@ using namespace pcmd;
 
 namespace pcmd {
 
+int psf_grid_of(const pcmd_obs *o) { return o->psf_grid == 4 ? 4 : 1; }
+
 bool uses_fft(const pcmd_obs *o) {
   return o->psf_k > 1 && (o->conv_path == PCMD_CONV_FFT ||
-                          (o->conv_path == PCMD_CONV_AUTO && o->psf_k >= 31 && fft_supported(o->nim)));
+                          (o->conv_path == PCMD_CONV_AUTO && o->psf_k >= 31 && psf_grid_of(o) == 1 &&
+                           fft_supported(o->nim)));
 }
 
 int validate_sim(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, const char *who) {
@@ -43,6 +46,10 @@ int validate_sim(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, const char
   if (K < 1 || (K & 1) == 0 || K > N || K > PCMD_MAX_PSF_K)
     return fail(c, PCMD_E_INVAL, "%s: psf_k %d must be odd, <= nim and <= %d", who, K, PCMD_MAX_PSF_K);
   if (K > 1 && !o->psf) return fail(c, PCMD_E_INVAL, "%s: psf is NULL", who);
+  if (o->psf_grid != 0 && o->psf_grid != 1 && o->psf_grid != 4)
+    return fail(c, PCMD_E_INVAL, "%s: psf_grid %d must be 0, 1 or 4", who, o->psf_grid);
+  if (o->psf_grid == 4 && K > 1 && uses_fft(o))
+    return fail(c, PCMD_E_UNSUPPORTED, "%s: the 4 x 4 sub-pixel PSF grid runs on the direct path", who);
   if (o->conv_path < 0 || o->conv_path > 2) return fail(c, PCMD_E_INVAL, "%s: bad conv_path", who);
   if (o->noise_model < 0 || o->noise_model > 2) return fail(c, PCMD_E_INVAL, "%s: bad noise_model", who);
   for (int b = 0; b < B; ++b) {
@@ -388,7 +395,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   }
   const float *Gp = (const float *)c->F.p;
   if (K > 1) {
-    ConvArgs ca{B, N, K, (const float *)c->F.p, o->psf, (float *)c->G.p, c->status};
+    ConvArgs ca{B, N, K, (const float *)c->F.p, o->psf, (float *)c->G.p, c->status, psf_grid_of(o)};
     e = launch_psf_check(ca, s);
     if (e != hipSuccess) return hip_fail(c, e, "psf check");
     ScopedTimer tm(c, PCMD_TIMER_CONV, 2.0 * (double)B * (double)npx, s);

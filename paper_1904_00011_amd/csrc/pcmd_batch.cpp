@@ -19,7 +19,7 @@ using namespace pcmd;
 namespace {
 
 struct JobInfo {
-  int E, B, N, npx, K, S, nchunks, pblocks, items;
+  int E, B, N, npx, K, S, nchunks, pblocks, items, grid;
   double cost;
   size_t o_rec, o_thr, o_pc, o_fl, o_part, o_img;
 };
@@ -125,6 +125,7 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
     ji.N = jobs[j].obs.nim;
     ji.npx = ji.N * ji.N;
     ji.K = jobs[j].obs.psf_k;
+    ji.grid = psf_grid_of(&jobs[j].obs);
     // Every batch job keeps both partial streams (unreddened, reddened), so the persistent
     // sampler has one instantiation; a job without a split draws no reddened stars, its second
     // stream holds zeros and the reduction's sums are unchanged (c + 0 = c).
@@ -246,7 +247,7 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
     rr.k0 = k0;
     rr.k1 = k1;
     ra[j] = rr;
-    ca[j] = ConvArgs{B, ji.N, ji.K, F, o->psf, G, c->status};
+    ca[j] = ConvArgs{B, ji.N, ji.K, F, o->psf, G, c->status, psf_grid_of(o)};
     NoiseArgs nn;
     memset(&nn, 0, sizeof nn);
     nn.B = B;
@@ -336,8 +337,8 @@ static hipError_t enqueue(pcmd_ctx *c, pcmd_batch_plan *p, hipStream_t s) {
   for (int j = 0; j < p->n_jobs && e == hipSuccess; ++j) {
     const JobInfo &ji = p->info[j];
     e = launch_reduce_job(ra, j, ji.npx, ji.B, s);
-    if (e == hipSuccess && ji.K > 1) e = launch_psf_check_job(ca, j, ji.B, s);
-    if (e == hipSuccess && ji.K > 1) e = launch_conv_direct_job(ca, j, ji.B, ji.N, ji.K, s);
+    if (e == hipSuccess && ji.K > 1) e = launch_psf_check_job(ca, j, ji.B, ji.grid, s);
+    if (e == hipSuccess && ji.K > 1) e = launch_conv_direct_job(ca, j, ji.B, ji.N, ji.K, ji.grid, s);
     if (e == hipSuccess) e = launch_noise_mag_job(na, j, ji.npx, s);
   }
   for (int j = 0; j < p->n_jobs && e == hipSuccess; ++j) {
@@ -358,6 +359,7 @@ static uint64_t batch_signature(pcmd_ctx *c, int n_jobs, const pcmd_job *jobs, c
     const int S = split_mode_of(&jobs[j].obs) == SPLIT_NONE ? 1 : 2;
     h = fnv(h, ((uint64_t)jobs[j].iso.n_entries << 32) | (uint32_t)jobs[j].obs.nim);
     h = fnv(h, ((uint64_t)jobs[j].obs.psf_k << 32) | (uint32_t)S);
+    h = fnv(h, (uint64_t)psf_grid_of(&jobs[j].obs));
   }
   return h;
 }

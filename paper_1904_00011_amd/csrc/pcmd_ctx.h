@@ -142,6 +142,7 @@ inline uint32_t split_q_of(const pcmd_obs *o) {
 int validate_sim(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, const char *who);
 // Whether a validated simulation convolves through the FFT path.
 bool uses_fft(const pcmd_obs *o);
+int psf_grid_of(const pcmd_obs *o);  // 1 or 4
 
 void batch_destroy(pcmd_ctx *c);
 

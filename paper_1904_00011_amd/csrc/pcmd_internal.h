@@ -92,9 +92,10 @@ struct ReduceArgs {
 struct ConvArgs {
   int B, N, K;
   const float *F;    // [B][N][N]
-  const float *psf;  // [B][K][K]
+  const float *psf;  // [B][R][K][K], R = grid * grid
   float *G;          // [B][N][N]
   uint32_t *status;
+  int grid;          // 1, or 4 for the 4 x 4 grid of sub-pixel PSFs
 };
 
 // Sky, noise and magnitudes (k_noise_mag).
@@ -150,10 +151,10 @@ hipError_t launch_reduce_job(const ReduceArgs *table, int j, int npx, int B, hip
 
 // k_image.hip
 hipError_t launch_psf_check(const ConvArgs &a, hipStream_t s);
-hipError_t launch_psf_check_job(const ConvArgs *table, int j, int B, hipStream_t s);
+hipError_t launch_psf_check_job(const ConvArgs *table, int j, int B, int grid, hipStream_t s);
 size_t conv_direct_lds_bytes(int K);
 hipError_t launch_conv_direct(const ConvArgs &a, hipStream_t s);
-hipError_t launch_conv_direct_job(const ConvArgs *table, int j, int B, int N, int K, hipStream_t s);
+hipError_t launch_conv_direct_job(const ConvArgs *table, int j, int B, int N, int K, int grid, hipStream_t s);
 hipError_t launch_noise_mag(const NoiseArgs &a, hipStream_t s);
 hipError_t launch_noise_mag_job(const NoiseArgs *table, int j, int npx, hipStream_t s);
 hipError_t launch_copy_f32(const float *src, float *dst, int64_t n, hipStream_t s);

@@ -179,6 +179,23 @@ def psf_stack(k: int, sigmas) -> np.ndarray:
     return np.stack([psf_gaussian(k, s) for s in sigmas]).astype(np.float32)
 
 
+def psf_gaussian_shifted(k: int, sigma: float, dy: float, dx: float) -> np.ndarray:
+    """K x K truncated circular Gaussian centred (dy, dx) px off the kernel centre, renormalised
+    to unit sum in FP64 and stored FP32."""
+    h = (k - 1) // 2
+    y, x = np.mgrid[-h:h + 1, -h:h + 1].astype(np.float64)
+    p = np.exp(-0.5 * ((x - dx) ** 2 + (y - dy) ** 2) / (sigma * sigma))
+    p /= p.sum()
+    return p.astype(np.float32)
+
+
+def psf_subpixel_stack(k: int, sigmas) -> np.ndarray:
+    """[B][16][K][K]: per band the 4 x 4 grid of sub-pixel PSFs, region r = 4 ry + rx centred
+    (ry / 4, rx / 4) px off the kernel centre (the paper's 4 x 4 sub-pixel model, Sec. 2.2)."""
+    return np.stack([np.stack([psf_gaussian_shifted(k, s, ry / 4.0, rx / 4.0) for ry in range(4) for rx in range(4)])
+                     for s in sigmas]).astype(np.float32)
+
+
 # ---------------------------------------------------------------------------
 # workloads
 # ---------------------------------------------------------------------------

@@ -28,6 +28,8 @@ def _jobs(n, seed0, psf_k=7, nim_log2=(4.0, 5.6), entries=(400, 2500)):
             obs.dust_frac = 0.3
         if len(out) % 4 == 3:
             obs.dust_model = 0          # some without dust (no split)
+        if len(out) % 5 == 2 and psf_k > 1:
+            obs.psf = si.psf_subpixel_stack(psf_k, (1.0, 1.2, 1.4))   # some with the 4 x 4 sub-pixel grid
         out.append(dict(lam=torch.from_numpy(lam).to(dev), flux=torch.from_numpy(f32).to(dev), obs=obs,
                         psf=torch.from_numpy(obs.psf).to(dev), conv_path=1))
     return out

@@ -447,3 +447,25 @@ def test_multi_cmd_loglike(ctx):
     ll = ev.loglike_multi(model, obs, cmds_g)
     ctx.sync()
     assert np.isfinite(float(ll.item()))
+
+
+@pytest.mark.parametrize("N", [48, 50])
+def test_subpixel_psf_grid(ctx, N):
+    """The 4 x 4 grid of sub-pixel PSFs (Sec. 2.2) on the direct path: the whole pipeline against
+    the oracle (N = 50: regions of 13 and 12 pixels); sixteen copies of one PSF reproduce the
+    single-PSF image bit for bit; the FFT path refuses the grid."""
+    import paper_1904_00011_amd as P
+    G, lam, f32, obs = _headline_lam(3.0, seed=1008, stride=25)
+    obs.nim = N
+    obs.psf = si.psf_subpixel_stack(7, (1.0, 1.2, 1.4))
+    _print_case("subpixel_psf", N=N, E=len(lam))
+    _full_compare(ctx, lam, f32, obs, conv_path=1)
+    one = si.psf_stack(7, (1.0, 1.2, 1.4))
+    obs.psf = one
+    a = pu.gpu_simulate(ctx, lam, f32, obs, conv_path=1)
+    obs.psf = np.ascontiguousarray(np.repeat(one[:, None], 16, axis=1))
+    b = pu.gpu_simulate(ctx, lam, f32, obs, conv_path=1)
+    assert np.array_equal(a["flux_psf"], b["flux_psf"])
+    obs.nim = 64  # a power of two, so only the grid makes the FFT path refuse
+    with pytest.raises(P.PcmdError):
+        pu.gpu_simulate(ctx, lam, f32, obs, conv_path=2)

@@ -244,3 +244,30 @@ def test_multi_cmd_loglike_is_the_sum_over_diagrams():
     c0 = ((0, 1, 1), g0, *oh.hess(data, g0, 0, 1, 1))
     one = op.loglike_multi_cmd(mags, [c1, c0]) - op.loglike_multi_cmd(mags, [c1])
     assert one == pytest.approx(500 * math.log(500.0) - 500.0 - math.lgamma(501.0), rel=1e-12)
+
+
+def test_subpixel_grid_reduces_to_single_psf_and_shifts():
+    """The 4 x 4 sub-pixel PSF grid (Sec. 2.2): sixteen copies of one PSF give the single-PSF
+    convolution; integer-shifted delta PSFs move each region's pixels by their own shift (exact);
+    region boundaries follow floor(4 y / N) also when N is not a multiple of 4."""
+    from oracle import psf as P
+    r = np.random.default_rng(5)
+    for N in (16, 18):
+        F = r.uniform(0.0, 1.0, (2, N, N))
+        one = si.psf_stack(5, (1.0, 1.5))
+        grid = np.repeat(one[:, None], 16, axis=1)
+        assert np.array_equal(P.convolve_periodic_subpixel(F, grid), P.convolve_periodic(F, one))
+        # delta PSF of region r displaced by (sy, sx) = (r // 4 - 1, r % 4 - 2) pixels
+        K, h = 7, 3
+        deltas = np.zeros((2, 16, K, K), np.float32)
+        for reg in range(16):
+            deltas[:, reg, h + reg // 4 - 1, h + reg % 4 - 2] = 1.0
+        G = P.convolve_periodic_subpixel(F, deltas)
+        reg_of = P.region_of(N, 4)
+        for y in range(N):
+            for x in range(N):
+                rr = reg_of[y, x]
+                sy, sx = rr // 4 - 1, rr % 4 - 2
+                assert np.array_equal(G[:, y, x], F[:, (y - sy) % N, (x - sx) % N])
+        assert reg_of[0, 0] == 0 and reg_of[N - 1, N - 1] == 15
+        assert reg_of[(N + 3) // 4, 0] == 4 and reg_of[(N + 3) // 4 - 1, 0] == 0
