@@ -97,13 +97,17 @@ typedef struct {
   const double *log_sfh; /* [host][n_age], S5 only */
 } pcmd_model;
 
-/* Host helper: IMF weight of every point (Salpeter-type power law m^-alpha integrated over the
- * point's mass bin, edges at geometric midpoints, outer edges half a log-step out; Sec. 2.2,
- * Table 2) and the star flux 10^(-0.4 M) per band.  Points of one isochrone must be contiguous
- * with increasing mass.  mass [host][E]; absmag [host][B][E]; imf_w_out [host][E];
- * flux_out [host][B][E] (FP32). */
+/* IMF forms (Sec. 2.2): a single power law m^-alpha (Salpeter, alpha = 2.35, the default) or
+ * the Kroupa (2001) broken power law, slopes 0.3 / 1.3 / 2.3 with breaks at 0.08 and 0.5 Msun,
+ * continuous at the breaks (alpha ignored). */
+enum { PCMD_IMF_POWER_LAW = 0, PCMD_IMF_KROUPA = 1 };
+
+/* Host helper: IMF weight of every point (the IMF integrated over the point's mass bin, edges at
+ * geometric midpoints, outer edges half a log-step out; Sec. 2.2, Table 2) and the star flux
+ * 10^(-0.4 M) per band.  Points of one isochrone must be contiguous with increasing mass.
+ * mass [host][E]; absmag [host][B][E]; imf_w_out [host][E]; flux_out [host][B][E] (FP32). */
 int pcmd_grid_prepare(int32_t n_entries, int32_t n_bands, const int32_t *iso_of_entry,
-                      const double *mass, const double *absmag, double alpha,
+                      const double *mass, const double *absmag, int32_t imf, double alpha,
                       double *imf_w_out, float *flux_out);
 
 /* Host helper: per-isochrone SFH x MDF weight and Npix for `model` (Sec. 2.2). w_out [host][n_iso]. */

@@ -48,13 +48,46 @@ def salpeter_bin_weight(m_lo, m_hi, alpha: float = 2.35):
     return (m_lo ** (1.0 - alpha) - m_hi ** (1.0 - alpha)) / (alpha - 1.0)
 
 
-def imf_weights(grid, alpha: float = 2.35) -> np.ndarray:
+# Kroupa (2001): xi(m) proportional to m^-0.3 below 0.08 Msun, m^-1.3 on [0.08, 0.5) and m^-2.3
+# above, joined continuously (Sec. 2.2 names it as the alternative to Salpeter).
+KROUPA_BREAKS = (0.08, 0.5)
+KROUPA_SLOPES = (0.3, 1.3, 2.3)
+
+
+def kroupa_pdf(m):
+    """Unnormalised Kroupa IMF, continuous at the breaks (value 1 * m^-0.3 below the first)."""
+    m = np.asarray(m, dtype=np.float64)
+    b1, b2 = KROUPA_BREAKS
+    a0, a1, a2 = KROUPA_SLOPES
+    c1 = b1 ** (a1 - a0)            # continuity at b1
+    c2 = c1 * b2 ** (a2 - a1)       # continuity at b2
+    return np.where(m < b1, m ** -a0, np.where(m < b2, c1 * m ** -a1, c2 * m ** -a2))
+
+
+def kroupa_bin_weight(m_lo, m_hi):
+    """Integral of kroupa_pdf over [m_lo, m_hi], segment by segment."""
+    m_lo = np.atleast_1d(np.asarray(m_lo, dtype=np.float64))
+    m_hi = np.atleast_1d(np.asarray(m_hi, dtype=np.float64))
+    b1, b2 = KROUPA_BREAKS
+    a0, a1, a2 = KROUPA_SLOPES
+    c1 = b1 ** (a1 - a0)
+    c2 = c1 * b2 ** (a2 - a1)
+    out = np.zeros_like(m_lo)
+    for lo_b, hi_b, c, a in ((0.0, b1, 1.0, a0), (b1, b2, c1, a1), (b2, np.inf, c2, a2)):
+        lo = np.maximum(m_lo, lo_b)
+        hi = np.minimum(m_hi, hi_b)
+        ok = hi > lo
+        out[ok] += c * (hi[ok] ** (1.0 - a) - lo[ok] ** (1.0 - a)) / (1.0 - a)
+    return out
+
+
+def imf_weights(grid, alpha: float = 2.35, imf: str = "salpeter") -> np.ndarray:
     """IMF weight of every entry, per isochrone (its own mass bins)."""
     w = np.empty(grid.n_entries, dtype=np.float64)
     for k in range(grid.n_iso):
         idx = np.nonzero(grid.iso_of_entry == k)[0]
         e = imf_bin_edges(grid.mass[idx])
-        w[idx] = salpeter_bin_weight(e[:-1], e[1:], alpha)
+        w[idx] = kroupa_bin_weight(e[:-1], e[1:]) if imf == "kroupa" else salpeter_bin_weight(e[:-1], e[1:], alpha)
     return w
 
 
@@ -120,7 +153,7 @@ def iso_weights(model, grid) -> np.ndarray:
 def build_entries(model, grid):
     """lambda_i = Npix * w_i / sum(w) with w_i = SFH x MDF x IMF weight, and the
     per-band star flux f_ib = 10^(-0.4 M_ib) (FP64, plus its FP32 copy)."""
-    w = iso_weights(model, grid)[grid.iso_of_entry] * imf_weights(grid, model.imf_alpha)
+    w = iso_weights(model, grid)[grid.iso_of_entry] * imf_weights(grid, model.imf_alpha, getattr(model, "imf", "salpeter"))
     lam = npix_of(model) * w / w.sum()
     flux64 = 10.0 ** (-0.4 * np.asarray(grid.absmag, dtype=np.float64))
     return lam, flux64, flux64.astype(np.float32)

@@ -111,7 +111,7 @@ def load(path: str = LIB_PATH):
         "pcmd_last_error": (C.c_char_p, [vp]),
         "pcmd_sync": (C.c_int, [vp, vp]),
         "pcmd_version": (C.c_char_p, []),
-        "pcmd_grid_prepare": (C.c_int, [i32, i32, vp, vp, vp, dbl, vp, vp]),
+        "pcmd_grid_prepare": (C.c_int, [i32, i32, vp, vp, vp, i32, dbl, vp, vp]),
         "pcmd_iso_weights": (C.c_int, [C.POINTER(ModelS), C.POINTER(IsoSet), vp, C.POINTER(dbl)]),
         "pcmd_entries": (C.c_int, [vp, C.POINTER(GridS), vp, dbl, vp, vp]),
         "pcmd_simulate": (C.c_int, [vp, C.POINTER(IsoS), C.POINTER(ObsS), vp, C.POINTER(DebugS), vp]),
@@ -161,7 +161,10 @@ def _stream(stream):
 # host helpers (a0)
 # ---------------------------------------------------------------------------------------------
 
-def grid_prepare(iso_of_entry, mass, absmag, alpha: float = 2.35):
+IMF_POWER_LAW, IMF_KROUPA = 0, 1
+
+
+def grid_prepare(iso_of_entry, mass, absmag, alpha: float = 2.35, imf: str = "salpeter"):
     """IMF weight per point and FP32 star flux per band (host)."""
     lib = load()
     iso = np.ascontiguousarray(iso_of_entry, dtype=np.int32)
@@ -170,7 +173,8 @@ def grid_prepare(iso_of_entry, mass, absmag, alpha: float = 2.35):
     B, E = absmag.shape
     w = np.empty(E, dtype=np.float64)
     f = np.empty((B, E), dtype=np.float32)
-    rc = lib.pcmd_grid_prepare(E, B, iso.ctypes.data, mass.ctypes.data, absmag.ctypes.data, float(alpha),
+    kind = IMF_KROUPA if imf == "kroupa" else IMF_POWER_LAW
+    rc = lib.pcmd_grid_prepare(E, B, iso.ctypes.data, mass.ctypes.data, absmag.ctypes.data, kind, float(alpha),
                                w.ctypes.data, f.ctypes.data)
     if rc != OK:
         raise PcmdError(rc, "pcmd_grid_prepare rejected its arguments")

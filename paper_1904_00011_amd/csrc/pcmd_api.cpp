@@ -152,10 +152,24 @@ int pcmd_sync(pcmd_ctx *c, pcmd_stream stream) {
 // a0 host helpers
 // ------------------------------------------------------------------------------------------
 
-int pcmd_grid_prepare(int32_t E, int32_t B, const int32_t *iso, const double *mass, const double *absmag,
+// Integral of the Kroupa (2001) IMF over [lo, hi]: xi(m) = k_i m^-a_i with a = 0.3 / 1.3 / 2.3 on
+// [0, 0.08) / [0.08, 0.5) / [0.5, inf) and k = 1 / 0.08 / 0.04 (continuous at the breaks).
+static double kroupa_integral(double lo, double hi) {
+  const double brk[4] = {0.0, 0.08, 0.5, INFINITY};
+  const double a[3] = {0.3, 1.3, 2.3}, k[3] = {1.0, 0.08, 0.04};
+  double s = 0.0;
+  for (int j = 0; j < 3; ++j) {
+    const double l = fmax(lo, brk[j]), h = fmin(hi, brk[j + 1]);
+    if (h > l) s += k[j] * (pow(h, 1.0 - a[j]) - pow(l, 1.0 - a[j])) / (1.0 - a[j]);
+  }
+  return s;
+}
+
+int pcmd_grid_prepare(int32_t E, int32_t B, const int32_t *iso, const double *mass, const double *absmag, int32_t imf,
                       double alpha, double *imf_w, float *flux) {
   if (E <= 0 || B < 1 || B > PCMD_MAX_BANDS || !iso || !mass || !absmag || !imf_w || !flux) return PCMD_E_INVAL;
-  if (!(alpha > 1.0) || !isfinite(alpha)) return PCMD_E_INVAL;
+  if (imf != PCMD_IMF_POWER_LAW && imf != PCMD_IMF_KROUPA) return PCMD_E_INVAL;
+  if (imf == PCMD_IMF_POWER_LAW && (!(alpha > 1.0) || !isfinite(alpha))) return PCMD_E_INVAL;
   int start = 0;
   while (start < E) {
     int end = start + 1;
@@ -177,7 +191,8 @@ int pcmd_grid_prepare(int32_t E, int32_t B, const int32_t *iso, const double *ma
         lo = exp(0.5 * (lprev + l));
         hi = exp(0.5 * (l + lnext));
       }
-      imf_w[i] = (pow(lo, 1.0 - alpha) - pow(hi, 1.0 - alpha)) / (alpha - 1.0);
+      imf_w[i] = imf == PCMD_IMF_KROUPA ? kroupa_integral(lo, hi)
+                                         : (pow(lo, 1.0 - alpha) - pow(hi, 1.0 - alpha)) / (alpha - 1.0);
     }
     start = end;
   }

@@ -15,14 +15,14 @@ class Evaluator:
     """Evaluate log L(theta) for a fixed isochrone grid, image size, PSF and Hess grid."""
 
     def __init__(self, ctx: _lib.Context, grid, nim: int, psf: np.ndarray | None, hess_grid: dict,
-                 bands=(0, 1, 1), imf_alpha: float = 2.35, device: str = "cuda"):
+                 bands=(0, 1, 1), imf_alpha: float = 2.35, device: str = "cuda", imf: str = "salpeter"):
         self.ctx = ctx
         self.grid = grid
         self.nim = int(nim)
         self.hess_grid = dict(hess_grid)
         self.bands = tuple(bands)
         self.dev = torch.device(device)
-        imf_w, flux = _lib.grid_prepare(grid.iso_of_entry, grid.mass, grid.absmag, imf_alpha)
+        imf_w, flux = _lib.grid_prepare(grid.iso_of_entry, grid.mass, grid.absmag, imf_alpha, imf)
         self.iso_imf_sum = np.bincount(grid.iso_of_entry, weights=imf_w, minlength=grid.n_iso)
         self.iso_d = torch.from_numpy(np.ascontiguousarray(grid.iso_of_entry, np.int32)).to(self.dev)
         self.imf_d = torch.from_numpy(imf_w).to(self.dev)

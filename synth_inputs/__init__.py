@@ -234,6 +234,7 @@ class Model:
     feh_sigma: float = 0.2
     mdf_prune: float = 0.01
     imf_alpha: float = 2.35
+    imf: str = "salpeter"        # salpeter (power law, imf_alpha) | kroupa
 
 
 def small_case(nim: int = 64, seed: int = 1):

@@ -47,6 +47,8 @@ def test_grid_prepare_matches_oracle():
         assert np.max(np.abs(w / wo - 1)) < 1e-12
         _, f64, f32 = oe.build_entries(si.Model(sfh="const", mdf="gauss" if g.n_iso > 1 else "single"), g)
         assert np.max(np.abs(f.astype(np.float64) / f32.astype(np.float64) - 1)) <= 6e-8
+        wk, _ = _lib.grid_prepare(g.iso_of_entry, g.mass, g.absmag, 2.35, imf="kroupa")
+        assert np.max(np.abs(wk / oe.imf_weights(g, imf="kroupa") - 1)) < 1e-12
 
 
 def test_iso_weights_match_oracle():
@@ -71,6 +73,13 @@ def test_host_helper_validation():
     g = si.small_case()[0]
     with pytest.raises(_lib.PcmdError):
         _lib.grid_prepare(g.iso_of_entry, g.mass, g.absmag, 0.5)
+    f = np.empty((g.n_bands, g.n_entries), np.float32)
+    w = np.empty(g.n_entries)
+    iso = np.ascontiguousarray(g.iso_of_entry, np.int32)
+    mass = np.ascontiguousarray(g.mass, np.float64)
+    mag = np.ascontiguousarray(g.absmag, np.float64)
+    assert _lib.load().pcmd_grid_prepare(g.n_entries, g.n_bands, iso.ctypes.data, mass.ctypes.data, mag.ctypes.data,
+                                         7, 2.35, w.ctypes.data, f.ctypes.data) != 0  # unknown IMF kind
     bad_mass = g.mass.copy()
     bad_mass[10] = bad_mass[9]
     with pytest.raises(_lib.PcmdError):

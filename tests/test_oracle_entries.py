@@ -80,3 +80,28 @@ def test_flux_is_ten_to_minus_0p4_mag():
     _, f64, f32 = E.build_entries(m, g)
     assert np.allclose(-2.5 * np.log10(f64), g.absmag, rtol=0, atol=1e-12)
     assert f32.dtype == np.float32
+
+
+def test_kroupa_imf_against_quadrature_and_shape():
+    """Kroupa (2001) IMF (Sec. 2.2's alternative to Salpeter): bin integrals against numerical
+    quadrature of the piecewise density, continuity at 0.08 and 0.5 Msun, and the logarithmic
+    slopes -0.3 / -1.3 / -2.3 of its three segments."""
+    for lo, hi in ((0.01, 0.05), (0.05, 0.2), (0.07, 0.09), (0.3, 0.7), (0.45, 3.0), (0.02, 20.0), (1.0, 40.0)):
+        q, _ = integrate.quad(E.kroupa_pdf, lo, hi, points=[p for p in (0.08, 0.5) if lo < p < hi], epsabs=0,
+                              epsrel=1e-12, limit=200)
+        assert E.kroupa_bin_weight(lo, hi)[0] == pytest.approx(q, rel=1e-10)
+    for b in (0.08, 0.5):
+        assert E.kroupa_pdf(b * (1 - 1e-12)) == pytest.approx(E.kroupa_pdf(b), rel=1e-9)
+    for m, slope in ((0.02, -0.3), (0.2, -1.3), (5.0, -2.3)):
+        d = math.log(E.kroupa_pdf(m * 1.001) / E.kroupa_pdf(m)) / math.log(1.001)
+        assert d == pytest.approx(slope, rel=1e-9)
+    # sum of lambda is still Npix with the Kroupa weights
+    G = si.headline_grid()
+    m = si.Model(sfh="tau", log_npix=3.0, tau_gyr=2.0, mdf="gauss", feh_mu=0.0, imf="kroupa")
+    lam, _, _ = E.build_entries(m, G)
+    assert lam.sum() == pytest.approx(1e3, rel=1e-12)
+    # Kroupa holds fewer low-mass stars per high-mass star than Salpeter
+    ms = si.Model(sfh="tau", log_npix=3.0, tau_gyr=2.0, mdf="gauss", feh_mu=0.0)
+    ls, _, _ = E.build_entries(ms, G)
+    low = G.mass < 0.3
+    assert lam[low].sum() < ls[low].sum()
