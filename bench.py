@@ -49,10 +49,12 @@ def parse():
     ap.add_argument("--cpu-pixels", type=int, default=None,
                     help="pixels in the oracle's timed sampler window (default 3072 headline, 512 large)")
     ap.add_argument("--conv", type=int, default=0, help="0 auto, 1 direct, 2 fft")
-    ap.add_argument("--workload", default="headline", choices=["headline", "large", "batch", "counters", "surrogate"],
+    ap.add_argument("--workload", default="headline",
+                    choices=["headline", "large", "batch", "counters", "surrogate", "scatter"],
                     help="headline: 256x256 single evaluations; large: 512x512 at Npix = 1e6 with a 63x63 PSF and "
                          "200x200 Hess; batch: 256 uneven jobs per step; counters: one headline simulation plus a "
-                         "copy of known size, for hardware-counter runs; surrogate: the learned screen")
+                         "copy of known size, for hardware-counter runs; surrogate: the learned screen; scatter: "
+                         "log-likelihood scatter against image size and the L_max ceiling")
     ap.add_argument("--jobs", type=int, default=256)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--train-pairs", type=int, default=16384)
@@ -61,6 +63,7 @@ def parse():
     ap.add_argument("--refine-pairs", type=int, default=8192)
     ap.add_argument("--refine-steps", type=int, default=2000)
     ap.add_argument("--mcmc-steps", type=int, default=300)
+    ap.add_argument("--seeds", type=int, default=64, help="re-simulations per image side (scatter workload)")
     return ap.parse_args()
 
 
@@ -314,6 +317,30 @@ def run_surrogate(args):
     print(json.dumps(res), flush=True)
 
 
+def run_scatter(args):
+    """Stochastic likelihoods (Appendix A): the fiducial-tau-like point re-simulated with 64 seeds
+    at image sides 64..512 against a data image of the same side; the scatter, its skew and the
+    median (the paper's ceiling L_max for a best fit), each side's seeds in one batched launch."""
+    import paper_1904_00011_amd as P
+    import synth_inputs as si
+    from paper_1904_00011_amd import stochastic as st
+
+    ctx = P.Context(0)
+    model, obs = si.theta_to_model(si.surrogate_truth(), seed=0, nim=256)
+    t0 = time.perf_counter()
+    rows = st.scatter_vs_image_size(ctx, si.headline_grid(), model, obs, (64, 128, 256, 512), args.seeds)
+    elapsed = time.perf_counter() - t0
+    sims = args.seeds * 4
+    ctx.close()
+    print(json.dumps({
+        "metric": "log-likelihood scatter vs image size (fiducial point, seeds re-simulated in batched launches)",
+        "value": sims / elapsed, "unit": "re-simulations/s (all sides)", "n_gpus": 1, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u32 counts / f64 sums / f32 images", "data": "synthetic",
+        "config": {"workload": f"{args.seeds} seeds per side, sides 64-512, 52,500 entries, 31x31 PSF (direct), "
+                               "100x100 Hess, Poisson logL"},
+        "rows": rows}), flush=True)
+
+
 def run_counters():
     """One headline simulation (the parameters of step 0) and a 2048x2048x3 FP32 image copy of
     known size (50,331,648 bytes read and written) that calibrates FETCH_SIZE / WRITE_SIZE."""
@@ -432,6 +459,9 @@ def main():
         return
     if args.workload == "surrogate":
         run_surrogate(args)
+        return
+    if args.workload == "scatter":
+        run_scatter(args)
         return
     import torch
 
