@@ -27,6 +27,11 @@ TAG_SPLIT_X = 2   # (pixel, entry, 2, j): dust split, further words
 TAG_PTRS = 3      # (pixel, entry, 3, j): transformed rejection, attempts 2j and 2j+1
 TAG_DUST = 4      # (pixel, 0, 4, 0): per-pixel log-normal dust draw
 TAG_NOISE = 5     # (pixel, band, 5, 0): per-pixel, per-band photometric noise
+# block-skip sampler (a separate stream; Sec. 2.1 footnote on Poisson superposition)
+TAG_BLOCK = 6       # (pixel, block, 6, 0): word 0 draws the block's star total by inversion
+TAG_BLOCK_PTRS = 7  # (pixel, block, 7, j): the total by transformed rejection, attempts 2j, 2j+1
+TAG_STAR = 8        # (pixel, block, 8, s // 4): word s % 4 places star s on a point
+TAG_STAR_SPLIT = 9  # (pixel, block, 9, s // 4): word s % 4 decides whether star s is reddened
 
 
 def philox4x32_10(c0, c1, c2, c3, seed: int):

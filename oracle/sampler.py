@@ -162,11 +162,11 @@ def ptrs_constants(lam: float) -> dict:
                 lninva=F32(math.log(inv_alpha)), vr=F32(vr))
 
 
-def ptrs_draw(c: dict, seed: int, px: np.ndarray, entry: int, max_attempts: int = 64):
+def ptrs_draw(c: dict, seed: int, px: np.ndarray, entry: int, max_attempts: int = 64, tag: int = TAG_PTRS):
     """Transformed-rejection Poisson draw for each pixel in `px` (entry fixed).
 
-    Attempt j uses words (2(j%2), 2(j%2)+1) of Philox(pixel, entry, TAG_PTRS, j//2).
-    Returns (counts, attempts_used)."""
+    Attempt j uses words (2(j%2), 2(j%2)+1) of Philox(pixel, entry, tag, j//2) (tag TAG_PTRS for
+    the per-point rule).  Returns (counts, attempts_used)."""
     npx = px.shape[0]
     out = np.zeros(npx, dtype=np.int64)
     done = np.zeros(npx, dtype=bool)
@@ -174,7 +174,7 @@ def ptrs_draw(c: dict, seed: int, px: np.ndarray, entry: int, max_attempts: int 
     words = None
     for j in range(max_attempts):
         if j % 2 == 0:
-            words = philox4x32_10(px, entry, TAG_PTRS, j // 2, seed)
+            words = philox4x32_10(px, entry, tag, j // 2, seed)
         u = u01_open_f32(words[2 * (j % 2)])
         V = u01_open_f32(words[2 * (j % 2) + 1])
         U = u - F32(0.5)
@@ -379,7 +379,11 @@ def simulate_flux(lam, flux32, obs, px0=0, px1=None, want_counts=False, px=None)
     if px is None:
         px = np.arange(px0, px1, dtype=np.int64)
     px = np.asarray(px, dtype=np.int64)
-    s = sample_pixels(lam, flux32, obs.seed, px, obs.dust_model, obs.dust_frac, want_counts)
+    if getattr(obs, "sampler", 0) == 1:
+        from .sampler_block import sample_pixels_block
+        s = sample_pixels_block(lam, flux32, obs.seed, px, obs.dust_model, obs.dust_frac, want_counts)
+    else:
+        s = sample_pixels(lam, flux32, obs.seed, px, obs.dust_model, obs.dust_frac, want_counts)
     F = pixel_flux(s["F_clr"], s["F_red"], px, obs.seed, obs.dmod, obs.dust_model, obs.dust_mu,
                    obs.dust_sigma, obs.dust_R[:flux32.shape[0]])
     return F, s
