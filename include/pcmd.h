@@ -141,6 +141,7 @@ typedef struct {
 enum { PCMD_DUST_NONE = 0, PCMD_DUST_SCREEN = 1, PCMD_DUST_LOGNORMAL = 2 };
 enum { PCMD_CONV_AUTO = 0, PCMD_CONV_DIRECT = 1, PCMD_CONV_FFT = 2 };
 enum { PCMD_NOISE_NONE = 0, PCMD_NOISE_GAUSS_MAG = 1, PCMD_NOISE_SHOT = 2 };
+enum { PCMD_SAMPLER_POINT = 0, PCMD_SAMPLER_BLOCK = 1 };
 
 /* Observation and nuisance model of one simulation.
  *  nim            image side (pixels = nim*nim), 1..8192
@@ -159,7 +160,15 @@ enum { PCMD_NOISE_NONE = 0, PCMD_NOISE_GAUSS_MAG = 1, PCMD_NOISE_SHOT = 2 };
  *                 (Sec. 2.2).  Direct path only (AUTO picks it; FFT is PCMD_E_UNSUPPORTED)
  *  conv_path      AUTO, DIRECT or FFT (FFT needs nim a power of two, 8..4096)
  *  noise_model    NONE, GAUSS_MAG (m += sigma_b z) or SHOT (c = G t_b 10^(0.4 zp_b) + sky_b,
- *                 c' = c + sqrt(c) z, m = -2.5 log10((c' - sky_b)/t_b) + zp_b; +inf if <= 0) */
+ *                 c' = c + sqrt(c) z, m = -2.5 log10((c' - sky_b)/t_b) + zp_b; +inf if <= 0)
+ *  sampler        POINT (0): one Poisson count per (pixel, point), the paper's rule (Sec. 2.1).
+ *                 BLOCK (1): the same law by Poisson superposition (Sec. 2.1 footnote): per
+ *                 pixel and block of 64 consecutive points one Poisson total, then each star's
+ *                 point by its cumulative share of the block's lambda (to 2^-32) and its dust
+ *                 screen by one uniform per star.  A different random stream; cheaper where most
+ *                 blocks draw no star (low Npix).  Each block's lambda sum must be < 2^22
+ *                 (else PCMD_E_INVAL at pcmd_sync, the block drawn as 0).  pcmd_simulate only
+ *                 (pcmd_batch_run rejects it with PCMD_E_UNSUPPORTED) */
 typedef struct {
   int32_t nim;
   int32_t dust_model;
@@ -174,6 +183,7 @@ typedef struct {
   double exptime[PCMD_MAX_BANDS];
   double zp[PCMD_MAX_BANDS];
   double sky[PCMD_MAX_BANDS];
+  int32_t sampler, pad_;
 } pcmd_obs;
 
 /* Optional debug outputs (any pointer may be NULL):

@@ -23,6 +23,7 @@ MDF = {"single": 0, "gauss": 1}
 DUST_NONE, DUST_SCREEN, DUST_LOGNORMAL = 0, 1, 2
 CONV_AUTO, CONV_DIRECT, CONV_FFT = 0, 1, 2
 NOISE_NONE, NOISE_GAUSS_MAG, NOISE_SHOT = 0, 1, 2
+SAMPLER_POINT, SAMPLER_BLOCK = 0, 1
 LL_POISSON, LL_GAUSS_PAPER, LL_GAUSS_LITERAL = 0, 1, 2
 LL_ACCUMULATE = 0x100  # OR-ed into mode: add to out instead of storing
 TIMER_SAMPLE, TIMER_CONV, TIMER_HESS, TIMER_BATCH, TIMER_GEMM = 0, 1, 2, 3, 4
@@ -63,7 +64,7 @@ class ObsS(C.Structure):
                 ("dust_mu", C.c_double), ("dust_sigma", C.c_double), ("dust_frac", C.c_double),
                 ("dust_R", D4), ("psf_k", C.c_int32), ("conv_path", C.c_int32), ("psf", C.c_void_p),
                 ("noise_model", C.c_int32), ("psf_grid", C.c_int32), ("noise_sigma_mag", D4), ("exptime", D4),
-                ("zp", D4), ("sky", D4)]
+                ("zp", D4), ("sky", D4), ("sampler", C.c_int32), ("pad_", C.c_int32)]
 
 
 class DebugS(C.Structure):
@@ -226,7 +227,8 @@ def obs_struct(obs, B: int, psf_tensor=None, conv_path: int = CONV_AUTO):
     return ObsS(int(obs.nim), int(obs.dust_model), int(obs.seed) & 0xFFFFFFFFFFFFFFFF, float(obs.dmod),
                 float(obs.dust_mu), float(obs.dust_sigma), float(obs.dust_frac), arr(obs.dust_R, 0.0), K,
                 int(conv_path), _ptr(psf_tensor), int(obs.noise_model), grid, arr(obs.noise_sigma_mag, 0.0),
-                arr(obs.exptime, 1.0), arr(obs.zp, 0.0), arr(obs.sky, 0.0))
+                arr(obs.exptime, 1.0), arr(obs.zp, 0.0), arr(obs.sky, 0.0), int(getattr(obs, "sampler", SAMPLER_POINT)),
+                0)
 
 
 def hess_grid_struct(g: dict, bands=(0, 1, 1)):

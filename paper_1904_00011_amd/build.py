@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libpcmd.so")
 
-SOURCES = ["pcmd_api.cpp", "pcmd_batch.cpp", "pcmd_mlp.cpp", "k_sample.hip", "k_image.hip", "k_hess.hip", "k_fft.hip", "k_batch.hip",
+SOURCES = ["pcmd_api.cpp", "pcmd_batch.cpp", "pcmd_mlp.cpp", "k_sample.hip", "k_sample_block.hip", "k_image.hip", "k_hess.hip", "k_fft.hip", "k_batch.hip",
            "k_mlp.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-Wall",

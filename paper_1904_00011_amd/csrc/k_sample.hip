@@ -61,37 +61,11 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
       l = 0.0;
     }
     if (l >= 10.0) {
-      const double slam = sqrt(l);
-      const double bb = 0.931 + 2.53 * slam;
-      const double aa = -0.059 + 0.02483 * bb;
-      const double inv_alpha = 1.1239 + 1.1328 / (bb - 3.4);
-      const double vr = 0.9277 - 3.6224 / (bb - 2.0);
-      PtrsConst c;
-      c.mu = (float)l;
-      c.lnmu = (float)log(l);
-      c.b = (float)bb;
-      c.a = (float)aa;
-      c.twoa = (float)(2.0 * aa);
-      c.lninva = (float)log(inv_alpha);
-      c.vr = (float)vr;
-      c.pad = 0.0f;
-      ((PtrsConst *)a.pc)[i] = c;
+      ((PtrsConst *)a.pc)[i] = ptrs_constants(l);
       r.kk = KIND_PTRS;
     } else if (l > 0.0) {
-      double p = exp(-l);
-      double F = p;
-      uint32_t K = 0;
       uint32_t *t = a.thr + (size_t)i * THR_STRIDE;
-      for (int k = 0; k < THR_STRIDE - 1; ++k) {
-        if (k > 0) {
-          p = p * l / (double)k;
-          F = F + p;
-        }
-        const double tk = floor(F * 4294967296.0);
-        if (tk >= 4294967296.0) break;
-        t[k] = (uint32_t)tk;
-        K = (uint32_t)(k + 1);
-      }
+      const uint32_t K = inversion_table(l, t);
       if (K > 0) {
         for (uint32_t k = 0; k < 3 && k < K; ++k) r.T[k] = t[k];
         r.kk = (K << 8) | KIND_INV;
@@ -135,34 +109,8 @@ hipError_t launch_prep_job(const PrepArgs *table, int j, int E, hipStream_t s) {
 // ---------------------------------------------------------------------------------------
 // Sampler.
 // ---------------------------------------------------------------------------------------
-__device__ __forceinline__ bool wave_any(bool v) { return __ballot(v) != 0ull; }
 
 __device__ __forceinline__ uint32_t low_mask(uint32_t cnt) { return cnt >= 32u ? 0xFFFFFFFFu : ((1u << cnt) - 1u); }
-
-// Transformed-rejection draw for entry i at pixel p (attempts 2j, 2j+1 share one Philox call).
-__device__ __forceinline__ uint32_t ptrs_draw(const PtrsConst &c, uint32_t p, uint32_t i, uint32_t k0, uint32_t k1,
-                                              const float *__restrict__ lnfact, uint32_t &failed) {
-  int k = 0;
-  bool done = false;
-  for (uint32_t j = 0; j < (uint32_t)(PTRS_MAX_ATTEMPTS / 2); ++j) {
-    const u4 w = philox10(p, i, TAG_PTRS, j, k0, k1);
-    int kk;
-    if (!done && ptrs_attempt(c, w.x, w.y, lnfact, kk)) {
-      k = kk;
-      done = true;
-    }
-    if (!done && ptrs_attempt(c, w.z, w.w, lnfact, kk)) {
-      k = kk;
-      done = true;
-    }
-    if (!wave_any(!done)) break;
-  }
-  if (!done) {  // reported once per wave at the end of the kernel (no stores inside the entry loop)
-    failed = 1u;
-    k = 0;
-  }
-  return (uint32_t)k;
-}
 
 // Reddened stars among n (dust split).  F = 1/2: one bit per star, the first 8 from the
 // entry's byte of its 16-entry split block, the rest from (p, i, TAG_SPLIT_X, j) blocks.
@@ -198,22 +146,6 @@ __device__ __forceinline__ uint32_t split_count(uint32_t n, uint32_t word, uint3
     }
   }
   return red;
-}
-
-// The entry tables are only read while sampling: reading them through the constant address
-// space lets the wave-uniform loads go through the scalar cache.
-#define PCMD_CONST __attribute__((address_space(4)))
-
-// Copy a struct out of constant-address-space memory word by word (scalar loads).
-template <typename T>
-__device__ __forceinline__ T ld_const(const PCMD_CONST T *p) {
-  static_assert(sizeof(T) % 4 == 0, "word-sized structs only");
-  T v;
-  uint32_t *d = reinterpret_cast<uint32_t *>(&v);
-  const PCMD_CONST uint32_t *s = reinterpret_cast<const PCMD_CONST uint32_t *>(p);
-#pragma unroll
-  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) d[k] = s[k];
-  return v;
 }
 
 template <int B, int S, bool DBG>
@@ -311,7 +243,7 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
           }
         } else {
           const PtrsConst c = ld_const(pc + i);
-          n = ptrs_draw(c, p, i, a.k0, a.k1, a.lnfact, ptrs_failed);
+          n = ptrs_draw(c, p, i, TAG_PTRS, a.k0, a.k1, a.lnfact, ptrs_failed);
         }
         if (!wave_any(n != 0u)) continue;
         uint32_t red = 0u;

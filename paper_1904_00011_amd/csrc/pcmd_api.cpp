@@ -52,6 +52,8 @@ int validate_sim(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, const char
     return fail(c, PCMD_E_UNSUPPORTED, "%s: the 4 x 4 sub-pixel PSF grid runs on the direct path", who);
   if (o->conv_path < 0 || o->conv_path > 2) return fail(c, PCMD_E_INVAL, "%s: bad conv_path", who);
   if (o->noise_model < 0 || o->noise_model > 2) return fail(c, PCMD_E_INVAL, "%s: bad noise_model", who);
+  if (o->sampler != PCMD_SAMPLER_POINT && o->sampler != PCMD_SAMPLER_BLOCK)
+    return fail(c, PCMD_E_INVAL, "%s: bad sampler %d", who, o->sampler);
   for (int b = 0; b < B; ++b) {
     if (o->noise_model == PCMD_NOISE_GAUSS_MAG && !(o->noise_sigma_mag[b] >= 0.0 && isfinite(o->noise_sigma_mag[b])))
       return fail(c, PCMD_E_INVAL, "%s: bad noise_sigma_mag", who);
@@ -118,7 +120,7 @@ void pcmd_destroy(pcmd_ctx *c) {
   batch_destroy(c);
   Buf *bufs[] = {&c->rec,     &c->thr,     &c->pc,      &c->fl64,    &c->part,     &c->F,       &c->G,
                  &c->mom_part, &c->fft,    &c->mlp_act, &c->mlp_pre, &c->mlp_dza, &c->mlp_dzb, &c->mlp_grad,
-                 &c->mlp_part, &c->mlp_ws, &c->ll_part};
+                 &c->mlp_part, &c->mlp_ws, &c->ll_part, &c->blk};
   for (Buf *b : bufs) release(*b);
   if (c->lnfact) (void)hipFree(c->lnfact);
   if (c->status) (void)hipFree(c->status);
@@ -330,63 +332,119 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   const int nchunks = (E + CHUNK - 1) / CHUNK;
   const int split_mode = split_mode_of(o);
   const int S = split_mode == SPLIT_NONE ? 1 : 2;
-  if ((r = ensure(c, c->rec, rec_bytes(E), "entry records"))) return r;
-  if ((r = ensure(c, c->thr, (size_t)E * THR_STRIDE * 4, "thresholds"))) return r;
-  if ((r = ensure(c, c->pc, (size_t)E * sizeof(PtrsConst), "rejection constants"))) return r;
+  const bool block = o->sampler == PCMD_SAMPLER_BLOCK;
+  const int nb = superblocks(E);
+  // block-skip tables: [nb] BlockRec, [nb][THR_STRIDE] thresholds, [nb] PtrsConst, [nb][SBLK] cth
+  const size_t blk_rec = (size_t)nb * sizeof(BlockRec), blk_thr = (size_t)nb * THR_STRIDE * 4,
+               blk_pc = (size_t)nb * sizeof(PtrsConst), blk_cth = (size_t)nb * SBLK * 4;
+  if (block) {
+    if ((r = ensure(c, c->blk, blk_rec + blk_thr + blk_pc + blk_cth, "block tables"))) return r;
+  } else {
+    if ((r = ensure(c, c->rec, rec_bytes(E), "entry records"))) return r;
+    if ((r = ensure(c, c->thr, (size_t)E * THR_STRIDE * 4, "thresholds"))) return r;
+    if ((r = ensure(c, c->pc, (size_t)E * sizeof(PtrsConst), "rejection constants"))) return r;
+  }
   if ((r = ensure(c, c->fl64, (size_t)E * BP * 8, "fluxes"))) return r;
   if ((r = ensure(c, c->part, (size_t)nchunks * S * B * npx * 8, "partial sums"))) return r;
   if ((r = ensure(c, c->F, (size_t)B * npx * 4, "image"))) return r;
   if ((r = ensure(c, c->G, (size_t)B * npx * 4, "convolved image"))) return r;
   if (K > 1 && use_fft && (r = ensure(c, c->fft, fft_scratch_bytes(B, N), "fft"))) return r;
 
-  PrepArgs pa{E,
-              B,
-              BP,
-              iso->lam,
-              iso->flux,
-              (EntryRec *)c->rec.p,
-              (GroupRec *)((EntryRec *)c->rec.p + entries_padded(E)),
-              (uint32_t *)c->thr.p,
-              c->pc.p,
-              (double *)c->fl64.p,
-              c->status};
-  hipError_t e = launch_prep(pa, s);
-  if (e != hipSuccess) return hip_fail(c, e, "k_prep");
-
   const uint32_t k0 = (uint32_t)(o->seed & 0xFFFFFFFFu), k1 = (uint32_t)(o->seed >> 32);
+  hipError_t e = hipSuccess;
   if (dbg && dbg->counts) {
     e = launch_fill_u32(dbg->counts, 0u, (px1 - px0) * E, s);
     if (e == hipSuccess && dbg->reddened) e = launch_fill_u32(dbg->reddened, 0u, (px1 - px0) * E, s);
     if (e != hipSuccess) return hip_fail(c, e, "clearing debug counts");
   }
-  SampleArgs a;
-  a.E = E;
-  a.B = B;
-  a.BP = BP;
-  a.npx = (int)npx;
-  a.nchunks = nchunks;
-  a.S = S;
-  a.k0 = k0;
-  a.k1 = k1;
-  a.split_mode = split_mode;
-  a.split_q = split_q_of(o);
-  a.rec = pa.rec;
-  a.grp = pa.grp;
-  a.thr = pa.thr;
-  a.pc = pa.pc;
-  a.fl64 = pa.fl64;
-  a.part = (double *)c->part.p;
-  a.dbg_counts = dbg ? dbg->counts : nullptr;
-  a.dbg_red = dbg ? dbg->reddened : nullptr;
-  a.px0 = px0;
-  a.px1 = px1;
-  a.status = c->status;
-  a.lnfact = c->lnfact;
-  {
-    ScopedTimer tm(c, PCMD_TIMER_SAMPLE, (double)npx * (double)E, s);
-    e = launch_sample(a, s);
+  if (block) {
+    char *base = (char *)c->blk.p;
+    BlockPrepArgs pb{E,
+                     B,
+                     BP,
+                     nb,
+                     iso->lam,
+                     iso->flux,
+                     (BlockRec *)base,
+                     (uint32_t *)(base + blk_rec),
+                     base + blk_rec + blk_thr,
+                     (uint32_t *)(base + blk_rec + blk_thr + blk_pc),
+                     (double *)c->fl64.p,
+                     c->status};
+    e = launch_prep_block(pb, s);
+    if (e != hipSuccess) return hip_fail(c, e, "k_prep_block");
+    BlockSampleArgs a;
+    a.E = E;
+    a.B = B;
+    a.BP = BP;
+    a.npx = (int)npx;
+    a.nb = nb;
+    a.nchunks = nchunks;
+    a.S = S;
+    a.k0 = k0;
+    a.k1 = k1;
+    a.split_mode = split_mode;
+    a.split_q = split_q_of(o);
+    a.brec = pb.brec;
+    a.thr = pb.thr;
+    a.pc = pb.pc;
+    a.cth = pb.cth;
+    a.fl64 = pb.fl64;
+    a.part = (double *)c->part.p;
+    a.dbg_counts = dbg ? dbg->counts : nullptr;
+    a.dbg_red = dbg ? dbg->reddened : nullptr;
+    a.px0 = px0;
+    a.px1 = px1;
+    a.status = c->status;
+    a.lnfact = c->lnfact;
+    {
+      ScopedTimer tm(c, PCMD_TIMER_SAMPLE, (double)npx * (double)E, s);
+      e = launch_sample_block(a, s);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "k_sample_block");
+  } else {
+    PrepArgs pa{E,
+                B,
+                BP,
+                iso->lam,
+                iso->flux,
+                (EntryRec *)c->rec.p,
+                (GroupRec *)((EntryRec *)c->rec.p + entries_padded(E)),
+                (uint32_t *)c->thr.p,
+                c->pc.p,
+                (double *)c->fl64.p,
+                c->status};
+    e = launch_prep(pa, s);
+    if (e != hipSuccess) return hip_fail(c, e, "k_prep");
+    SampleArgs a;
+    a.E = E;
+    a.B = B;
+    a.BP = BP;
+    a.npx = (int)npx;
+    a.nchunks = nchunks;
+    a.S = S;
+    a.k0 = k0;
+    a.k1 = k1;
+    a.split_mode = split_mode;
+    a.split_q = split_q_of(o);
+    a.rec = pa.rec;
+    a.grp = pa.grp;
+    a.thr = pa.thr;
+    a.pc = pa.pc;
+    a.fl64 = pa.fl64;
+    a.part = (double *)c->part.p;
+    a.dbg_counts = dbg ? dbg->counts : nullptr;
+    a.dbg_red = dbg ? dbg->reddened : nullptr;
+    a.px0 = px0;
+    a.px1 = px1;
+    a.status = c->status;
+    a.lnfact = c->lnfact;
+    {
+      ScopedTimer tm(c, PCMD_TIMER_SAMPLE, (double)npx * (double)E, s);
+      e = launch_sample(a, s);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "k_sample");
   }
-  if (e != hipSuccess) return hip_fail(c, e, "k_sample");
 
   ReduceArgs ra;
   ra.B = B;

@@ -15,6 +15,8 @@ constexpr uint32_t PH_W1 = 0xBB67AE85u;
 
 // Stream tags (counter word 2).
 constexpr uint32_t TAG_MAIN = 0, TAG_SPLIT = 1, TAG_SPLIT_X = 2, TAG_PTRS = 3, TAG_DUST = 4, TAG_NOISE = 5;
+// block-skip sampler: block total by inversion / rejection, star placement, star dust screen
+constexpr uint32_t TAG_BLOCK = 6, TAG_BLOCK_PTRS = 7, TAG_STAR = 8, TAG_STAR_SPLIT = 9;
 
 // Entry kinds written by the preparation kernel.
 constexpr uint32_t KIND_ZERO = 0, KIND_INV = 1, KIND_PTRS = 2;
@@ -146,6 +148,90 @@ __device__ __forceinline__ bool ptrs_attempt(const PtrsConst &c, uint32_t wu, ui
   const float lhs = (ln_f32(V) + c.lninva) - ln_f32(q);
   const float rhs = ((-c.mu) + kf * c.lnmu) - lnfact_f32(kf, lnfact_table);
   return lhs <= rhs;
+}
+
+// Tables that are only read while sampling: reading them through the constant address space
+// lets the wave-uniform loads go through the scalar cache.
+#define PCMD_CONST __attribute__((address_space(4)))
+
+// Copy a struct out of constant-address-space memory word by word (scalar loads).
+template <typename T>
+__device__ __forceinline__ T ld_const(const PCMD_CONST T *p) {
+  static_assert(sizeof(T) % 4 == 0, "word-sized structs only");
+  T v;
+  uint32_t *d = reinterpret_cast<uint32_t *>(&v);
+  const PCMD_CONST uint32_t *s = reinterpret_cast<const PCMD_CONST uint32_t *>(p);
+#pragma unroll
+  for (int k = 0; k < (int)(sizeof(T) / 4); ++k) d[k] = s[k];
+  return v;
+}
+
+__device__ __forceinline__ bool wave_any(bool v) { return __ballot(v) != 0ull; }
+
+// Transformed-rejection draw of stream (p, i, tag): attempts 2j, 2j+1 use words (0,1), (2,3) of
+// Philox(p, i, tag, j).  A lane that exhausts PTRS_MAX_ATTEMPTS draws 0 and sets `failed`
+// (reported once per wave by the caller, so the loop holds no store).
+__device__ __forceinline__ uint32_t ptrs_draw(const PtrsConst &c, uint32_t p, uint32_t i, uint32_t tag, uint32_t k0,
+                                              uint32_t k1, const float *__restrict__ lnfact, uint32_t &failed) {
+  int k = 0;
+  bool done = false;
+  for (uint32_t j = 0; j < (uint32_t)(PTRS_MAX_ATTEMPTS / 2); ++j) {
+    const u4 w = philox10(p, i, tag, j, k0, k1);
+    int kk;
+    if (!done && ptrs_attempt(c, w.x, w.y, lnfact, kk)) {
+      k = kk;
+      done = true;
+    }
+    if (!done && ptrs_attempt(c, w.z, w.w, lnfact, kk)) {
+      k = kk;
+      done = true;
+    }
+    if (!wave_any(!done)) break;
+  }
+  if (!done) {
+    failed = 1u;
+    k = 0;
+  }
+  return (uint32_t)k;
+}
+
+// C1 table of a Poisson(l) count, 0 < l < 10: T_k = floor(2^32 F(k)) for k = 0, 1, ... while
+// T_k < 2^32 (at most THR_STRIDE - 1 values), the cdf F built in FP64 by the pmf recurrence
+// p_k = p_{k-1} l / k from p_0 = e^-l.  Returns K, the number of thresholds written.
+__device__ inline uint32_t inversion_table(double l, uint32_t *t) {
+  double pk = exp(-l);
+  double F = pk;
+  uint32_t K = 0;
+  for (int k = 0; k < THR_STRIDE - 1; ++k) {
+    if (k > 0) {
+      pk = pk * l / (double)k;
+      F = F + pk;
+    }
+    const double tk = floor(F * 4294967296.0);
+    if (tk >= 4294967296.0) break;
+    t[k] = (uint32_t)tk;
+    K = (uint32_t)(k + 1);
+  }
+  return K;
+}
+
+// C2 constants of a Poisson(l) count, l >= 10: computed in FP64 and rounded to FP32.
+__device__ inline PtrsConst ptrs_constants(double l) {
+  const double slam = sqrt(l);
+  const double bb = 0.931 + 2.53 * slam;
+  const double aa = -0.059 + 0.02483 * bb;
+  const double inv_alpha = 1.1239 + 1.1328 / (bb - 3.4);
+  const double vr = 0.9277 - 3.6224 / (bb - 2.0);
+  PtrsConst c;
+  c.mu = (float)l;
+  c.lnmu = (float)log(l);
+  c.b = (float)bb;
+  c.a = (float)aa;
+  c.twoa = (float)(2.0 * aa);
+  c.lninva = (float)log(inv_alpha);
+  c.vr = (float)vr;
+  c.pad = 0.0f;
+  return c;
 }
 
 #pragma clang fp contract(on)

@@ -76,6 +76,46 @@ struct SampleArgs {
   const float *lnfact;
 };
 
+// Block-skip sampler (Poisson superposition, Sec. 2.1 footnote): per pixel and per block of
+// SBLK consecutive entries, the block's star total and then each star's entry.
+constexpr int SBLK = 64;  // entries per block = lanes of a wave
+inline int superblocks(int E) { return (E + SBLK - 1) / SBLK; }
+// One block's record (32 bytes, scalar loads): the total's rule as in EntryRec, and istar, the
+// first entry of the block whose cumulative threshold is 2^32 (the last entry with stars).
+struct BlockRec {
+  uint32_t T[3];
+  uint32_t kk;
+  uint32_t istar;
+  uint32_t pad[3];
+};
+struct BlockPrepArgs {
+  int E, B, BP, nb;
+  const double *lam;   // [E]
+  const float *flux;   // [B][E]
+  BlockRec *brec;      // [nb]
+  uint32_t *thr;       // [nb][THR_STRIDE]
+  void *pc;            // [nb] PtrsConst
+  uint32_t *cth;       // [nb][SBLK] cumulative thresholds below istar, 0xFFFFFFFF from istar on
+  double *fl64;        // [E][BP]
+  uint32_t *status;
+};
+struct BlockSampleArgs {
+  int E, B, BP, npx, nb, nchunks, S;
+  uint32_t k0, k1;
+  int split_mode;
+  uint32_t split_q;
+  const BlockRec *brec;
+  const uint32_t *thr;
+  const void *pc;
+  const uint32_t *cth;
+  const double *fl64;
+  double *part;  // [nchunks][S][B][npx], as SampleArgs
+  uint32_t *dbg_counts, *dbg_red;
+  int64_t px0, px1;
+  uint32_t *status;
+  const float *lnfact;
+};
+
 // Chunk reduction and dust / distance epilogue (k_reduce).
 struct ReduceArgs {
   int B, npx, nchunks, S;
@@ -148,6 +188,10 @@ hipError_t launch_sample_persistent(const BatchSampleJob *jobs, int n_jobs, int 
 hipError_t launch_reset_counter(uint32_t *counter, hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s);
 hipError_t launch_reduce_job(const ReduceArgs *table, int j, int npx, int B, hipStream_t s);
+
+// k_sample_block.hip
+hipError_t launch_prep_block(const BlockPrepArgs &a, hipStream_t s);
+hipError_t launch_sample_block(const BlockSampleArgs &a, hipStream_t s);
 
 // k_image.hip
 hipError_t launch_psf_check(const ConvArgs &a, hipStream_t s);

@@ -95,6 +95,24 @@ def explain_count_mismatches(lam, seed, px0, got, want):
     return unexplained
 
 
+def explain_block_mismatches(lam, seed, px0, got, want):
+    """Block-skip sampler: the (pixel, block) pairs whose counts differ and are NOT explained by
+    the block total's 32-bit word lying within 1 of an inversion threshold of Lambda_b."""
+    from oracle import sampler_block as sb
+    tot = sb.block_sums(lam)
+    unexplained = []
+    for r, b in sorted({(int(r), int(i) // sb.BLOCK) for r, i in np.argwhere(got != want)}):
+        p = px0 + r
+        L = float(tot[b])
+        if L >= osamp.LAM_SWITCH:
+            unexplained.append((p, b))
+            continue
+        u = int(orng.philox4x32_10(p, b, orng.TAG_BLOCK, 0, seed)[0])
+        if not any(abs(u - t) <= 1 for t in osamp.inversion_thresholds(L)):
+            unexplained.append((p, b))
+    return unexplained
+
+
 def rel_err(a, b, floor=1e-300):
     a = np.asarray(a, np.float64)
     b = np.asarray(b, np.float64)

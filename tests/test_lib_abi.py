@@ -94,3 +94,34 @@ def test_null_context_is_rejected_without_a_gpu(lib):
     assert lib.pcmd_loglike(None, None, None, 1, None, None, 0, 0.01, None, None) == -1
     assert lib.pcmd_entries(None, None, None, 1.0, None, None) == -1
     assert lib.pcmd_last_error(None) == b"null context"
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's sizes and field offsets."""
+    import shutil
+    import subprocess
+    from paper_1904_00011_amd import _lib
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = [("pcmd_isoset", _lib.IsoSet), ("pcmd_model", _lib.ModelS), ("pcmd_grid", _lib.GridS),
+             ("pcmd_iso", _lib.IsoS), ("pcmd_obs", _lib.ObsS), ("pcmd_debug", _lib.DebugS),
+             ("pcmd_hess_grid", _lib.HessGridS), ("pcmd_job", _lib.JobS), ("pcmd_batch_tuning", _lib.TuningS),
+             ("pcmd_mlp", _lib.MlpS)]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in pairs:
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f in py._fields_:
+            lines.append(f'  printf("{cname} {f[0]} %zu\\n", offsetof({cname}, {f[0]}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-o", str(exe), str(src)], check=True)
+    got = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    want = []
+    for cname, py in pairs:
+        want.append(f"{cname} size {C.sizeof(py)}")
+        for f in py._fields_:
+            want.append(f"{cname} {f[0]} {getattr(py, f[0]).offset}")
+    assert [g for g in got if g] == want
