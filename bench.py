@@ -14,6 +14,7 @@ Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on one 
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -50,7 +51,7 @@ def parse():
                     help="pixels in the oracle's timed sampler window (default 3072 headline, 512 large)")
     ap.add_argument("--conv", type=int, default=0, help="0 auto, 1 direct, 2 fft")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "large", "batch", "counters", "surrogate", "scatter"],
+                    choices=["headline", "large", "batch", "counters", "surrogate", "scatter", "ablation"],
                     help="headline: 256x256 single evaluations; large: 512x512 at Npix = 1e6 with a 63x63 PSF and "
                          "200x200 Hess; batch: 256 uneven jobs per step; counters: one headline simulation plus a "
                          "copy of known size, for hardware-counter runs; surrogate: the learned screen; scatter: "
@@ -341,6 +342,68 @@ def run_scatter(args):
         "rows": rows}), flush=True)
 
 
+def run_ablation(args):
+    """Block-skip sampler (Poisson superposition over 64-point blocks) against the per-point rule
+    on the headline workload at fixed log Npix = 1 .. 5: sampler kernel time and whole
+    likelihood evaluations per second of each, the same parameters and seeds for both."""
+    import torch
+
+    import paper_1904_00011_amd as P
+    import synth_inputs as si
+
+    dev = torch.device("cuda:0")
+    ctx = P.Context(0)
+    grid = si.headline_grid()
+    model_d, obs_d = si.draw_headline_params(2)
+    ev = P.Evaluator(ctx, grid, obs_d.nim, obs_d.psf, dict(x0=0.0, dx=0.05, y0=0.0, dy=0.05, nx=100, ny=100))
+    mags_d = ev.simulate(model_d, obs_d).clone()
+    ctx.sync()
+    md = mags_d.cpu().numpy().astype(np.float64)
+    fin = np.isfinite(md).all(axis=0)
+    ev.hess_grid = si.hess_grid_from_median(float(np.median((md[0] - md[1])[fin])), float(np.median(md[1][fin])),
+                                            100, 100)
+    data_hess = torch.empty(100 * 100, dtype=torch.int32, device=dev)
+    data_mom = torch.empty(3, dtype=torch.float64, device=dev)
+    ev.hess_of(mags_d, data_hess, data_mom)
+    out = torch.empty(1, dtype=torch.float64, device=dev)
+    rows = []
+    for lnp in (1.0, 2.0, 3.0, 4.0, 5.0):
+        params = [si.draw_headline_params(1000 + k, log_npix=lnp) for k in range(args.steps + args.warmup)]
+        row = {"log_npix": lnp}
+        for name, sampler in (("point", P.SAMPLER_POINT), ("block", P.SAMPLER_BLOCK)):
+            runs = [(m, dataclasses.replace(o, sampler=sampler)) for m, o in params]
+            for m, o in runs[:args.warmup]:
+                out.copy_(ev.loglike(m, o, data_hess, data_mom))
+            torch.cuda.synchronize()
+            ctx.timer_enable(True)
+            t0 = time.perf_counter()
+            for m, o in runs[args.warmup:]:
+                out.copy_(ev.loglike(m, o, data_hess, data_mom))
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ctx.sync()
+            s_ms, s_n, _ = ctx.timer_read(P._lib.TIMER_SAMPLE)
+            ctx.timer_enable(False)
+            row[name] = {"sample_ms": s_ms / max(s_n, 1), "evals_per_s": args.steps / (t1 - t0)}
+        row["sampler_speedup"] = row["point"]["sample_ms"] / row["block"]["sample_ms"]
+        row["eval_speedup"] = row["block"]["evals_per_s"] / row["point"]["evals_per_s"]
+        rows.append(row)
+        print(f"[ablation] log Npix {lnp}: k_sample {row['point']['sample_ms']:.3f} ms, k_sample_block "
+              f"{row['block']['sample_ms']:.3f} ms", file=sys.stderr, flush=True)
+    ctx.close()
+    at2 = next(r for r in rows if r["log_npix"] == 2.0)
+    print(json.dumps({
+        "metric": "block-skip sampler speed-up over the per-point rule (sampler kernel time, 256^2, 52,500 points, "
+                  "log Npix = 2)",
+        "value": at2["sampler_speedup"], "unit": "x", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32 counts / f64 sums / f32 images", "data": "synthetic",
+        "config": {"workload": "headline workload (256x256, 3 bands, 52,500 entries, log-normal dust F=0.5, 31x31 "
+                               "PSF, shot noise, 100x100 Hess) at fixed log Npix 1-5, both samplers on the same "
+                               "parameters and seeds"},
+        "rows": rows}), flush=True)
+
+
 def run_counters():
     """One headline simulation (the parameters of step 0) and a 2048x2048x3 FP32 image copy of
     known size (50,331,648 bytes read and written) that calibrates FETCH_SIZE / WRITE_SIZE."""
@@ -462,6 +525,9 @@ def main():
         return
     if args.workload == "scatter":
         run_scatter(args)
+        return
+    if args.workload == "ablation":
+        run_ablation(args)
         return
     import torch
 
