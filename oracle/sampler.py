@@ -9,12 +9,27 @@ fraction F_dust of the stars; distance enters as the distance modulus mu_d.
 
 How a Poisson count is drawn is not fixed by the paper.  The rule here:
 
-* C1, lambda < 10 -- inversion in the integer domain.  p_0 = exp(-lambda),
+* C1, lambda < 2 -- inversion in the integer domain.  p_0 = exp(-lambda),
   p_k = p_{k-1} * lambda / k, F_k = F_{k-1} + p_k (FP64, in that order);
   T_k = floor(F_k * 2^32).  K is the first k with T_k >= 2^32, or 63.  With u a
   32-bit word, n = #{k < K : T_k <= u}, i.e. the least k with u < T_k.  Exact to
-  2^-32 per outcome.
-* C2, lambda >= 10 -- transformed rejection with squeeze (Hormann 1993, "The
+  2^-32 per outcome.  (The block-skip sampler's block totals use this rule below
+  lambda = 10.)
+* C1b, 2 <= lambda < 512 -- the same quantised law by an integer alias table
+  (Walker 1977; construction of Vose 1991).  The C1 recurrence, uncapped, runs
+  until T_k >= 2^32 - 1; that last threshold is taken as 2^32 (so the outcome
+  takes the last word too: the FP64 sum can stall just below 1).  With k_lo = #{k : T_k = 0}, outcome k_lo + j has
+  mass m_j = T_{k_lo+j} - T_{k_lo+j-1} (T_{k_lo-1} = 0).  M = the smallest power
+  of two >= the number of outcomes, at least 16; column j of M holds height
+  h_j <= 2^32/M and alias a_j; with u the entry's inversion word, column
+  c = u >> (32 - log2 M) and r = u mod 2^(32 - log2 M), n = k_lo + (c if r < h_c
+  else a_c).  Vose's construction in integers: columns with m_j < 2^32/M on a
+  "small" stack, the rest on a "large" stack, both pushed in ascending j;
+  repeatedly pop s from small and l from large, set h_s = m_s, a_s = l,
+  m_l -= 2^32/M - m_s and push l on the stack its new mass selects; columns left
+  on large get h = 2^32/M, a = j.  Every outcome then has exactly mass m_j over
+  the 2^32 words (exact to 2^-32, like C1), at one table read per draw.
+* C2, lambda >= 512 -- transformed rejection with squeeze (Hormann 1993, "The
   transformed rejection method for generating Poisson random variables"),
   decisions taken in IEEE FP32 operation by operation, with a logarithm written
   here from the atanh series and ln k! from an FP64-built table (k < 256) or a
@@ -29,7 +44,7 @@ How a Poisson count is drawn is not fixed by the paper.  The rule here:
   below floor(F * 2^32).
 
 Random words come from Philox4x32-10 keyed by the seed with counters
-(pixel, entry // 4, TAG_MAIN, 0) word entry % 4 (inversion),
+(pixel, entry // 4, TAG_MAIN, 0) word entry % 4 (inversion and alias),
 (pixel, entry, TAG_PTRS, j) (rejection attempts 2j and 2j+1),
 (pixel, entry // 16, TAG_SPLIT, 0) and (pixel, entry, TAG_SPLIT_X, j) (dust split),
 and (pixel, 0, TAG_DUST, 0) (per-pixel dust).
@@ -75,6 +90,82 @@ def inversion_thresholds(lam: float) -> list[int]:
             break
         out.append(int(t))
     return out
+
+
+ALIAS_MIN = 2.0
+ALIAS_MAX = 512.0
+ALIAS_MIN_COLS = 16
+ALIAS_MAX_COLS = 512
+
+
+def alias_masses(lam: float, p0: float | None = None):
+    """(k_lo, m): the C1b outcome masses (integers summing to 2^32) of outcomes k_lo, k_lo + 1, ...
+    p0 replaces exp(-lambda) (for checking how a last-bit difference of exp would move them)."""
+    lam = float(lam)
+    p = math.exp(-lam) if p0 is None else float(p0)
+    F = p
+    T = []                      # T_0, T_1, ... with the last one set to 2^32
+    k = 0
+    while True:
+        if k > 0:
+            p = p * lam / k
+            F = F + p
+        t = math.floor(F * 4294967296.0)
+        if t >= TWO32 - 1:             # the last word or more: the rest of the mass goes here
+            T.append(TWO32)
+            break
+        T.append(int(t))
+        k += 1
+    k_lo = next(kk for kk, t in enumerate(T) if t > 0)
+    m = [T[k_lo]] + [T[kk] - T[kk - 1] for kk in range(k_lo + 1, len(T))]
+    return k_lo, m
+
+
+def alias_columns(n_outcomes: int) -> int:
+    """M: the smallest power of two >= the number of outcomes, at least 16."""
+    M = ALIAS_MIN_COLS
+    while M < n_outcomes:
+        M *= 2
+    return M
+
+
+def alias_table(lam: float, p0: float | None = None):
+    """(k_lo, log2 M, packed[M] uint32): column j's height h_j (stored as min(h_j, 2^32/M - 1);
+    alias = j when h_j = 2^32/M) in the top 32 - log2 M bits, its alias a_j in the low log2 M."""
+    k_lo, m = alias_masses(lam, p0)
+    M = alias_columns(len(m))
+    assert M <= ALIAS_MAX_COLS, "support too wide for the alias rule"
+    bits = M.bit_length() - 1
+    cap = TWO32 // M
+    w = list(m) + [0] * (M - len(m))
+    small = [j for j in range(M) if w[j] < cap]
+    large = [j for j in range(M) if w[j] >= cap]
+    h = [0] * M
+    a = [0] * M
+    while small and large:
+        sj = small.pop()
+        lj = large.pop()
+        h[sj] = w[sj]
+        a[sj] = lj
+        w[lj] -= cap - w[sj]
+        (small if w[lj] < cap else large).append(lj)
+    for j in large:
+        h[j] = cap
+        a[j] = j
+    assert not small, "masses do not sum to 2^32"
+    packed = np.array([(min(h[j], cap - 1) << bits) | a[j] for j in range(M)], dtype=np.uint32)
+    return k_lo, bits, packed
+
+
+def count_from_alias(u: np.ndarray, k_lo: int, bits: int, packed: np.ndarray) -> np.ndarray:
+    """n = k_lo + (c if u mod 2^(32-b) < h_c else a_c), c = u >> (32 - b), M = 2^b columns."""
+    u = np.asarray(u, dtype=np.uint64)
+    sh = np.uint64(32 - bits)
+    c = (u >> sh).astype(np.int64)
+    r = u & np.uint64((1 << (32 - bits)) - 1)
+    x = packed[c].astype(np.uint64)
+    j = np.where(r < (x >> np.uint64(bits)), c, (x & np.uint64((1 << bits) - 1)).astype(np.int64))
+    return (k_lo + j).astype(np.int64)
 
 
 def count_from_thresholds(u: np.ndarray, thr: list[int]) -> np.ndarray:
@@ -256,7 +347,7 @@ def sample_pixels(lam: np.ndarray, flux32: np.ndarray, seed: int, px: np.ndarray
     """Star counts and unreddened / reddened flux sums for the pixels listed in `px`.
 
     Entries are handled a block at a time, vectorised over (pixel, entry); each count follows
-    the C1 / C2 rule of its entry and each split the C3 rule.  Returns dict with F_clr, F_red
+    the C1 / C1b / C2 rule of its entry and each split the C3 rule.  Returns dict with F_clr, F_red
     ([B][npx] FP64) and, if asked, counts n and reddened counts r ([npx][E] int64)."""
     lam = np.asarray(lam, dtype=np.float64)
     E = lam.shape[0]
@@ -279,7 +370,7 @@ def sample_pixels(lam: np.ndarray, flux32: np.ndarray, seed: int, px: np.ndarray
         U = np.stack(w, axis=-1).reshape(npx, 4 * len(g))[:, : e1 - e0].astype(np.uint64)
         n = np.zeros((npx, e1 - e0), dtype=np.int64)
         lb = lam[e0:e1]
-        inv = np.nonzero(lb < LAM_SWITCH)[0]
+        inv = np.nonzero(lb < ALIAS_MIN)[0]
         tables = [inversion_thresholds(lb[j]) for j in inv]
         K = np.array([len(t) for t in tables], dtype=np.int64)
         # n = #{k : T_k <= u}; entries bucketed by table length, tables padded with 2^32
@@ -292,7 +383,9 @@ def sample_pixels(lam: np.ndarray, flux32: np.ndarray, seed: int, px: np.ndarray
                 T[r_, : K[j]] = tables[j]
             cols = inv[sel]
             n[:, cols] = (U[:, cols, None] >= T[None, :, :]).sum(axis=-1)
-        for j in np.nonzero(lb >= LAM_SWITCH)[0]:
+        for j in np.nonzero((lb >= ALIAS_MIN) & (lb < ALIAS_MAX))[0]:
+            n[:, j] = count_from_alias(U[:, j], *alias_table(lb[j]))
+        for j in np.nonzero(lb >= ALIAS_MAX)[0]:
             n[:, j], _ = ptrs_draw(ptrs_constants(lb[j]), seed, px, e0 + j)
         if split and 0.0 < frac < 1.0:
             W = None

@@ -60,9 +60,11 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
       atomicOr(a.status, STATUS_BAD_LAMBDA);
       l = 0.0;
     }
-    if (l >= 10.0) {
+    if (l >= ALIAS_MAX) {
       ((PtrsConst *)a.pc)[i] = ptrs_constants(l);
       r.kk = KIND_PTRS;
+    } else if (l >= ALIAS_MIN) {
+      r.kk = KIND_ALIAS;  // k_prep_alias builds the columns and completes the record
     } else if (l > 0.0) {
       uint32_t *t = a.thr + (size_t)i * THR_STRIDE;
       const uint32_t K = inversion_table(l, t);
@@ -77,7 +79,7 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
   // group of entries GRP g .. GRP g + GRP - 1 = neighbouring lanes of one wave (256-thread blocks)
   const uint32_t kind = r.kk & 0xFFu;
   const uint32_t t0m1 = kind == KIND_INV ? r.T[0] - 1u : 0xFFFFFFFFu;
-  const uint32_t fl = kind == KIND_INV ? GRP_INV : (kind == KIND_PTRS ? GRP_PTRS : 0u);
+  const uint32_t fl = kind == KIND_INV ? GRP_INV : kind == KIND_PTRS ? GRP_PTRS : kind == KIND_ALIAS ? GRP_ALIAS : 0u;
   const int first = (int)(threadIdx.x & 63u) & ~(GRP - 1);
   GroupRec gr;
   gr.flags = 0u;
@@ -95,6 +97,132 @@ __global__ void __launch_bounds__(256) k_prep(PrepArgs a) { prep_body(a, blockId
 __global__ void __launch_bounds__(256) k_prep_job(const PrepArgs *__restrict__ t, int j) {
   const PrepArgs a = t[j];
   prep_body(a, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// Alias columns of the entries with ALIAS_MIN <= lambda < ALIAS_MAX (rule C1b), one wave per
+// entry.  Lane 0 runs the inversion rule's FP64 recurrence without its cap until T_k reaches
+// 2^32 - 1 (that threshold then counts as 2^32: the FP64 sum can stall just below 1); with
+// k_lo = #{k : T_k = 0}, outcome k_lo + j has mass m_j = T_{k_lo+j} - T_{k_lo+j-1}
+// (T_{k_lo-1} = 0).  M = the smallest power of two >= the number of outcomes, at least 16.
+// Vose's construction then splits the masses over M columns of 2^32 / M words: "small"
+// (m < 2^32 / M) and "large" column stacks, both filled in ascending order; pop s from small and
+// l from large, column s keeps height m_s and alias l, m_l -= 2^32 / M - m_s, and l goes back on
+// the stack its mass now selects; columns left on the large stack are full.  All integer: the
+// table selects every outcome on exactly m_j of the 2^32 words.  The record keeps
+// k_lo << 12 | log2 M << 8 | KIND_ALIAS.
+constexpr int ALIAS_WAVES = 4;  // entries per 256-thread block
+
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i) {
+  __shared__ uint32_t m_s[ALIAS_WAVES][ALIAS_COLS];
+  __shared__ uint16_t small_s[ALIAS_WAVES][ALIAS_COLS], large_s[ALIAS_WAVES][ALIAS_COLS],
+      alias_s[ALIAS_WAVES][ALIAS_COLS];
+  __shared__ int nout_s[ALIAS_WAVES];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (i >= a.E) return;  // whole waves: i is wave-uniform
+  if ((a.rec[i].kk & 0xFFu) != KIND_ALIAS) return;
+  uint32_t *m = m_s[wv];
+  uint16_t *sm = small_s[wv], *lg = large_s[wv], *al = alias_s[wv];
+  for (int j = lane; j < ALIAS_COLS; j += 64) {
+    m[j] = 0u;
+    al[j] = (uint16_t)j;
+  }
+  wave_lds_sync();
+  if (lane == 0) {
+    const double l = a.lam[i];
+    double pk = exp(-l);
+    double F = pk;
+    int klo = -1, J = 0;
+    uint32_t prev = 0u;
+    for (int k = 0;; ++k) {
+      if (k > 0) {
+        pk = pk * l / (double)k;
+        F = F + pk;
+      }
+      const double t = floor(F * 4294967296.0);
+      if (t >= 4294967295.0) {  // the last word or more: the rest of the mass goes to outcome k
+        m[J++] = 0u - prev;     // 2^32 - T_{k-1}; prev >= 1 (the cdf passes 2^-32 first)
+        break;
+      }
+      const uint32_t T = (uint32_t)t;
+      if (klo < 0 && T > 0u) klo = k;
+      if (klo >= 0) {
+        m[J++] = T - prev;
+        prev = T;
+        if (J == ALIAS_COLS) {  // wider than the table (not reached below ALIAS_MAX)
+          atomicOr(a.status, STATUS_BAD_LAMBDA);
+          break;
+        }
+      }
+    }
+    int bits = 4;
+    while ((1 << bits) < J) ++bits;
+    nout_s[wv] = bits;
+    a.rec[i].kk = ((uint32_t)klo << 12) | ((uint32_t)bits << 8) | KIND_ALIAS;
+  }
+  wave_lds_sync();
+  const int bits = nout_s[wv];
+  const int M = 1 << bits;
+  const uint32_t cap = 1u << (32 - bits);
+  // stacks in ascending column order: each lane takes one column of every 64, ballots give the
+  // positions
+  int ns = 0, nl = 0;
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int c0 = 0; c0 < M; c0 += 64) {
+    const int j = c0 + lane;
+    const bool in = j < M;
+    const bool is_small = in && m[j] < cap;
+    const bool is_large = in && !(m[j] < cap);
+    const uint64_t bs = __ballot(is_small), bl = __ballot(is_large);
+    if (is_small) sm[ns + __popcll(bs & below)] = (uint16_t)j;
+    if (is_large) lg[nl + __popcll(bl & below)] = (uint16_t)j;
+    ns += __popcll(bs);
+    nl += __popcll(bl);
+  }
+  wave_lds_sync();
+  if (lane == 0) {
+    while (ns > 0 && nl > 0) {
+      const int sj = sm[--ns];
+      const int lj = lg[--nl];
+      al[sj] = (uint16_t)lj;
+      const uint32_t ml = m[lj] - (cap - m[sj]);
+      m[lj] = ml;
+      if (ml < cap)
+        sm[ns++] = (uint16_t)lj;
+      else
+        lg[nl++] = (uint16_t)lj;
+    }
+  }
+  wave_lds_sync();
+  // a column whose alias is itself is full (2^32 / M words, stored as 2^32 / M - 1: the last word
+  // then falls to the alias, the column itself)
+  uint32_t *out = a.alias + (size_t)i * ALIAS_COLS;
+  for (int j = lane; j < M; j += 64) {
+    const uint32_t h = al[j] == (uint16_t)j ? cap - 1u : m[j];
+    out[j] = (h << bits) | (uint32_t)al[j];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_prep_alias(PrepArgs a) {
+  prep_alias_body(a, (int)(blockIdx.x * ALIAS_WAVES + (threadIdx.x >> 6)));
+}
+__global__ void __launch_bounds__(256) k_prep_alias_job(const PrepArgs *__restrict__ t, int j) {
+  const PrepArgs a = t[j];
+  prep_alias_body(a, (int)(blockIdx.x * ALIAS_WAVES + (threadIdx.x >> 6)));
+}
+
+hipError_t launch_prep_alias(const PrepArgs &a, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep_alias, dim3((unsigned)((a.E + ALIAS_WAVES - 1) / ALIAS_WAVES)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_prep_alias_job(const PrepArgs *table, int j, int E, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep_alias_job, dim3((unsigned)((E + ALIAS_WAVES - 1) / ALIAS_WAVES)), dim3(256), 0, s, table, j);
+  return hipGetLastError();
 }
 
 hipError_t launch_prep(const PrepArgs &a, hipStream_t s) {
@@ -191,7 +319,7 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
     // the first thresholds are loaded only now: held across the Philox rounds they pushed the
     // scalar register file into spilling inside this loop
     __builtin_amdgcn_sched_barrier(0);
-    if (!(flags & GRP_PTRS) &&
+    if (!(flags & (GRP_PTRS | GRP_ALIAS)) &&
         (__ballot(wa.x > gr->t0m1[0]) | __ballot(wa.y > gr->t0m1[1]) | __ballot(wa.z > gr->t0m1[2]) |
          __ballot(wa.w > gr->t0m1[3]) | __ballot(wb.x > gr->t0m1[4]) | __ballot(wb.y > gr->t0m1[5]) |
          __ballot(wb.z > gr->t0m1[6]) | __ballot(wb.w > gr->t0m1[7])) == 0ull)
@@ -217,7 +345,7 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
         const EntryRec rq = ld_const(rec + i);  // padded to a multiple of GRP
         uint32_t n = 0;
         const uint32_t kind = rq.kk & 0xFFu;
-        if (kind != KIND_PTRS) {  // inversion; a KIND_ZERO entry never passes its first threshold
+        if (kind <= KIND_INV) {  // inversion; a KIND_ZERO entry never passes its first threshold
           // n = #{k < K : T_k <= u}, walking up while any lane of the wave is still above
           const uint32_t u = word_of(w, q);
           const uint32_t K = rq.kk >> 8;
@@ -241,6 +369,14 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
               }
             }
           }
+        } else if (kind == KIND_ALIAS) {
+          // one column read: n = k_lo + (c if r < height_c else alias_c), u = c << (32 - b) | r
+          // for M = 2^b columns; the record holds k_lo << 12 | b << 8 | kind
+          const uint32_t u = word_of(w, q);
+          const uint32_t b = (rq.kk >> 8) & 0xFu;
+          const uint32_t c = u >> (32u - b);
+          const uint32_t x = a.alias[(size_t)i * ALIAS_COLS + c];
+          n = (rq.kk >> 12) + ((u & (0xFFFFFFFFu >> b)) < (x >> b) ? c : (x & ((1u << b) - 1u)));
         } else {
           const PtrsConst c = ld_const(pc + i);
           n = ptrs_draw(c, p, i, TAG_PTRS, a.k0, a.k1, a.lnfact, ptrs_failed);

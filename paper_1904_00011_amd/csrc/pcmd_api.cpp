@@ -120,7 +120,7 @@ void pcmd_destroy(pcmd_ctx *c) {
   batch_destroy(c);
   Buf *bufs[] = {&c->rec,     &c->thr,     &c->pc,      &c->fl64,    &c->part,     &c->F,       &c->G,
                  &c->mom_part, &c->fft,    &c->mlp_act, &c->mlp_pre, &c->mlp_dza, &c->mlp_dzb, &c->mlp_grad,
-                 &c->mlp_part, &c->mlp_ws, &c->ll_part, &c->blk};
+                 &c->mlp_part, &c->mlp_ws, &c->ll_part, &c->blk, &c->alias};
   for (Buf *b : bufs) release(*b);
   if (c->lnfact) (void)hipFree(c->lnfact);
   if (c->status) (void)hipFree(c->status);
@@ -343,6 +343,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
     if ((r = ensure(c, c->rec, rec_bytes(E), "entry records"))) return r;
     if ((r = ensure(c, c->thr, (size_t)E * THR_STRIDE * 4, "thresholds"))) return r;
     if ((r = ensure(c, c->pc, (size_t)E * sizeof(PtrsConst), "rejection constants"))) return r;
+    if ((r = ensure(c, c->alias, (size_t)E * ALIAS_COLS * 4, "alias columns"))) return r;
   }
   if ((r = ensure(c, c->fl64, (size_t)E * BP * 8, "fluxes"))) return r;
   if ((r = ensure(c, c->part, (size_t)nchunks * S * B * npx * 8, "partial sums"))) return r;
@@ -413,8 +414,10 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
                 (uint32_t *)c->thr.p,
                 c->pc.p,
                 (double *)c->fl64.p,
-                c->status};
+                c->status,
+                (uint32_t *)c->alias.p};
     e = launch_prep(pa, s);
+    if (e == hipSuccess) e = launch_prep_alias(pa, s);
     if (e != hipSuccess) return hip_fail(c, e, "k_prep");
     SampleArgs a;
     a.E = E;
@@ -439,6 +442,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
     a.px1 = px1;
     a.status = c->status;
     a.lnfact = c->lnfact;
+    a.alias = pa.alias;
     {
       ScopedTimer tm(c, PCMD_TIMER_SAMPLE, (double)npx * (double)E, s);
       e = launch_sample(a, s);

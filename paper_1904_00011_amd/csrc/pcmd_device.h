@@ -19,7 +19,12 @@ constexpr uint32_t TAG_MAIN = 0, TAG_SPLIT = 1, TAG_SPLIT_X = 2, TAG_PTRS = 3, T
 constexpr uint32_t TAG_BLOCK = 6, TAG_BLOCK_PTRS = 7, TAG_STAR = 8, TAG_STAR_SPLIT = 9;
 
 // Entry kinds written by the preparation kernel.
-constexpr uint32_t KIND_ZERO = 0, KIND_INV = 1, KIND_PTRS = 2;
+constexpr uint32_t KIND_ZERO = 0, KIND_INV = 1, KIND_PTRS = 2, KIND_ALIAS = 3;
+// Alias rule for ALIAS_MIN <= lambda < ALIAS_MAX: M = 2^b <= ALIAS_COLS columns of 2^(32-b) words
+// each (column = top b bits of the inversion word), one packed word per column:
+// height << b | alias.  Each entry's table has room for ALIAS_COLS columns.
+constexpr double ALIAS_MIN = 2.0, ALIAS_MAX = 512.0;
+constexpr int ALIAS_COLS = 512;
 constexpr int THR_STRIDE = 64;       // thresholds per entry slot (K <= 63)
 constexpr int CHUNK = 1024;          // entries per slice (the number of slices is ceil(E / CHUNK))
 constexpr int PTRS_MAX_ATTEMPTS = 64;

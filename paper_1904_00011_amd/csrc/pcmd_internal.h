@@ -17,7 +17,7 @@ namespace pcmd {
 // thresholds inline (the rest in the threshold table) and K << 8 | kind.
 struct EntryRec {
   uint32_t T[3];  // T_0..T_2 (valid below K)
-  uint32_t kk;    // (number of thresholds K) << 8 | kind (KIND_ZERO, KIND_INV, KIND_PTRS)
+  uint32_t kk;    // (number of thresholds K, or k_lo of an alias entry) << 8 | kind
 };
 
 // Summary of eight consecutive entries (64 bytes, scalar loads), enough to finish a group in
@@ -30,7 +30,7 @@ struct GroupRec {
   uint32_t flags;  // GRP_INV | GRP_PTRS
   uint32_t pad[7];
 };
-constexpr uint32_t GRP_INV = 1u, GRP_PTRS = 2u;
+constexpr uint32_t GRP_INV = 1u, GRP_PTRS = 2u, GRP_ALIAS = 4u;
 
 // The record table holds E rounded up to a multiple of GRP entry records (the padding records
 // have KIND_ZERO), then one group record per GRP entries and one spare group record (the
@@ -56,6 +56,7 @@ struct PrepArgs {
   void *pc;            // [E] PtrsConst
   double *fl64;        // [E][BP]
   uint32_t *status;
+  uint32_t *alias;     // [E][ALIAS_COLS] packed alias columns (entries of KIND_ALIAS only)
 };
 
 // Sampler over (pixel block of 256, chunk of CHUNK entries) tiles (k_sample).
@@ -74,6 +75,7 @@ struct SampleArgs {
   int64_t px0, px1;
   uint32_t *status;
   const float *lnfact;
+  const uint32_t *alias;  // [E][ALIAS_COLS]
 };
 
 // Block-skip sampler (Poisson superposition, Sec. 2.1 footnote): per pixel and per block of
@@ -182,6 +184,8 @@ struct BatchSampleJob {
 hipError_t launch_entries(const pcmd_grid *g, const double *scale, double *lam, uint32_t *status, hipStream_t s);
 hipError_t launch_prep(const PrepArgs &a, hipStream_t s);
 hipError_t launch_prep_job(const PrepArgs *table, int j, int E, hipStream_t s);
+hipError_t launch_prep_alias(const PrepArgs &a, hipStream_t s);
+hipError_t launch_prep_alias_job(const PrepArgs *table, int j, int E, hipStream_t s);
 hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
 hipError_t launch_sample_persistent(const BatchSampleJob *jobs, int n_jobs, int total_items, int B, uint32_t *counter,
                                     int n_workgroups, hipStream_t s);

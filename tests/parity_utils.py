@@ -85,7 +85,18 @@ def explain_count_mismatches(lam, seed, px0, got, want):
     for r, i in bad:
         p = px0 + int(r)
         li = float(lam[i])
-        if li >= osamp.LAM_SWITCH:
+        if osamp.ALIAS_MIN <= li < osamp.ALIAS_MAX:
+            # alias rule: explained if exp(-lambda) one ulp off would change the table
+            e = math.exp(-li)
+            ref = osamp.alias_table(li)
+            moved = False
+            for d in (0.0, 1.0):
+                alt = osamp.alias_table(li, np.nextafter(e, d))
+                moved |= alt[:2] != ref[:2] or not np.array_equal(alt[2], ref[2])
+            if not moved:
+                unexplained.append((p, int(i)))
+            continue
+        if li >= osamp.ALIAS_MAX:
             unexplained.append((p, int(i)))
             continue
         w = orng.philox4x32_10(p, i // 4, orng.TAG_MAIN, 0, seed)[i % 4]

@@ -32,6 +32,76 @@ def test_inversion_counts_on_stratified_words(lam):
     assert np.all(np.abs(emp - stats.poisson.cdf(np.arange(12), lam)) <= 2 ** -16 + 1e-12)
 
 
+@pytest.mark.parametrize("lam", [2.0, 3.3, 10.0, 10.5, 37.3, 100.0, 255.5, 511.9])
+def test_alias_masses_match_poisson_pmf(lam):
+    """C1b: the cumulative outcome masses are the Poisson cdf times 2^32 to within the floor (and
+    the FP64 recurrence), the support is the cdf's, and the masses sum to 2^32."""
+    k_lo, m = S.alias_masses(lam)
+    m = np.array(m, dtype=np.int64)
+    assert m.sum() == 2 ** 32 and (m >= 0).all() and m[0] > 0
+    cum = np.cumsum(m)[:-1].astype(np.float64)
+    cdf = stats.poisson.cdf(k_lo + np.arange(len(cum)), lam) * 2.0 ** 32
+    assert np.max(np.abs(cum - cdf)) <= 1.0 + 2.0 ** 32 * 1e-12
+    # below k_lo the cdf is under 2^-32; above the last outcome less than 2^-31 is left
+    assert k_lo == 0 or stats.poisson.cdf(k_lo - 1, lam) < 2.0 ** -32
+    assert stats.poisson.sf(k_lo + len(m) - 1, lam) < 2.0 ** -31
+    assert S.alias_columns(len(m)) <= S.ALIAS_MAX_COLS
+
+
+@pytest.mark.parametrize("lam", [2.0, 10.0, 63.0, 255.5, 511.9])
+def test_alias_table_realises_the_masses_exactly(lam):
+    """Summing, over the M columns, the words that select each outcome (h_c to the column,
+    2^32/M - h_c to its alias) gives back every outcome mass exactly: the table draws the C1b
+    law to the last of the 2^32 words."""
+    k_lo, m = S.alias_masses(lam)
+    k2, bits, packed = S.alias_table(lam)
+    M = 1 << bits
+    cap = 2 ** 32 // M
+    assert k2 == k_lo and M == S.alias_columns(len(m)) and len(packed) == M
+    h = (packed >> bits).astype(np.int64)
+    a = (packed & (M - 1)).astype(np.int64)
+    # a column whose alias is itself is full (height 2^32/M, stored as 2^32/M - 1)
+    ht = np.where(a == np.arange(M), cap, h)
+    got = np.zeros(M, dtype=np.int64)
+    for c in range(M):
+        got[c] += ht[c]
+        got[a[c]] += cap - ht[c]
+    want = np.zeros(M, dtype=np.int64)
+    want[:len(m)] = m
+    assert np.array_equal(got, want)
+    # the draw, over every word of three columns (the most and least massive and a middle one),
+    # selects the column exactly h_c times and its alias the rest
+    for c in {int(np.argmax(want)), int(np.argmin(ht)), int(np.argmin(np.abs(ht - cap // 2)))}:
+        if cap > 1 << 24:
+            r = np.concatenate([np.arange(1 << 20, dtype=np.uint64), np.uint64(cap) - 1 - np.arange(1 << 20, dtype=np.uint64),
+                                np.uint64(ht[c]) + np.arange(-4, 4).astype(np.uint64) if 4 <= ht[c] < cap - 4 else
+                                np.zeros(0, np.uint64)])
+            r = np.unique(r)
+        else:
+            r = np.arange(cap, dtype=np.uint64)
+        u = (np.uint64(c) << np.uint64(32 - bits)) | r
+        n = S.count_from_alias(u, k_lo, bits, packed)
+        expect = np.where(r < np.uint64(ht[c]), k_lo + c, k_lo + a[c])
+        if a[c] == c:
+            expect[:] = k_lo + c
+        assert np.array_equal(n, expect)
+
+
+@pytest.mark.parametrize("lam", [12.0, 140.0])
+def test_alias_draws_chi_square(lam):
+    """Counts from the per-pixel sampler for an entry in the C1b range follow Poisson(lambda)."""
+    f = np.ones((1, 1), np.float32)
+    n = S.sample_pixels(np.array([lam]), f, 21, np.arange(200000), want_counts=True)["counts"][:, 0]
+    lo, hi = int(lam - 4 * math.sqrt(lam)), int(lam + 4 * math.sqrt(lam))
+    edges = np.arange(max(lo, 1), hi + 1)
+    obs = np.array([(n < edges[0]).sum()] + [(n == k).sum() for k in edges] + [(n > edges[-1]).sum()])
+    p = np.concatenate([[stats.poisson.cdf(edges[0] - 1, lam)], stats.poisson.pmf(edges, lam),
+                        [stats.poisson.sf(edges[-1], lam)]])
+    chi2 = ((obs - p * len(n)) ** 2 / (p * len(n))).sum()
+    assert stats.chi2.sf(chi2, len(obs) - 1) > 1e-4
+    assert abs(n.mean() - lam) < 5 * math.sqrt(lam / len(n))
+
+
 def test_ln32_accuracy():
     x = np.geomspace(2.0 ** -24, 2.0 ** 24, 200001).astype(np.float32)
     got = S.ln32(x).astype(np.float64)
