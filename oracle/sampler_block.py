@@ -5,8 +5,8 @@ summed mean.  The plain rule draws one count per (pixel, point); this rule draws
 block of BLOCK = 64 consecutive points
 
 * the block total N ~ Poisson(Lambda_b), Lambda_b = sum of the block's lambda_i (FP64, left to
-  right), by the same C1 / C2 rule as a single point: C1 inversion with word 0 of
-  Philox(pixel, b, TAG_BLOCK, 0), C2 transformed rejection with Philox(pixel, b, TAG_BLOCK_PTRS, j);
+  right): below 10 by C1 inversion with word 0 of Philox(pixel, b, TAG_BLOCK, 0), from 10 on by
+  C2 transformed rejection with Philox(pixel, b, TAG_BLOCK_PTRS, j);
 * the point of each of its N stars: star s takes word s mod 4 of Philox(pixel, b, TAG_STAR, s // 4)
   and lands on the first point i of the block whose cumulative threshold
   C_i = floor(2^32 sum_{k <= i} lambda_k / Lambda_b) (FP64, left to right; C_63 = 2^32) exceeds the

@@ -46,7 +46,8 @@ hipError_t launch_entries(const pcmd_grid *g, const double *scale, double *lam, 
 }
 
 // ---------------------------------------------------------------------------------------
-// Per-entry tables: inversion thresholds (lambda < 10) or rejection constants (lambda >= 10)
+// Per-entry tables: inversion thresholds (lambda < ALIAS_MIN), an alias marker (the columns come
+// from k_prep_alias) or rejection constants (lambda >= ALIAS_MAX)
 // and FP64 star fluxes laid out [E][BP] for scalar loads.
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {

@@ -3,8 +3,8 @@
 // A sum of independent Poisson counts is Poisson with the summed mean, and given that sum the
 // individual counts are multinomial.  Per pixel and per block b of SBLK = 64 consecutive entries:
 //   * the block total N ~ Poisson(Lambda_b), Lambda_b = sum of the block's lambda_i (FP64, left
-//     to right), by the same C1 / C2 rule as one entry: C1 inversion of word 0 of
-//     Philox(p, b, TAG_BLOCK, 0), C2 transformed rejection on Philox(p, b, TAG_BLOCK_PTRS, j);
+//     to right): below 10 by inversion of word 0 of Philox(p, b, TAG_BLOCK, 0), from 10 on by
+//     transformed rejection on Philox(p, b, TAG_BLOCK_PTRS, j) (the per-entry routines);
 //   * star s of the block takes word s mod 4 of Philox(p, b, TAG_STAR, s / 4) and lands on the
 //     first entry i whose cumulative threshold C_i = floor(2^32 cum_i / Lambda_b) exceeds it
 //     (entry i with probability lambda_i / Lambda_b to 2^-32);

@@ -220,7 +220,8 @@ __device__ inline uint32_t inversion_table(double l, uint32_t *t) {
   return K;
 }
 
-// C2 constants of a Poisson(l) count, l >= 10: computed in FP64 and rounded to FP32.
+// C2 constants of a Poisson(l) count (entries with l >= ALIAS_MAX, block totals with l >= 10):
+// computed in FP64 and rounded to FP32.
 __device__ inline PtrsConst ptrs_constants(double l) {
   const double slam = sqrt(l);
   const double bb = 0.931 + 2.53 * slam;

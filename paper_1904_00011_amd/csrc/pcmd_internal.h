@@ -23,7 +23,7 @@ struct EntryRec {
 // Summary of eight consecutive entries (64 bytes, scalar loads), enough to finish a group in
 // which no pixel of the wave draws a star: T_0 - 1 of each entry drawn by inversion
 // (0xFFFFFFFF otherwise, so u > t0m1 never holds) and the kinds present.  For inversion
-// entries T_0 >= 1 (lambda < 10), so u >= T_0 is exactly u > T_0 - 1.
+// entries T_0 >= 1 (lambda < ALIAS_MIN), so u >= T_0 is exactly u > T_0 - 1.
 constexpr int GRP = 8;  // entries per group record (two Philox blocks)
 struct GroupRec {
   uint32_t t0m1[GRP];
