@@ -9,6 +9,7 @@
 namespace pcmd {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ float gelu_f(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
@@ -17,60 +18,65 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 }
 
 // ---------------------------------------------------------------------------------------
-// C[M][N] = sum_k A(m, k) B(n, k) on v_mfma_f32_32x32x16_bf16.
-// A(m, k) = AT ? A[k lda + m] : A[m lda + k];  B(n, k) = BT ? B[k ldb + n] : B[n ldb + k].
+// C[M][N] = sum_k A[m][k] B[n][k] on v_mfma_f32_32x32x16_bf16 (both operands K-contiguous).
 // 128 x 128 block tile, 4 waves of 64 x 64 (2 x 2 MFMA tiles of 32 x 32), K step 32 staged in
 // LDS as [row][k] (row stride 40 halves = 80 bytes, so every 8-element run is 16-byte aligned).
 // Two LDS buffers: the next K step's global loads are issued into registers before the MFMAs of
-// the current one and written to the other buffer after them, one barrier per K step.
+// the current one and written to the other buffer after them, one barrier per K step.  An
+// operand stored K-major (A(m, k) = A[k][m]) is first transposed into the workspace by
+// k_transpose_bf16, so that every product runs this one layout with 16-byte loads and stores.
 // ---------------------------------------------------------------------------------------
 constexpr int GBM = 128, GBN = 128, GBK = 32, GLDS = GBK + 8;
+constexpr int GRUNS = GBM * GBK / (256 * 8);  // 8-element runs per thread and operand
 
-// One thread's share of a 128 x 32 operand tile: two runs of 8 elements.
+// One thread's share of a GBM x GBK operand tile: GRUNS runs of 8 elements.
 struct TileRegs {
-  bf16x8 v[2];
+  bf16x8 v[GRUNS];
 };
 
-template <bool T>
+// rows x K row-major: run idx takes row idx / (GBK / 8), k run idx mod (GBK / 8)
 __device__ __forceinline__ void load_regs(TileRegs &t, const __bf16 *__restrict__ src, int ld, int rows, int K,
                                           int r0, int k0, bool vec_ok) {
 #pragma unroll
-  for (int it = 0; it < 2; ++it) {
+  for (int it = 0; it < GRUNS; ++it) {
     const int idx = threadIdx.x + 256 * it;
-    if (!T) {
-      // rows x K row-major: (row idx/4, 8 consecutive k)
-      const int gr = r0 + (idx >> 2), gk = k0 + (idx & 3) * 8;
-      if (vec_ok && gr < rows && gk + 8 <= K) {
-        t.v[it] = *reinterpret_cast<const bf16x8 *>(src + (size_t)gr * ld + gk);
-      } else {
-#pragma unroll
-        for (int i = 0; i < 8; ++i) t.v[it][i] = (gr < rows && gk + i < K) ? src[(size_t)gr * ld + gk + i] : (__bf16)0.0f;
-      }
+    const int gr = r0 + idx / (GBK / 8), gk = k0 + (idx % (GBK / 8)) * 8;
+    if (vec_ok && gr < rows && gk + 8 <= K) {
+      t.v[it] = *reinterpret_cast<const bf16x8 *>(src + (size_t)gr * ld + gk);
     } else {
-      // K x rows row-major: (k idx/16, 8 consecutive rows)
-      const int gk = k0 + (idx >> 4), gr = r0 + (idx & 15) * 8;
-      if (vec_ok && gk < K && gr + 8 <= rows) {
-        t.v[it] = *reinterpret_cast<const bf16x8 *>(src + (size_t)gk * ld + gr);
-      } else {
 #pragma unroll
-        for (int i = 0; i < 8; ++i) t.v[it][i] = (gk < K && gr + i < rows) ? src[(size_t)gk * ld + gr + i] : (__bf16)0.0f;
-      }
+      for (int i = 0; i < 8; ++i) t.v[it][i] = (gr < rows && gk + i < K) ? src[(size_t)gr * ld + gk + i] : (__bf16)0.0f;
     }
   }
 }
 
-template <bool T>
 __device__ __forceinline__ void store_lds(__bf16 *lds, const TileRegs &t) {
 #pragma unroll
-  for (int it = 0; it < 2; ++it) {
+  for (int it = 0; it < GRUNS; ++it) {
     const int idx = threadIdx.x + 256 * it;
-    if (!T) {
-      *reinterpret_cast<bf16x8 *>(lds + (idx >> 2) * GLDS + (idx & 3) * 8) = t.v[it];
-    } else {  // transposed into [row][k]
-      const int kk = idx >> 4, rc = (idx & 15) * 8;
+    *reinterpret_cast<bf16x8 *>(lds + (idx / (GBK / 8)) * GLDS + (idx % (GBK / 8)) * 8) = t.v[it];
+  }
+}
+
+// dst[c][r] = src[r][c] for r < rows, c < cols (64 x 64 tiles through LDS, padded rows so that
+// the column reads hit distinct banks).
+__global__ void __launch_bounds__(256) k_transpose_bf16(const __bf16 *__restrict__ src, int lds_, int rows, int cols,
+                                                        __bf16 *__restrict__ dst, int ldd) {
+  __shared__ uint16_t tile[64][66];
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const uint16_t *s16 = reinterpret_cast<const uint16_t *>(src);
+  uint16_t *d16 = reinterpret_cast<uint16_t *>(dst);
 #pragma unroll
-      for (int i = 0; i < 8; ++i) lds[(rc + i) * GLDS + kk] = t.v[it][i];
-    }
+  for (int i = 0; i < 16; ++i) {
+    const int r = r0 + ty + 4 * i, c = c0 + tx;
+    tile[ty + 4 * i][tx] = (r < rows && c < cols) ? s16[(size_t)r * lds_ + c] : (uint16_t)0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int c = c0 + ty + 4 * i, r = r0 + tx;
+    if (c < cols && r < rows) d16[(size_t)c * ldd + r] = tile[tx][ty + 4 * i];
   }
 }
 
@@ -89,7 +95,7 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs &g, int row, int co
   }
 }
 
-template <bool AT, bool BT, int EPI>
+template <int EPI>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) __bf16 As[2][GBM * GLDS];
   __shared__ __attribute__((aligned(16))) __bf16 Bs[2][GBN * GLDS];
@@ -111,17 +117,17 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
   const int ke = g.part ? min(g.K, kb + g.kchunk) : g.K;
   const int nk = (ke - kb + GBK - 1) / GBK;
   TileRegs ra, rb;
-  load_regs<AT>(ra, g.A, g.lda, g.M, ke, bm, kb, va);
-  load_regs<BT>(rb, g.B, g.ldb, g.N, ke, bn, kb, vb);
-  store_lds<AT>(As[0], ra);
-  store_lds<BT>(Bs[0], rb);
+  load_regs(ra, g.A, g.lda, g.M, ke, bm, kb, va);
+  load_regs(rb, g.B, g.ldb, g.N, ke, bn, kb, vb);
+  store_lds(As[0], ra);
+  store_lds(Bs[0], rb);
   __syncthreads();
   for (int kt = 0; kt < nk; ++kt) {
     const int cur = kt & 1;
     const bool more = kt + 1 < nk;
     if (more) {
-      load_regs<AT>(ra, g.A, g.lda, g.M, ke, bm, kb + (kt + 1) * GBK, va);
-      load_regs<BT>(rb, g.B, g.ldb, g.N, ke, bn, kb + (kt + 1) * GBK, vb);
+      load_regs(ra, g.A, g.lda, g.M, ke, bm, kb + (kt + 1) * GBK, va);
+      load_regs(rb, g.B, g.ldb, g.N, ke, bn, kb + (kt + 1) * GBK, vb);
     }
     const __bf16 *as = As[cur];
     const __bf16 *bs = Bs[cur];
@@ -138,8 +144,8 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
         for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
     }
     if (more) {
-      store_lds<AT>(As[cur ^ 1], ra);
-      store_lds<BT>(Bs[cur ^ 1], rb);
+      store_lds(As[cur ^ 1], ra);
+      store_lds(Bs[cur ^ 1], rb);
     }
     __syncthreads();
   }
@@ -185,34 +191,66 @@ static int gemm_splits(int M, int N, int K, int &kchunk) {
   return (K + kchunk - 1) / kchunk;
 }
 
-size_t gemm_workspace_elems(int M, int N, int K) {
+// Workspace layout: [A transposed: M x ldk bf16][B transposed: N x ldk bf16][split-K partials:
+// splits x M x N FP32], each part 256-byte aligned and present only when needed.
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static int transposed_ld(int K) { return (K + 7) & ~7; }  // keeps the 16-byte loads of k_gemm
+
+size_t gemm_workspace_bytes(int M, int N, int K, bool at, bool bt) {
   int kchunk;
   const int splits = gemm_splits(M, N, K, kchunk);
-  return splits > 1 ? (size_t)splits * M * N : 0;
+  const size_t lk = (size_t)transposed_ld(K);
+  size_t b = 0;
+  if (at) b += align256((size_t)M * lk * 2);
+  if (bt) b += align256((size_t)N * lk * 2);
+  if (splits > 1) b += (size_t)splits * M * N * 4;
+  return b;
 }
 
-hipError_t launch_gemm(const GemmArgs &g0, bool at, bool bt, int epi, float *ws, size_t ws_elems, hipStream_t s) {
+static hipError_t launch_transpose(const __bf16 *src, int ld, int rows, int cols, __bf16 *dst, int ldd, hipStream_t s) {
+  dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((rows + 63) / 64));
+  hipLaunchKernelGGL(k_transpose_bf16, grid, dim3(256), 0, s, src, ld, rows, cols, dst, ldd);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(const GemmArgs &g0, bool at, bool bt, int epi, void *ws, size_t ws_bytes, hipStream_t s) {
   GemmArgs g = g0;
+  if (ws_bytes < gemm_workspace_bytes(g.M, g.N, g.K, at, bt)) return hipErrorInvalidValue;
+  char *w = (char *)ws;
+  const int lk = transposed_ld(g.K);
+  if (at) {  // A(m, k) = A[k][m]: K rows of M
+    __bf16 *t = (__bf16 *)w;
+    const hipError_t e = launch_transpose(g.A, g.lda, g.K, g.M, t, lk, s);
+    if (e != hipSuccess) return e;
+    g.A = t;
+    g.lda = lk;
+    w += align256((size_t)g.M * lk * 2);
+  }
+  if (bt) {
+    __bf16 *t = (__bf16 *)w;
+    const hipError_t e = launch_transpose(g.B, g.ldb, g.K, g.N, t, lk, s);
+    if (e != hipSuccess) return e;
+    g.B = t;
+    g.ldb = lk;
+    w += align256((size_t)g.N * lk * 2);
+  }
   int kchunk;
   const int splits = gemm_splits(g.M, g.N, g.K, kchunk);
-  const bool split = splits > 1 && ws && ws_elems >= (size_t)splits * g.M * g.N;
-  g.part = split ? ws : nullptr;
+  const bool split = splits > 1;
+  g.part = split ? (float *)w : nullptr;
   g.kchunk = split ? kchunk : g.K;
   dim3 grid((g.N + GBN - 1) / GBN, (g.M + GBM - 1) / GBM, split ? splits : 1);
   const unsigned rblocks = (unsigned)(((int64_t)g.M * g.N + 255) / 256);
-#define PCMD_GEMM_CASE(A_, B_, E_)                                                                   \
-  if (at == A_ && bt == B_ && epi == E_) {                                                           \
-    hipLaunchKernelGGL((k_gemm<A_, B_, E_>), grid, dim3(256), 0, s, g);                              \
+#define PCMD_GEMM_CASE(E_)                                                                             \
+  if (epi == E_) {                                                                                     \
+    hipLaunchKernelGGL((k_gemm<E_>), grid, dim3(256), 0, s, g);                                        \
     if (split) hipLaunchKernelGGL((k_gemm_splitk_reduce<E_>), dim3(rblocks), dim3(256), 0, s, g, splits); \
-    return hipGetLastError();                                                                        \
+    return hipGetLastError();                                                                          \
   }
-  PCMD_GEMM_CASE(false, false, EPI_STORE)
-  PCMD_GEMM_CASE(false, false, EPI_BIAS)
-  PCMD_GEMM_CASE(false, false, EPI_BIAS_GELU)
-  PCMD_GEMM_CASE(false, false, EPI_GELU_GRAD)
-  PCMD_GEMM_CASE(true, true, EPI_STORE)
-  PCMD_GEMM_CASE(true, false, EPI_STORE)
-  PCMD_GEMM_CASE(false, true, EPI_STORE)
+  PCMD_GEMM_CASE(EPI_STORE)
+  PCMD_GEMM_CASE(EPI_BIAS)
+  PCMD_GEMM_CASE(EPI_BIAS_GELU)
+  PCMD_GEMM_CASE(EPI_GELU_GRAD)
 #undef PCMD_GEMM_CASE
   return hipErrorInvalidValue;
 }
@@ -230,14 +268,35 @@ hipError_t launch_f32_to_bf16(const float *x, void *y, int64_t n, hipStream_t s)
   return hipGetLastError();
 }
 
-// dy = 2 (y - t) / (n M) stored in BF16; per-block partial sums of (y - t)^2 in FP64.
+// dy = 2 (y - t) / (n M) stored in BF16; per-block partial sums of (y - t)^2 in FP64.  Threads
+// take runs of four elements (16-byte loads, 8-byte stores) when the pointers allow it.
 __global__ void __launch_bounds__(256) k_mse_grad(const float *__restrict__ y, const float *__restrict__ t, int64_t n,
                                                   double scale, __bf16 *__restrict__ dy, double *__restrict__ part) {
   __shared__ double red[256];
   double s = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+  const float g = (float)(2.0 * scale);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool vec = ((((uintptr_t)y) | ((uintptr_t)t)) & 15) == 0 && (((uintptr_t)dy) & 7) == 0;
+  const int64_t n4 = vec ? n / 4 : 0;
+  for (int64_t i = first; i < n4; i += stride) {
+    const float4 a = reinterpret_cast<const float4 *>(y)[i];
+    const float4 b = reinterpret_cast<const float4 *>(t)[i];
+    const float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z, d3 = a.w - b.w;
+    bf16x4 o;
+    o[0] = (__bf16)(g * d0);
+    o[1] = (__bf16)(g * d1);
+    o[2] = (__bf16)(g * d2);
+    o[3] = (__bf16)(g * d3);
+    reinterpret_cast<bf16x4 *>(dy)[i] = o;
+    s += (double)d0 * (double)d0;
+    s += (double)d1 * (double)d1;
+    s += (double)d2 * (double)d2;
+    s += (double)d3 * (double)d3;
+  }
+  for (int64_t i = 4 * n4 + first; i < n; i += stride) {
     const float d = y[i] - t[i];
-    dy[i] = (__bf16)((float)(2.0 * scale) * d);
+    dy[i] = (__bf16)(g * d);
     s += (double)d * (double)d;
   }
   red[threadIdx.x] = s;
@@ -249,12 +308,17 @@ __global__ void __launch_bounds__(256) k_mse_grad(const float *__restrict__ y, c
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_loss_final(const double *__restrict__ part, int nb, double scale, float *__restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int k = 0; k < nb; ++k) s += part[k];
-    out[0] = (float)(s * scale);
+// Loss = scale x the sum of the MSE_BLOCKS partials, by a fixed tree over one block.
+__global__ void __launch_bounds__(256) k_loss_final(const double *__restrict__ part, int nb, double scale,
+                                                    float *__restrict__ out) {
+  __shared__ double red[256];
+  red[threadIdx.x] = threadIdx.x < (unsigned)nb ? part[threadIdx.x] : 0.0;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < (unsigned)k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) out[0] = (float)(red[0] * scale);
 }
 
 constexpr int MSE_BLOCKS = 256;
@@ -264,21 +328,38 @@ hipError_t launch_mse_grad(const float *y, const float *t, int64_t n, double sca
   hipLaunchKernelGGL(k_mse_grad, dim3(MSE_BLOCKS), dim3(256), 0, s, y, t, n, scale, (__bf16 *)dy, part);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !loss_out) return e;
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, s, part, MSE_BLOCKS, scale, loss_out);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, part, MSE_BLOCKS, scale, loss_out);
   return hipGetLastError();
 }
 
-// db[m] = sum_n dz[n][m] (FP32, fixed order over n)
-__global__ void __launch_bounds__(256) k_colsum(const __bf16 *__restrict__ dz, int n, int m, float *__restrict__ db) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= m) return;
+// db[m] = sum_n dz[n][m] in FP32.  A block takes 64 columns (one per lane, so every row read is
+// 128 contiguous bytes) and its COLSUM_WAVES waves split the rows: wave w sums rows w,
+// w + COLSUM_WAVES, ... in order, and the partial sums are added in wave order.  The order is
+// fixed by n alone, so results do not depend on the launch.
+constexpr int COLSUM_WAVES = 16;
+
+__global__ void __launch_bounds__(64 * COLSUM_WAVES) k_colsum(const __bf16 *__restrict__ dz, int n, int m,
+                                                              float *__restrict__ db) {
+  __shared__ float part[COLSUM_WAVES][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
   float s = 0.0f;
-  for (int r = 0; r < n; ++r) s += (float)dz[(size_t)r * m + c];
-  db[c] = s;
+  if (c < m) {
+#pragma unroll 8
+    for (int r = w; r < n; r += COLSUM_WAVES) s += (float)dz[(size_t)r * m + c];
+  }
+  part[w][lane] = s;
+  __syncthreads();
+  if (w == 0 && c < m) {
+    float t = part[0][lane];
+#pragma unroll
+    for (int k = 1; k < COLSUM_WAVES; ++k) t += part[k][lane];
+    db[c] = t;
+  }
 }
 
 hipError_t launch_colsum(const void *dz, int n, int m, float *db, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum, dim3((m + 255) / 256), dim3(256), 0, s, (const __bf16 *)dz, n, m, db);
+  hipLaunchKernelGGL(k_colsum, dim3((m + 63) / 64), dim3(64 * COLSUM_WAVES), 0, s, (const __bf16 *)dz, n, m, db);
   return hipGetLastError();
 }
 

@@ -78,7 +78,7 @@ hipError_t forward_impl(pcmd_ctx *c, const pcmd_mlp *net, const Layout &lay, int
     }
     {
       ScopedTimer tm(c, PCMD_TIMER_GEMM, 2.0 * (double)n * (double)din * (double)dout, s);
-      e = launch_gemm(g, false, false, last ? EPI_BIAS : EPI_BIAS_GELU, (float *)c->mlp_ws.p, c->mlp_ws.n / 4, s);
+      e = launch_gemm(g, false, false, last ? EPI_BIAS : EPI_BIAS_GELU, c->mlp_ws.p, c->mlp_ws.n, s);
     }
     aoff += (int64_t)n * din;
     poff += (int64_t)n * dout;
@@ -99,15 +99,15 @@ int ensure_mlp_scratch(pcmd_ctx *c, const Layout &lay, int n) {
   if ((r = ensure(c, c->mlp_dzb, (size_t)n * lay.dmax * 2, "network gradients"))) return r;
   if ((r = ensure(c, c->mlp_grad, (size_t)lay.params * 4, "parameter gradients"))) return r;
   if ((r = ensure(c, c->mlp_part, 256 * 8, "loss partials"))) return r;
-  // split-K workspace: the largest over the forward, weight-gradient and input-gradient products
+  // GEMM workspace: the largest over the forward, weight-gradient and input-gradient products
   size_t ws = 0;
   for (int l = 0; l < lay.L; ++l) {
     const int din = lay.d[l], dout = lay.d[l + 1];
-    ws = std::max(ws, gemm_workspace_elems(n, dout, din));
-    ws = std::max(ws, gemm_workspace_elems(dout, din, n));
-    ws = std::max(ws, gemm_workspace_elems(n, din, dout));
+    ws = std::max(ws, gemm_workspace_bytes(n, dout, din, false, false));
+    ws = std::max(ws, gemm_workspace_bytes(dout, din, n, true, true));
+    ws = std::max(ws, gemm_workspace_bytes(n, din, dout, false, false));
   }
-  if (ws && (r = ensure(c, c->mlp_ws, ws * 4, "split-K workspace"))) return r;
+  if (ws && (r = ensure(c, c->mlp_ws, ws, "GEMM workspace"))) return r;
   return PCMD_OK;
 }
 
@@ -210,7 +210,7 @@ int pcmd_mlp_train_step(pcmd_ctx *c, const pcmd_mlp *net, int32_t n, const float
       gw.ldc = din;
       {
         ScopedTimer tm(c, PCMD_TIMER_GEMM, 2.0 * (double)n * (double)din * (double)dout, s);
-        e = launch_gemm(gw, true, true, EPI_STORE, (float *)c->mlp_ws.p, c->mlp_ws.n / 4, s);
+        e = launch_gemm(gw, true, true, EPI_STORE, c->mlp_ws.p, c->mlp_ws.n, s);
       }
       if (e == hipSuccess) e = launch_colsum(dz, n, dout, grad + lay.off[l] + (int64_t)dout * din, s);
       if (e == hipSuccess && l > 0) {
@@ -228,7 +228,7 @@ int pcmd_mlp_train_step(pcmd_ctx *c, const pcmd_mlp *net, int32_t n, const float
         gx.ldz = din;
         {
           ScopedTimer tm(c, PCMD_TIMER_GEMM, 2.0 * (double)n * (double)din * (double)dout, s);
-          e = launch_gemm(gx, false, false, EPI_GELU_GRAD, (float *)c->mlp_ws.p, c->mlp_ws.n / 4, s);
+          e = launch_gemm(gx, false, false, EPI_GELU_GRAD, c->mlp_ws.p, c->mlp_ws.n, s);
         }
         __bf16 *tmp = dz;
         dz = dz2;
@@ -292,13 +292,13 @@ int pcmd_gemm_bf16(pcmd_ctx *c, int32_t M, int32_t N, int32_t K, const uint16_t 
   g.ldb = ldb;
   g.C = C;
   g.ldc = ldc;
-  const size_t ws = gemm_workspace_elems(M, N, K);
+  const size_t ws = gemm_workspace_bytes(M, N, K, a_trans != 0, b_trans != 0);
   int r;
-  if (ws && (r = ensure(c, c->mlp_ws, ws * 4, "split-K workspace"))) return r;
+  if (ws && (r = ensure(c, c->mlp_ws, ws, "GEMM workspace"))) return r;
   hipError_t e;
   {
     ScopedTimer tm(c, PCMD_TIMER_GEMM, 2.0 * (double)M * (double)N * (double)K, (hipStream_t)stream);
-    e = launch_gemm(g, a_trans != 0, b_trans != 0, EPI_STORE, (float *)c->mlp_ws.p, c->mlp_ws.n / 4,
+    e = launch_gemm(g, a_trans != 0, b_trans != 0, EPI_STORE, c->mlp_ws.p, c->mlp_ws.n,
                     (hipStream_t)stream);
   }
   if (e != hipSuccess) return hip_fail(c, e, "pcmd_gemm_bf16");

@@ -34,9 +34,10 @@ struct AdamArgs {
   float lr, beta1, beta2, eps, bc1, bc2;
 };
 
-// Workspace (FP32 elements) launch_gemm needs for an M x N x K product (0: no split over K).
-size_t gemm_workspace_elems(int M, int N, int K);
-hipError_t launch_gemm(const GemmArgs &g, bool at, bool bt, int epi, float *ws, size_t ws_elems, hipStream_t s);
+// Workspace (bytes) launch_gemm needs for an M x N x K product: transposed copies of K-major
+// operands (at: A(m, k) = A[k][m]; bt: B(n, k) = B[k][n]) and split-K partials.
+size_t gemm_workspace_bytes(int M, int N, int K, bool at, bool bt);
+hipError_t launch_gemm(const GemmArgs &g, bool at, bool bt, int epi, void *ws, size_t ws_bytes, hipStream_t s);
 hipError_t launch_f32_to_bf16(const float *x, void *y, int64_t n, hipStream_t s);
 hipError_t launch_mse_grad(const float *y, const float *t, int64_t n, double scale, void *dy, double *part,
                            float *loss_out, hipStream_t s);

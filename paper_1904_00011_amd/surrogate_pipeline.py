@@ -86,8 +86,11 @@ class SurrogateWorkflow:
         n = x.shape[0]
         loss = torch.empty(1, dtype=torch.float32, device=self.dev)
         hist = []
+        # every step's batch indices in one copy: a host-to-device copy per step would wait for
+        # the previous step's kernels and leave the GPU idle while the next step is launched
+        all_idx = torch.randint(0, n, (steps, batch), generator=g).to(self.dev)
         for s in range(steps):
-            idx = torch.randint(0, n, (batch,), generator=g).to(self.dev)
+            idx = all_idx[s]
             xb = x.index_select(0, idx).contiguous()
             tb = t.index_select(0, idx).contiguous()
             cur = lr * (lr_final / lr) ** (s / max(steps - 1, 1))
