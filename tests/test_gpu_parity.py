@@ -228,6 +228,21 @@ def test_edge_cases(ctx):
     _full_compare(ctx, lam1, f1, obs1)
 
 
+def test_rule_boundaries(ctx):
+    """Entries on both sides of every switch of the count rule (inversion / alias at lambda = 2,
+    alias / rejection at 512), the widest alias tables (M = 512) and the narrowest (M = 32), with
+    and without a dust split: every count against the oracle."""
+    lam = np.array([1.9999999, 2.0, 2.0000001, 3.7, 9.99, 10.0, 63.5, 255.0, 300.0, 511.9, 511.999999,
+                    512.0, 512.5, 700.0, 0.0, 0.7])
+    E = len(lam)
+    f32 = np.linspace(0.2, 1.0, 2 * E).reshape(2, E).astype(np.float32) * 1e-3
+    for dust in (0, 2):
+        obs = si.Obs(nim=20, seed=4242 + dust, dmod=24.0, psf=None, noise_model=0, dust_model=dust, dust_frac=0.5,
+                     dust_R=(3.0, 2.0))
+        _print_case("rule_boundaries", E=E, dust=dust)
+        _full_compare(ctx, lam, f32, obs)
+
+
 def test_determinism_and_streams(ctx):
     import torch
     G, lam, f32, obs = _headline_lam(4.0, seed=1004, stride=5)
