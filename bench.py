@@ -613,7 +613,7 @@ def main():
         # each per pixel and band; Hess: read the two magnitude planes it bins, 4 B each per
         # pixel, write the bins) over the timed launches' average duration, against 8 TB/s
         "conv_roofline": hbm_roofline(8.0 * 3 * obs_d.nim ** 2, c_ms / max(c_n, 1),
-                                      "PSF convolution (FFT chain)" if obs_d.psf.shape[-1] >= 31 else "PSF convolution"),
+                                      "PSF convolution (FFT chain)" if obs_d.psf.shape[-1] >= 48 else "PSF convolution (direct)"),
         "hess_roofline": hbm_roofline(8.0 * obs_d.nim ** 2 + 4.0 * nh * nh, h_ms / max(h_n, 1), "k_hess"),
         "roofline": {"bound": "alu", "kernel": "k_sample", "achieved": achieved / 1e12,
                      "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "T lane-instr/s (VALU)",

@@ -158,7 +158,8 @@ enum { PCMD_SAMPLER_POINT = 0, PCMD_SAMPLER_BLOCK = 1 };
  *                 r = 4 ry + rx take the PSF psf[b][r] (psf is [dev][B][16][K][K]): the paper's
  *                 sub-pixel model, each region with a PSF shifted by a fraction of a pixel
  *                 (Sec. 2.2).  Direct path only (AUTO picks it; FFT is PCMD_E_UNSUPPORTED)
- *  conv_path      AUTO, DIRECT or FFT (FFT needs nim a power of two, 8..4096)
+ *  conv_path      AUTO (direct below K = 48, FFT from 48 on where supported), DIRECT or FFT (FFT
+ *                 needs nim a power of two, 8..4096)
  *  noise_model    NONE, GAUSS_MAG (m += sigma_b z) or SHOT (c = G t_b 10^(0.4 zp_b) + sky_b,
  *                 c' = c + sqrt(c) z, m = -2.5 log10((c' - sky_b)/t_b) + zp_b; +inf if <= 0)
  *  sampler        POINT (0): one Poisson count per (pixel, point), the paper's rule (Sec. 2.1).

@@ -186,7 +186,8 @@ __device__ __forceinline__ void loglike_bins_body(const LoglikeArgs &a, int blk)
   __shared__ double shd[LL_THREADS];
   const int t = threadIdx.x;
   unsigned long long sm = 0, sd = 0;
-  for (int j = t; j < nbins; j += LL_THREADS) {
+#pragma unroll 8
+  for (int j = t; j < nbins; j += LL_THREADS) {  // unrolled: the loads overlap
     sm += hm[j];
     sd += hd[j];
   }
@@ -215,10 +216,19 @@ __device__ __forceinline__ void loglike_bins_body(const LoglikeArgs &a, int blk)
 }
 
 __device__ __forceinline__ void loglike_final_body(const LoglikeArgs &a) {
-  if (threadIdx.x != 0) return;
+  // the 64 lanes fetch the block sums together; lane 0 adds them in block order
+  __shared__ double ps[256];
   const int nb = loglike_blocks(a.nbins);
   double r = 0.0;
-  for (int b = 0; b < nb; ++b) r += a.part[b];
+  for (int b0 = 0; b0 < nb; b0 += 256) {
+    const int n = min(256, nb - b0);
+    for (int k = threadIdx.x; k < n; k += 64) ps[k] = a.part[b0 + k];
+    __syncthreads();
+    if (threadIdx.x == 0)
+      for (int k = 0; k < n; ++k) r += ps[k];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
   if (a.mode != PCMD_LL_POISSON) {
     const double Cm = a.mom_m[0] / a.mom_m[2], Mm = a.mom_m[1] / a.mom_m[2];
     const double Cd = a.mom_d[0] / a.mom_d[2], Md = a.mom_d[1] / a.mom_d[2];
