@@ -343,9 +343,10 @@ def run_scatter(args):
 
 
 def run_ablation(args):
-    """Block-skip sampler (Poisson superposition over 64-point blocks) against the per-point rule
-    on the headline workload at fixed log Npix = 1 .. 5: sampler kernel time and whole
-    likelihood evaluations per second of each, the same parameters and seeds for both."""
+    """Block-skip sampler (Poisson superposition over 64-point blocks) and the hybrid (block rule
+    below a block sum of 10, per-point rule above) against the per-point rule on the headline
+    workload at fixed log Npix = 1 .. 5: sampler time (the hybrid's two kernels together) and
+    whole likelihood evaluations per second of each, the same parameters and seeds for all."""
     import torch
 
     import paper_1904_00011_amd as P
@@ -370,7 +371,7 @@ def run_ablation(args):
     for lnp in (1.0, 2.0, 3.0, 4.0, 5.0):
         params = [si.draw_headline_params(1000 + k, log_npix=lnp) for k in range(args.steps + args.warmup)]
         row = {"log_npix": lnp}
-        for name, sampler in (("point", P.SAMPLER_POINT), ("block", P.SAMPLER_BLOCK)):
+        for name, sampler in (("point", P.SAMPLER_POINT), ("block", P.SAMPLER_BLOCK), ("hybrid", P.SAMPLER_HYBRID)):
             runs = [(m, dataclasses.replace(o, sampler=sampler)) for m, o in params]
             for m, o in runs[:args.warmup]:
                 out.copy_(ev.loglike(m, o, data_hess, data_mom))
@@ -387,9 +388,11 @@ def run_ablation(args):
             row[name] = {"sample_ms": s_ms / max(s_n, 1), "evals_per_s": args.steps / (t1 - t0)}
         row["sampler_speedup"] = row["point"]["sample_ms"] / row["block"]["sample_ms"]
         row["eval_speedup"] = row["block"]["evals_per_s"] / row["point"]["evals_per_s"]
+        row["hybrid_sampler_speedup"] = row["point"]["sample_ms"] / row["hybrid"]["sample_ms"]
         rows.append(row)
         print(f"[ablation] log Npix {lnp}: k_sample {row['point']['sample_ms']:.3f} ms, k_sample_block "
-              f"{row['block']['sample_ms']:.3f} ms", file=sys.stderr, flush=True)
+              f"{row['block']['sample_ms']:.3f} ms, hybrid {row['hybrid']['sample_ms']:.3f} ms", file=sys.stderr,
+              flush=True)
     ctx.close()
     at2 = next(r for r in rows if r["log_npix"] == 2.0)
     print(json.dumps({

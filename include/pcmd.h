@@ -141,7 +141,7 @@ typedef struct {
 enum { PCMD_DUST_NONE = 0, PCMD_DUST_SCREEN = 1, PCMD_DUST_LOGNORMAL = 2 };
 enum { PCMD_CONV_AUTO = 0, PCMD_CONV_DIRECT = 1, PCMD_CONV_FFT = 2 };
 enum { PCMD_NOISE_NONE = 0, PCMD_NOISE_GAUSS_MAG = 1, PCMD_NOISE_SHOT = 2 };
-enum { PCMD_SAMPLER_POINT = 0, PCMD_SAMPLER_BLOCK = 1 };
+enum { PCMD_SAMPLER_POINT = 0, PCMD_SAMPLER_BLOCK = 1, PCMD_SAMPLER_HYBRID = 2 };
 
 /* Observation and nuisance model of one simulation.
  *  nim            image side (pixels = nim*nim), 1..8192
@@ -168,8 +168,11 @@ enum { PCMD_SAMPLER_POINT = 0, PCMD_SAMPLER_BLOCK = 1 };
  *                 point by its cumulative share of the block's lambda (to 2^-32) and its dust
  *                 screen by one uniform per star.  A different random stream; cheaper where most
  *                 blocks draw no star (low Npix).  Each block's lambda sum must be < 2^22
- *                 (else PCMD_E_INVAL at pcmd_sync, the block drawn as 0).  pcmd_simulate only
- *                 (pcmd_batch_run rejects it with PCMD_E_UNSUPPORTED) */
+ *                 (else PCMD_E_INVAL at pcmd_sync, the block drawn as 0).
+ *                 HYBRID (2): blocks whose lambda sum is below 10 by the BLOCK rule, the other
+ *                 blocks' points by the POINT rule (the cheaper rule on each side; any block sum
+ *                 allowed).  BLOCK and HYBRID: pcmd_simulate only (pcmd_batch_run rejects them
+ *                 with PCMD_E_UNSUPPORTED) */
 typedef struct {
   int32_t nim;
   int32_t dust_model;

@@ -475,6 +475,9 @@ def simulate_flux(lam, flux32, obs, px0=0, px1=None, want_counts=False, px=None)
     if getattr(obs, "sampler", 0) == 1:
         from .sampler_block import sample_pixels_block
         s = sample_pixels_block(lam, flux32, obs.seed, px, obs.dust_model, obs.dust_frac, want_counts)
+    elif getattr(obs, "sampler", 0) == 2:
+        from .sampler_block import sample_pixels_hybrid
+        s = sample_pixels_hybrid(lam, flux32, obs.seed, px, obs.dust_model, obs.dust_frac, want_counts)
     else:
         s = sample_pixels(lam, flux32, obs.seed, px, obs.dust_model, obs.dust_frac, want_counts)
     F = pixel_flux(s["F_clr"], s["F_red"], px, obs.seed, obs.dmod, obs.dust_model, obs.dust_mu,

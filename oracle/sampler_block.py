@@ -18,6 +18,9 @@ Given N the points are multinomial with probabilities lambda_i / Lambda_b, so th
 counts are again independent Poisson(lambda_i): the same law as the plain rule with fewer random
 numbers where most blocks are empty (Lambda_b << 1), but a different stream.
 
+The hybrid rule draws the blocks with Lambda_b < 10 by the block rule and the entries of the
+other blocks one by one with the per-point rule: the cheaper rule on each side of the crossover.
+
 Pins (tests/test_oracle_block.py): per-point means and variances against lambda_i, block totals
 against the Poisson pmf by chi-square, independence of two points of one block (correlation), the
 cumulative thresholds against the block's probabilities, and the split fraction.
@@ -109,3 +112,35 @@ def sample_pixels_block(lam: np.ndarray, flux32: np.ndarray, seed: int, px: np.n
     F_clr = f @ (counts - red).T.astype(np.float64)
     F_red = f @ red.T.astype(np.float64)
     return dict(F_clr=F_clr, F_red=F_red, counts=counts if want_counts else None, red=red if want_counts else None)
+
+
+def hybrid_split(lam: np.ndarray):
+    """The hybrid rule's partition: (lambda of the blocks drawn by the block rule, lambda of the
+    blocks drawn entry by entry), each with the other blocks' entries set to zero.  A block takes
+    the block rule when Lambda_b < 10 (its total is then drawn by inversion)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    tot = block_sums(lam)
+    lam_blk = lam.copy()
+    lam_pt = lam.copy()
+    for b, L in enumerate(tot):
+        sl = slice(b * BLOCK, (b + 1) * BLOCK)
+        if L < LAM_SWITCH:
+            lam_pt[sl] = 0.0
+        else:
+            lam_blk[sl] = 0.0
+    return lam_blk, lam_pt
+
+
+def sample_pixels_hybrid(lam: np.ndarray, flux32: np.ndarray, seed: int, px: np.ndarray, dust_model: int = 0,
+                         dust_frac: float = 0.5, want_counts: bool = False):
+    """Hybrid rule: blocks with Lambda_b < 10 by the block rule (this module's stream), the other
+    blocks' entries by the per-point rule (sampler.sample_pixels' stream).  Same law as both."""
+    from .sampler import sample_pixels
+    lam_blk, lam_pt = hybrid_split(lam)
+    a = sample_pixels_block(lam_blk, flux32, seed, px, dust_model, dust_frac, want_counts)
+    c = sample_pixels(lam_pt, flux32, seed, px, dust_model, dust_frac, want_counts)
+    out = dict(F_clr=a["F_clr"] + c["F_clr"], F_red=a["F_red"] + c["F_red"], counts=None, red=None)
+    if want_counts:
+        out["counts"] = a["counts"] + c["counts"]
+        out["red"] = a["red"] + c["red"]
+    return out

@@ -23,7 +23,7 @@ MDF = {"single": 0, "gauss": 1}
 DUST_NONE, DUST_SCREEN, DUST_LOGNORMAL = 0, 1, 2
 CONV_AUTO, CONV_DIRECT, CONV_FFT = 0, 1, 2
 NOISE_NONE, NOISE_GAUSS_MAG, NOISE_SHOT = 0, 1, 2
-SAMPLER_POINT, SAMPLER_BLOCK = 0, 1
+SAMPLER_POINT, SAMPLER_BLOCK, SAMPLER_HYBRID = 0, 1, 2
 LL_POISSON, LL_GAUSS_PAPER, LL_GAUSS_LITERAL = 0, 1, 2
 LL_ACCUMULATE = 0x100  # OR-ed into mode: add to out instead of storing
 TIMER_SAMPLE, TIMER_CONV, TIMER_HESS, TIMER_BATCH, TIMER_GEMM = 0, 1, 2, 3, 4

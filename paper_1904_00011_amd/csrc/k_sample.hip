@@ -61,6 +61,7 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
       atomicOr(a.status, STATUS_BAD_LAMBDA);
       l = 0.0;
     }
+    if (a.brec && a.brec[i / SBLK].pad[0] == 0u) l = 0.0;  // hybrid: the block rule draws this block
     if (l >= ALIAS_MAX) {
       ((PtrsConst *)a.pc)[i] = ptrs_constants(l);
       r.kk = KIND_PTRS;

@@ -49,7 +49,9 @@ __global__ void __launch_bounds__(256) k_prep_block(BlockPrepArgs a) {
   for (int k = 0; k <= lane; ++k) cum += lam_s[w][k];
   const double L = __shfl(cum, SBLK - 1, 64);  // Lambda_b = cum_63
   BlockRec r{{0u, 0u, 0u}, KIND_ZERO, (uint32_t)SBLK - 1u, {0u, 0u, 0u}};
-  if (!(L < 4194304.0)) {  // the block total must stay in the per-entry rule's range
+  if (a.hybrid && L >= 10.0) {  // hybrid: this block's entries go to the per-point rule
+    r.pad[0] = 1u;
+  } else if (!(L < 4194304.0)) {  // the block total must stay in the per-entry rule's range
     if (lane == 0) atomicOr(a.status, STATUS_BAD_LAMBDA);
   } else if (L > 0.0) {
     // C_l = floor(2^32 cum_l / Lambda_b); the last entry with stars reaches cum = Lambda_b
@@ -173,8 +175,12 @@ __global__ void __launch_bounds__(256) k_sample_block(BlockSampleArgs a) {
   const size_t plane = (size_t)a.npx;
 #pragma unroll
   for (int k = 0; k < B; ++k) {
-    a.part[((size_t)(chunk * S + 0) * B + k) * plane + p] = acc_c[k];
-    if (S == 2) a.part[((size_t)(chunk * S + 1) * B + k) * plane + p] = acc_r[k];
+    double *pc = a.part + ((size_t)(chunk * S + 0) * B + k) * plane + p;
+    *pc = a.accumulate ? *pc + acc_c[k] : acc_c[k];
+    if (S == 2) {
+      double *pr = a.part + ((size_t)(chunk * S + 1) * B + k) * plane + p;
+      *pr = a.accumulate ? *pr + acc_r[k] : acc_r[k];
+    }
   }
 }
 

@@ -56,7 +56,7 @@ int validate_sim(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, const char
     return fail(c, PCMD_E_UNSUPPORTED, "%s: the 4 x 4 sub-pixel PSF grid runs on the direct path", who);
   if (o->conv_path < 0 || o->conv_path > 2) return fail(c, PCMD_E_INVAL, "%s: bad conv_path", who);
   if (o->noise_model < 0 || o->noise_model > 2) return fail(c, PCMD_E_INVAL, "%s: bad noise_model", who);
-  if (o->sampler != PCMD_SAMPLER_POINT && o->sampler != PCMD_SAMPLER_BLOCK)
+  if (o->sampler < PCMD_SAMPLER_POINT || o->sampler > PCMD_SAMPLER_HYBRID)
     return fail(c, PCMD_E_INVAL, "%s: bad sampler %d", who, o->sampler);
   for (int b = 0; b < B; ++b) {
     if (o->noise_model == PCMD_NOISE_GAUSS_MAG && !(o->noise_sigma_mag[b] >= 0.0 && isfinite(o->noise_sigma_mag[b])))
@@ -336,14 +336,15 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   const int nchunks = (E + CHUNK - 1) / CHUNK;
   const int split_mode = split_mode_of(o);
   const int S = split_mode == SPLIT_NONE ? 1 : 2;
-  const bool block = o->sampler == PCMD_SAMPLER_BLOCK;
+  const bool block = o->sampler == PCMD_SAMPLER_BLOCK, hybrid = o->sampler == PCMD_SAMPLER_HYBRID;
   const int nb = superblocks(E);
   // block-skip tables: [nb] BlockRec, [nb][THR_STRIDE] thresholds, [nb] PtrsConst, [nb][SBLK] cth
   const size_t blk_rec = (size_t)nb * sizeof(BlockRec), blk_thr = (size_t)nb * THR_STRIDE * 4,
                blk_pc = (size_t)nb * sizeof(PtrsConst), blk_cth = (size_t)nb * SBLK * 4;
-  if (block) {
+  if (block || hybrid) {
     if ((r = ensure(c, c->blk, blk_rec + blk_thr + blk_pc + blk_cth, "block tables"))) return r;
-  } else {
+  }
+  if (!block) {
     if ((r = ensure(c, c->rec, rec_bytes(E), "entry records"))) return r;
     if ((r = ensure(c, c->thr, (size_t)E * THR_STRIDE * 4, "thresholds"))) return r;
     if ((r = ensure(c, c->pc, (size_t)E * sizeof(PtrsConst), "rejection constants"))) return r;
@@ -362,51 +363,56 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
     if (e == hipSuccess && dbg->reddened) e = launch_fill_u32(dbg->reddened, 0u, (px1 - px0) * E, s);
     if (e != hipSuccess) return hip_fail(c, e, "clearing debug counts");
   }
-  if (block) {
+  // block totals, tables and cumulative thresholds (block-skip and hybrid samplers)
+  BlockPrepArgs pb{};
+  if (block || hybrid) {
     char *base = (char *)c->blk.p;
-    BlockPrepArgs pb{E,
-                     B,
-                     BP,
-                     nb,
-                     iso->lam,
-                     iso->flux,
-                     (BlockRec *)base,
-                     (uint32_t *)(base + blk_rec),
-                     base + blk_rec + blk_thr,
-                     (uint32_t *)(base + blk_rec + blk_thr + blk_pc),
-                     (double *)c->fl64.p,
-                     c->status};
+    pb = BlockPrepArgs{E,
+                       B,
+                       BP,
+                       nb,
+                       iso->lam,
+                       iso->flux,
+                       (BlockRec *)base,
+                       (uint32_t *)(base + blk_rec),
+                       base + blk_rec + blk_thr,
+                       (uint32_t *)(base + blk_rec + blk_thr + blk_pc),
+                       (double *)c->fl64.p,
+                       c->status,
+                       hybrid ? 1 : 0};
+  }
+  BlockSampleArgs ab{};
+  if (block || hybrid) {
     e = launch_prep_block(pb, s);
     if (e != hipSuccess) return hip_fail(c, e, "k_prep_block");
-    BlockSampleArgs a;
-    a.E = E;
-    a.B = B;
-    a.BP = BP;
-    a.npx = (int)npx;
-    a.nb = nb;
-    a.nchunks = nchunks;
-    a.S = S;
-    a.k0 = k0;
-    a.k1 = k1;
-    a.split_mode = split_mode;
-    a.split_q = split_q_of(o);
-    a.brec = pb.brec;
-    a.thr = pb.thr;
-    a.pc = pb.pc;
-    a.cth = pb.cth;
-    a.fl64 = pb.fl64;
-    a.part = (double *)c->part.p;
-    a.dbg_counts = dbg ? dbg->counts : nullptr;
-    a.dbg_red = dbg ? dbg->reddened : nullptr;
-    a.px0 = px0;
-    a.px1 = px1;
-    a.status = c->status;
-    a.lnfact = c->lnfact;
-    {
-      ScopedTimer tm(c, PCMD_TIMER_SAMPLE, (double)npx * (double)E, s);
-      e = launch_sample_block(a, s);
-    }
-    if (e != hipSuccess) return hip_fail(c, e, "k_sample_block");
+    ab.E = E;
+    ab.B = B;
+    ab.BP = BP;
+    ab.npx = (int)npx;
+    ab.nb = nb;
+    ab.nchunks = nchunks;
+    ab.S = S;
+    ab.k0 = k0;
+    ab.k1 = k1;
+    ab.split_mode = split_mode;
+    ab.split_q = split_q_of(o);
+    ab.brec = pb.brec;
+    ab.thr = pb.thr;
+    ab.pc = pb.pc;
+    ab.cth = pb.cth;
+    ab.fl64 = pb.fl64;
+    ab.part = (double *)c->part.p;
+    ab.dbg_counts = dbg ? dbg->counts : nullptr;
+    ab.dbg_red = dbg ? dbg->reddened : nullptr;
+    ab.px0 = px0;
+    ab.px1 = px1;
+    ab.status = c->status;
+    ab.lnfact = c->lnfact;
+    ab.accumulate = hybrid ? 1 : 0;  // hybrid: k_sample has written the partials first
+  }
+  if (block) {
+    ScopedTimer tm(c, PCMD_TIMER_SAMPLE, (double)npx * (double)E, s);
+    e = launch_sample_block(ab, s);
   } else {
     PrepArgs pa{E,
                 B,
@@ -419,7 +425,8 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
                 c->pc.p,
                 (double *)c->fl64.p,
                 c->status,
-                (uint32_t *)c->alias.p};
+                (uint32_t *)c->alias.p,
+                hybrid ? pb.brec : nullptr};
     e = launch_prep(pa, s);
     if (e == hipSuccess) e = launch_prep_alias(pa, s);
     if (e != hipSuccess) return hip_fail(c, e, "k_prep");
@@ -447,12 +454,11 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
     a.status = c->status;
     a.lnfact = c->lnfact;
     a.alias = pa.alias;
-    {
-      ScopedTimer tm(c, PCMD_TIMER_SAMPLE, (double)npx * (double)E, s);
-      e = launch_sample(a, s);
-    }
-    if (e != hipSuccess) return hip_fail(c, e, "k_sample");
+    ScopedTimer tm(c, PCMD_TIMER_SAMPLE, (double)npx * (double)E, s);
+    e = launch_sample(a, s);
+    if (e == hipSuccess && hybrid) e = launch_sample_block(ab, s);
   }
+  if (e != hipSuccess) return hip_fail(c, e, "sampler");
 
   ReduceArgs ra;
   ra.B = B;

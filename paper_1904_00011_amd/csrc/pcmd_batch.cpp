@@ -102,7 +102,8 @@ static int batch_validate(pcmd_ctx *c, int n_jobs, const pcmd_job *jobs, const p
     if (uses_fft(&jobs[j].obs))
       return fail(c, PCMD_E_UNSUPPORTED, "%s: job %d resolves to the FFT convolution; batches use the direct path", who, j);
     if (jobs[j].obs.sampler != PCMD_SAMPLER_POINT)
-      return fail(c, PCMD_E_UNSUPPORTED, "%s: job %d asks for the block-skip sampler; batches use the per-point rule", who, j);
+      return fail(c, PCMD_E_UNSUPPORTED, "%s: job %d asks for the block-skip or hybrid sampler; batches use the per-point rule",
+                  who, j);
   }
   if (g->b_blue < 0 || g->b_blue >= B || g->b_red < 0 || g->b_red >= B || g->b_mag < 0 || g->b_mag >= B)
     return fail(c, PCMD_E_INVAL, "%s: band index out of range", who);

@@ -45,6 +45,8 @@ constexpr uint32_t STATUS_PTRS_RETRY = 1u, STATUS_BAD_LAMBDA = 2u, STATUS_BAD_PS
 
 enum SplitMode { SPLIT_NONE = 0, SPLIT_HALF = 1, SPLIT_GENERAL = 2, SPLIT_ALL = 3 };
 
+struct BlockRec;  // block-skip sampler record, below
+
 // Per-entry tables built from lambda and the star fluxes (k_prep).
 struct PrepArgs {
   int E, B, BP;
@@ -57,6 +59,7 @@ struct PrepArgs {
   double *fl64;        // [E][BP]
   uint32_t *status;
   uint32_t *alias;     // [E][ALIAS_COLS] packed alias columns (entries of KIND_ALIAS only)
+  const BlockRec *brec;  // hybrid sampler: entries of blocks without pad[0] set are drawn as 0
 };
 
 // Sampler over (pixel block of 256, chunk of CHUNK entries) tiles (k_sample).
@@ -84,6 +87,7 @@ constexpr int SBLK = 64;  // entries per block = lanes of a wave
 inline int superblocks(int E) { return (E + SBLK - 1) / SBLK; }
 // One block's record (32 bytes, scalar loads): the total's rule as in EntryRec, and istar, the
 // first entry of the block whose cumulative threshold is 2^32 (the last entry with stars).
+// pad[0] = 1 marks a block the hybrid sampler leaves to the per-point rule.
 struct BlockRec {
   uint32_t T[3];
   uint32_t kk;
@@ -100,6 +104,7 @@ struct BlockPrepArgs {
   uint32_t *cth;       // [nb][SBLK] cumulative thresholds below istar, 0xFFFFFFFF from istar on
   double *fl64;        // [E][BP]
   uint32_t *status;
+  int hybrid;          // blocks with Lambda_b >= 10 go to the per-point rule (pad[0] = 1)
 };
 struct BlockSampleArgs {
   int E, B, BP, npx, nb, nchunks, S;
@@ -116,6 +121,7 @@ struct BlockSampleArgs {
   int64_t px0, px1;
   uint32_t *status;
   const float *lnfact;
+  int accumulate;  // add to the partial sums k_sample wrote (hybrid) instead of storing
 };
 
 // Chunk reduction and dust / distance epilogue (k_reduce).

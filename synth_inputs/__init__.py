@@ -218,7 +218,7 @@ class Obs:
     exptime: tuple = (3620.0, 3235.0, 3000.0)
     zp: tuple = (26.0, 25.5, 25.0)
     sky: tuple = (0.0, 0.0, 0.0)
-    sampler: int = 0             # 0 one count per (pixel, point); 1 block-skip superposition
+    sampler: int = 0             # 0 one count per (pixel, point); 1 block-skip superposition; 2 hybrid
 
 
 @dataclass

@@ -129,8 +129,8 @@ def test_edge_cases(ctx):
 
 def test_law_matches_per_point_rule(ctx):
     """Same law as the per-point rule (no oracle involved): over 65,536 pixels the per-point star
-    totals of both samplers are Poisson(65,536 lambda_i) to a few sigma, and the total of each
-    block has the Poisson variance."""
+    totals of the three samplers are Poisson(65,536 lambda_i) to a few sigma, and the total of
+    each block has the Poisson variance."""
     r = np.random.default_rng(21)
     lam = np.concatenate([r.uniform(0.0, 0.02, 128), r.uniform(0.05, 0.4, 64), np.full(40, 0.25)])
     E = len(lam)
@@ -139,7 +139,7 @@ def test_law_matches_per_point_rule(ctx):
     obs = si.Obs(nim=256, seed=77, dmod=25.0, psf=None, noise_model=0, dust_model=2, dust_frac=0.3,
                  dust_R=(3.0, 2.0), sampler=1)
     _print_case("block_law", E=E, npx=npx)
-    for sampler in (1, 0):
+    for sampler in (1, 0, 2):
         g = pu.gpu_simulate(ctx, lam, f32, dataclasses.replace(obs, sampler=sampler), window=(0, npx),
                             want_flux=False)
         n = g["counts"]
@@ -153,6 +153,48 @@ def test_law_matches_per_point_rule(ctx):
             assert abs(Nb.var() / L - 1.0) < 6 * np.sqrt(2.0 / npx) + 0.02, (sampler, b, Nb.var(), L)
 
 
+def _compare_window_hybrid(ctx, lam, f32, obs, px0, px1):
+    g = pu.gpu_simulate(ctx, lam, f32, obs, window=(px0, px1))
+    Fo, s = osamp.simulate_flux(lam, f32, obs, px0, px1, want_counts=True)
+    lam_blk, lam_pt = sb.hybrid_split(lam)
+    on_blk = lam_blk > 0
+    gb, ob = np.where(on_blk, g["counts"], 0), np.where(on_blk, s["counts"], 0)
+    gp, op_ = np.where(on_blk, 0, g["counts"]), np.where(on_blk, 0, s["counts"])
+    assert not pu.explain_block_mismatches(lam_blk, obs.seed, px0, gb, ob)
+    assert not pu.explain_count_mismatches(lam_pt, obs.seed, px0, gp, op_)
+    assert np.array_equal(g["red"], s["red"])
+    assert np.max(pu.rel_err(g["flux_pre"][:, px0:px1], Fo)) <= pu.FLUX_RTOL
+    return g, s
+
+
+@pytest.mark.parametrize("log_npix,dust_model,frac", [(1.0, 2, 0.5), (3.5, 1, 0.3), (4.5, 2, 1.0), (5.0, 0, 0.5)])
+def test_hybrid_variants(ctx, log_npix, dust_model, frac):
+    """Hybrid sampler (blocks with Lambda_b < 10 by the block rule, the others per point) on the
+    headline grid's every 10th point, 24x24: every count and flux against the oracle."""
+    G = si.headline_grid().subsample(10)
+    model, obs = si.draw_headline_params(1003, log_npix=log_npix)
+    lam, _, f32 = oe.build_entries(model, G)
+    obs = dataclasses.replace(obs, nim=24, dust_model=dust_model, dust_frac=frac, sampler=2,
+                              psf=si.psf_stack(5, (1.0, 1.2, 1.4)))
+    tot = sb.block_sums(lam)
+    _print_case("hybrid_variant", log_npix=log_npix, dust=dust_model, frac=frac,
+                block_rule=int(((tot > 0) & (tot < 10)).sum()), point_rule=int((tot >= 10).sum()))
+    _compare_window_hybrid(ctx, lam, f32, obs, 0, 24 * 24)
+
+
+def test_hybrid_full_size_sampled(ctx):
+    """256x256, all 52,500 points at Npix = 1e4 (both rules in use): two sampled windows."""
+    model, obs = si.draw_headline_params(1000, log_npix=4.0)
+    obs = dataclasses.replace(obs, sampler=2)
+    lam, _, f32 = oe.build_entries(model, si.headline_grid())
+    tot = sb.block_sums(lam)
+    _print_case("hybrid_full_size", E=len(lam), block_rule=int(((tot > 0) & (tot < 10)).sum()),
+                point_rule=int((tot >= 10).sum()))
+    assert ((tot > 0) & (tot < 10)).sum() > 50 and (tot >= 10).sum() > 50
+    for px0 in (0, 40001):
+        _compare_window_hybrid(ctx, lam, f32, obs, px0, px0 + 40)
+
+
 def test_validation(ctx):
     import paper_1904_00011_amd as P
     f32 = np.ones((2, 64), np.float32)
@@ -163,8 +205,10 @@ def test_validation(ctx):
     assert ei.value.code == P._lib.E_INVAL
     ctx.sync()
     with pytest.raises(P.PcmdError) as ei:
-        pu.gpu_simulate(ctx, np.full(64, 0.1), f32, dataclasses.replace(obs, sampler=2), want_flux=False)
+        pu.gpu_simulate(ctx, np.full(64, 0.1), f32, dataclasses.replace(obs, sampler=3), want_flux=False)
     assert ei.value.code == P._lib.E_INVAL
+    # the hybrid rule leaves such a block to the per-point rule: no error
+    pu.gpu_simulate(ctx, np.full(64, 1e5), f32, dataclasses.replace(obs, sampler=2), want_flux=False)
     # batches keep the per-point rule
     import torch
     dev = torch.device("cuda")

@@ -60,3 +60,25 @@ def test_category_thresholds_and_split_fraction():
     assert none["red"].sum() == 0 and np.array_equal(none["counts"], all_red["counts"])
     # fluxes are the counts weighted by the point fluxes
     assert np.allclose(out["F_clr"][0] + out["F_red"][0], out["counts"].sum(axis=1))
+
+
+def test_hybrid_partition_and_law():
+    """The hybrid rule splits the entries by block total (the two parts add up to the input, no
+    block in both), draws each part with its own rule (so each part equals that rule on the part
+    alone), and keeps the Poisson law per entry."""
+    from oracle import sampler as sp
+    lam = _lam()
+    blk, pt = sb.hybrid_split(lam)
+    assert np.array_equal(blk + pt, lam) and not np.any((blk > 0) & (pt > 0))
+    tot = sb.block_sums(lam)
+    assert all((tot[b] < 10) == (pt[64 * b:64 * (b + 1)].sum() == 0) for b in range(len(tot)))
+    f = np.ones((1, len(lam)), np.float32)
+    px = np.arange(20000)
+    h = sb.sample_pixels_hybrid(lam, f, 99, px, dust_model=2, dust_frac=0.3, want_counts=True)
+    a = sb.sample_pixels_block(blk, f, 99, px[:500], dust_model=2, dust_frac=0.3, want_counts=True)
+    c = sp.sample_pixels(pt, f, 99, px[:500], dust_model=2, dust_frac=0.3, want_counts=True)
+    assert np.array_equal(h["counts"][:500], a["counts"] + c["counts"])
+    assert np.array_equal(h["red"][:500], a["red"] + c["red"])
+    n = h["counts"]
+    se = np.sqrt(np.maximum(lam, 1e-12) / len(px))
+    assert np.all(np.abs(n.mean(axis=0) - lam) <= 5 * se + 1e-12)
