@@ -186,10 +186,21 @@ __device__ __forceinline__ void loglike_bins_body(const LoglikeArgs &a, int blk)
   __shared__ double shd[LL_THREADS];
   const int t = threadIdx.x;
   unsigned long long sm = 0, sd = 0;
-#pragma unroll 8
-  for (int j = t; j < nbins; j += LL_THREADS) {  // unrolled: the loads overlap
-    sm += hm[j];
-    sd += hd[j];
+  // batches of 8 bins per thread loaded into separate registers before they are added, so the
+  // 16 loads are in flight together (one register reused for every load serialised them)
+  for (int j0 = t; j0 < nbins; j0 += 8 * LL_THREADS) {
+    uint32_t vm[8], vd[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u * LL_THREADS;
+      vm[u] = j < nbins ? hm[j] : 0u;
+      vd[u] = j < nbins ? hd[j] : 0u;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sm += vm[u];
+      sd += vd[u];
+    }
   }
   const double Nm = (double)block_sum_ordered(sm, shu);
   const double Nd = (double)block_sum_ordered(sd, shu);
@@ -199,7 +210,8 @@ __device__ __forceinline__ void loglike_bins_body(const LoglikeArgs &a, int blk)
     const double m = (double)hm[j], d = (double)hd[j];
     if (mode == PCMD_LL_POISSON) {
       const double lam = Nd * (m + eps) / (Nm + eps * (double)nbins);
-      acc = d * log(lam) - lam - lgamma(d + 1.0);
+      const double lf = (a.lnfact64 && d < (double)LNFACT64_N) ? a.lnfact64[(int)d] : lgamma(d + 1.0);
+      acc = d * log(lam) - lam - lf;
     } else if (mode == PCMD_LL_GAUSS_PAPER) {
       const double mh = m * Nd / Nm;
       const double sig = fmax(sqrt(d + mh), 2.0);

@@ -396,7 +396,8 @@ hipError_t launch_adam_layer(const AdamArgs &a, hipStream_t s) {
 
 // Surrogate log-likelihood: one block per sample, lam_j = N_d exp(y_j - max) / sum exp(y - max).
 __global__ void __launch_bounds__(256) k_surrogate_loglike(const float *__restrict__ y, int nbins,
-                                                           const uint32_t *__restrict__ d, double *__restrict__ out) {
+                                                           const uint32_t *__restrict__ d, double *__restrict__ out,
+                                                           const double *__restrict__ lnfact64, int nlf) {
   __shared__ double red[256];
   const float *ys = y + (size_t)blockIdx.x * nbins;
   const int t = threadIdx.x;
@@ -435,7 +436,8 @@ __global__ void __launch_bounds__(256) k_surrogate_loglike(const float *__restri
   for (int j = t; j < nbins; j += 256) {
     const double lam = nd * exp((double)ys[j] - mx) / se;
     const double dj = (double)d[j];
-    acc += dj * log(lam) - lam - lgamma(dj + 1.0);
+    const double lf = (lnfact64 && dj < (double)nlf) ? lnfact64[(int)dj] : lgamma(dj + 1.0);
+    acc += dj * log(lam) - lam - lf;
   }
   red[t] = acc;
   __syncthreads();
@@ -446,8 +448,9 @@ __global__ void __launch_bounds__(256) k_surrogate_loglike(const float *__restri
   if (t == 0) out[blockIdx.x] = red[0];
 }
 
-hipError_t launch_surrogate_loglike(const float *y, int n, int nbins, const uint32_t *d, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_surrogate_loglike, dim3(n), dim3(256), 0, s, y, nbins, d, out);
+hipError_t launch_surrogate_loglike(const float *y, int n, int nbins, const uint32_t *d, double *out,
+                                   const double *lnfact64, int nlf, hipStream_t s) {
+  hipLaunchKernelGGL(k_surrogate_loglike, dim3(n), dim3(256), 0, s, y, nbins, d, out, lnfact64, nlf);
   return hipGetLastError();
 }
 

@@ -55,13 +55,22 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
   const int E = a.E, B = a.B, BP = a.BP;
   EntryRec r{{0u, 0u, 0u}, KIND_ZERO};
   if (i < E) {
-    for (int b = 0; b < BP; ++b) a.fl64[(size_t)i * BP + b] = b < B ? (double)a.flux[(size_t)b * E + i] : 0.0;
+    // every load before the first store (the output could alias the inputs for the compiler,
+    // which otherwise waits for each load in turn)
+    double fv[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {  // band min(b, B - 1) is always in range: no branch around the load
+      const float v = a.flux[(size_t)min(b, B - 1) * E + i];
+      fv[b] = b < B ? (double)v : 0.0;
+    }
     double l = a.lam[i];
+    const bool block_rule = a.brec && a.brec[i / SBLK].pad[0] == 0u;  // hybrid: the block rule draws it
+    for (int b = 0; b < BP; ++b) a.fl64[(size_t)i * BP + b] = fv[b];
     if (!(l >= 0.0 && l < 4194304.0)) {  // NaN, negative or too large: drawn as zero, reported
       atomicOr(a.status, STATUS_BAD_LAMBDA);
       l = 0.0;
     }
-    if (a.brec && a.brec[i / SBLK].pad[0] == 0u) l = 0.0;  // hybrid: the block rule draws this block
+    if (block_rule) l = 0.0;
     if (l >= ALIAS_MAX) {
       ((PtrsConst *)a.pc)[i] = ptrs_constants(l);
       r.kk = KIND_PTRS;

@@ -33,8 +33,14 @@ __global__ void __launch_bounds__(256) k_prep_block(BlockPrepArgs a) {
   const int i = b * SBLK + lane;
   double l = 0.0;
   if (i < a.E) {
-    for (int k = 0; k < a.BP; ++k) a.fl64[(size_t)i * a.BP + k] = k < a.B ? (double)a.flux[(size_t)k * a.E + i] : 0.0;
+    double fv[4];  // every load before the first store
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {  // band min(k, B - 1) is always in range: no branch around the load
+      const float v = a.flux[(size_t)min(k, a.B - 1) * a.E + i];
+      fv[k] = k < a.B ? (double)v : 0.0;
+    }
     l = a.lam[i];
+    for (int k = 0; k < a.BP; ++k) a.fl64[(size_t)i * a.BP + k] = fv[k];
     if (!(l >= 0.0 && l < 4194304.0)) {  // NaN, negative or too large: drawn as zero, reported
       atomicOr(a.status, STATUS_BAD_LAMBDA);
       l = 0.0;

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -99,14 +100,18 @@ int pcmd_create(pcmd_ctx **out, int hip_device) {
     acc = acc + log((double)k);
     tab[k] = (float)acc;
   }
+  // ln k! in FP64 for the likelihoods' ln d_j! (k < LNFACT64_N; lgamma beyond)
+  std::vector<double> lf(LNFACT64_N);
+  for (int k = 0; k < LNFACT64_N; ++k) lf[k] = std::lgamma((double)k + 1.0);
   if (hipMalloc(&c->lnfact, sizeof tab) != hipSuccess || hipMalloc(&c->status, 8) != hipSuccess ||
-      hipMalloc(&c->counter, 8) != hipSuccess) {
+      hipMalloc(&c->counter, 8) != hipSuccess || hipMalloc(&c->lnfact64, LNFACT64_N * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     pcmd_destroy(c);
     return PCMD_E_NOMEM;
   }
   uint32_t zeros[2] = {0u, 0u};
   if (hipMemcpy(c->lnfact, tab, sizeof tab, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->lnfact64, lf.data(), LNFACT64_N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->status, zeros, 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->counter, zeros, 8, hipMemcpyHostToDevice) != hipSuccess) {
     pcmd_destroy(c);
@@ -127,6 +132,7 @@ void pcmd_destroy(pcmd_ctx *c) {
                  &c->mlp_part, &c->mlp_ws, &c->ll_part, &c->blk, &c->alias};
   for (Buf *b : bufs) release(*b);
   if (c->lnfact) (void)hipFree(c->lnfact);
+  if (c->lnfact64) (void)hipFree(c->lnfact64);
   if (c->status) (void)hipFree(c->status);
   if (c->counter) (void)hipFree(c->counter);
   delete c;
@@ -576,7 +582,7 @@ int pcmd_loglike(pcmd_ctx *c, const uint32_t *hm, const uint32_t *hd, int32_t nb
   DeviceGuard dg(c->device);
   int r;
   if ((r = ensure(c, c->ll_part, (size_t)loglike_blocks(nbins) * 8, "likelihood partials"))) return r;
-  LoglikeArgs a{hm, hd, nbins, mode, mom_m, mom_d, eps, out, (double *)c->ll_part.p, accumulate ? 1 : 0};
+  LoglikeArgs a{hm, hd, nbins, mode, mom_m, mom_d, eps, out, (double *)c->ll_part.p, accumulate ? 1 : 0, c->lnfact64};
   hipError_t e = launch_loglike(a, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(c, e, "k_loglike");
   c->err.clear();

@@ -291,7 +291,7 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
     hh.use_lds = hess_use_lds(p->nbins);
     ha[j] = hh;
     la[j] = LoglikeArgs{hh.hess, hess_data,    p->nbins,    mode, hh.moments, mom_data, eps, logl_out + j,
-                        (double *)p->ll_part.p + (size_t)j * loglike_blocks(p->nbins), 0};
+                        (double *)p->ll_part.p + (size_t)j * loglike_blocks(p->nbins), 0, c->lnfact64};
   }
   for (int t = 0; t < p->n_jobs; ++t) {
     const int j = p->order[t];

@@ -32,6 +32,7 @@ struct pcmd_ctx {
   Buf rec, thr, pc, fl64, part, F, G, mom_part, fft, ll_part, blk, alias;
   Buf mlp_act, mlp_pre, mlp_dza, mlp_dzb, mlp_grad, mlp_part, mlp_ws;
   float *lnfact = nullptr;     // [256]
+  double *lnfact64 = nullptr;  // [LNFACT64_N] ln k! in FP64 (likelihoods)
   uint32_t *status = nullptr;  // [1]
   uint32_t *counter = nullptr; // [1]
   pcmd_batch_plan *batch = nullptr;

@@ -178,7 +178,9 @@ struct LoglikeArgs {
   double *out;
   double *part;  // [loglike_blocks(nbins)] block sums
   int accumulate;  // add to *out instead of storing
+  const double *lnfact64;  // ln k! for k < LNFACT64_N (host lgamma), or NULL
 };
+constexpr int LNFACT64_N = 4096;
 
 // Sampler job of the persistent batched kernel: its tiles are items [item0, item0 + items).
 struct BatchSampleJob {

@@ -269,7 +269,7 @@ int pcmd_surrogate_loglike(pcmd_ctx *c, const float *y, int32_t n, int32_t nbins
   if (!y || !hess_data || !out || n < 1 || nbins < 1 || nbins > 1 << 20)
     return fail(c, PCMD_E_INVAL, "pcmd_surrogate_loglike: bad argument");
   DeviceGuard dg(c->device);
-  hipError_t e = launch_surrogate_loglike(y, n, nbins, hess_data, out, (hipStream_t)stream);
+  hipError_t e = launch_surrogate_loglike(y, n, nbins, hess_data, out, c->lnfact64, LNFACT64_N, (hipStream_t)stream);
   if (e != hipSuccess) return hip_fail(c, e, "pcmd_surrogate_loglike");
   c->err.clear();
   return PCMD_OK;

@@ -43,6 +43,8 @@ hipError_t launch_mse_grad(const float *y, const float *t, int64_t n, double sca
                            float *loss_out, hipStream_t s);
 hipError_t launch_colsum(const void *dz, int n, int m, float *db, hipStream_t s);
 hipError_t launch_adam_layer(const AdamArgs &a, hipStream_t s);
-hipError_t launch_surrogate_loglike(const float *y, int n, int nbins, const uint32_t *d, double *out, hipStream_t s);
+// lnfact64[k] = ln k! for k < nlf (lgamma beyond, or everywhere when lnfact64 is NULL)
+hipError_t launch_surrogate_loglike(const float *y, int n, int nbins, const uint32_t *d, double *out,
+                                   const double *lnfact64, int nlf, hipStream_t s);
 
 }  // namespace pcmd
