@@ -74,7 +74,15 @@ __host__ __device__ inline int conv_tile_w(int K) { return CT_X + conv_kp(K) + 4
 size_t conv_direct_lds_bytes(int K) {
   return ((size_t)(CT_Y + K - 1) * conv_tile_w(K) + (size_t)K * conv_kp(K)) * sizeof(float);
 }
+// Row splits RS > 1: RS groups of 256 threads share one output tile, group g taking PSF rows
+// [g K / RS, (g + 1) K / RS); groups 1.. leave their FP64 sums in LDS and group 0 adds them in
+// group order.  Used when the image is too small for one-group blocks to fill the chip.
+constexpr int CONV_RS = 4;
+static size_t conv_split_lds_bytes(int K) {
+  return conv_direct_lds_bytes(K) + (size_t)(CONV_RS - 1) * 256 * 4 * sizeof(double);
+}
 
+template <int RS>
 __device__ __forceinline__ void conv_direct_body(const ConvArgs &ca) {
   extern __shared__ float4 lds4[];
   float *tile = reinterpret_cast<float *>(lds4);
@@ -96,7 +104,7 @@ __device__ __forceinline__ void conv_direct_body(const ConvArgs &ca) {
   const float *Fb = F + (size_t)b * N * N;
   const float *psf = ca.psf + (size_t)blockIdx.z * K * K;
   // tile[ty][tx] = F[(oy - h + ty) mod N][(ox - h + tx) mod N]; columns past the halo are padding
-  for (int idx = threadIdx.x; idx < TW * TH; idx += 256) {
+  for (int idx = threadIdx.x; idx < TW * TH; idx += 256 * RS) {
     const int ty = idx / TW, tx = idx - ty * TW;
     int gy = (oy - h + ty) % N;
     if (gy < 0) gy += N;
@@ -104,15 +112,17 @@ __device__ __forceinline__ void conv_direct_body(const ConvArgs &ca) {
     if (gx < 0) gx += N;
     tile[idx] = Fb[(size_t)gy * N + gx];
   }
-  for (int idx = threadIdx.x; idx < K * Kp; idx += 256) {
+  for (int idx = threadIdx.x; idx < K * Kp; idx += 256 * RS) {
     const int a = idx / Kp, c = idx - a * Kp;
     Pf[idx] = c < K ? psf[(size_t)(K - 1 - a) * K + (K - 1 - c)] : 0.0f;
   }
   __syncthreads();
-  const int tx4 = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int grp = threadIdx.x >> 8, lt = threadIdx.x & 255;
+  const int tx4 = lt & 15, ty = lt >> 4;
   // output (oy + ty, ox + 4 tx4 + i) = sum_{a,c} Pf[a][c] tile[ty + a][4 tx4 + i + c]
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int a = 0; a < K; ++a) {
+  const int a0 = grp * K / RS, a1 = (grp + 1) * K / RS;
+  for (int a = a0; a < a1; ++a) {
     const float *row = tile + (ty + a) * TW + 4 * tx4;
     const float *prow = Pf + a * Kp;
     float d0 = 0.0f, d1 = 0.0f, d2 = 0.0f, d3 = 0.0f;
@@ -136,6 +146,19 @@ __device__ __forceinline__ void conv_direct_body(const ConvArgs &ca) {
     acc[2] += (double)d2;
     acc[3] += (double)d3;
   }
+  if (RS > 1) {
+    double *part = reinterpret_cast<double *>(Pf + K * Kp);  // [RS - 1][256][4]
+    if (grp > 0) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) part[((grp - 1) * 256 + lt) * 4 + i] = acc[i];
+    }
+    __syncthreads();
+    if (grp > 0) return;
+#pragma unroll
+    for (int g = 1; g < RS; ++g)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) acc[i] += part[((g - 1) * 256 + lt) * 4 + i];
+  }
   const int y = oy + ty;
   if (y < y1r) {
 #pragma unroll
@@ -146,10 +169,12 @@ __device__ __forceinline__ void conv_direct_body(const ConvArgs &ca) {
   }
 }
 
-__global__ void __launch_bounds__(256) k_conv_direct(ConvArgs a) { conv_direct_body(a); }
-__global__ void __launch_bounds__(256) k_conv_direct_job(const ConvArgs *__restrict__ t, int j) {
+template <int RS>
+__global__ void __launch_bounds__(256 * RS) k_conv_direct(ConvArgs a) { conv_direct_body<RS>(a); }
+template <int RS>
+__global__ void __launch_bounds__(256 * RS) k_conv_direct_job(const ConvArgs *__restrict__ t, int j) {
   const ConvArgs a = t[j];
-  conv_direct_body(a);
+  conv_direct_body<RS>(a);
 }
 
 // Blocks per region side: the largest region of a grid x grid split is ceil(N / grid) wide.
@@ -158,16 +183,30 @@ static dim3 conv_grid(int B, int N, int grid) {
   return dim3((side + CT_X - 1) / CT_X, (side + CT_Y - 1) / CT_Y, B * grid * grid);
 }
 
+// Row splits when one-group blocks would leave most SIMDs with a single wave (fewer than 2048
+// blocks) and the split's LDS fits.
+static bool conv_use_split(dim3 g, int K) {
+  return (int64_t)g.x * g.y * g.z < 2048 && conv_split_lds_bytes(K) <= 160 * 1024;
+}
+
 hipError_t launch_conv_direct(const ConvArgs &a, hipStream_t s) {
   const size_t lds = conv_direct_lds_bytes(a.K);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_conv_direct, conv_grid(a.B, a.N, a.grid), dim3(256), lds, s, a);
+  const dim3 g = conv_grid(a.B, a.N, a.grid);
+  if (conv_use_split(g, a.K))
+    hipLaunchKernelGGL(k_conv_direct<CONV_RS>, g, dim3(256 * CONV_RS), conv_split_lds_bytes(a.K), s, a);
+  else
+    hipLaunchKernelGGL(k_conv_direct<1>, g, dim3(256), lds, s, a);
   return hipGetLastError();
 }
 hipError_t launch_conv_direct_job(const ConvArgs *table, int j, int B, int N, int K, int grid, hipStream_t s) {
   const size_t lds = conv_direct_lds_bytes(K);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_conv_direct_job, conv_grid(B, N, grid), dim3(256), lds, s, table, j);
+  const dim3 g = conv_grid(B, N, grid);
+  if (conv_use_split(g, K))
+    hipLaunchKernelGGL(k_conv_direct_job<CONV_RS>, g, dim3(256 * CONV_RS), conv_split_lds_bytes(K), s, table, j);
+  else
+    hipLaunchKernelGGL(k_conv_direct_job<1>, g, dim3(256), lds, s, table, j);
   return hipGetLastError();
 }
 
