@@ -579,6 +579,23 @@ def main():
     h_ms, h_n, _ = ctx.timer_read(P._lib.TIMER_HESS)
     ctx.timer_enable(False)
     ll = logls.cpu().numpy()[args.warmup:]
+    # the same evaluations with the PSF convolution forced onto the FFT path (AUTO takes the
+    # direct path below 48x48: faster at 31x31), reported beside the headline value
+    fft = None
+    n_im = obs_d.nim
+    if not large and args.conv == P.CONV_AUTO and (n_im & (n_im - 1)) == 0 and 8 <= n_im <= 4096:
+        ctx.timer_enable(True)
+        torch.cuda.synchronize()
+        t0f = time.perf_counter()
+        for k in range(args.warmup, args.warmup + args.steps):
+            m, o = params[k]
+            logls[k:k + 1].copy_(ev.loglike(m, o, data_hess, data_mom, P.LL_POISSON, 0.01, P.CONV_FFT))
+        torch.cuda.synchronize()
+        t1f = time.perf_counter()
+        ctx.sync()
+        cf_ms, cf_n, _ = ctx.timer_read(P._lib.TIMER_CONV)
+        ctx.timer_enable(False)
+        fft = {"evals_per_s": args.steps / (t1f - t0f), "conv_ms_per_eval": cf_ms / max(cf_n, 1)}
     assert np.all(np.isfinite(ll)), "non-finite log-likelihood"
     elapsed = t1 - t0
     evals_per_s = args.steps / elapsed
@@ -623,6 +640,7 @@ def main():
                      "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": None if large else SAMPLE_TRAFFIC_BYTES,
                      "ops_per_draw": OPS_PER_DRAW, "avg_launch_ms": avg_sample_s * 1e3},
         "mean_logL": float(ll.mean()),
+        "fft_conv_path": fft,
     }
     if not large:
         res["image_plane_at_scale"] = image_plane_at_scale(ctx, P, si, hgrid)
