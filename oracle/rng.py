@@ -32,6 +32,8 @@ TAG_BLOCK = 6       # (pixel, block, 6, 0): word 0 draws the block's star total 
 TAG_BLOCK_PTRS = 7  # (pixel, block, 7, j): the total by transformed rejection, attempts 2j, 2j+1
 TAG_STAR = 8        # (pixel, block, 8, s // 4): word s % 4 places star s on a point
 TAG_STAR_SPLIT = 9  # (pixel, block, 9, s // 4): word s % 4 decides whether star s is reddened
+TAG_RED = 10        # (pixel, entry // 4, 10, 0): word entry % 4 draws a thinned entry's reddened count
+TAG_PTRS_RED = 11   # (pixel, entry, 11, j): that count by transformed rejection, attempts 2j, 2j+1
 
 
 def philox4x32_10(c0, c1, c2, c3, seed: int):

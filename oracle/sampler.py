@@ -34,6 +34,17 @@ How a Poisson count is drawn is not fixed by the paper.  The rule here:
   decisions taken in IEEE FP32 operation by operation, with a logarithm written
   here from the atanh series and ln k! from an FP64-built table (k < 256) or a
   Stirling series.  Both sides of the parity test take the same FP32 steps.
+* C3b, thinning -- for an entry drawn by C1b or C2 (lambda >= 2) under a split
+  0 < F < 1 other than 1/2 (which keeps the one-bit-per-star rule of C3, cheaper at
+  the counts where most of these entries sit), the unreddened and reddened counts
+  are drawn directly as independent
+  Poisson((1 - F) lambda) and Poisson(F lambda) counts (the two products in
+  FP64): the first with the entry's inversion word, the second with word
+  (entry mod 4) of Philox(pixel, entry // 4, TAG_RED, 0), each part by the alias
+  rule below 512 and by transformed rejection above (attempts on
+  (pixel, entry, TAG_PTRS, j) and (pixel, entry, TAG_PTRS_RED, j)).  Independent
+  thinning of a Poisson count gives exactly this law; it costs two draws however
+  many stars the entry has, where C3 needs a random bit or word per star.
 * C3, dust split -- each of the n stars is reddened independently with
   probability F_dust (reading of "fraction of stars that are reddened").  For
   F_dust = 1/2 one random bit per star: the first 8 stars of entry i use byte
@@ -61,7 +72,7 @@ import math
 
 import numpy as np
 
-from .rng import (TAG_DUST, TAG_MAIN, TAG_PTRS, TAG_SPLIT, TAG_SPLIT_X, box_muller_f64,
+from .rng import (TAG_DUST, TAG_MAIN, TAG_PTRS, TAG_PTRS_RED, TAG_RED, TAG_SPLIT, TAG_SPLIT_X, box_muller_f64,
                   philox4x32_10, u01_open_f32)
 
 LAM_SWITCH = 10.0
@@ -166,6 +177,15 @@ def count_from_alias(u: np.ndarray, k_lo: int, bits: int, packed: np.ndarray) ->
     x = packed[c].astype(np.uint64)
     j = np.where(r < (x >> np.uint64(bits)), c, (x & np.uint64((1 << bits) - 1)).astype(np.int64))
     return (k_lo + j).astype(np.int64)
+
+
+def draw_part(mu: float, u: np.ndarray, seed: int, px: np.ndarray, entry: int, tag_ptrs: int) -> np.ndarray:
+    """Poisson(mu) counts for one entry: the alias rule (C1b) with words u below ALIAS_MAX,
+    transformed rejection (C2) on (pixel, entry, tag_ptrs, j) above."""
+    if mu < ALIAS_MAX:
+        return count_from_alias(u, *alias_table(mu))
+    n, _ = ptrs_draw(ptrs_constants(mu), seed, px, entry, tag=tag_ptrs)
+    return n
 
 
 def count_from_thresholds(u: np.ndarray, thr: list[int]) -> np.ndarray:
@@ -383,10 +403,24 @@ def sample_pixels(lam: np.ndarray, flux32: np.ndarray, seed: int, px: np.ndarray
                 T[r_, : K[j]] = tables[j]
             cols = inv[sel]
             n[:, cols] = (U[:, cols, None] >= T[None, :, :]).sum(axis=-1)
-        for j in np.nonzero((lb >= ALIAS_MIN) & (lb < ALIAS_MAX))[0]:
-            n[:, j] = count_from_alias(U[:, j], *alias_table(lb[j]))
-        for j in np.nonzero(lb >= ALIAS_MAX)[0]:
-            n[:, j], _ = ptrs_draw(ptrs_constants(lb[j]), seed, px, e0 + j)
+        thin = split and 0.0 < frac < 1.0 and frac != 0.5
+        tab = np.nonzero(lb >= ALIAS_MIN)[0]          # entries drawn by C1b or C2
+        n_red_thin = None
+        if thin and len(tab):
+            # C3b: two independent Poisson parts, (1 - F) lambda and F lambda
+            wr = philox4x32_10(px[:, None], g[None, :], TAG_RED, 0, seed)
+            UR = np.stack(wr, axis=-1).reshape(npx, 4 * len(g))[:, : e1 - e0].astype(np.uint64)
+            n_red_thin = np.zeros((npx, len(tab)), dtype=np.int64)
+            for c_, j in enumerate(tab):
+                lc = float(lb[j]) * (1.0 - frac)
+                lr = float(lb[j]) * frac
+                nc = draw_part(lc, U[:, j], seed, px, e0 + j, TAG_PTRS)
+                nr = draw_part(lr, UR[:, j], seed, px, e0 + j, TAG_PTRS_RED)
+                n[:, j] = nc + nr
+                n_red_thin[:, c_] = nr
+        else:
+            for j in tab:
+                n[:, j] = draw_part(float(lb[j]), U[:, j], seed, px, e0 + j, TAG_PTRS)
         if split and 0.0 < frac < 1.0:
             W = None
             if frac == 0.5:
@@ -395,7 +429,12 @@ def sample_pixels(lam: np.ndarray, flux32: np.ndarray, seed: int, px: np.ndarray
                 words = np.stack(sw, axis=-1).reshape(npx, 4 * len(g16)).astype(np.uint64)
                 q = ents - 16 * g16[0]                       # entry's position from the first block
                 W = (words[:, q // 4] >> (np.uint64(8) * (q % 4).astype(np.uint64))) & np.uint64(0xFF)
-            r = split_block(n, W, frac, seed, px, ents)
+            n_split = n.copy()
+            if n_red_thin is not None:
+                n_split[:, tab] = 0                      # thinned entries are already split
+            r = split_block(n_split, W, frac, seed, px, ents)
+            if n_red_thin is not None:
+                r[:, tab] = n_red_thin
         elif split and frac >= 1.0:
             r = n.copy()
         else:

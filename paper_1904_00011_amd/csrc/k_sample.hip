@@ -71,11 +71,25 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
       l = 0.0;
     }
     if (block_rule) l = 0.0;
-    if (l >= ALIAS_MAX) {
-      ((PtrsConst *)a.pc)[i] = ptrs_constants(l);
-      r.kk = KIND_PTRS;
-    } else if (l >= ALIAS_MIN) {
-      r.kk = KIND_ALIAS;  // k_prep_alias builds the columns and completes the record
+    if (l >= ALIAS_MIN) {
+      // table entry: the count (or, thinned, the unreddened part) in slot 0, the reddened part in
+      // slot 1; alias parts are built by k_prep_alias, which completes their descriptors
+      const double l0 = a.thin ? l * (1.0 - a.frac) : l;
+      if (l0 >= ALIAS_MAX) {
+        ((PtrsConst *)a.pc)[2 * (size_t)i] = ptrs_constants(l0);
+        r.kk = KIND_PTRS;
+      } else {
+        r.kk = KIND_ALIAS;
+      }
+      if (a.thin) {
+        const double l1 = l * a.frac;
+        if (l1 >= ALIAS_MAX) {
+          ((PtrsConst *)a.pc)[2 * (size_t)i + 1] = ptrs_constants(l1);
+          a.rdesc[i] = KIND_PTRS;
+        } else {
+          a.rdesc[i] = KIND_ALIAS;
+        }
+      }
     } else if (l > 0.0) {
       uint32_t *t = a.thr + (size_t)i * THR_STRIDE;
       const uint32_t K = inversion_table(l, t);
@@ -129,14 +143,15 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i) {
+__device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int part) {
   __shared__ uint32_t m_s[ALIAS_WAVES][ALIAS_COLS];
   __shared__ uint16_t small_s[ALIAS_WAVES][ALIAS_COLS], large_s[ALIAS_WAVES][ALIAS_COLS],
       alias_s[ALIAS_WAVES][ALIAS_COLS];
   __shared__ int nout_s[ALIAS_WAVES];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (i >= a.E) return;  // whole waves: i is wave-uniform
-  if ((a.rec[i].kk & 0xFFu) != KIND_ALIAS) return;
+  // part 0: the entry's count (or its unreddened part); part 1: the reddened part (thinned)
+  if (part == 0 ? (a.rec[i].kk & 0xFFu) != KIND_ALIAS : !a.thin || (a.rdesc[i] & 0xFFu) != KIND_ALIAS) return;
   uint32_t *m = m_s[wv];
   uint16_t *sm = small_s[wv], *lg = large_s[wv], *al = alias_s[wv];
   for (int j = lane; j < ALIAS_COLS; j += 64) {
@@ -145,7 +160,8 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i) {
   }
   wave_lds_sync();
   if (lane == 0) {
-    const double l = a.lam[i];
+    const double lam = a.lam[i];
+    const double l = !a.thin ? lam : part == 0 ? lam * (1.0 - a.frac) : lam * a.frac;
     double pk = exp(-l);
     double F = pk;
     int klo = -1, J = 0;
@@ -174,7 +190,11 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i) {
     int bits = 4;
     while ((1 << bits) < J) ++bits;
     nout_s[wv] = bits;
-    a.rec[i].kk = ((uint32_t)klo << 12) | ((uint32_t)bits << 8) | KIND_ALIAS;
+    const uint32_t desc = ((uint32_t)klo << 12) | ((uint32_t)bits << 8) | KIND_ALIAS;
+    if (part == 0)
+      a.rec[i].kk = desc;
+    else
+      a.rdesc[i] = desc;
   }
   wave_lds_sync();
   const int bits = nout_s[wv];
@@ -212,27 +232,29 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i) {
   wave_lds_sync();
   // a column whose alias is itself is full (2^32 / M words, stored as 2^32 / M - 1: the last word
   // then falls to the alias, the column itself)
-  uint32_t *out = a.alias + (size_t)i * ALIAS_COLS;
+  uint32_t *out = a.alias + ((size_t)i * 2 + part) * ALIAS_COLS;
   for (int j = lane; j < M; j += 64) {
     const uint32_t h = al[j] == (uint16_t)j ? cap - 1u : m[j];
     out[j] = (h << bits) | (uint32_t)al[j];
   }
 }
 
+// grid.y = 2: the second row of blocks builds the reddened parts of thinned entries
 __global__ void __launch_bounds__(256) k_prep_alias(PrepArgs a) {
-  prep_alias_body(a, (int)(blockIdx.x * ALIAS_WAVES + (threadIdx.x >> 6)));
+  prep_alias_body(a, (int)(blockIdx.x * ALIAS_WAVES + (threadIdx.x >> 6)), (int)blockIdx.y);
 }
 __global__ void __launch_bounds__(256) k_prep_alias_job(const PrepArgs *__restrict__ t, int j) {
   const PrepArgs a = t[j];
-  prep_alias_body(a, (int)(blockIdx.x * ALIAS_WAVES + (threadIdx.x >> 6)));
+  prep_alias_body(a, (int)(blockIdx.x * ALIAS_WAVES + (threadIdx.x >> 6)), (int)blockIdx.y);
 }
 
 hipError_t launch_prep_alias(const PrepArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_prep_alias, dim3((unsigned)((a.E + ALIAS_WAVES - 1) / ALIAS_WAVES)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_prep_alias, dim3((unsigned)((a.E + ALIAS_WAVES - 1) / ALIAS_WAVES), 2), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_prep_alias_job(const PrepArgs *table, int j, int E, hipStream_t s) {
-  hipLaunchKernelGGL(k_prep_alias_job, dim3((unsigned)((E + ALIAS_WAVES - 1) / ALIAS_WAVES)), dim3(256), 0, s, table, j);
+  hipLaunchKernelGGL(k_prep_alias_job, dim3((unsigned)((E + ALIAS_WAVES - 1) / ALIAS_WAVES), 2), dim3(256), 0, s, table,
+                     j);
   return hipGetLastError();
 }
 
@@ -287,13 +309,32 @@ __device__ __forceinline__ uint32_t split_count(uint32_t n, uint32_t word, uint3
   return red;
 }
 
-template <int B, int S, bool DBG>
+// Poisson count of one table part: desc = k_lo << 12 | log2 M << 8 | KIND_ALIAS (one column of
+// the alias table: n = k_lo + (c if r < height_c else alias_c), u = c << (32 - b) | r) or
+// KIND_PTRS (transformed rejection on (p, i, tag, j) with the part's constants).
+__device__ __forceinline__ uint32_t table_draw(uint32_t desc, uint32_t u, const uint32_t *__restrict__ tab,
+                                               const PCMD_CONST PtrsConst *pcp, uint32_t p, uint32_t i, uint32_t tag,
+                                               uint32_t k0, uint32_t k1, const float *__restrict__ lnfact,
+                                               uint32_t &failed) {
+  if ((desc & 0xFFu) == KIND_ALIAS) {
+    const uint32_t b = (desc >> 8) & 0xFu;
+    const uint32_t c = u >> (32u - b);
+    const uint32_t x = tab[c];
+    return (desc >> 12) + ((u & (0xFFFFFFFFu >> b)) < (x >> b) ? c : (x & ((1u << b) - 1u)));
+  }
+  const PtrsConst cst = ld_const(pcp);
+  return ptrs_draw(cst, p, i, tag, k0, k1, lnfact, failed);
+}
+
+// THIN: a split 0 < F < 1, F != 1/2 draws table entries as two independent parts (thinning).
+template <int B, int S, bool DBG, bool THIN>
 __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int chunk) {
   constexpr int BP = B <= 2 ? 2 : 4;
   const PCMD_CONST EntryRec *rec = (const PCMD_CONST EntryRec *)a.rec;
   const PCMD_CONST uint32_t *thr = (const PCMD_CONST uint32_t *)a.thr;
   const PCMD_CONST PtrsConst *pc = (const PCMD_CONST PtrsConst *)a.pc;
   const PCMD_CONST double *fl64 = (const PCMD_CONST double *)a.fl64;
+  const PCMD_CONST uint32_t *rdesc = (const PCMD_CONST uint32_t *)a.rdesc;
   const bool live = p < (uint32_t)a.npx;
   const bool dbg = DBG && live && (int64_t)p >= a.px0 && (int64_t)p < a.px1;
 
@@ -349,12 +390,15 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
       uint32_t n0[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) n0[q] = word_of(w, q) > gr->t0m1[4 * h + q] ? 1u : 0u;
+      u4 wr{0u, 0u, 0u, 0u};  // THIN: the quad's reddened-part words
+      bool wr_ok = false;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const uint32_t i = (uint32_t)(q0 + q);
         // one record at a time keeps the scalar registers of the loop below the spill point
         const EntryRec rq = ld_const(rec + i);  // padded to a multiple of GRP
-        uint32_t n = 0;
+        uint32_t n = 0, red_thin = 0u;
+        bool thinned = false;
         const uint32_t kind = rq.kk & 0xFFu;
         if (kind <= KIND_INV) {  // inversion; a KIND_ZERO entry never passes its first threshold
           // n = #{k < K : T_k <= u}, walking up while any lane of the wave is still above
@@ -380,22 +424,27 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
               }
             }
           }
-        } else if (kind == KIND_ALIAS) {
-          // one column read: n = k_lo + (c if r < height_c else alias_c), u = c << (32 - b) | r
-          // for M = 2^b columns; the record holds k_lo << 12 | b << 8 | kind
-          const uint32_t u = word_of(w, q);
-          const uint32_t b = (rq.kk >> 8) & 0xFu;
-          const uint32_t c = u >> (32u - b);
-          const uint32_t x = a.alias[(size_t)i * ALIAS_COLS + c];
-          n = (rq.kk >> 12) + ((u & (0xFFFFFFFFu >> b)) < (x >> b) ? c : (x & ((1u << b) - 1u)));
         } else {
-          const PtrsConst c = ld_const(pc + i);
-          n = ptrs_draw(c, p, i, TAG_PTRS, a.k0, a.k1, a.lnfact, ptrs_failed);
+          // table entry: slot 0 holds the count (or, thinned, the unreddened part), slot 1 the
+          // reddened part, each an alias column read or a rejection draw
+          n = table_draw(rq.kk, word_of(w, q), a.alias + (size_t)i * 2 * ALIAS_COLS, pc + 2 * (size_t)i, p, i,
+                         TAG_PTRS, a.k0, a.k1, a.lnfact, ptrs_failed);
+          if (S == 2 && THIN) {
+            if (!wr_ok) {  // the quad's reddened-part words, drawn once
+              wr = philox10(p, i >> 2, TAG_RED, 0u, a.k0, a.k1);
+              wr_ok = true;
+            }
+            const uint32_t d = ld_const(rdesc + i);
+            red_thin = table_draw(d, word_of(wr, q), a.alias + ((size_t)i * 2 + 1) * ALIAS_COLS, pc + 2 * (size_t)i + 1,
+                                  p, i, TAG_PTRS_RED, a.k0, a.k1, a.lnfact, ptrs_failed);
+            n += red_thin;
+            thinned = true;
+          }
         }
         if (!wave_any(n != 0u)) continue;
         uint32_t red = 0u;
         if (S == 2) {
-          red = split_count(n, sq, 8u * q, a.split_mode, a.split_q, p, i, a.k0, a.k1);
+          red = THIN && thinned ? red_thin : split_count(n, sq, 8u * q, a.split_mode, a.split_q, p, i, a.k0, a.k1);
         }
         const PCMD_CONST double *f = fl64 + (size_t)i * BP;
         // a stream with no star in any lane adds exact zeros: skipped
@@ -428,11 +477,11 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
   }
 }
 
-template <int B, int S, bool DBG>
+template <int B, int S, bool DBG, bool THIN>
 __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
   const int nblk_px = (a.npx + 255) >> 8;
   const int chunk = blockIdx.x / nblk_px;
-  sample_tile<B, S, DBG>(a, (uint32_t)((blockIdx.x - chunk * nblk_px) * 256 + threadIdx.x), chunk);
+  sample_tile<B, S, DBG, THIN>(a, (uint32_t)((blockIdx.x - chunk * nblk_px) * 256 + threadIdx.x), chunk);
 }
 
 template <int B>
@@ -440,14 +489,19 @@ static hipError_t launch_sample_b(const SampleArgs &a, hipStream_t s) {
   const int nblk_px = (a.npx + 255) / 256;
   dim3 grid((unsigned)(nblk_px * a.nchunks));
   const bool dbg = a.dbg_counts != nullptr;
-  if (a.S == 2 && dbg)
-    hipLaunchKernelGGL((k_sample<B, 2, true>), grid, dim3(256), 0, s, a);
+  const bool thin = a.S == 2 && a.split_mode == SPLIT_GENERAL;
+  if (thin && dbg)
+    hipLaunchKernelGGL((k_sample<B, 2, true, true>), grid, dim3(256), 0, s, a);
+  else if (thin)
+    hipLaunchKernelGGL((k_sample<B, 2, false, true>), grid, dim3(256), 0, s, a);
+  else if (a.S == 2 && dbg)
+    hipLaunchKernelGGL((k_sample<B, 2, true, false>), grid, dim3(256), 0, s, a);
   else if (a.S == 2)
-    hipLaunchKernelGGL((k_sample<B, 2, false>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_sample<B, 2, false, false>), grid, dim3(256), 0, s, a);
   else if (dbg)
-    hipLaunchKernelGGL((k_sample<B, 1, true>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_sample<B, 1, true, false>), grid, dim3(256), 0, s, a);
   else
-    hipLaunchKernelGGL((k_sample<B, 1, false>), grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_sample<B, 1, false, false>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
@@ -502,7 +556,11 @@ __global__ void __launch_bounds__(256) k_sample_persistent(const BatchSampleJob 
     const int chunk = local / pblocks;
     const int pblk = local - chunk * pblocks;
     const SampleArgs a = ld_const(&cj[j].a);
-    sample_tile<B, 2, false>(a, (uint32_t)(pblk * 64) + lane, chunk);  // batch jobs always carry two streams
+    // batch jobs always carry two streams
+    if (a.split_mode == SPLIT_GENERAL)
+      sample_tile<B, 2, false, true>(a, (uint32_t)(pblk * 64) + lane, chunk);
+    else
+      sample_tile<B, 2, false, false>(a, (uint32_t)(pblk * 64) + lane, chunk);
   }
 }
 

@@ -129,7 +129,7 @@ void pcmd_destroy(pcmd_ctx *c) {
   batch_destroy(c);
   Buf *bufs[] = {&c->rec,     &c->thr,     &c->pc,      &c->fl64,    &c->part,     &c->F,       &c->G,
                  &c->mom_part, &c->fft,    &c->mlp_act, &c->mlp_pre, &c->mlp_dza, &c->mlp_dzb, &c->mlp_grad,
-                 &c->mlp_part, &c->mlp_ws, &c->ll_part, &c->blk, &c->alias};
+                 &c->mlp_part, &c->mlp_ws, &c->ll_part, &c->blk, &c->alias, &c->rdesc};
   for (Buf *b : bufs) release(*b);
   if (c->lnfact) (void)hipFree(c->lnfact);
   if (c->lnfact64) (void)hipFree(c->lnfact64);
@@ -353,8 +353,9 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   if (!block) {
     if ((r = ensure(c, c->rec, rec_bytes(E), "entry records"))) return r;
     if ((r = ensure(c, c->thr, (size_t)E * THR_STRIDE * 4, "thresholds"))) return r;
-    if ((r = ensure(c, c->pc, (size_t)E * sizeof(PtrsConst), "rejection constants"))) return r;
-    if ((r = ensure(c, c->alias, (size_t)E * ALIAS_COLS * 4, "alias columns"))) return r;
+    if ((r = ensure(c, c->pc, (size_t)E * 2 * sizeof(PtrsConst), "rejection constants"))) return r;
+    if ((r = ensure(c, c->alias, (size_t)E * 2 * ALIAS_COLS * 4, "alias columns"))) return r;
+    if ((r = ensure(c, c->rdesc, (size_t)E * 4, "reddened-part descriptors"))) return r;
   }
   if ((r = ensure(c, c->fl64, (size_t)E * BP * 8, "fluxes"))) return r;
   if ((r = ensure(c, c->part, (size_t)nchunks * S * B * npx * 8, "partial sums"))) return r;
@@ -432,7 +433,10 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
                 (double *)c->fl64.p,
                 c->status,
                 (uint32_t *)c->alias.p,
-                hybrid ? pb.brec : nullptr};
+                hybrid ? pb.brec : nullptr,
+                split_mode == SPLIT_GENERAL ? 1 : 0,
+                o->dust_frac,
+                (uint32_t *)c->rdesc.p};
     e = launch_prep(pa, s);
     if (e == hipSuccess) e = launch_prep_alias(pa, s);
     if (e != hipSuccess) return hip_fail(c, e, "k_prep");
@@ -460,6 +464,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
     a.status = c->status;
     a.lnfact = c->lnfact;
     a.alias = pa.alias;
+    a.rdesc = pa.rdesc;
     ScopedTimer tm(c, PCMD_TIMER_SAMPLE, (double)npx * (double)E, s);
     e = launch_sample(a, s);
     if (e == hipSuccess && hybrid) e = launch_sample_block(ab, s);

@@ -21,7 +21,7 @@ namespace {
 struct JobInfo {
   int E, B, N, npx, K, S, nchunks, pblocks, items, grid;
   double cost;
-  size_t o_rec, o_thr, o_pc, o_fl, o_part, o_img, o_alias;
+  size_t o_rec, o_thr, o_pc, o_fl, o_part, o_img, o_alias, o_rdesc;
 };
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -33,7 +33,7 @@ struct pcmd_batch_plan {
   int n_jobs = 0, B = 0, nbins = 0, total_items = 0, wg = 0, order_mode = 0;
   std::vector<JobInfo> info;
   std::vector<int> order;  // sampler table position -> job
-  Buf rec, thr, pc, fl, part, F, G, mags, hess, mom, mom_part, ll_part, counters, desc, alias;
+  Buf rec, thr, pc, fl, part, F, G, mags, hess, mom, mom_part, ll_part, counters, desc, alias, rdesc;
   void *desc_host = nullptr;
   size_t desc_bytes = 0;
   size_t o_prep = 0, o_samp = 0, o_red = 0, o_conv = 0, o_noise = 0, o_hess = 0, o_ll = 0;
@@ -52,7 +52,7 @@ static void plan_free_device(pcmd_batch_plan *p) {
   p->exec = nullptr;
   p->graph = nullptr;
   Buf *bufs[] = {&p->rec, &p->thr, &p->pc, &p->fl, &p->part, &p->F, &p->G, &p->mags, &p->hess, &p->mom, &p->mom_part, &p->ll_part,
-                 &p->counters, &p->desc, &p->alias};
+                 &p->counters, &p->desc, &p->alias, &p->rdesc};
   for (Buf *b : bufs) release(*b);
   if (p->desc_host) (void)hipHostFree(p->desc_host);
   p->desc_host = nullptr;
@@ -120,7 +120,7 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
   p->order_mode = c->tune_order;
   p->info.assign(n_jobs, JobInfo{});
   const int B = p->B, BP = B <= 2 ? 2 : 4;
-  size_t n_rec = 0, n_thr = 0, n_pc = 0, n_fl = 0, n_part = 0, n_img = 0, n_alias = 0;
+  size_t n_rec = 0, n_thr = 0, n_pc = 0, n_fl = 0, n_part = 0, n_img = 0, n_alias = 0, n_rdesc = 0;
   for (int j = 0; j < n_jobs; ++j) {
     JobInfo &ji = p->info[j];
     ji.E = jobs[j].iso.n_entries;
@@ -144,13 +144,15 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
     ji.o_part = n_part;
     ji.o_img = n_img;
     ji.o_alias = n_alias;
+    ji.o_rdesc = n_rdesc;
     n_rec += rec_bytes(ji.E) / sizeof(EntryRec);
     n_thr += (size_t)ji.E * THR_STRIDE;
-    n_pc += (size_t)ji.E;
+    n_pc += (size_t)ji.E * 2;
     n_fl += (size_t)ji.E * BP;
     n_part += (size_t)ji.nchunks * ji.S * B * ji.npx;
     n_img += (size_t)B * ji.npx;
-    n_alias += (size_t)ji.E * ALIAS_COLS;
+    n_alias += (size_t)ji.E * 2 * ALIAS_COLS;
+    n_rdesc += (size_t)ji.E;
   }
   p->order.resize(n_jobs);
   std::iota(p->order.begin(), p->order.end(), 0);
@@ -164,6 +166,7 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
   if ((r = ensure(c, p->thr, n_thr * 4, "batch thresholds"))) return r;
   if ((r = ensure(c, p->pc, n_pc * sizeof(PtrsConst), "batch rejection constants"))) return r;
   if ((r = ensure(c, p->alias, n_alias * 4, "batch alias columns"))) return r;
+  if ((r = ensure(c, p->rdesc, n_rdesc * 4, "batch reddened-part descriptors"))) return r;
   if ((r = ensure(c, p->fl, n_fl * 8, "batch fluxes"))) return r;
   if ((r = ensure(c, p->part, n_part * 8, "batch partial sums"))) return r;
   if ((r = ensure(c, p->F, n_img * 4, "batch images"))) return r;
@@ -236,8 +239,23 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
     float *mags = (float *)p->mags.p + ji.o_img;
     const uint32_t k0 = (uint32_t)(o->seed & 0xFFFFFFFFu), k1 = (uint32_t)(o->seed >> 32);
     GroupRec *grp = (GroupRec *)(rec + entries_padded(ji.E));
-    pa[j] = PrepArgs{ji.E, B, BP, jobs[j].iso.lam, jobs[j].iso.flux, rec, grp, thr, pc, fl, c->status,
-                     (uint32_t *)p->alias.p + ji.o_alias};
+    const int sm = split_mode_of(&jobs[j].obs);
+    pa[j] = PrepArgs{ji.E,
+                     B,
+                     BP,
+                     jobs[j].iso.lam,
+                     jobs[j].iso.flux,
+                     rec,
+                     grp,
+                     thr,
+                     pc,
+                     fl,
+                     c->status,
+                     (uint32_t *)p->alias.p + ji.o_alias,
+                     nullptr,
+                     sm == SPLIT_GENERAL ? 1 : 0,
+                     jobs[j].obs.dust_frac,
+                     (uint32_t *)p->rdesc.p + ji.o_rdesc};
     ReduceArgs rr;
     memset(&rr, 0, sizeof rr);
     rr.B = B;
@@ -319,6 +337,7 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
     s.status = c->status;
     s.lnfact = c->lnfact;
     s.alias = (const uint32_t *)p->alias.p + ji.o_alias;
+    s.rdesc = (const uint32_t *)p->rdesc.p + ji.o_rdesc;
     bj.item0 = first_item[j];
     bj.items = ji.items;
     bj.pblocks = ji.pblocks;

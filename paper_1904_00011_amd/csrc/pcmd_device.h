@@ -17,6 +17,8 @@ constexpr uint32_t PH_W1 = 0xBB67AE85u;
 constexpr uint32_t TAG_MAIN = 0, TAG_SPLIT = 1, TAG_SPLIT_X = 2, TAG_PTRS = 3, TAG_DUST = 4, TAG_NOISE = 5;
 // block-skip sampler: block total by inversion / rejection, star placement, star dust screen
 constexpr uint32_t TAG_BLOCK = 6, TAG_BLOCK_PTRS = 7, TAG_STAR = 8, TAG_STAR_SPLIT = 9;
+// thinned entries: the reddened part's word (p, i / 4, TAG_RED, 0) and rejection attempts
+constexpr uint32_t TAG_RED = 10, TAG_PTRS_RED = 11;
 
 // Entry kinds written by the preparation kernel.
 constexpr uint32_t KIND_ZERO = 0, KIND_INV = 1, KIND_PTRS = 2, KIND_ALIAS = 3;

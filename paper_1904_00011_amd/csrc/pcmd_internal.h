@@ -55,11 +55,14 @@ struct PrepArgs {
   EntryRec *rec;       // [entries_padded(E)]
   GroupRec *grp;       // [entries_padded(E) / GRP + 1]
   uint32_t *thr;       // [E][THR_STRIDE]
-  void *pc;            // [E] PtrsConst
+  void *pc;            // [E][2] PtrsConst: the entry (or its unreddened part), its reddened part
   double *fl64;        // [E][BP]
   uint32_t *status;
-  uint32_t *alias;     // [E][ALIAS_COLS] packed alias columns (entries of KIND_ALIAS only)
+  uint32_t *alias;     // [E][2][ALIAS_COLS] packed alias columns of the same two parts
   const BlockRec *brec;  // hybrid sampler: entries of blocks without pad[0] set are drawn as 0
+  int thin;            // dust split 0 < F < 1, F != 1/2: entries at lambda >= ALIAS_MIN draw two parts
+  double frac;         // F
+  uint32_t *rdesc;     // [E] reddened part: k_lo << 12 | log2 M << 8 | KIND_ALIAS, or KIND_PTRS
 };
 
 // Sampler over (pixel block of 256, chunk of CHUNK entries) tiles (k_sample).
@@ -78,7 +81,8 @@ struct SampleArgs {
   int64_t px0, px1;
   uint32_t *status;
   const float *lnfact;
-  const uint32_t *alias;  // [E][ALIAS_COLS]
+  const uint32_t *alias;  // [E][2][ALIAS_COLS]
+  const uint32_t *rdesc;  // [E]
 };
 
 // Block-skip sampler (Poisson superposition, Sec. 2.1 footnote): per pixel and per block of

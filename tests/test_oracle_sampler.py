@@ -255,3 +255,42 @@ def test_lognormal_dust_draws():
     le = np.log10(e)
     assert abs(le.mean() + 0.5) < 5 * 0.2 / math.sqrt(len(px))
     assert abs(le.std() - 0.2) < 0.01
+
+
+@pytest.mark.parametrize("lam,frac", [(40.0, 0.3), (5.0, 0.7), (2000.0, 0.6), (700.0, 0.8)])
+def test_thinning_parts_are_independent_poisson(lam, frac):
+    """C3b: for an entry at lambda >= 2 under a split 0 < F < 1 the unreddened and reddened counts
+    are independent Poisson((1 - F) lambda) and Poisson(F lambda) (alias parts below 512,
+    rejection above), so the total is Poisson(lambda) and each star is reddened with
+    probability F."""
+    f = np.ones((1, 1), np.float32)
+    N = 60000
+    s = S.sample_pixels(np.array([lam]), f, 31, np.arange(N), dust_model=2, dust_frac=frac, want_counts=True)
+    n, r = s["counts"][:, 0], s["red"][:, 0]
+    c = n - r
+    for x, mu in ((c, lam * (1 - frac)), (r, lam * frac), (n, lam)):
+        assert abs(x.mean() - mu) < 5 * math.sqrt(mu / N)
+        assert abs(x.var() / mu - 1) < 5 * math.sqrt((2 + 1 / mu) / N)
+    assert abs(np.corrcoef(c, r)[0, 1]) < 5 / math.sqrt(N)
+    lo, hi = int(lam - 4 * math.sqrt(lam)), int(lam + 4 * math.sqrt(lam))
+    edges = np.arange(max(lo, 1), hi + 1)
+    obs = np.array([(n < edges[0]).sum()] + [(n == k).sum() for k in edges] + [(n > edges[-1]).sum()])
+    p = np.concatenate([[stats.poisson.cdf(edges[0] - 1, lam)], stats.poisson.pmf(edges, lam),
+                        [stats.poisson.sf(edges[-1], lam)]])
+    chi2 = ((obs - p * N) ** 2 / (p * N)).sum()
+    assert stats.chi2.sf(chi2, len(obs) - 1) > 1e-4
+
+
+def test_thinning_uses_its_own_words():
+    """C3b draws the unreddened part from the entry's inversion word through the alias table of
+    (1 - F) lambda, and the reddened part from the TAG_RED word through that of F lambda."""
+    lam, frac, seed = 30.0, 0.25, 77
+    px = np.arange(64)
+    s = S.sample_pixels(np.array([0.0, 0.0, lam]), np.ones((1, 3), np.float32), seed, px, dust_model=1,
+                        dust_frac=frac, want_counts=True)
+    u = rng.philox4x32_10(px, 0, rng.TAG_MAIN, 0, seed)[2]
+    v = rng.philox4x32_10(px, 0, rng.TAG_RED, 0, seed)[2]
+    want_c = S.count_from_alias(u, *S.alias_table(lam * (1 - frac)))
+    want_r = S.count_from_alias(v, *S.alias_table(lam * frac))
+    assert np.array_equal(s["red"][:, 2], want_r)
+    assert np.array_equal(s["counts"][:, 2] - s["red"][:, 2], want_c)
