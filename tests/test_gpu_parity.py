@@ -230,16 +230,18 @@ def test_edge_cases(ctx):
 
 def test_rule_boundaries(ctx):
     """Entries on both sides of every switch of the count rule (inversion / alias at lambda = 2,
-    alias / rejection at 512), the widest alias tables (M = 512) and the narrowest (M = 32), with
-    and without a dust split: every count against the oracle."""
+    alias / rejection at 512), the widest alias tables (M = 512) and the narrowest, without dust,
+    with the F = 1/2 bit split and with thinning (F = 0.3, 0.8): every count against the oracle."""
     lam = np.array([1.9999999, 2.0, 2.0000001, 3.7, 9.99, 10.0, 63.5, 255.0, 300.0, 511.9, 511.999999,
-                    512.0, 512.5, 700.0, 0.0, 0.7])
+                    512.0, 512.5, 700.0, 0.0, 0.7, 1000.0, 1500.0])
     E = len(lam)
     f32 = np.linspace(0.2, 1.0, 2 * E).reshape(2, E).astype(np.float32) * 1e-3
-    for dust in (0, 2):
-        obs = si.Obs(nim=20, seed=4242 + dust, dmod=24.0, psf=None, noise_model=0, dust_model=dust, dust_frac=0.5,
+    # F = 0.3 and 0.8 thin the entries at lambda >= 2 into two parts, whose own lambdas fall on
+    # both sides of 512 (700 x 0.8, 1000 x 0.3, 1500 x 0.3) and below 2 (2.0 x 0.3)
+    for dust, frac in ((0, 0.5), (2, 0.5), (2, 0.3), (1, 0.8)):
+        obs = si.Obs(nim=20, seed=4242 + dust, dmod=24.0, psf=None, noise_model=0, dust_model=dust, dust_frac=frac,
                      dust_R=(3.0, 2.0))
-        _print_case("rule_boundaries", E=E, dust=dust)
+        _print_case("rule_boundaries", E=E, dust=dust, frac=frac)
         _full_compare(ctx, lam, f32, obs)
 
 
