@@ -9,7 +9,7 @@ magnitudes -> Hess -> log-likelihood.  Parameters are drawn per step from the mo
 mu_d ~ U[24, 30]) with seeds 1000, 1001, ...; the data Hess comes from seed 2.  All inputs are
 synthetic and resident on the GPU before the timed region starts.
 
-Prints one JSON line.  `--gpus N` with N > 1 is refused: this build runs on one GPU.
+Prints one JSON line.  `--gpus N` with N > 1 is refused: the library runs on one GPU.
 """
 from __future__ import annotations
 

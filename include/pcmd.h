@@ -42,7 +42,7 @@ enum {
   PCMD_E_INVAL = -1,        /* an argument failed validation                         */
   PCMD_E_HIP = -2,          /* a HIP runtime call or kernel launch failed            */
   PCMD_E_NOMEM = -3,        /* device scratch could not be allocated                 */
-  PCMD_E_UNSUPPORTED = -4,  /* valid request this build does not implement           */
+  PCMD_E_UNSUPPORTED = -4,  /* valid request the library does not implement         */
   PCMD_E_PTRS_RETRY = -5    /* a rejection draw used up its attempts (see pcmd_sync) */
 };
 

@@ -3,7 +3,7 @@
 Training pairs (theta, log-Hess) come from the batched simulator (one persistent launch per 256
 parameter points, replayed from a HIP graph); the network trains on the library's BF16 MFMA
 kernels; the surrogate log-likelihood screens proposals in delayed-acceptance MCMC with the
-simulator's log-likelihood as the judge.
+simulator's log-likelihood taking the final accept/reject decision.
 """
 from __future__ import annotations
 

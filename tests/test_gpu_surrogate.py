@@ -1,5 +1,5 @@
 """End to end: the surrogate trained on the simulator's own Hess diagrams, and what it gains as a
-proposal screen inside MCMC with the simulator as the judge."""
+proposal screen inside MCMC, the simulator making the final decision."""
 import numpy as np
 import pytest
 from scipy import stats
