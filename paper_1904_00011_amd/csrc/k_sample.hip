@@ -249,12 +249,15 @@ __global__ void __launch_bounds__(256) k_prep_alias_job(const PrepArgs *__restri
 }
 
 hipError_t launch_prep_alias(const PrepArgs &a, hipStream_t s) {
-  hipLaunchKernelGGL(k_prep_alias, dim3((unsigned)((a.E + ALIAS_WAVES - 1) / ALIAS_WAVES), 2), dim3(256), 0, s, a);
+  // grid.y: part 1 (the reddened part of a thinned entry) exists only when entries are thinned
+  hipLaunchKernelGGL(k_prep_alias, dim3((unsigned)((a.E + ALIAS_WAVES - 1) / ALIAS_WAVES), a.thin ? 2 : 1), dim3(256), 0, s,
+                     a);
   return hipGetLastError();
 }
-hipError_t launch_prep_alias_job(const PrepArgs *table, int j, int E, hipStream_t s) {
-  hipLaunchKernelGGL(k_prep_alias_job, dim3((unsigned)((E + ALIAS_WAVES - 1) / ALIAS_WAVES), 2), dim3(256), 0, s, table,
-                     j);
+hipError_t launch_prep_alias_job(const PrepArgs *table, int j, int E, int parts, hipStream_t s) {
+  if (parts != 1 && parts != 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_prep_alias_job, dim3((unsigned)((E + ALIAS_WAVES - 1) / ALIAS_WAVES), parts), dim3(256), 0, s,
+                     table, j);
   return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@ namespace {
 
 struct JobInfo {
   int E, B, N, npx, K, S, nchunks, pblocks, items, grid;
+  int alias_parts;  // 2 when table entries are thinned into two parts, else 1
   double cost;
   size_t o_rec, o_thr, o_pc, o_fl, o_part, o_img, o_alias, o_rdesc;
 };
@@ -128,6 +129,7 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
     ji.N = jobs[j].obs.nim;
     ji.npx = ji.N * ji.N;
     ji.K = jobs[j].obs.psf_k;
+    ji.alias_parts = split_mode_of(&jobs[j].obs) == SPLIT_GENERAL ? 2 : 1;
     ji.grid = psf_grid_of(&jobs[j].obs);
     // Every batch job keeps both partial streams (unreddened, reddened), so the persistent
     // sampler has one instantiation; a job without a split draws no reddened stars, its second
@@ -359,7 +361,7 @@ static hipError_t enqueue(pcmd_ctx *c, pcmd_batch_plan *p, hipStream_t s) {
   hipError_t e = hipSuccess;
   for (int j = 0; j < p->n_jobs && e == hipSuccess; ++j) {
     e = launch_prep_job(pa, j, p->info[j].E, s);
-    if (e == hipSuccess) e = launch_prep_alias_job(pa, j, p->info[j].E, s);
+    if (e == hipSuccess) e = launch_prep_alias_job(pa, j, p->info[j].E, p->info[j].alias_parts, s);
   }
   if (e == hipSuccess) e = launch_reset_counter(persist, s);
   if (e == hipSuccess)

@@ -197,7 +197,7 @@ hipError_t launch_entries(const pcmd_grid *g, const double *scale, double *lam, 
 hipError_t launch_prep(const PrepArgs &a, hipStream_t s);
 hipError_t launch_prep_job(const PrepArgs *table, int j, int E, hipStream_t s);
 hipError_t launch_prep_alias(const PrepArgs &a, hipStream_t s);
-hipError_t launch_prep_alias_job(const PrepArgs *table, int j, int E, hipStream_t s);
+hipError_t launch_prep_alias_job(const PrepArgs *table, int j, int E, int parts, hipStream_t s);
 hipError_t launch_sample(const SampleArgs &a, hipStream_t s);
 hipError_t launch_sample_persistent(const BatchSampleJob *jobs, int n_jobs, int total_items, int B, uint32_t *counter,
                                     int n_workgroups, hipStream_t s);
