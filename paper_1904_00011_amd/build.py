@@ -14,8 +14,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libpcmd.so")
 
-SOURCES = ["pcmd_api.cpp", "pcmd_batch.cpp", "pcmd_mlp.cpp", "k_sample.hip", "k_sample_block.hip", "k_image.hip", "k_hess.hip", "k_fft.hip", "k_batch.hip",
-           "k_mlp.hip"]
+SOURCES = ["pcmd_api.cpp", "pcmd_batch.cpp", "pcmd_mlp.cpp", "k_sample.hip", "k_sample_block.hip", "k_image.hip",
+           "k_hess.hip", "k_fft.hip", "k_mlp.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-Wall",
          "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -30,7 +30,7 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
     tmp = LIB + ".tmp"
     cmd = [hipcc()] + FLAGS + ["-I", INCLUDE, "-I", CSRC, "-o", tmp] + srcs
     if verbose:
