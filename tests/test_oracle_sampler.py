@@ -23,6 +23,31 @@ def test_inversion_thresholds_match_poisson_cdf(lam):
         assert 1 - stats.poisson.cdf(len(T) - 1, lam) < 2 ** -31 or len(T) == 0
 
 
+def test_inversion_tail_is_constant_once_the_cdf_stalls():
+    """The property the device table builder uses to stop dividing: once k >= lambda (later pmf
+    terms shrink) and a term leaves the FP64 cdf unchanged, every later threshold equals the
+    current one, so the table runs to the cap with a constant tail."""
+    rs = np.random.default_rng(7)
+    lams = np.concatenate([rs.uniform(0.0, 2.0, 3000), rs.uniform(2.0, 10.0, 1000), 10.0 ** rs.uniform(-9, 0, 1000)])
+    stalled = 0
+    for lam in lams:
+        T = S.inversion_thresholds(float(lam))
+        p = math.exp(-lam)
+        F = p
+        for k in range(1, S.KMAX):
+            p = p * lam / k
+            if F + p == F and k >= lam:
+                stalled += 1
+                assert len(T) == S.KMAX
+                assert all(t == T[k - 1] for t in T[k:])
+                break
+            F = F + p
+            if math.floor(F * 4294967296.0) >= 2 ** 32:
+                assert len(T) == k
+                break
+    assert stalled > 500  # the stall is common: the case matters
+
+
 @pytest.mark.parametrize("lam", [0.05, 0.9, 6.0])
 def test_inversion_counts_on_stratified_words(lam):
     # 65536 equally spaced words: P(n <= k) is hit to within 2^-16
