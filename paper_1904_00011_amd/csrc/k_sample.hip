@@ -91,10 +91,11 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
         }
       }
     } else if (l > 0.0) {
-      uint32_t *t = a.thr + (size_t)i * THR_STRIDE;
-      const uint32_t K = inversion_table(l, t);
+      // k-major: threshold k of entry i at thr[k EP + i], so that a wave's stores coalesce
+      uint32_t first[3] = {0u, 0u, 0u};
+      const uint32_t K = inversion_table(l, a.thr + i, (size_t)entries_padded(E), first);
       if (K > 0) {
-        for (uint32_t k = 0; k < 3 && k < K; ++k) r.T[k] = t[k];
+        for (uint32_t k = 0; k < 3 && k < K; ++k) r.T[k] = first[k];
         r.kk = (K << 8) | KIND_INV;
       }
     }
@@ -417,9 +418,10 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
                 c = u >= rq.T[2] ? 1u : 0u;
                 if (wave_any(c != 0u)) {
                   n += c;
-                  const PCMD_CONST uint32_t *t = thr + (size_t)i * THR_STRIDE;
+                  const PCMD_CONST uint32_t *t = thr + i;  // threshold k at t[k EP]
+                  const size_t ep = (size_t)entries_padded(a.E);
                   for (uint32_t k = 3; k < K; ++k) {
-                    c = u >= t[k] ? 1u : 0u;
+                    c = u >= t[k * ep] ? 1u : 0u;
                     if (!wave_any(c != 0u)) break;
                     n += c;
                   }

@@ -72,10 +72,10 @@ __global__ void __launch_bounds__(256) k_prep_block(BlockPrepArgs a) {
         ((PtrsConst *)a.pc)[b] = ptrs_constants(L);
         r.kk = KIND_PTRS;
       } else {
-        uint32_t *t = a.thr + (size_t)b * THR_STRIDE;
-        const uint32_t K = inversion_table(L, t);
+        uint32_t first[3] = {0u, 0u, 0u};
+        const uint32_t K = inversion_table(L, a.thr + (size_t)b * THR_STRIDE, 1, first);
         if (K > 0) {
-          for (uint32_t k = 0; k < 3 && k < K; ++k) r.T[k] = t[k];
+          for (uint32_t k = 0; k < 3 && k < K; ++k) r.T[k] = first[k];
           r.kk = (K << 8) | KIND_INV;
         }
       }

@@ -352,7 +352,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   }
   if (!block) {
     if ((r = ensure(c, c->rec, rec_bytes(E), "entry records"))) return r;
-    if ((r = ensure(c, c->thr, (size_t)E * THR_STRIDE * 4, "thresholds"))) return r;
+    if ((r = ensure(c, c->thr, (size_t)entries_padded(E) * THR_STRIDE * 4, "thresholds"))) return r;
     if ((r = ensure(c, c->pc, (size_t)E * 2 * sizeof(PtrsConst), "rejection constants"))) return r;
     if ((r = ensure(c, c->alias, (size_t)E * 2 * ALIAS_COLS * 4, "alias columns"))) return r;
     if ((r = ensure(c, c->rdesc, (size_t)E * 4, "reddened-part descriptors"))) return r;

@@ -148,7 +148,7 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
     ji.o_alias = n_alias;
     ji.o_rdesc = n_rdesc;
     n_rec += rec_bytes(ji.E) / sizeof(EntryRec);
-    n_thr += (size_t)ji.E * THR_STRIDE;
+    n_thr += (size_t)entries_padded(ji.E) * THR_STRIDE;
     n_pc += (size_t)ji.E * 2;
     n_fl += (size_t)ji.E * BP;
     n_part += (size_t)ji.nchunks * ji.S * B * ji.npx;

@@ -204,12 +204,13 @@ __device__ __forceinline__ uint32_t ptrs_draw(const PtrsConst &c, uint32_t p, ui
 
 // C1 table of a Poisson(l) count, 0 < l < 10: T_k = floor(2^32 F(k)) for k = 0, 1, ... while
 // T_k < 2^32 (at most THR_STRIDE - 1 values), the cdf F built in FP64 by the pmf recurrence
-// p_k = p_{k-1} l / k from p_0 = e^-l.  Returns K, the number of thresholds written.
+// p_k = p_{k-1} l / k from p_0 = e^-l.  T_k goes to t[k * stride] and, for k < 3, also to
+// first[k].  Returns K, the number of thresholds written.
 // The FP64 sum often stalls just below 1 and then runs to the cap.  Once k >= l every later term
 // is smaller than p_k by at least the factor k / (k + 1) < 1, so when F + p_k rounds back to F,
 // rounding (monotone in the addend) keeps F fixed for good: the remaining thresholds all equal
 // the last one and are written without the divisions (the same table as the full recurrence).
-__device__ inline uint32_t inversion_table(double l, uint32_t *t) {
+__device__ inline uint32_t inversion_table(double l, uint32_t *t, size_t stride, uint32_t first[3]) {
   double pk = exp(-l);
   double F = pk;
   uint32_t K = 0, tlast = 0u;
@@ -218,7 +219,10 @@ __device__ inline uint32_t inversion_table(double l, uint32_t *t) {
       pk = pk * l / (double)k;
       const double Fn = F + pk;
       if (Fn == F && (double)k >= l) {  // tlast = floor(2^32 F) < 2^32, stored by the previous step
-        for (int j = k; j < THR_STRIDE - 1; ++j) t[j] = tlast;
+        for (int j = k; j < THR_STRIDE - 1; ++j) {
+          t[(size_t)j * stride] = tlast;
+          if (j < 3) first[j] = tlast;
+        }
         return (uint32_t)(THR_STRIDE - 1);
       }
       F = Fn;
@@ -226,7 +230,8 @@ __device__ inline uint32_t inversion_table(double l, uint32_t *t) {
     const double tk = floor(F * 4294967296.0);
     if (tk >= 4294967296.0) break;
     tlast = (uint32_t)tk;
-    t[k] = tlast;
+    t[(size_t)k * stride] = tlast;
+    if (k < 3) first[k] = tlast;
     K = (uint32_t)(k + 1);
   }
   return K;

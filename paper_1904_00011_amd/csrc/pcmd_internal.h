@@ -54,7 +54,7 @@ struct PrepArgs {
   const float *flux;   // [B][E]
   EntryRec *rec;       // [entries_padded(E)]
   GroupRec *grp;       // [entries_padded(E) / GRP + 1]
-  uint32_t *thr;       // [E][THR_STRIDE]
+  uint32_t *thr;       // [THR_STRIDE][EP]: threshold k of entry i at k EP + i (EP = E padded to GRP)
   void *pc;            // [E][2] PtrsConst: the entry (or its unreddened part), its reddened part
   double *fl64;        // [E][BP]
   uint32_t *status;
@@ -73,7 +73,7 @@ struct SampleArgs {
   uint32_t split_q;
   const EntryRec *rec;
   const GroupRec *grp;
-  const uint32_t *thr;
+  const uint32_t *thr;  // [THR_STRIDE][EP], k-major as in PrepArgs
   const void *pc;
   const double *fl64;
   double *part;  // [nchunks][S][B][npx]
@@ -116,7 +116,7 @@ struct BlockSampleArgs {
   int split_mode;
   uint32_t split_q;
   const BlockRec *brec;
-  const uint32_t *thr;
+  const uint32_t *thr;  // [nb][THR_STRIDE]
   const void *pc;
   const uint32_t *cth;
   const double *fl64;
