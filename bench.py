@@ -38,7 +38,7 @@ OPS_PER_DRAW = 40 / 4 + 1
 # HBM bytes per k_sample launch of the first headline step, from FETCH_SIZE and WRITE_SIZE
 # calibrated against a copy of known size (profiles/k_sample_headline_256x256_52500_counters.md).
 # Set to None whenever k_sample changes until the counters are taken again.
-SAMPLE_TRAFFIC_BYTES = 194.1e6
+SAMPLE_TRAFFIC_BYTES = 190.9e6
 
 
 def parse():

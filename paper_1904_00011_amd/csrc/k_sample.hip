@@ -362,112 +362,122 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
   const int stride = a.nchunks * (16 / GRP);
   auto slice_group = [&](int j) { return chunk * (16 / GRP) + (j >> 1) * stride + (j & 1); };
   static_assert(GRP == 8, "two groups per 16-entry block");
-  for (int j = 0, gi = slice_group(0); gi < ngrp; ++j, gi = slice_group(j)) {
-    const int g0 = gi * GRP;
-    const PCMD_CONST GroupRec *gr = grp + gi;
-    // at small lambda most groups end after two Philox blocks and eight compares, without
-    // touching the entry records
-    const uint32_t flags = gr->flags;
-    if (flags == 0u) continue;  // no entry of the group has stars
-    // inversion words of the group's two quads: counters (p, i / 4, TAG_MAIN, 0)
-    const u4 wa = philox10(p, (uint32_t)(2 * gi), TAG_MAIN, 0u, a.k0, a.k1);
-    const u4 wb = philox10(p, (uint32_t)(2 * gi + 1), TAG_MAIN, 0u, a.k0, a.k1);
-    // the first thresholds are loaded only now: held across the Philox rounds they pushed the
-    // scalar register file into spilling inside this loop
-    __builtin_amdgcn_sched_barrier(0);
-    if (!(flags & (GRP_PTRS | GRP_ALIAS)) &&
-        (__ballot(wa.x > gr->t0m1[0]) | __ballot(wa.y > gr->t0m1[1]) | __ballot(wa.z > gr->t0m1[2]) |
-         __ballot(wa.w > gr->t0m1[3]) | __ballot(wb.x > gr->t0m1[4]) | __ballot(wb.y > gr->t0m1[5]) |
-         __ballot(wb.z > gr->t0m1[6]) | __ballot(wb.w > gr->t0m1[7])) == 0ull)
-      continue;
-    // the split bits of the group's 16-entry block: a slow group almost always has a star to
-    // split, and the two groups of a block share them
-    if (S == 2 && a.split_mode == SPLIT_HALF && split_blk != (gi >> 1)) {
-      sw = philox10(p, (uint32_t)(gi >> 1), TAG_SPLIT, 0u, a.k0, a.k1);
-      split_blk = gi >> 1;
-    }
+  const int lane = (int)(threadIdx.x & 63u);
+  for (int jb = 0; slice_group(jb) < ngrp; jb += 64) {
+    // lane l reads the flags of the slice's group jb + l: one vector load finds the groups with
+    // entries to draw among the next 64, where one dependent scalar load per group kept a wave
+    // waiting through runs of groups with nothing to draw (pruned isochrones; the hybrid
+    // sampler's block-rule entries)
+    const int gl = slice_group(jb + lane);
+    const uint32_t fl = gl < ngrp ? grp[gl].flags : 0u;
+    for (uint64_t pend = __ballot(fl != 0u); pend != 0ull; pend &= pend - 1ull) {
+      const int lsel = (int)__builtin_ctzll(pend);  // wave-uniform
+      const int gi = slice_group(jb + lsel);
+      const int g0 = gi * GRP;
+      const PCMD_CONST GroupRec *gr = grp + gi;
+      // at small lambda most groups end after two Philox blocks and eight compares, without
+      // touching the entry records
+      const uint32_t flags = (uint32_t)__builtin_amdgcn_readlane((int)fl, lsel);
+      // inversion words of the group's two quads: counters (p, i / 4, TAG_MAIN, 0)
+      const u4 wa = philox10(p, (uint32_t)(2 * gi), TAG_MAIN, 0u, a.k0, a.k1);
+      const u4 wb = philox10(p, (uint32_t)(2 * gi + 1), TAG_MAIN, 0u, a.k0, a.k1);
+      // the first thresholds are loaded only now: held across the Philox rounds they pushed the
+      // scalar register file into spilling inside this loop
+      __builtin_amdgcn_sched_barrier(0);
+      if (!(flags & (GRP_PTRS | GRP_ALIAS)) &&
+          (__ballot(wa.x > gr->t0m1[0]) | __ballot(wa.y > gr->t0m1[1]) | __ballot(wa.z > gr->t0m1[2]) |
+           __ballot(wa.w > gr->t0m1[3]) | __ballot(wb.x > gr->t0m1[4]) | __ballot(wb.y > gr->t0m1[5]) |
+           __ballot(wb.z > gr->t0m1[6]) | __ballot(wb.w > gr->t0m1[7])) == 0ull)
+        continue;
+      // the split bits of the group's 16-entry block: a slow group almost always has a star to
+      // split, and the two groups of a block share them
+      if (S == 2 && a.split_mode == SPLIT_HALF && split_blk != (gi >> 1)) {
+        sw = philox10(p, (uint32_t)(gi >> 1), TAG_SPLIT, 0u, a.k0, a.k1);
+        split_blk = gi >> 1;
+      }
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int q0 = g0 + 4 * h;  // first entry of the quad
-      const u4 &w = h ? wb : wa;
-      const uint32_t sq = word_of(sw, 2 * (gi & 1) + h);  // the quad's word of the split block
-      uint32_t n0[4];
+      for (int h = 0; h < 2; ++h) {
+        const int q0 = g0 + 4 * h;  // first entry of the quad
+        const u4 &w = h ? wb : wa;
+        const uint32_t sq = word_of(sw, 2 * (gi & 1) + h);  // the quad's word of the split block
+        uint32_t n0[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) n0[q] = word_of(w, q) > gr->t0m1[4 * h + q] ? 1u : 0u;
-      u4 wr{0u, 0u, 0u, 0u};  // THIN: the quad's reddened-part words
-      bool wr_ok = false;
+        for (int q = 0; q < 4; ++q) n0[q] = word_of(w, q) > gr->t0m1[4 * h + q] ? 1u : 0u;
+        u4 wr{0u, 0u, 0u, 0u};  // THIN: the quad's reddened-part words
+        bool wr_ok = false;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t i = (uint32_t)(q0 + q);
-        // one record at a time keeps the scalar registers of the loop below the spill point
-        const EntryRec rq = ld_const(rec + i);  // padded to a multiple of GRP
-        uint32_t n = 0, red_thin = 0u;
-        bool thinned = false;
-        const uint32_t kind = rq.kk & 0xFFu;
-        if (kind <= KIND_INV) {  // inversion; a KIND_ZERO entry never passes its first threshold
-          // n = #{k < K : T_k <= u}, walking up while any lane of the wave is still above
-          const uint32_t u = word_of(w, q);
-          const uint32_t K = rq.kk >> 8;
-          n = n0[q];
-          if (!wave_any(n != 0u)) continue;
-          if (K > 1) {
-            uint32_t c = u >= rq.T[1] ? 1u : 0u;
-            if (wave_any(c != 0u)) {
-              n += c;
-              if (K > 2) {
-                c = u >= rq.T[2] ? 1u : 0u;
-                if (wave_any(c != 0u)) {
-                  n += c;
-                  const PCMD_CONST uint32_t *t = thr + i;  // threshold k at t[k EP]
-                  const size_t ep = (size_t)entries_padded(a.E);
-                  for (uint32_t k = 3; k < K; ++k) {
-                    c = u >= t[k * ep] ? 1u : 0u;
-                    if (!wave_any(c != 0u)) break;
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t i = (uint32_t)(q0 + q);
+          // one record at a time keeps the scalar registers of the loop below the spill point
+          const EntryRec rq = ld_const(rec + i);  // padded to a multiple of GRP
+          uint32_t n = 0, red_thin = 0u;
+          bool thinned = false;
+          const uint32_t kind = rq.kk & 0xFFu;
+          if (kind <= KIND_INV) {  // inversion; a KIND_ZERO entry never passes its first threshold
+            // n = #{k < K : T_k <= u}, walking up while any lane of the wave is still above
+            const uint32_t u = word_of(w, q);
+            const uint32_t K = rq.kk >> 8;
+            n = n0[q];
+            if (!wave_any(n != 0u)) continue;
+            if (K > 1) {
+              uint32_t c = u >= rq.T[1] ? 1u : 0u;
+              if (wave_any(c != 0u)) {
+                n += c;
+                if (K > 2) {
+                  c = u >= rq.T[2] ? 1u : 0u;
+                  if (wave_any(c != 0u)) {
                     n += c;
+                    const PCMD_CONST uint32_t *t = thr + i;  // threshold k at t[k EP]
+                    const size_t ep = (size_t)entries_padded(a.E);
+                    for (uint32_t k = 3; k < K; ++k) {
+                      c = u >= t[k * ep] ? 1u : 0u;
+                      if (!wave_any(c != 0u)) break;
+                      n += c;
+                    }
                   }
                 }
               }
             }
-          }
-        } else {
-          // table entry: slot 0 holds the count (or, thinned, the unreddened part), slot 1 the
-          // reddened part, each an alias column read or a rejection draw
-          n = table_draw(rq.kk, word_of(w, q), a.alias + (size_t)i * 2 * ALIAS_COLS, pc + 2 * (size_t)i, p, i,
-                         TAG_PTRS, a.k0, a.k1, a.lnfact, ptrs_failed);
-          if (S == 2 && THIN) {
-            if (!wr_ok) {  // the quad's reddened-part words, drawn once
-              wr = philox10(p, i >> 2, TAG_RED, 0u, a.k0, a.k1);
-              wr_ok = true;
+          } else {
+            // table entry: slot 0 holds the count (or, thinned, the unreddened part), slot 1 the
+            // reddened part, each an alias column read or a rejection draw
+            n = table_draw(rq.kk, word_of(w, q), a.alias + (size_t)i * 2 * ALIAS_COLS, pc + 2 * (size_t)i, p, i,
+                           TAG_PTRS, a.k0, a.k1, a.lnfact, ptrs_failed);
+            if (S == 2 && THIN) {
+              if (!wr_ok) {  // the quad's reddened-part words, drawn once
+                wr = philox10(p, i >> 2, TAG_RED, 0u, a.k0, a.k1);
+                wr_ok = true;
+              }
+              const uint32_t d = ld_const(rdesc + i);
+              red_thin = table_draw(d, word_of(wr, q), a.alias + ((size_t)i * 2 + 1) * ALIAS_COLS, pc + 2 * (size_t)i + 1,
+                                    p, i, TAG_PTRS_RED, a.k0, a.k1, a.lnfact, ptrs_failed);
+              n += red_thin;
+              thinned = true;
             }
-            const uint32_t d = ld_const(rdesc + i);
-            red_thin = table_draw(d, word_of(wr, q), a.alias + ((size_t)i * 2 + 1) * ALIAS_COLS, pc + 2 * (size_t)i + 1,
-                                  p, i, TAG_PTRS_RED, a.k0, a.k1, a.lnfact, ptrs_failed);
-            n += red_thin;
-            thinned = true;
           }
-        }
-        if (!wave_any(n != 0u)) continue;
-        uint32_t red = 0u;
-        if (S == 2) {
-          red = THIN && thinned ? red_thin : split_count(n, sq, 8u * q, a.split_mode, a.split_q, p, i, a.k0, a.k1);
-        }
-        const PCMD_CONST double *f = fl64 + (size_t)i * BP;
-        // a stream with no star in any lane adds exact zeros: skipped
-        const uint32_t nc = n - red;
-        if (S == 1 || wave_any(nc != 0u)) {
-          const double dc = (double)nc;
+          if (!wave_any(n != 0u)) continue;
+          uint32_t red = 0u;
+          if (S == 2) {
+            red = THIN && thinned ? red_thin : split_count(n, sq, 8u * q, a.split_mode, a.split_q, p, i, a.k0, a.k1);
+          }
+          const PCMD_CONST double *f = fl64 + (size_t)i * BP;
+          // a stream with no star in any lane adds exact zeros: skipped
+          const uint32_t nc = n - red;
+          if (S == 1 || wave_any(nc != 0u)) {
+            const double dc = (double)nc;
 #pragma unroll
-          for (int b = 0; b < B; ++b) acc_c[b] = fma(dc, f[b], acc_c[b]);
-        }
-        if (S == 2 && wave_any(red != 0u)) {
-          const double dr = (double)red;
+            for (int b = 0; b < B; ++b) acc_c[b] = fma(dc, f[b], acc_c[b]);
+          }
+          if (S == 2 && wave_any(red != 0u)) {
+            const double dr = (double)red;
 #pragma unroll
-          for (int b = 0; b < B; ++b) acc_r[b] = fma(dr, f[b], acc_r[b]);
-        }
-        if (DBG && dbg) {
-          const size_t o = (size_t)((int64_t)p - a.px0) * (size_t)a.E + i;
-          a.dbg_counts[o] = n;
-          if (a.dbg_red) a.dbg_red[o] = red;
+            for (int b = 0; b < B; ++b) acc_r[b] = fma(dr, f[b], acc_r[b]);
+          }
+          if (DBG && dbg) {
+            const size_t o = (size_t)((int64_t)p - a.px0) * (size_t)a.E + i;
+            a.dbg_counts[o] = n;
+            if (a.dbg_red) a.dbg_red[o] = red;
+          }
         }
       }
     }
