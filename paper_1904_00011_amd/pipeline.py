@@ -51,12 +51,16 @@ class Evaluator:
         self.ctx.hess(mags, self.B, mags.shape[1], self.hess_grid, hess_out, mom_out, self.bands, stream)
 
     def loglike(self, model, obs, data_hess, data_mom, mode: int = _lib.LL_POISSON, eps: float = 0.01,
-                conv_path: int = _lib.CONV_AUTO, stream=None):
-        """Queue one full evaluation; the result lands in self.out (device)."""
+                conv_path: int = _lib.CONV_AUTO, stream=None, out=None):
+        """Queue one full evaluation; the result lands in `out` (a one-element float64 device
+        tensor, e.g. a slot of a results vector) or, by default, in self.out."""
+        dst = self.out if out is None else out
+        if dst.dtype != torch.float64 or dst.numel() != 1 or not dst.is_cuda:
+            raise ValueError("out must be a one-element float64 device tensor")
         self.simulate(model, obs, conv_path, stream)
         self.hess_of(self.mags, self.hess, self.mom, stream)
-        self.ctx.loglike(self.hess, data_hess, self.mom, data_mom, self.out, mode, eps, stream)
-        return self.out
+        self.ctx.loglike(self.hess, data_hess, self.mom, data_mom, dst, mode, eps, stream)
+        return dst
 
     def loglike_multi(self, model, obs, cmds, mode: int = _lib.LL_POISSON, eps: float = 0.01,
                       conv_path: int = _lib.CONV_AUTO, stream=None):
