@@ -514,8 +514,8 @@ def cpu_baseline(grid, model, obs, hgrid, n_px_sample):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding is "
-              "described in DESIGN.md but not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): sharding the image across GPUs "
+              "is not built", file=sys.stderr)
         sys.exit(2)
     if args.workload == "batch":
         run_batch(args)
