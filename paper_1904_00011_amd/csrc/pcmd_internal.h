@@ -33,8 +33,9 @@ struct GroupRec {
 constexpr uint32_t GRP_INV = 1u, GRP_PTRS = 2u, GRP_ALIAS = 4u;
 
 // The record table holds E rounded up to a multiple of GRP entry records (the padding records
-// have KIND_ZERO), then one group record per GRP entries and one spare group record (the
-// sampler reads the next group's record one iteration ahead; the spare's value is never used).
+// have KIND_ZERO), then one group record per GRP entries and one spare group record (not read
+// by the sampler, which finds its groups by index bounds; it keeps any read one group past the
+// table inside the allocation).
 __host__ __device__ inline int entries_padded(int E) { return (E + GRP - 1) / GRP * GRP; }
 inline size_t rec_bytes(int E) {
   return (size_t)entries_padded(E) * sizeof(EntryRec) + (size_t)(entries_padded(E) / GRP + 1) * sizeof(GroupRec);
