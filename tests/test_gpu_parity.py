@@ -486,3 +486,29 @@ def test_subpixel_psf_grid(ctx, N):
     obs.nim = 64  # a power of two, so only the grid makes the FFT path refuse
     with pytest.raises(P.PcmdError):
         pu.gpu_simulate(ctx, lam, f32, obs, conv_path=2)
+
+
+def test_evaluator_writes_into_a_result_slot(ctx):
+    """Evaluator.loglike(out=...) writes into one slot of a results vector: the value of the
+    default output, the neighbouring slots untouched; an output of the wrong shape is refused."""
+    import torch
+    import paper_1904_00011_amd as P
+    grid, model, obs = si.small_case(nim=32, seed=3)
+    dev = torch.device("cuda")
+    _print_case("evaluator_out_slot", nim=32)
+    ev = P.Evaluator(ctx, grid, obs.nim, obs.psf, dict(x0=0.0, dx=0.05, y0=0.0, dy=0.05, nx=60, ny=60))
+    m = ev.simulate(model, obs).cpu().numpy().astype(np.float64)
+    fin = np.isfinite(m).all(axis=0)
+    ev.hess_grid = si.hess_grid_from_median(float(np.median((m[0] - m[1])[fin])), float(np.median(m[1][fin])), 60, 60)
+    dh = torch.empty(3600, dtype=torch.int32, device=dev)
+    dm = torch.empty(3, dtype=torch.float64, device=dev)
+    ev.hess_of(ev.simulate(model, dataclasses.replace(obs, seed=obs.seed + 1)).clone(), dh, dm)
+    ref = float(ev.loglike(model, obs, dh, dm).item())
+    res = torch.full((4,), -7.0, dtype=torch.float64, device=dev)
+    got = ev.loglike(model, obs, dh, dm, out=res[2:3])
+    ctx.sync()
+    r = res.cpu().numpy()
+    assert got.data_ptr() == res[2:3].data_ptr()
+    assert np.isfinite(ref) and r[2] == ref and np.all(r[[0, 1, 3]] == -7.0)
+    with pytest.raises(ValueError):
+        ev.loglike(model, obs, dh, dm, out=res[0:2])
