@@ -32,6 +32,18 @@ __device__ __forceinline__ int bin_of(double t, int n) {
   return (int)t;
 }
 
+// bin_of((d) / dx) without the division where it cannot matter: t = d * (1 / dx) is within
+// 2^-51 |t| of the correctly rounded quotient (two roundings of the product, one of the
+// quotient), so when t - e and t + e (e = 2^-50 |t|) fall in the same bin, that is the bin of the
+// quotient (bin_of is monotone); otherwise, near a bin edge, and for infinite d, the FP64
+// division decides.  NaN takes bin 0 either way.
+__device__ __forceinline__ int bin_fast(double d, double inv_dx, double dx, int n) {
+  const double t = d * inv_dx;
+  const double e = 0x1p-50 * fabs(t);
+  const int lo = bin_of(t - e, n);
+  return lo == bin_of(t + e, n) ? lo : bin_of(d / dx, n);
+}
+
 __device__ __forceinline__ double block_sum(double v, double *red) {
   // fixed-order tree: within each wave by shuffles, then over the waves in order (deterministic)
   for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -63,6 +75,7 @@ __device__ __forceinline__ void hess_body(const HessArgs &a) {
     __syncthreads();
   }
   double sx = 0.0, sy = 0.0, cnt = 0.0;
+  const double inv_dx = 1.0 / a.dx, inv_dy = 1.0 / a.dy;
   const float *mb = a.mags + (size_t)a.bb * a.npx;
   const float *mr = a.mags + (size_t)a.br * a.npx;
   const float *mm = a.mags + (size_t)a.bm * a.npx;
@@ -70,8 +83,8 @@ __device__ __forceinline__ void hess_body(const HessArgs &a) {
        p += (int64_t)gridDim.x * HESS_THREADS) {
     const double vb = (double)mb[p], vr = (double)mr[p], vm = (double)mm[p];
     const double x = vb - vr, y = vm;
-    const int ix = bin_of((x - a.x0) / a.dx, a.nx);
-    const int iy = bin_of((y - a.y0) / a.dy, a.ny);
+    const int ix = bin_fast(x - a.x0, inv_dx, a.dx, a.nx);
+    const int iy = bin_fast(y - a.y0, inv_dy, a.dy, a.ny);
     const int j = iy * a.nx + ix;
     if (a.use_lds)
       atomicAdd(&lh[j], 1u);

@@ -83,7 +83,14 @@ def test_hess_bit_exact_on_identical_magnitudes(ctx):
     mags[1, 25:75] = np.inf
     mags[2, 100:110] = -np.inf
     mags[0, 200:210] = np.nan
+    # magnitudes on a 0.25 lattice and their FP32 neighbours: with the 0.25-wide grid below, the
+    # bin quotients are integers or straddle them, where the kernel takes the exact division
+    lat = (18.0 + 0.25 * r.integers(0, 40, (3, 3000))).astype(np.float32)
+    lat[:, 1000:2000] = np.nextafter(lat[:, 1000:2000], np.float32(np.inf))
+    lat[:, 2000:3000] = np.nextafter(lat[:, 2000:3000], np.float32(-np.inf))
+    mags[:, 1000:4000] = lat
     for grid, bands in ((dict(x0=-1.0, dx=0.05, nx=60, y0=19.0, dy=0.05, ny=50), (0, 1, 1)),
+                        (dict(x0=-5.0, dx=0.25, nx=40, y0=17.0, dy=0.25, ny=24), (0, 1, 1)),
                         (dict(x0=-0.5, dx=0.02, nx=200, y0=18.5, dy=0.02, ny=200), (1, 2, 2)),
                         (dict(x0=-3.0, dx=0.05, nx=256, y0=15.0, dy=0.05, ny=256), (0, 2, 1))):
         _print_case("hess_identical", nx=grid["nx"], ny=grid["ny"], bands=bands)
