@@ -264,7 +264,8 @@ typedef struct {
  * image size and entry count load-balance; the other steps run per job.  All jobs share n_bands;
  * a job's convolution must resolve to the direct path (PCMD_E_UNSUPPORTED otherwise).
  * use_graph != 0: the first call with a given shape signature (n_jobs, each job's nim, n_entries,
- * psf_k and whether dust splits its stars, the Hess size, the tuning) captures the launch
+ * psf_k and how dust splits its stars: none, F = 1/2, F = 1 or another F, the Hess size, the
+ * tuning) captures the launch
  * sequence into a HIP graph; later calls with that signature replay it with this call's
  * parameters, seeds and input pointers.  Scratch for all jobs stays allocated in the context.
  * jobs [host][n_jobs]; hess_data [dev][nx*ny]; mom_data [dev][3] (Gaussian modes);

@@ -11,10 +11,14 @@ How a Poisson count is drawn is not fixed by the paper.  The rule here:
 
 * C1, lambda < 2 -- inversion in the integer domain.  p_0 = exp(-lambda),
   p_k = p_{k-1} * lambda / k, F_k = F_{k-1} + p_k (FP64, in that order);
-  T_k = floor(F_k * 2^32).  K is the first k with T_k >= 2^32, or 63.  With u a
-  32-bit word, n = #{k < K : T_k <= u}, i.e. the least k with u < T_k.  Exact to
-  2^-32 per outcome.  (The block-skip sampler's block totals use this rule below
-  lambda = 10.)
+  T_k = floor(F_k * 2^32).  K is the first k with T_k >= 2^32 - 1, or 63; that
+  threshold counts as 2^32, so outcome K takes the last word too (the FP64 sum can
+  stall just below 1, where floor(F 2^32) = 2^32 - 1: ending there keeps the
+  largest word from reaching a count the Poisson law gives less than 2^-32).  With
+  u a 32-bit word, n = #{k < K : T_k <= u}, i.e. the least k with u < T_k (T_K =
+  2^32).  Exact to 2^-32 per outcome; a point with lambda below about 2^-32 has
+  K = 0 and never draws a star (the rule's 2^-32 floor).  (The block-skip
+  sampler's block totals use this rule below lambda = 10.)
 * C1b, 2 <= lambda < 512 -- the same quantised law by an integer alias table
   (Walker 1977; construction of Vose 1991).  The C1 recurrence, uncapped, runs
   until T_k >= 2^32 - 1; that last threshold is taken as 2^32 (so the outcome
@@ -87,7 +91,8 @@ F32 = np.float32
 
 
 def inversion_thresholds(lam: float) -> list[int]:
-    """Thresholds T_0..T_{K-1} (all < 2^32) of the integer inversion rule."""
+    """Thresholds T_0..T_{K-1} (all < 2^32 - 1) of the integer inversion rule; outcome K takes
+    the words from T_{K-1} to 2^32 - 1."""
     lam = float(lam)
     p = math.exp(-lam)
     F = p
@@ -97,7 +102,7 @@ def inversion_thresholds(lam: float) -> list[int]:
             p = p * lam / k
             F = F + p
         t = math.floor(F * 4294967296.0)
-        if t >= TWO32:
+        if t >= TWO32 - 1:             # the last word or more: outcome k takes the rest
             break
         out.append(int(t))
     return out

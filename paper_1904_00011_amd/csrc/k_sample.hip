@@ -134,8 +134,9 @@ __global__ void __launch_bounds__(256) k_prep_job(const PrepArgs *__restrict__ t
 // (m < 2^32 / M) and "large" column stacks, both filled in ascending order; pop s from small and
 // l from large, column s keeps height m_s and alias l, m_l -= 2^32 / M - m_s, and l goes back on
 // the stack its mass now selects; columns left on the large stack are full.  All integer: the
-// table selects every outcome on exactly m_j of the 2^32 words.  The record keeps
-// k_lo << 12 | log2 M << 8 | KIND_ALIAS.
+// table selects every outcome on exactly m_j of the 2^32 words.  A part so small (below about
+// 2^-32) that T_0 already reaches 2^32 - 1 has the single outcome 0: every column then holds
+// height 0 and alias 0.  The record keeps k_lo << 12 | log2 M << 8 | KIND_ALIAS.
 constexpr int ALIAS_WAVES = 4;  // entries per 256-thread block
 
 __device__ __forceinline__ void wave_lds_sync() {
@@ -166,6 +167,7 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
     double pk = exp(-l);
     double F = pk;
     int klo = -1, J = 0;
+    bool single = false;
     uint32_t prev = 0u;
     for (int k = 0;; ++k) {
       if (k > 0) {
@@ -174,7 +176,12 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
       }
       const double t = floor(F * 4294967296.0);
       if (t >= 4294967295.0) {  // the last word or more: the rest of the mass goes to outcome k
-        m[J++] = 0u - prev;     // 2^32 - T_{k-1}; prev >= 1 (the cdf passes 2^-32 first)
+        if (klo < 0) {          // all of it (a part below about 2^-32): every word draws k
+          klo = k;
+          single = true;
+        } else {
+          m[J++] = 0u - prev;   // 2^32 - T_{k-1}; prev >= 1 here (T_{klo} > 0)
+        }
         break;
       }
       const uint32_t T = (uint32_t)t;
@@ -190,7 +197,7 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
     }
     int bits = 4;
     while ((1 << bits) < J) ++bits;
-    nout_s[wv] = bits;
+    nout_s[wv] = bits | (single ? 0x100 : 0);
     const uint32_t desc = ((uint32_t)klo << 12) | ((uint32_t)bits << 8) | KIND_ALIAS;
     if (part == 0)
       a.rec[i].kk = desc;
@@ -198,9 +205,14 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
       a.rdesc[i] = desc;
   }
   wave_lds_sync();
-  const int bits = nout_s[wv];
+  const int bits = nout_s[wv] & 0xFF;
   const int M = 1 << bits;
   const uint32_t cap = 1u << (32 - bits);
+  uint32_t *out = a.alias + ((size_t)i * 2 + part) * ALIAS_COLS;
+  if (nout_s[wv] & 0x100) {  // one outcome: height 0 and alias 0 in every column, n = k_lo always
+    for (int j = lane; j < M; j += 64) out[j] = 0u;
+    return;
+  }
   // stacks in ascending column order: each lane takes one column of every 64, ballots give the
   // positions
   int ns = 0, nl = 0;
@@ -233,7 +245,6 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
   wave_lds_sync();
   // a column whose alias is itself is full (2^32 / M words, stored as 2^32 / M - 1: the last word
   // then falls to the alias, the column itself)
-  uint32_t *out = a.alias + ((size_t)i * 2 + part) * ALIAS_COLS;
   for (int j = lane; j < M; j += 64) {
     const uint32_t h = al[j] == (uint16_t)j ? cap - 1u : m[j];
     out[j] = (h << bits) | (uint32_t)al[j];

@@ -388,9 +388,11 @@ static uint64_t batch_signature(pcmd_ctx *c, int n_jobs, const pcmd_job *jobs, c
   h = fnv(h, ((uint64_t)g->nx << 32) | (uint32_t)g->ny);
   h = fnv(h, ((uint64_t)c->tune_wg_per_cu << 32) | (uint32_t)c->tune_order);
   for (int j = 0; j < n_jobs; ++j) {
-    const int S = split_mode_of(&jobs[j].obs) == SPLIT_NONE ? 1 : 2;
+    // the split mode fixes the plan's alias rows (a thinned job builds its reddened parts' tables
+    // too) and with them the captured launches, so every mode is part of the signature
+    const int sm = split_mode_of(&jobs[j].obs);
     h = fnv(h, ((uint64_t)jobs[j].iso.n_entries << 32) | (uint32_t)jobs[j].obs.nim);
-    h = fnv(h, ((uint64_t)jobs[j].obs.psf_k << 32) | (uint32_t)S);
+    h = fnv(h, ((uint64_t)jobs[j].obs.psf_k << 32) | (uint32_t)sm);
     h = fnv(h, (uint64_t)psf_grid_of(&jobs[j].obs));
   }
   return h;

@@ -203,35 +203,26 @@ __device__ __forceinline__ uint32_t ptrs_draw(const PtrsConst &c, uint32_t p, ui
 }
 
 // C1 table of a Poisson(l) count, 0 < l < 10: T_k = floor(2^32 F(k)) for k = 0, 1, ... while
-// T_k < 2^32 (at most THR_STRIDE - 1 values), the cdf F built in FP64 by the pmf recurrence
-// p_k = p_{k-1} l / k from p_0 = e^-l.  T_k goes to t[k * stride] and, for k < 3, also to
-// first[k].  Returns K, the number of thresholds written.
-// The FP64 sum often stalls just below 1 and then runs to the cap.  Once k >= l every later term
-// is smaller than p_k by at least the factor k / (k + 1) < 1, so when F + p_k rounds back to F,
-// rounding (monotone in the addend) keeps F fixed for good: the remaining thresholds all equal
-// the last one and are written without the divisions (the same table as the full recurrence).
+// T_k < 2^32 - 1 (at most THR_STRIDE - 1 values), the cdf F built in FP64 by the pmf recurrence
+// p_k = p_{k-1} l / k from p_0 = e^-l.  The first threshold that reaches 2^32 - 1 counts as 2^32
+// and is not stored: its outcome K takes the last word too.  (The FP64 sum can stall just below
+// 1, where floor(2^32 F) = 2^32 - 1; a table that ran on there would give word 2^32 - 1 the
+// 63-star cap.)  T_k goes to t[k * stride] and, for k < 3, also to first[k].  Returns K, the
+// number of thresholds written; K = 0 (l below about 2^-32) draws no star.
 __device__ inline uint32_t inversion_table(double l, uint32_t *t, size_t stride, uint32_t first[3]) {
   double pk = exp(-l);
   double F = pk;
-  uint32_t K = 0, tlast = 0u;
+  uint32_t K = 0;
   for (int k = 0; k < THR_STRIDE - 1; ++k) {
     if (k > 0) {
       pk = pk * l / (double)k;
-      const double Fn = F + pk;
-      if (Fn == F && (double)k >= l) {  // tlast = floor(2^32 F) < 2^32, stored by the previous step
-        for (int j = k; j < THR_STRIDE - 1; ++j) {
-          t[(size_t)j * stride] = tlast;
-          if (j < 3) first[j] = tlast;
-        }
-        return (uint32_t)(THR_STRIDE - 1);
-      }
-      F = Fn;
+      F = F + pk;
     }
     const double tk = floor(F * 4294967296.0);
-    if (tk >= 4294967296.0) break;
-    tlast = (uint32_t)tk;
-    t[(size_t)k * stride] = tlast;
-    if (k < 3) first[k] = tlast;
+    if (tk >= 4294967295.0) break;
+    const uint32_t tv = (uint32_t)tk;
+    t[(size_t)k * stride] = tv;
+    if (k < 3) first[k] = tv;
     K = (uint32_t)(k + 1);
   }
   return K;

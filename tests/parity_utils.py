@@ -5,7 +5,8 @@ Bars:
 * star counts and reddened counts: bit-exact;
 * per-pixel fluxes (before and after the PSF): within 1e-5 relative of the FP64 oracle;
 * magnitudes: within 1e-4 mag;
-* Hess: bit-exact except pixels whose oracle position lies within 1e-4 mag of a bin edge;
+* Hess: every pixel in the same bin, except pixels whose oracle position lies within 1e-4 mag of
+  a bin edge (checked pixel by pixel);
 * log-likelihood: within 1e-3 absolute.
 """
 from __future__ import annotations
@@ -78,40 +79,55 @@ def gpu_loglike(ctx, hm, hd, mom_m, mom_d, mode, eps=0.01):
 
 
 def explain_count_mismatches(lam, seed, px0, got, want):
-    """Count mismatches that are NOT explained by a 32-bit word lying exactly on an inversion
-    threshold (where two FP64 exp() implementations may legitimately differ by one)."""
+    """Sort the (pixel, entry) pairs whose counts differ into (unexplained, on_threshold): a pair is
+    on a threshold when its 32-bit word lies within 1 of an inversion threshold, or when its alias
+    table would move under a one-ulp change of exp(-lambda) (where two FP64 exp implementations may
+    legitimately differ).  Diagnostic only: the tests require both lists empty."""
     bad = np.argwhere(got != want)
-    unexplained = []
+    unexplained, on_threshold = [], []
     for r, i in bad:
         p = px0 + int(r)
         li = float(lam[i])
         if osamp.ALIAS_MIN <= li < osamp.ALIAS_MAX:
-            # alias rule: explained if exp(-lambda) one ulp off would change the table
             e = math.exp(-li)
             ref = osamp.alias_table(li)
             moved = False
             for d in (0.0, 1.0):
                 alt = osamp.alias_table(li, np.nextafter(e, d))
                 moved |= alt[:2] != ref[:2] or not np.array_equal(alt[2], ref[2])
-            if not moved:
-                unexplained.append((p, int(i)))
+            (on_threshold if moved else unexplained).append((p, int(i)))
             continue
         if li >= osamp.ALIAS_MAX:
             unexplained.append((p, int(i)))
             continue
         w = orng.philox4x32_10(p, i // 4, orng.TAG_MAIN, 0, seed)[i % 4]
         u = int(w)
-        if not any(abs(u - t) <= 1 for t in osamp.inversion_thresholds(li)):
-            unexplained.append((p, int(i)))
-    return unexplained
+        near = any(abs(u - t) <= 1 for t in osamp.inversion_thresholds(li))
+        (on_threshold if near else unexplained).append((p, int(i)))
+    return unexplained, on_threshold
+
+
+def assert_counts_exact(lam, seed, px0, got, want, what="counts"):
+    """Star counts bit-exact: every (pixel, entry) equal.  Prints the number compared and, on a
+    failure, how many mismatches sit on a threshold (see explain_count_mismatches)."""
+    got = np.asarray(got)
+    want = np.asarray(want)
+    assert got.shape == want.shape, (got.shape, want.shape)
+    n_bad = int((got != want).sum())
+    print(f"[bit-exact] {what}: {got.size} compared, {n_bad} differ", flush=True)
+    if n_bad:
+        unexplained, on_thr = explain_count_mismatches(lam, seed, px0, got, want)
+        raise AssertionError(f"{what}: {n_bad} of {got.size} differ ({len(on_thr)} on a threshold, "
+                             f"{len(unexplained)} not); first {(unexplained or on_thr)[:5]}")
 
 
 def explain_block_mismatches(lam, seed, px0, got, want):
-    """Block-skip sampler: the (pixel, block) pairs whose counts differ and are NOT explained by
-    the block total's 32-bit word lying within 1 of an inversion threshold of Lambda_b."""
+    """Block-skip sampler: the (pixel, block) pairs whose counts differ, sorted into (unexplained,
+    on_threshold) like explain_count_mismatches (the block total's word within 1 of an inversion
+    threshold of Lambda_b).  Diagnostic only."""
     from oracle import sampler_block as sb
     tot = sb.block_sums(lam)
-    unexplained = []
+    unexplained, on_threshold = [], []
     for r, b in sorted({(int(r), int(i) // sb.BLOCK) for r, i in np.argwhere(got != want)}):
         p = px0 + r
         L = float(tot[b])
@@ -119,9 +135,21 @@ def explain_block_mismatches(lam, seed, px0, got, want):
             unexplained.append((p, b))
             continue
         u = int(orng.philox4x32_10(p, b, orng.TAG_BLOCK, 0, seed)[0])
-        if not any(abs(u - t) <= 1 for t in osamp.inversion_thresholds(L)):
-            unexplained.append((p, b))
-    return unexplained
+        near = any(abs(u - t) <= 1 for t in osamp.inversion_thresholds(L))
+        (on_threshold if near else unexplained).append((p, b))
+    return unexplained, on_threshold
+
+
+def assert_block_counts_exact(lam, seed, px0, got, want, what="block-rule counts"):
+    got = np.asarray(got)
+    want = np.asarray(want)
+    assert got.shape == want.shape, (got.shape, want.shape)
+    n_bad = int((got != want).sum())
+    print(f"[bit-exact] {what}: {got.size} compared, {n_bad} differ", flush=True)
+    if n_bad:
+        unexplained, on_thr = explain_block_mismatches(lam, seed, px0, got, want)
+        raise AssertionError(f"{what}: {n_bad} of {got.size} differ ({len(on_thr)} blocks on a threshold, "
+                             f"{len(unexplained)} not); first {(unexplained or on_thr)[:5]}")
 
 
 def rel_err(a, b, floor=1e-300):
@@ -153,5 +181,17 @@ def near_edge_pixels(mags64, grid, bands=(0, 1, 1), tol=MAG_ATOL):
     return near
 
 
-def hess_diff_explained(h_gpu, h_ora, n_near):
-    return int(np.abs(h_gpu - h_ora).sum()) <= 2 * int(n_near)
+def assert_hess_per_pixel(gpu_mags, ora_mags64, grid, bands=(0, 1, 1), tol=MAG_ATOL, what="Hess"):
+    """Per pixel: the bin of the GPU magnitudes and the bin of the oracle's (both by the oracle's
+    rule) are identical for every pixel whose oracle colour and magnitude lie more than `tol` mag
+    from a bin edge.  Returns (pixels compared, pixels near an edge, near-edge pixels that moved)."""
+    ixg, iyg, _, _ = oh.pixel_bins(np.asarray(gpu_mags, np.float32), grid, *bands)
+    ixo, iyo, _, _ = oh.pixel_bins(np.asarray(ora_mags64, np.float32), grid, *bands)
+    near = near_edge_pixels(ora_mags64, grid, bands, tol)
+    moved = (ixg != ixo) | (iyg != iyo)
+    far_moved = int((moved & ~near).sum())
+    print(f"[bit-exact] {what}: {moved.size} pixels binned, {int(near.sum())} within {tol} mag of an edge, "
+          f"{int((moved & near).sum())} of those moved, {far_moved} others moved", flush=True)
+    assert far_moved == 0, (f"{what}: {far_moved} pixels away from a bin edge land in another bin",
+                            np.nonzero(moved & ~near)[0][:5])
+    return moved.size, int(near.sum()), int((moved & near).sum())

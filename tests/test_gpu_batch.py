@@ -1,5 +1,7 @@
 """Batched persistent launch: bit-identical to sequential single calls, under every schedule and
 under graph replay with new parameters."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -149,3 +151,35 @@ def test_batch_autotune_and_validation(ctx):
     with pytest.raises(P.PcmdError):
         ctx.batch_run(two, grid, hess_d, mom_d, ll)
     ctx.batch_set_tuning(4, 0)
+
+
+def test_batch_graph_replay_when_the_split_mode_changes(ctx):
+    """Same shapes, but the jobs' dust fraction moves from 1/2 (one bit per star) to 0.3 (entries
+    at lambda >= 2 thinned into two parts, each with its own alias table) and back: every replay
+    equals the sequential calls.  A plan keyed on the shapes alone would keep the 1/2 plan, whose
+    launches build no tables for the reddened parts."""
+    import torch
+    dev = torch.device("cuda")
+    hess_d, mom_d, grid = _data(ctx)
+    base = si.batch_workload(6, 50, nim_log2=(4.0, 5.0), entries=(1000, 2500), psf_k=7)
+    jobs0 = []
+    for k, (g, model, obs) in enumerate(base):
+        model.log_npix = 4.5                     # entries above lambda = 2, drawn by alias tables
+        lam, _, f32 = oe.build_entries(model, g)
+        assert (lam >= 2.0).sum() > 10
+        obs.dust_model = 2
+        jobs0.append(dict(lam=torch.from_numpy(lam).to(dev), flux=torch.from_numpy(f32).to(dev), obs=obs,
+                          psf=torch.from_numpy(obs.psf).to(dev), conv_path=1))
+    for rep, frac in enumerate((0.5, 0.3, 0.5, 0.8)):
+        jobs = []
+        for k, j in enumerate(jobs0):
+            o = dataclasses.replace(j["obs"], dust_frac=frac, seed=700 + 10 * rep + k)
+            jobs.append(dict(j, obs=o))
+        print(f"[case] split mode replay {rep} frac={frac}", flush=True)
+        ll_s, h_s = _sequential(ctx, jobs, grid, hess_d, mom_d, 0)
+        ll_g = torch.empty(len(jobs), dtype=torch.float64, device=dev)
+        h_g = torch.empty((len(jobs), 100 * 100), dtype=torch.int32, device=dev)
+        ctx.batch_run(jobs, grid, hess_d, mom_d, ll_g, hess_out=h_g, use_graph=True)
+        ctx.sync()
+        assert np.array_equal(h_g.cpu().numpy(), h_s), rep
+        assert np.array_equal(ll_g.cpu().numpy(), ll_s), rep

@@ -34,8 +34,7 @@ def _block(obs):
 def _compare_window(ctx, lam, f32, obs, px0, px1, conv_path=0):
     g = pu.gpu_simulate(ctx, lam, f32, obs, conv_path, window=(px0, px1))
     Fo, s = osamp.simulate_flux(lam, f32, obs, px0, px1, want_counts=True)
-    bad = pu.explain_block_mismatches(lam, obs.seed, px0, g["counts"], s["counts"])
-    assert not bad, f"count mismatches at (pixel, block) {bad[:5]}"
+    pu.assert_block_counts_exact(lam, obs.seed, px0, g["counts"], s["counts"])
     assert np.array_equal(g["red"], s["red"])
     assert np.max(pu.rel_err(g["flux_pre"][:, px0:px1], Fo)) <= pu.FLUX_RTOL
     return g, s
@@ -50,7 +49,7 @@ def test_small_case_end_to_end(ctx):
     npx = obs.nim * obs.nim
     g = pu.gpu_simulate(ctx, lam, f32, obs, window=(0, npx))
     ora = op.simulate(lam, f32, obs, want_counts=True)
-    assert not pu.explain_block_mismatches(lam, obs.seed, 0, g["counts"], ora["counts"])
+    pu.assert_block_counts_exact(lam, obs.seed, 0, g["counts"], ora["counts"])
     assert np.array_equal(g["red"], ora["red"])
     assert np.max(pu.rel_err(g["flux_pre"], ora["F"])) <= pu.FLUX_RTOL
     assert np.max(pu.rel_err(g["flux_psf"], ora["G"])) <= pu.FLUX_RTOL
@@ -160,8 +159,8 @@ def _compare_window_hybrid(ctx, lam, f32, obs, px0, px1):
     on_blk = lam_blk > 0
     gb, ob = np.where(on_blk, g["counts"], 0), np.where(on_blk, s["counts"], 0)
     gp, op_ = np.where(on_blk, 0, g["counts"]), np.where(on_blk, 0, s["counts"])
-    assert not pu.explain_block_mismatches(lam_blk, obs.seed, px0, gb, ob)
-    assert not pu.explain_count_mismatches(lam_pt, obs.seed, px0, gp, op_)
+    pu.assert_block_counts_exact(lam_blk, obs.seed, px0, gb, ob, "hybrid: block-rule counts")
+    pu.assert_counts_exact(lam_pt, obs.seed, px0, gp, op_, "hybrid: per-point counts")
     assert np.array_equal(g["red"], s["red"])
     assert np.max(pu.rel_err(g["flux_pre"][:, px0:px1], Fo)) <= pu.FLUX_RTOL
     return g, s

@@ -18,34 +18,50 @@ def test_inversion_thresholds_match_poisson_cdf(lam):
     for k, t in enumerate(T):
         # T_k / 2^32 is the cdf to within 2^-32 (floor) plus FP64 summation error
         assert abs(t / 2 ** 32 - cdf[k]) <= 2 ** -32 + 1e-14
-    # past the table, the cdf has reached 1 within 2^-32 (or the table is capped at 63)
-    if len(T) < S.KMAX:
-        assert 1 - stats.poisson.cdf(len(T) - 1, lam) < 2 ** -31 or len(T) == 0
+        assert t < 2 ** 32 - 1
+    # past the table, less than 2^-31 of the Poisson mass is left: outcome K takes it
+    assert stats.poisson.sf(len(T), lam) < 2 ** -31
 
 
-def test_inversion_tail_is_constant_once_the_cdf_stalls():
-    """The property the device table builder uses to stop dividing: once k >= lambda (later pmf
-    terms shrink) and a term leaves the FP64 cdf unchanged, every later threshold equals the
-    current one, so the table runs to the cap with a constant tail."""
+def _table_moments(T):
+    """Exact mean and second moment of the count that the inversion table T gives over all 2^32
+    words: outcome k (k < K) takes the words [T_{k-1}, T_k), outcome K the words [T_{K-1}, 2^32)."""
+    edges = [0] + list(T) + [2 ** 32]
+    mass = np.array([edges[k + 1] - edges[k] for k in range(len(T) + 1)], dtype=np.float64)
+    k = np.arange(len(T) + 1, dtype=np.float64)
+    return float((mass * k).sum() / 2.0 ** 32), float((mass * k * k).sum() / 2.0 ** 32)
+
+
+def test_inversion_table_moments_by_enumeration():
+    """The count an inversion table gives has, over all 2^32 words, mean lambda and variance
+    lambda (the Poisson law) to its 2^-32 quantisation, and the table never runs past the support
+    of the law: the count of the largest word is one the Poisson law reaches with probability at
+    least 2^-33.  A table that ran on to the 63 cap when the FP64 cdf stalls just below 1 (so that
+    word 2^32 - 1 drew 63 stars) fails both: it adds 63^2 2^-32 to the second moment, which for the
+    faintest-weight, brightest points is many times lambda itself."""
     rs = np.random.default_rng(7)
-    lams = np.concatenate([rs.uniform(0.0, 2.0, 3000), rs.uniform(2.0, 10.0, 1000), 10.0 ** rs.uniform(-9, 0, 1000)])
-    stalled = 0
+    lams = np.concatenate([10.0 ** rs.uniform(-10, -6, 2000), 10.0 ** rs.uniform(-6, 0, 2000),
+                           rs.uniform(1.0, 2.0, 1000), rs.uniform(2.0, 10.0, 500),
+                           [2.0 ** -32 * 1.01, 2.0 ** -32 * 0.99, 1e-10, 3e-10, 1.999999]])
+    q = 2.0 ** -32
     for lam in lams:
-        T = S.inversion_thresholds(float(lam))
-        p = math.exp(-lam)
-        F = p
-        for k in range(1, S.KMAX):
-            p = p * lam / k
-            if F + p == F and k >= lam:
-                stalled += 1
-                assert len(T) == S.KMAX
-                assert all(t == T[k - 1] for t in T[k:])
-                break
-            F = F + p
-            if math.floor(F * 4294967296.0) >= 2 ** 32:
-                assert len(T) == k
-                break
-    assert stalled > 500  # the stall is common: the case matters
+        lam = float(lam)
+        T = S.inversion_thresholds(lam)
+        K = len(T)
+        # support: the largest count drawn is one the law gives at least 2^-33
+        assert K == 0 or stats.poisson.sf(K - 1, lam) >= q / 2, (lam, K)
+        m1, m2 = _table_moments(T)
+        # each threshold is the cdf floored to 2^-32 (plus FP64 rounding): the moments move by at
+        # most (K + 1) 2^-32 and (K + 1)^2 2^-32, plus the law's mass above K (< 2^-31)
+        tail = stats.poisson.sf(K, lam)
+        tail_m1 = sum(stats.poisson.sf(j, lam) for j in range(K, K + 40))
+        tail_m2 = sum((2 * j + 1) * stats.poisson.sf(j, lam) for j in range(K, K + 40))
+        assert abs(m1 - lam) <= (K + 1) * q + tail_m1 + 1e-15, (lam, K, m1)
+        assert abs((m2 - m1 * m1) - lam) <= (K + 1) ** 2 * q + tail_m2 + 1e-14, (lam, K, m2 - m1 * m1)
+        assert tail < 2 ** -31
+    # the floor: below lambda ~ 2^-32 the table is empty and no star is ever drawn
+    assert S.inversion_thresholds(1e-10) == []
+    assert len(S.inversion_thresholds(3e-10)) == 1
 
 
 @pytest.mark.parametrize("lam", [0.05, 0.9, 6.0])
