@@ -180,22 +180,24 @@ def test_headline_grid_dust_ptrs_fft_sized_psf(ctx):
     assert pu.mags_close(g["mags"], mo).all()
 
 
-@pytest.mark.parametrize("log_npix,dust_model,frac,noise,K", [
-    (5.0, 1, 0.3, 1, 5),      # fixed screen, general split fraction (one word per star)
-    (6.0, 2, 0.5, 1, 5),      # rejection-heavy (mean lambda ~190), log-normal screen
-    (4.0, 2, 1.0, 0, 1),      # all stars reddened, no PSF, no noise
-    (3.0, 2, 0.0, 2, 3),      # dust with F = 0 (no star reddened)
-    (2.0, 0, 0.5, 1, 7),      # no dust at all
+@pytest.mark.parametrize("log_npix,dust_model,frac,noise,K,sky", [
+    (5.0, 1, 0.3, 1, 5, 0.0),      # fixed screen, general split fraction (one word per star)
+    (6.0, 2, 0.5, 1, 5, 0.0),      # rejection-heavy (mean lambda ~190), log-normal screen
+    (4.0, 2, 1.0, 0, 1, 0.0),      # all stars reddened, no PSF, no noise
+    (3.0, 2, 0.0, 2, 3, 0.0),      # dust with F = 0 (no star reddened)
+    (2.0, 0, 0.5, 1, 7, 0.0),      # no dust at all
+    (3.5, 2, 0.5, 2, 5, 1e5),      # shot noise over a sky as bright as the pixels (1e5 electrons)
 ])
-def test_dust_and_noise_variants(ctx, log_npix, dust_model, frac, noise, K):
+def test_dust_and_noise_variants(ctx, log_npix, dust_model, frac, noise, K, sky):
     G, lam, f32, obs = _headline_lam(log_npix, seed=1003, stride=10)
     obs.nim = 24
     obs.dust_model = dust_model
     obs.dust_frac = frac
     obs.noise_model = noise
     obs.noise_sigma_mag = (0.02, 0.03, 0.04)
+    obs.sky = (sky, 0.5 * sky, 2.0 * sky)
     obs.psf = None if K == 1 else si.psf_stack(K, (1.0, 1.2, 1.4))
-    _print_case("variant", log_npix=log_npix, dust=dust_model, frac=frac, noise=noise, K=K, E=len(lam))
+    _print_case("variant", log_npix=log_npix, dust=dust_model, frac=frac, noise=noise, K=K, sky=sky, E=len(lam))
     _full_compare(ctx, lam, f32, obs)
 
 

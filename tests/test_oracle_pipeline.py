@@ -84,6 +84,16 @@ def test_shot_noise_variance_equals_counts():
     cp = 1000.0 * 10 ** (-0.4 * (m[0] - 25.0))
     assert abs(cp.mean() - c) < 5 * math.sqrt(c / len(cp))
     assert cp.var() == pytest.approx(c, rel=0.02)
+    # with sky: the sky adds to the counts the noise is drawn from and is subtracted after it, so
+    # the sky-subtracted counts keep the source mean and take variance source + sky
+    sky = 3.0 * c
+    os_ = si.Obs(nim=1, seed=6, dmod=0, noise_model=2, exptime=(1000.0,), zp=(25.0,), sky=(sky,))
+    ms = N.magnitudes(G, os_)
+    fin = np.isfinite(ms[0])
+    cs = np.where(fin, 1000.0 * 10 ** (-0.4 * (ms[0] - 25.0)), 0.0)   # +inf magnitude: counts <= 0
+    assert (~fin).mean() < 1e-3
+    assert abs(cs.mean() - c) < 5 * math.sqrt((c + sky) / len(cs)) + c * (~fin).mean()
+    assert cs.var() == pytest.approx(c + sky, rel=0.03)
     # no noise: exact flux -> magnitude
     o0 = si.Obs(nim=1, seed=5, dmod=0, noise_model=0)
     assert N.magnitudes(np.array([[1e-10, 0.0]]), o0)[0, 0] == pytest.approx(25.0, abs=1e-12)
@@ -198,6 +208,29 @@ def test_gaussian_loglike_identical_hess_is_mean_term():
     # floor of 2 on sigma: a single-count difference costs 1/8
     h2 = h.copy(); d2 = h.copy(); h2[:] = 0; d2[:] = 0; h2[0, 0] = 1; d2[0, 1] = 1
     assert L.loglike(h2, d2, mom_d, mom_d, L.GAUSS_PAPER) == pytest.approx(-2 * (1.0 / 8.0), rel=1e-14)
+
+
+def test_gaussian_loglikes_hand_worked_above_the_floor():
+    """Both Gaussian forms on a hand-worked 2 x 2 example whose bins all sit above the floor of 2,
+    with model and data totals that differ (tests/golden/gauss_loglike_2x2_example.txt)."""
+    from fractions import Fraction as Fr
+    vals = {}
+    for line in open(os.path.join(GOLD, "gauss_loglike_2x2_example.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        t = line.split()
+        vals[t[0]] = t[1:]
+    d = np.array([int(v) for v in vals["d"]])
+    m = np.array([int(v) for v in vals["m"]])
+    mom_d = np.array([float(v) for v in vals["mom_d"]])
+    mom_m = np.array([float(v) for v in vals["mom_m"]])
+    paper = float(Fr(vals["paper"][0]))
+    literal = float(-sum(Fr(v) for v in vals["literal_terms"]) + Fr(vals["mean_term"][0]))
+    assert L.mean_term(mom_m, mom_d) == pytest.approx(float(Fr(vals["mean_term"][0])), rel=1e-12)
+    assert L.loglike(m, d, mom_m, mom_d, L.GAUSS_PAPER) == pytest.approx(paper, rel=1e-13)
+    assert L.loglike(m, d, mom_m, mom_d, L.GAUSS_LITERAL) == pytest.approx(literal, rel=1e-13)
+    # the Hess part of the printed form is tiny next to the mean term: its units clash
+    assert abs(literal - float(Fr(vals["mean_term"][0]))) < 2e-5
 
 
 def test_poisson_loglike_scatter_shrinks_with_image_size():
