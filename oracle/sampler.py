@@ -38,9 +38,11 @@ How a Poisson count is drawn is not fixed by the paper.  The rule here:
   decisions taken in IEEE FP32 operation by operation, with a logarithm written
   here from the atanh series and ln k! from an FP64-built table (k < 256) or a
   Stirling series.  Both sides of the parity test take the same FP32 steps.
-* C3b, thinning -- for an entry drawn by C1b or C2 (lambda >= 2) under a split
-  0 < F < 1 other than 1/2 (which keeps the one-bit-per-star rule of C3, cheaper at
-  the counts where most of these entries sit), the unreddened and reddened counts
+* C3b, thinning -- for an entry drawn by C1b or C2 under a split 0 < F < 1 --
+  every such entry (lambda >= 2) when F is not 1/2; at F = 1/2 the entries with
+  lambda >= 64 (below that the one-bit-per-star rule of C3 is cheaper: most of their
+  stars take bits of a block shared by 16 entries; above it a few hundred stars
+  would each need a bit) -- the unreddened and reddened counts
   are drawn directly as independent
   Poisson((1 - F) lambda) and Poisson(F lambda) counts (the two products in
   FP64): the first with the entry's inversion word, the second with word
@@ -80,6 +82,7 @@ from .rng import (TAG_DUST, TAG_MAIN, TAG_PTRS, TAG_PTRS_RED, TAG_RED, TAG_SPLIT
                   philox4x32_10, u01_open_f32)
 
 LAM_SWITCH = 10.0
+LAM_THIN_HALF = 64.0     # F = 1/2: entries at or above this lambda are thinned (C3b)
 KMAX = 63
 TWO32 = 2 ** 32
 F32 = np.float32
@@ -408,24 +411,27 @@ def sample_pixels(lam: np.ndarray, flux32: np.ndarray, seed: int, px: np.ndarray
                 T[r_, : K[j]] = tables[j]
             cols = inv[sel]
             n[:, cols] = (U[:, cols, None] >= T[None, :, :]).sum(axis=-1)
-        thin = split and 0.0 < frac < 1.0 and frac != 0.5
         tab = np.nonzero(lb >= ALIAS_MIN)[0]          # entries drawn by C1b or C2
+        # C3b: the thinned entries (all of tab when F != 1/2; those at lambda >= 64 when F = 1/2)
+        if split and 0.0 < frac < 1.0:
+            thin = tab if frac != 0.5 else np.nonzero(lb >= LAM_THIN_HALF)[0]
+        else:
+            thin = tab[:0]
         n_red_thin = None
-        if thin and len(tab):
-            # C3b: two independent Poisson parts, (1 - F) lambda and F lambda
+        if len(thin):
+            # two independent Poisson parts, (1 - F) lambda and F lambda
             wr = philox4x32_10(px[:, None], g[None, :], TAG_RED, 0, seed)
             UR = np.stack(wr, axis=-1).reshape(npx, 4 * len(g))[:, : e1 - e0].astype(np.uint64)
-            n_red_thin = np.zeros((npx, len(tab)), dtype=np.int64)
-            for c_, j in enumerate(tab):
+            n_red_thin = np.zeros((npx, len(thin)), dtype=np.int64)
+            for c_, j in enumerate(thin):
                 lc = float(lb[j]) * (1.0 - frac)
                 lr = float(lb[j]) * frac
                 nc = draw_part(lc, U[:, j], seed, px, e0 + j, TAG_PTRS)
                 nr = draw_part(lr, UR[:, j], seed, px, e0 + j, TAG_PTRS_RED)
                 n[:, j] = nc + nr
                 n_red_thin[:, c_] = nr
-        else:
-            for j in tab:
-                n[:, j] = draw_part(float(lb[j]), U[:, j], seed, px, e0 + j, TAG_PTRS)
+        for j in np.setdiff1d(tab, thin):
+            n[:, j] = draw_part(float(lb[j]), U[:, j], seed, px, e0 + j, TAG_PTRS)
         if split and 0.0 < frac < 1.0:
             W = None
             if frac == 0.5:
@@ -436,10 +442,10 @@ def sample_pixels(lam: np.ndarray, flux32: np.ndarray, seed: int, px: np.ndarray
                 W = (words[:, q // 4] >> (np.uint64(8) * (q % 4).astype(np.uint64))) & np.uint64(0xFF)
             n_split = n.copy()
             if n_red_thin is not None:
-                n_split[:, tab] = 0                      # thinned entries are already split
+                n_split[:, thin] = 0                     # thinned entries are already split
             r = split_block(n_split, W, frac, seed, px, ents)
             if n_red_thin is not None:
-                r[:, tab] = n_red_thin
+                r[:, thin] = n_red_thin
         elif split and frac >= 1.0:
             r = n.copy()
         else:

@@ -298,12 +298,13 @@ def test_lognormal_dust_draws():
     assert abs(le.std() - 0.2) < 0.01
 
 
-@pytest.mark.parametrize("lam,frac", [(40.0, 0.3), (5.0, 0.7), (2000.0, 0.6), (700.0, 0.8)])
+@pytest.mark.parametrize("lam,frac", [(40.0, 0.3), (5.0, 0.7), (2000.0, 0.6), (700.0, 0.8), (64.0, 0.5),
+                                      (3000.0, 0.5)])
 def test_thinning_parts_are_independent_poisson(lam, frac):
-    """C3b: for an entry at lambda >= 2 under a split 0 < F < 1 the unreddened and reddened counts
-    are independent Poisson((1 - F) lambda) and Poisson(F lambda) (alias parts below 512,
-    rejection above), so the total is Poisson(lambda) and each star is reddened with
-    probability F."""
+    """C3b: for an entry at lambda >= 2 under a split 0 < F < 1 (at F = 1/2: lambda >= 64) the
+    unreddened and reddened counts are independent Poisson((1 - F) lambda) and Poisson(F lambda)
+    (alias parts below 512, rejection above), so the total is Poisson(lambda) and each star is
+    reddened with probability F."""
     f = np.ones((1, 1), np.float32)
     N = 60000
     s = S.sample_pixels(np.array([lam]), f, 31, np.arange(N), dust_model=2, dust_frac=frac, want_counts=True)
@@ -335,3 +336,27 @@ def test_thinning_uses_its_own_words():
     want_r = S.count_from_alias(v, *S.alias_table(lam * frac))
     assert np.array_equal(s["red"][:, 2], want_r)
     assert np.array_equal(s["counts"][:, 2] - s["red"][:, 2], want_c)
+
+
+@pytest.mark.parametrize("lam,thinned", [(64.0, True), (63.9, False), (1500.0, True), (10.0, False)])
+def test_half_split_thins_from_lambda_64(lam, thinned):
+    """At F = 1/2 an entry at lambda >= 64 draws its two halves from its own words through the
+    tables of lambda / 2 (C3b); below 64 its count is drawn whole and split one bit per star
+    (C3), so the reddened count is the popcount of its split bits."""
+    seed = 78
+    px = np.arange(256)
+    s = S.sample_pixels(np.array([0.0, 0.0, 0.0, lam]), np.ones((1, 4), np.float32), seed, px, dust_model=2,
+                        dust_frac=0.5, want_counts=True)
+    n, r = s["counts"][:, 3], s["red"][:, 3]
+    u = rng.philox4x32_10(px, 0, rng.TAG_MAIN, 0, seed)[3]
+    if thinned:
+        v = rng.philox4x32_10(px, 0, rng.TAG_RED, 0, seed)[3]
+        want_c = S.draw_part(lam / 2, u.astype(np.uint64), seed, px, 3, rng.TAG_PTRS)
+        want_r = S.draw_part(lam / 2, v.astype(np.uint64), seed, px, 3, rng.TAG_PTRS_RED)
+        assert np.array_equal(r, want_r)
+        assert np.array_equal(n - r, want_c)
+    else:
+        assert np.array_equal(n, S.draw_part(lam, u.astype(np.uint64), seed, px, 3, rng.TAG_PTRS))
+        byte = S.split_first_byte(px, 3, seed)
+        want_r = S.split_reddened(n, byte, 0.5, seed, px, 3)
+        assert np.array_equal(r, want_r)
