@@ -38,7 +38,9 @@ OPS_PER_DRAW = 40 / 4 + 1
 # HBM bytes per k_sample launch of the first headline step, from FETCH_SIZE and WRITE_SIZE
 # calibrated against a copy of known size (profiles/k_sample_headline_256x256_52500_counters.md).
 # Set to None whenever k_sample changes until the counters are taken again.
-SAMPLE_TRAFFIC_BYTES = 190.9e6
+SAMPLE_TRAFFIC_BYTES = None
+# The same for the first 512x512, Npix = 1e6 step (None until its counters are taken).
+LARGE_SAMPLE_TRAFFIC_BYTES = None
 
 
 def parse():
@@ -48,14 +50,17 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=None,
-                    help="pixels in the oracle's timed sampler window (default 3072 headline, 512 large)")
+                    help="pixels of the oracle's timed sampler sample (default 32768 headline, 8192 large)")
     ap.add_argument("--conv", type=int, default=0, help="0 auto, 1 direct, 2 fft")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "large", "batch", "counters", "surrogate", "scatter", "ablation"],
+                    choices=["headline", "large", "small", "batch", "counters", "surrogate", "scatter", "ablation"],
                     help="headline: 256x256 single evaluations; large: 512x512 at Npix = 1e6 with a 63x63 PSF and "
-                         "200x200 Hess; batch: 256 uneven jobs per step; counters: one headline simulation plus a "
+                         "200x200 Hess; small: 64x64, 500 points, the oracle timed on whole evaluations; "
+                         "batch: 256 uneven jobs per step; counters: one headline simulation plus a "
                          "copy of known size, for hardware-counter runs; surrogate: the learned screen; scatter: "
                          "log-likelihood scatter against image size and the L_max ceiling")
+    ap.add_argument("--counters-of", default="headline", choices=["headline", "large"],
+                    help="counters workload: the simulation it runs")
     ap.add_argument("--jobs", type=int, default=256)
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--train-pairs", type=int, default=16384)
@@ -407,9 +412,10 @@ def run_ablation(args):
         "rows": rows}), flush=True)
 
 
-def run_counters():
-    """One headline simulation (the parameters of step 0) and a 2048x2048x3 FP32 image copy of
-    known size (50,331,648 bytes read and written) that calibrates FETCH_SIZE / WRITE_SIZE."""
+def run_counters(args):
+    """One simulation (the headline benchmark's first step, or with --counters-of large the first
+    512x512 step) and a 2048x2048x3 FP32 image copy of known size (50,331,648 bytes read and
+    written) that calibrates FETCH_SIZE / WRITE_SIZE."""
     import torch
 
     import paper_1904_00011_amd as P
@@ -417,7 +423,7 @@ def run_counters():
 
     ctx = P.Context(0)
     grid = si.headline_grid()
-    model, obs = si.draw_headline_params(1000)
+    model, obs = si.draw_large_params(1000) if args.counters_of == "large" else si.draw_headline_params(1000)
     ev = P.Evaluator(ctx, grid, obs.nim, obs.psf, dict(x0=0.0, dx=0.05, y0=0.0, dy=0.05, nx=100, ny=100))
     ev.simulate(model, obs)
     ctx.sync()
@@ -476,39 +482,141 @@ def hbm_roofline(nbytes: float, ms: float, kernel: str) -> dict:
             "frac": gbs / HBM_PEAK_GBS if gbs else None, "bytes": nbytes, "avg_launch_ms": ms}
 
 
-def cpu_baseline(grid, model, obs, hgrid, n_px_sample):
-    """Time the oracle (single thread) on a bounded sample of one evaluation."""
-    from threadpoolctl import threadpool_limits
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
+
+def cpu_baseline(grid, model, obs, hgrid, n_px_sample, min_seconds: float = 0.0):
+    """Time the oracle on every host core this process may use (pixel slabs of the sampler and
+    one band per process of the convolution, as `oracle.parallel` splits them) on a bounded
+    sample of one evaluation: entries, the sampler on n_px_sample pixels (its cost is linear in
+    pixels, so the time is scaled to the image), then PSF, noise, Hess and logL at full size on an
+    image tiled from the sampled pixels.  n_px_sample = 0 runs the sampler on the whole image.
+    The evaluation is repeated until min_seconds have passed and the mean time is reported."""
     from oracle import entries as oe
     from oracle import hess as oh
     from oracle import loglike as ol
     from oracle import noise as on
-    from oracle import psf as ops
-    from oracle import sampler as osamp
+    from oracle import parallel as opar
 
     N = obs.nim
     npx = N * N
-    with threadpool_limits(1):
+    n_s = npx if not n_px_sample else min(npx, n_px_sample)
+    workers = opar.default_workers()
+    # the sample: up to 64 windows spread over the image
+    n_win = min(max(1, n_s // 128), 64)
+    step = npx // n_win
+    wins = [(k * step, k * step + n_s // n_win) for k in range(n_win)]
+    n_s = sum(b - a for a, b in wins)
+    t_evals, t_samp, t_all = [], [], 0.0
+    while True:
         t0 = time.perf_counter()
         lam, _, f32 = oe.build_entries(model, grid)
         t1 = time.perf_counter()
-        F, _ = osamp.simulate_flux(lam, f32, obs, 0, n_px_sample)
+        F, _, _ = opar.simulate_flux(lam, f32, obs, wins, workers=workers)
         t2 = time.perf_counter()
-        # image-plane steps at full size on an image tiled from the sampled window
-        reps = int(np.ceil(npx / n_px_sample))
+        reps = int(np.ceil(npx / n_s))
         Ffull = np.tile(F, (1, reps))[:, :npx].reshape(F.shape[0], N, N)
-        G = ops.convolve_periodic(Ffull, obs.psf)
+        G = opar.convolve(Ffull, obs.psf, workers=workers) if obs.psf is not None else Ffull
         m = on.magnitudes(G.reshape(F.shape[0], npx), obs)
         H, mom = oh.hess(m, hgrid)
         ol.loglike(H, H, mom, mom, ol.POISSON, 0.01)
         t3 = time.perf_counter()
-    t_eval = (t1 - t0) + (t2 - t1) * (npx / n_px_sample) + (t3 - t2)
-    return dict(value=1.0 / t_eval, unit="evals/s", cores=1, kind="oracle",
-                sample=(f"oracle in one thread: entries + sampler on {n_px_sample} of {npx} pixels "
-                        f"(time scaled x{npx / n_px_sample:g}) + PSF, noise, Hess and logL at full size; "
-                        f"log Npix = {model.log_npix:.3f}; measured {t3 - t0:.1f} s"),
-                sampler_draws_per_s=n_px_sample * len(lam) / (t2 - t1))
+        t_evals.append((t1 - t0) + (t2 - t1) * (npx / n_s) + (t3 - t2))
+        t_samp.append(t2 - t1)
+        t_all += t3 - t0
+        if t_all >= min_seconds:
+            break
+    t_eval = float(np.mean(t_evals))
+    what = (f"the whole image" if n_s == npx else
+            f"{n_s} of {npx} pixels ({n_win} windows; time scaled x{npx / n_s:.2f})")
+    return dict(value=1.0 / t_eval, unit="evals/s", cores=workers, kind="oracle",
+                cpu=cpu_model(), host_cpu_count=os.cpu_count(),
+                sample=(f"oracle on {workers} processes: entries + sampler on {what} + PSF, noise, Hess and logL at "
+                        f"full size; log Npix = {model.log_npix:.3f}; {len(t_evals)} evaluation(s), measured "
+                        f"{t_all:.1f} s"),
+                sampler_draws_per_s=n_s * len(lam) / float(np.mean(t_samp)))
+
+
+def run_small(args):
+    """The small configuration: 64x64 px, 2 bands, one isochrone of 500 masses (Salpeter, Npix =
+    100), no dust, 5x5 PSF, Gaussian magnitude noise 0.02, 100x100 Hess.  Each step is one whole
+    evaluation with a new seed (1000, 1001, ...) against the data Hess of seed 2; far too little
+    work to fill the GPU, so the value is a latency figure.  The oracle is timed on the whole
+    evaluation (no sampling)."""
+    import torch
+
+    import paper_1904_00011_amd as P
+    import synth_inputs as si
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    ctx = P.Context(0)
+    grid, model, obs = si.small_case(64, seed=2)
+    nh = 100
+    ev = P.Evaluator(ctx, grid, obs.nim, obs.psf, dict(x0=0.0, dx=0.05, y0=0.0, dy=0.05, nx=nh, ny=nh))
+    mags_d = ev.simulate(model, obs).clone()
+    ctx.sync()
+    md = mags_d.cpu().numpy().astype(np.float64)
+    fin = np.isfinite(md).all(axis=0)
+    hgrid = si.hess_grid_from_median(float(np.median((md[0] - md[1])[fin])), float(np.median(md[1][fin])), nh, nh)
+    ev.hess_grid = hgrid
+    data_hess = torch.empty(nh * nh, dtype=torch.int32, device=dev)
+    data_mom = torch.empty(3, dtype=torch.float64, device=dev)
+    ev.hess_of(mags_d, data_hess, data_mom)
+    obss = [dataclasses.replace(obs, seed=1000 + k) for k in range(args.steps + args.warmup)]
+    logls = torch.empty(args.steps + args.warmup, dtype=torch.float64, device=dev)
+    for k in range(args.warmup):
+        ev.loglike(model, obss[k], data_hess, data_mom, P.LL_POISSON, 0.01, out=logls[k:k + 1])
+    torch.cuda.synchronize()
+    ctx.timer_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.warmup, args.warmup + args.steps):
+        ev.loglike(model, obss[k], data_hess, data_mom, P.LL_POISSON, 0.01, out=logls[k:k + 1])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ctx.sync()
+    s_ms, s_n, s_units = ctx.timer_read(P._lib.TIMER_SAMPLE)
+    c_ms, c_n, _ = ctx.timer_read(P._lib.TIMER_CONV)
+    h_ms, h_n, _ = ctx.timer_read(P._lib.TIMER_HESS)
+    ctx.timer_enable(False)
+    ll = logls.cpu().numpy()[args.warmup:]
+    assert np.all(np.isfinite(ll)), "non-finite log-likelihood"
+    elapsed = t1 - t0
+    draws = s_units / max(s_n, 1)
+    avg_sample_s = s_ms / max(s_n, 1) / 1e3
+    achieved = OPS_PER_DRAW * draws / avg_sample_s
+    res = {
+        "metric": "likelihood evals/sec (64^2 image, 500 isochrone points)",
+        "value": args.steps / elapsed, "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32 counts / f64 sums / f32 images", "data": "synthetic",
+        "config": {"workload": "64x64 px, 2 bands, 500 masses of one isochrone (Salpeter, Npix = 100), no dust, "
+                               "5x5 PSF, Gaussian magnitude noise 0.02, 100x100 Hess, Poisson logL",
+                   "nim": 64, "entries": grid.n_entries, "bands": 2, "psf_k": 5, "hess": [nh, nh],
+                   "parallelism": "1 GPU"},
+        "poisson_draws_per_s": s_units / (s_ms / 1e3) if s_ms > 0 else None,
+        "draws_per_eval": draws,
+        "kernel_ms_per_eval": {"sample": s_ms / max(s_n, 1), "conv": c_ms / max(c_n, 1), "hess": h_ms / max(h_n, 1)},
+        "roofline": {"bound": "alu", "kernel": "k_sample", "achieved": achieved / 1e12,
+                     "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "T lane-instr/s (VALU)",
+                     "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": None, "ops_per_draw": OPS_PER_DRAW,
+                     "avg_launch_ms": avg_sample_s * 1e3,
+                     "note": "2.05e6 draws per launch fill 4,096 lanes only: launch- and latency-bound"},
+        "mean_logL": float(ll.mean()),
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(grid, model, obss[args.warmup], hgrid, 0, min_seconds=10.0)
+    ctx.close()
+    print(json.dumps(res), flush=True)
 
 
 def main():
@@ -521,7 +629,7 @@ def main():
         run_batch(args)
         return
     if args.workload == "counters":
-        run_counters()
+        run_counters(args)
         return
     if args.workload == "surrogate":
         run_surrogate(args)
@@ -531,6 +639,9 @@ def main():
         return
     if args.workload == "ablation":
         run_ablation(args)
+        return
+    if args.workload == "small":
+        run_small(args)
         return
     import torch
 
@@ -544,7 +655,7 @@ def main():
     large = args.workload == "large"
     draw = si.draw_large_params if large else si.draw_headline_params
     nh = 200 if large else 100
-    cpu_pixels = args.cpu_pixels if args.cpu_pixels else (512 if large else 3072)
+    cpu_pixels = args.cpu_pixels if args.cpu_pixels else (8192 if large else 32768)
     model_d, obs_d = draw(2)
     # data image and Hess grid (untimed set-up)
     ev = P.Evaluator(ctx, grid, obs_d.nim, obs_d.psf, dict(x0=0.0, dx=0.05, y0=0.0, dy=0.05, nx=nh, ny=nh))
@@ -665,8 +776,14 @@ def main():
         "hess_roofline": hbm_roofline(8.0 * obs_d.nim ** 2 + 4.0 * nh * nh, h_ms / max(h_n, 1), "k_hess"),
         "roofline": {"bound": "alu", "kernel": "k_sample", "achieved": achieved / 1e12,
                      "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "T lane-instr/s (VALU)",
-                     "frac": achieved / VALU_LANE_OPS_PEAK, "traffic": None if large else SAMPLE_TRAFFIC_BYTES,
-                     "ops_per_draw": OPS_PER_DRAW, "avg_launch_ms": avg_sample_s * 1e3},
+                     "frac": achieved / VALU_LANE_OPS_PEAK,
+                     "traffic": (LARGE_SAMPLE_TRAFFIC_BYTES if large else SAMPLE_TRAFFIC_BYTES),
+                     "ops_per_draw": OPS_PER_DRAW, "avg_launch_ms": avg_sample_s * 1e3,
+                     # the same lane-instruction rate against the published FP32 peaks (one
+                     # lane-instruction counted as one operation): an integer random-number
+                     # generator issues no packed FP32 FMAs, so 157.3 TFLOP/s is out of its reach
+                     "frac_of_fp32_78_6_tflops": achieved / 78.6e12,
+                     "frac_of_fp32_packed_157_3_tflops": achieved / 157.3e12},
         "mean_logL": float(ll.mean()),
         "fft_conv_path": fft,
         "hybrid_sampler": hyb,

@@ -103,12 +103,15 @@ typedef struct {
 enum { PCMD_IMF_POWER_LAW = 0, PCMD_IMF_KROUPA = 1 };
 
 /* Host helper: IMF weight of every point (the IMF integrated over the point's mass bin, edges at
- * geometric midpoints, outer edges half a log-step out; Sec. 2.2, Table 2) and the star flux
- * 10^(-0.4 M) per band.  Points of one isochrone must be contiguous with increasing mass.
- * mass [host][E]; absmag [host][B][E]; imf_w_out [host][E]; flux_out [host][B][E] (FP32). */
+ * geometric midpoints, outer edges half a log-step out; Sec. 2.2, Table 2), the star flux
+ * 10^(-0.4 M) per band and, if iso_imf_sum_out is not NULL, the IMF weight summed over the points
+ * of each of the n_iso isochrones (the per-isochrone normalisation that pcmd_entries needs; every
+ * iso_of_entry must then lie in [0, n_iso)).  Points of one isochrone must be contiguous with
+ * increasing mass.  mass [host][E]; absmag [host][B][E]; imf_w_out [host][E]; flux_out
+ * [host][B][E] (FP32); iso_imf_sum_out [host][n_iso] or NULL. */
 int pcmd_grid_prepare(int32_t n_entries, int32_t n_bands, const int32_t *iso_of_entry,
                       const double *mass, const double *absmag, int32_t imf, double alpha,
-                      double *imf_w_out, float *flux_out);
+                      double *imf_w_out, float *flux_out, int32_t n_iso, double *iso_imf_sum_out);
 
 /* Host helper: per-isochrone SFH x MDF weight and Npix for `model` (Sec. 2.2). w_out [host][n_iso]. */
 int pcmd_iso_weights(const pcmd_model *model, const pcmd_isoset *set, double *w_out, double *npix_out);
@@ -171,8 +174,7 @@ enum { PCMD_SAMPLER_POINT = 0, PCMD_SAMPLER_BLOCK = 1, PCMD_SAMPLER_HYBRID = 2 }
  *                 (else PCMD_E_INVAL at pcmd_sync, the block drawn as 0).
  *                 HYBRID (2): blocks whose lambda sum is below 10 by the BLOCK rule, the other
  *                 blocks' points by the POINT rule (the cheaper rule on each side; any block sum
- *                 allowed).  BLOCK and HYBRID: pcmd_simulate only (pcmd_batch_run rejects them
- *                 with PCMD_E_UNSUPPORTED) */
+ *                 allowed).  Batches take all three, job by job */
 typedef struct {
   int32_t nim;
   int32_t dust_model;
@@ -259,13 +261,14 @@ typedef struct {
 } pcmd_job;
 
 /* Simulate, bin and score n_jobs independent simulations, each bit-identical to pcmd_simulate +
- * pcmd_hess + pcmd_loglike on the same inputs.  The sampler runs as one persistent launch whose
- * (job, 256-pixel block, entry chunk) tiles are drawn from a shared counter, so jobs of uneven
- * image size and entry count load-balance; the other steps run per job.  All jobs share n_bands;
+ * pcmd_hess + pcmd_loglike on the same inputs.  The per-point sampler runs as one persistent
+ * launch whose (job, 64-pixel block, entry chunk) tiles are drawn from a shared counter, so jobs of
+ * uneven image size and entry count load-balance; a job with the block-skip or hybrid sampler
+ * draws its block-rule stars in a launch of its own after it; the other steps run per job.  All jobs share n_bands;
  * a job's convolution must resolve to the direct path (PCMD_E_UNSUPPORTED otherwise).
  * use_graph != 0: the first call with a given shape signature (n_jobs, each job's nim, n_entries,
- * psf_k and how dust splits its stars: none, F = 1/2, F = 1 or another F, the Hess size, the
- * tuning) captures the launch
+ * psf_k, sampler, PSF grid and how dust splits its stars: none, F = 1/2, F = 1 or another F, the
+ * Hess size, the tuning) captures the launch
  * sequence into a HIP graph; later calls with that signature replay it with this call's
  * parameters, seeds and input pointers.  Scratch for all jobs stays allocated in the context.
  * jobs [host][n_jobs]; hess_data [dev][nx*ny]; mom_data [dev][3] (Gaussian modes);
@@ -321,11 +324,30 @@ int64_t pcmd_mlp_weight_count(const int32_t *dims, int32_t n_layers);
 int pcmd_mlp_refresh(pcmd_ctx *ctx, const pcmd_mlp *net, pcmd_stream stream);
 /* Inference: x [dev][n][dims[0]] FP32 -> y [dev][n][dims[n_layers]] FP32. */
 int pcmd_mlp_forward(pcmd_ctx *ctx, const pcmd_mlp *net, int32_t n, const float *x, float *y, pcmd_stream stream);
-/* One training step on a batch: forward, loss = mean((y - t)^2), backward, and (if apply_update)
- * one Adam step number `step` (>= 1) with learning rate lr.  loss_out [dev][1] or NULL;
- * grad_out [dev][param_count] or NULL receives the packed FP32 gradient of the loss. */
+/* Forward, loss = mean((y - t)^2) over the batch and its outputs, and backward of one batch of n
+ * samples: grad_out [dev][param_count] receives the packed FP32 gradient of the loss;
+ * loss_out [dev][1] or NULL.  rows [dev][n] int32 or NULL: sample k of the batch is row rows[k] of
+ * x [n_total][dims[0]] and of t [n_total][dims[n_layers]] (the gather runs inside the input
+ * conversion and the loss kernel; a row outside [0, n_total) is read as row 0 and reported by
+ * pcmd_sync as PCMD_E_INVAL); NULL: rows 0 .. n-1 (n_total ignored). */
+int pcmd_mlp_backward(pcmd_ctx *ctx, const pcmd_mlp *net, int32_t n, const float *x, const float *t,
+                      const int32_t *rows, int64_t n_total, float *loss_out, float *grad_out, pcmd_stream stream);
+/* One Adam step number `step` (>= 1) with learning rate lr on the master weights from the packed
+ * gradient grad [dev][param_count], then the BF16 copies refreshed. */
+int pcmd_mlp_adam(pcmd_ctx *ctx, const pcmd_mlp *net, const float *grad, float lr, int32_t step, pcmd_stream stream);
+/* pcmd_mlp_backward on rows 0 .. n-1 followed (if apply_update) by pcmd_mlp_adam.  grad_out
+ * [dev][param_count] or NULL (the context then keeps the gradient). */
 int pcmd_mlp_train_step(pcmd_ctx *ctx, const pcmd_mlp *net, int32_t n, const float *x, const float *t, float lr,
                         int32_t step, float *loss_out, float *grad_out, int32_t apply_update, pcmd_stream stream);
+/* Mean squared error of the network over a whole set of n samples (rows as in pcmd_mlp_backward),
+ * forward passes of at most 1024 samples, squared errors summed in FP64: mse_out [dev][1] FP64. */
+int pcmd_mlp_loss(pcmd_ctx *ctx, const pcmd_mlp *net, int32_t n, const float *x, const float *t, const int32_t *rows,
+                  int64_t n_total, double *mse_out, pcmd_stream stream);
+/* Training targets of the surrogate from simulated Hess diagrams: for each of n rows of n_bins
+ * counts, out[r][j] = ln((H[r][j] + 1/2) / (N_r + n_bins / 2)) with N_r the row total (computed in
+ * FP64, stored FP32).  hess [dev][n][n_bins] u32; out [dev][n][n_bins] FP32. */
+int pcmd_log_hess_target(pcmd_ctx *ctx, const uint32_t *hess, int32_t n, int32_t n_bins, float *out,
+                         pcmd_stream stream);
 /* Surrogate Poisson log-likelihood of a data Hess under predicted log-Hess diagrams:
  * lam_j = N_d exp(y_j) / sum_k exp(y_k), logL = sum_j d_j ln lam_j - lam_j - ln d_j!.
  * y [dev][n][nbins] FP32; hess_data [dev][nbins]; out [dev][n] FP64. */

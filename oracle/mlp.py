@@ -19,8 +19,11 @@ Backward (the chain rule written out):
   GELU'(z) = Phi(z) + z phi(z).
 Adam (Kingma & Ba 2015) on the FP32 master weights.
 
+Targets: ln((H_j + 1/2) / (N + n_bins / 2)) of a simulated Hess diagram (N its total).
+
 Pins: finite differences of the pure-FP64 network (no rounding) against the backward formulas;
-GELU and its derivative against numerical differentiation (tests/test_oracle_mlp.py).
+GELU and its derivative against numerical differentiation; the target shares of a diagram sum to
+one and equal counts give equal targets (tests/test_oracle_mlp.py).
 """
 from __future__ import annotations
 
@@ -117,6 +120,20 @@ def adam_update(master, grad, m, v, step: int, lr: float, beta1=0.9, beta2=0.999
     mh = m / (1.0 - beta1 ** step)
     vh = v / (1.0 - beta2 ** step)
     return master - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def log_hess_target(hess):
+    """Training target of one or more Hess diagrams (rows of counts): the log of each bin's share
+    with half a count added to every bin, ln((H_j + 1/2) / (N + n_bins / 2)), N the row's total.
+    The shares of a row sum to one, and an empty bin keeps a finite target."""
+    h = np.atleast_2d(np.asarray(hess, dtype=np.float64))
+    N = h.sum(axis=1, keepdims=True)
+    return np.log((h + 0.5) / (N + 0.5 * h.shape[1]))
+
+
+def mse(y, t) -> float:
+    """Mean squared error over all samples and outputs."""
+    return float(np.mean((np.asarray(y, dtype=np.float64) - np.asarray(t, dtype=np.float64)) ** 2))
 
 
 def surrogate_loglike(logh_pred, hess_data):

@@ -112,7 +112,7 @@ def load(path: str = LIB_PATH):
         "pcmd_last_error": (C.c_char_p, [vp]),
         "pcmd_sync": (C.c_int, [vp, vp]),
         "pcmd_version": (C.c_char_p, []),
-        "pcmd_grid_prepare": (C.c_int, [i32, i32, vp, vp, vp, i32, dbl, vp, vp]),
+        "pcmd_grid_prepare": (C.c_int, [i32, i32, vp, vp, vp, i32, dbl, vp, vp, i32, vp]),
         "pcmd_iso_weights": (C.c_int, [C.POINTER(ModelS), C.POINTER(IsoSet), vp, C.POINTER(dbl)]),
         "pcmd_entries": (C.c_int, [vp, C.POINTER(GridS), vp, dbl, vp, vp]),
         "pcmd_simulate": (C.c_int, [vp, C.POINTER(IsoS), C.POINTER(ObsS), vp, C.POINTER(DebugS), vp]),
@@ -128,6 +128,10 @@ def load(path: str = LIB_PATH):
         "pcmd_mlp_refresh": (C.c_int, [vp, C.POINTER(MlpS), vp]),
         "pcmd_mlp_forward": (C.c_int, [vp, C.POINTER(MlpS), i32, vp, vp, vp]),
         "pcmd_mlp_train_step": (C.c_int, [vp, C.POINTER(MlpS), i32, vp, vp, C.c_float, i32, vp, vp, i32, vp]),
+        "pcmd_mlp_backward": (C.c_int, [vp, C.POINTER(MlpS), i32, vp, vp, vp, i64, vp, vp, vp]),
+        "pcmd_mlp_adam": (C.c_int, [vp, C.POINTER(MlpS), vp, C.c_float, i32, vp]),
+        "pcmd_mlp_loss": (C.c_int, [vp, C.POINTER(MlpS), i32, vp, vp, vp, i64, vp, vp]),
+        "pcmd_log_hess_target": (C.c_int, [vp, vp, i32, i32, vp, vp]),
         "pcmd_surrogate_loglike": (C.c_int, [vp, vp, i32, i32, vp, vp, vp]),
         "pcmd_gemm_bf16": (C.c_int, [vp, i32, i32, i32, vp, i32, i32, vp, i32, i32, vp, i32, vp]),
         "pcmd_timer_enable": (C.c_int, [vp, C.c_int]),
@@ -165,8 +169,9 @@ def _stream(stream):
 IMF_POWER_LAW, IMF_KROUPA = 0, 1
 
 
-def grid_prepare(iso_of_entry, mass, absmag, alpha: float = 2.35, imf: str = "salpeter"):
-    """IMF weight per point and FP32 star flux per band (host)."""
+def grid_prepare(iso_of_entry, mass, absmag, alpha: float = 2.35, imf: str = "salpeter", n_iso: int | None = None):
+    """IMF weight per point and FP32 star flux per band (host); with n_iso also the IMF weight
+    summed over each isochrone's points: (imf_w, flux) or (imf_w, flux, iso_imf_sum)."""
     lib = load()
     iso = np.ascontiguousarray(iso_of_entry, dtype=np.int32)
     mass = np.ascontiguousarray(mass, dtype=np.float64)
@@ -174,12 +179,14 @@ def grid_prepare(iso_of_entry, mass, absmag, alpha: float = 2.35, imf: str = "sa
     B, E = absmag.shape
     w = np.empty(E, dtype=np.float64)
     f = np.empty((B, E), dtype=np.float32)
+    sums = None if n_iso is None else np.empty(int(n_iso), dtype=np.float64)
     kind = IMF_KROUPA if imf == "kroupa" else IMF_POWER_LAW
     rc = lib.pcmd_grid_prepare(E, B, iso.ctypes.data, mass.ctypes.data, absmag.ctypes.data, kind, float(alpha),
-                               w.ctypes.data, f.ctypes.data)
+                               w.ctypes.data, f.ctypes.data, 0 if n_iso is None else int(n_iso),
+                               None if sums is None else sums.ctypes.data)
     if rc != OK:
         raise PcmdError(rc, "pcmd_grid_prepare rejected its arguments")
-    return w, f
+    return (w, f) if sums is None else (w, f, sums)
 
 
 def model_struct(model, keep: list):
@@ -367,6 +374,27 @@ class Context:
         self._check(self.lib.pcmd_mlp_train_step(self.h, C.byref(net), int(x.shape[0]), _ptr(x), _ptr(t), float(lr),
                                                  int(step), _ptr(loss_out), _ptr(grad_out), int(bool(apply_update)),
                                                  _stream(stream)), "pcmd_mlp_train_step")
+
+    def mlp_backward(self, net, x, t, grad_out, rows=None, loss_out=None, n: int | None = None, stream=None):
+        """Gradient of one batch: the rows `rows` (int32 device vector) of x and t, or all of x."""
+        nb = int(rows.shape[0]) if rows is not None else int(x.shape[0]) if n is None else int(n)
+        self._check(self.lib.pcmd_mlp_backward(self.h, C.byref(net), nb, _ptr(x), _ptr(t), _ptr(rows), int(x.shape[0]),
+                                               _ptr(loss_out), _ptr(grad_out), _stream(stream)), "pcmd_mlp_backward")
+
+    def mlp_adam(self, net, grad, lr: float, step: int, stream=None):
+        self._check(self.lib.pcmd_mlp_adam(self.h, C.byref(net), _ptr(grad), float(lr), int(step), _stream(stream)),
+                    "pcmd_mlp_adam")
+
+    def mlp_loss(self, net, x, t, mse_out, rows=None, stream=None):
+        """Mean squared error over the rows `rows` of x and t (all rows by default) into mse_out."""
+        n = int(rows.shape[0]) if rows is not None else int(x.shape[0])
+        self._check(self.lib.pcmd_mlp_loss(self.h, C.byref(net), n, _ptr(x), _ptr(t), _ptr(rows), int(x.shape[0]),
+                                           _ptr(mse_out), _stream(stream)), "pcmd_mlp_loss")
+
+    def log_hess_target(self, hess, out, stream=None):
+        n, nb = int(hess.shape[0]), int(hess.shape[1])
+        self._check(self.lib.pcmd_log_hess_target(self.h, _ptr(hess), n, nb, _ptr(out), _stream(stream)),
+                    "pcmd_log_hess_target")
 
     def surrogate_loglike(self, y, hess_data, out, stream=None):
         n, nb = int(y.shape[0]), int(y.shape[1])

@@ -4,6 +4,7 @@
 #include <math.h>
 
 #include "pcmd_device.h"
+#include "pcmd_internal.h"
 #include "pcmd_mlp.h"
 
 namespace pcmd {
@@ -268,35 +269,98 @@ hipError_t launch_f32_to_bf16(const float *x, void *y, int64_t n, hipStream_t s)
   return hipGetLastError();
 }
 
-// dy = 2 (y - t) / (n M) stored in BF16; per-block partial sums of (y - t)^2 in FP64.  Threads
-// take runs of four elements (16-byte loads, 8-byte stores) when the pointers allow it.
+// Row index of batch sample k: rows[k] when a row vector is given (one outside [0, n_total) is
+// taken as row 0 and flagged in *status), else k.
+__device__ __forceinline__ int64_t batch_row(const int32_t *__restrict__ rows, int64_t k, int64_t n_total,
+                                             uint32_t *status) {
+  if (!rows) return k;
+  const int32_t r = rows[k];
+  if (r < 0 || (int64_t)r >= n_total) {
+    atomicOr(status, STATUS_BAD_ROW);
+    return 0;
+  }
+  return r;
+}
+
+// y[k][j] = bf16(x[row k][j]) for a batch of n samples of d inputs.
+__global__ void __launch_bounds__(256) k_gather_f32_to_bf16(const float *__restrict__ x, const int32_t *__restrict__ rows,
+                                                            int64_t n_total, int d, int64_t n, __bf16 *__restrict__ y,
+                                                            uint32_t *status) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * d) return;
+  const int64_t k = i / d, j = i - k * d;
+  y[i] = (__bf16)x[batch_row(rows, k, n_total, status) * d + j];
+}
+
+hipError_t launch_gather_f32_to_bf16(const float *x, const int32_t *rows, int64_t n_total, int d, int64_t n, void *y,
+                                     uint32_t *status, hipStream_t s) {
+  hipLaunchKernelGGL(k_gather_f32_to_bf16, dim3((unsigned)((n * d + 255) / 256)), dim3(256), 0, s, x, rows, n_total, d,
+                     n, (__bf16 *)y, status);
+  return hipGetLastError();
+}
+
+// Training targets of the surrogate: out[r][j] = ln((H[r][j] + 1/2) / (N_r + n_bins / 2)) with
+// N_r the row's total, in FP64 (one block per row; the total is exact in FP64 below 2^53).
+__global__ void __launch_bounds__(256) k_log_hess_target(const uint32_t *__restrict__ h, int nbins,
+                                                         float *__restrict__ out) {
+  __shared__ uint64_t red[256];
+  const uint32_t *hr = h + (size_t)blockIdx.x * nbins;
+  float *o = out + (size_t)blockIdx.x * nbins;
+  const int t = threadIdx.x;
+  uint64_t n = 0;
+  for (int j = t; j < nbins; j += 256) n += hr[j];
+  red[t] = n;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (t < k) red[t] += red[t + k];
+    __syncthreads();
+  }
+  const double den = (double)red[0] + 0.5 * (double)nbins;
+  for (int j = t; j < nbins; j += 256) o[j] = (float)log(((double)hr[j] + 0.5) / den);
+}
+
+hipError_t launch_log_hess_target(const uint32_t *h, int n, int nbins, float *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_log_hess_target, dim3(n), dim3(256), 0, s, h, nbins, out);
+  return hipGetLastError();
+}
+
+// dy = 2 (y - t) / (n M) stored in BF16 (skipped when dy is NULL); per-block partial sums of
+// (y - t)^2 in FP64.  y is [n / M][M]; the target row of sample k is batch_row(rows, k).  Threads
+// take runs of four elements (16-byte loads, 8-byte stores) when the pointers and the row length
+// allow it.
 __global__ void __launch_bounds__(256) k_mse_grad(const float *__restrict__ y, const float *__restrict__ t, int64_t n,
-                                                  double scale, __bf16 *__restrict__ dy, double *__restrict__ part) {
+                                                  int M, const int32_t *__restrict__ rows, int64_t n_total,
+                                                  double scale, __bf16 *__restrict__ dy, double *__restrict__ part,
+                                                  uint32_t *status) {
   __shared__ double red[256];
   double s = 0.0;
   const float g = (float)(2.0 * scale);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t first = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool vec = ((((uintptr_t)y) | ((uintptr_t)t)) & 15) == 0 && (((uintptr_t)dy) & 7) == 0;
+  const bool vec = ((((uintptr_t)y) | ((uintptr_t)t)) & 15) == 0 && (((uintptr_t)dy) & 7) == 0 && (M & 3) == 0;
   const int64_t n4 = vec ? n / 4 : 0;
   for (int64_t i = first; i < n4; i += stride) {
+    const int64_t k = (4 * i) / M, j = 4 * i - k * M;
     const float4 a = reinterpret_cast<const float4 *>(y)[i];
-    const float4 b = reinterpret_cast<const float4 *>(t)[i];
+    const float4 b = *reinterpret_cast<const float4 *>(t + batch_row(rows, k, n_total, status) * M + j);
     const float d0 = a.x - b.x, d1 = a.y - b.y, d2 = a.z - b.z, d3 = a.w - b.w;
-    bf16x4 o;
-    o[0] = (__bf16)(g * d0);
-    o[1] = (__bf16)(g * d1);
-    o[2] = (__bf16)(g * d2);
-    o[3] = (__bf16)(g * d3);
-    reinterpret_cast<bf16x4 *>(dy)[i] = o;
+    if (dy) {
+      bf16x4 o;
+      o[0] = (__bf16)(g * d0);
+      o[1] = (__bf16)(g * d1);
+      o[2] = (__bf16)(g * d2);
+      o[3] = (__bf16)(g * d3);
+      reinterpret_cast<bf16x4 *>(dy)[i] = o;
+    }
     s += (double)d0 * (double)d0;
     s += (double)d1 * (double)d1;
     s += (double)d2 * (double)d2;
     s += (double)d3 * (double)d3;
   }
   for (int64_t i = 4 * n4 + first; i < n; i += stride) {
-    const float d = y[i] - t[i];
-    dy[i] = (__bf16)(g * d);
+    const int64_t k = i / M, j = i - k * M;
+    const float d = y[i] - t[batch_row(rows, k, n_total, status) * M + j];
+    if (dy) dy[i] = (__bf16)(g * d);
     s += (double)d * (double)d;
   }
   red[threadIdx.x] = s;
@@ -321,14 +385,34 @@ __global__ void __launch_bounds__(256) k_loss_final(const double *__restrict__ p
   if (threadIdx.x == 0) out[0] = (float)(red[0] * scale);
 }
 
-constexpr int MSE_BLOCKS = 256;
-
-hipError_t launch_mse_grad(const float *y, const float *t, int64_t n, double scale, void *dy, double *part,
-                           float *loss_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_mse_grad, dim3(MSE_BLOCKS), dim3(256), 0, s, y, t, n, scale, (__bf16 *)dy, part);
+hipError_t launch_mse_grad(const float *y, const float *t, int64_t n, int M, const int32_t *rows, int64_t n_total,
+                           double scale, void *dy, double *part, float *loss_out, uint32_t *status, hipStream_t s) {
+  hipLaunchKernelGGL(k_mse_grad, dim3(MSE_BLOCKS), dim3(256), 0, s, y, t, n, M, rows, n_total, scale, (__bf16 *)dy,
+                     part, status);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !loss_out) return e;
   hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(256), 0, s, part, MSE_BLOCKS, scale, loss_out);
+  return hipGetLastError();
+}
+
+// out = scale x the sum of nb partials: thread t sums partials t, t + 256, ... in order, then a
+// fixed tree over the block (the order depends on nb alone).
+__global__ void __launch_bounds__(256) k_sum_partials(const double *__restrict__ part, int64_t nb, double scale,
+                                                      double *__restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < nb; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < (unsigned)k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0] * scale;
+}
+
+hipError_t launch_sum_partials(const double *part, int64_t nb, double scale, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, part, nb, scale, out);
   return hipGetLastError();
 }
 

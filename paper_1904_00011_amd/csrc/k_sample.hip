@@ -71,17 +71,21 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
       l = 0.0;
     }
     if (block_rule) l = 0.0;
+    // thinned: the unreddened and reddened counts are two independent parts
+    const bool thin = l >= ALIAS_MIN && (a.thin == THIN_TABLE || (a.thin == THIN_HALF_HIGH && l >= LAM_THIN_HALF));
+    if (a.thin != THIN_NONE) a.rdesc[i] = KIND_ZERO;  // overwritten below for a thinned entry
     if (l >= ALIAS_MIN) {
       // table entry: the count (or, thinned, the unreddened part) in slot 0, the reddened part in
       // slot 1; alias parts are built by k_prep_alias, which completes their descriptors
-      const double l0 = a.thin ? l * (1.0 - a.frac) : l;
+      const double l0 = thin ? l * (1.0 - a.frac) : l;
       if (l0 >= ALIAS_MAX) {
         ((PtrsConst *)a.pc)[2 * (size_t)i] = ptrs_constants(l0);
         r.kk = KIND_PTRS;
       } else {
         r.kk = KIND_ALIAS;
       }
-      if (a.thin) {
+      if (thin) {
+        r.kk |= FLAG_THIN;
         const double l1 = l * a.frac;
         if (l1 >= ALIAS_MAX) {
           ((PtrsConst *)a.pc)[2 * (size_t)i + 1] = ptrs_constants(l1);
@@ -103,9 +107,10 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
   const int EP = entries_padded(E);
   if (i < EP) a.rec[i] = r;
   // group of entries GRP g .. GRP g + GRP - 1 = neighbouring lanes of one wave (256-thread blocks)
-  const uint32_t kind = r.kk & 0xFFu;
+  const uint32_t kind = r.kk & KIND_MASK;
   const uint32_t t0m1 = kind == KIND_INV ? r.T[0] - 1u : 0xFFFFFFFFu;
-  const uint32_t fl = kind == KIND_INV ? GRP_INV : kind == KIND_PTRS ? GRP_PTRS : kind == KIND_ALIAS ? GRP_ALIAS : 0u;
+  const uint32_t fl = (r.kk & FLAG_THIN) ? GRP_THIN
+                      : kind == KIND_INV ? GRP_INV : kind == KIND_PTRS ? GRP_PTRS : kind == KIND_ALIAS ? GRP_ALIAS : 0u;
   const int first = (int)(threadIdx.x & 63u) & ~(GRP - 1);
   GroupRec gr;
   gr.flags = 0u;
@@ -153,7 +158,9 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (i >= a.E) return;  // whole waves: i is wave-uniform
   // part 0: the entry's count (or its unreddened part); part 1: the reddened part (thinned)
-  if (part == 0 ? (a.rec[i].kk & 0xFFu) != KIND_ALIAS : !a.thin || (a.rdesc[i] & 0xFFu) != KIND_ALIAS) return;
+  // (rdesc holds KIND_ZERO for every entry that is not thinned whenever thinning is on)
+  if (part == 0 ? (a.rec[i].kk & KIND_MASK) != KIND_ALIAS : a.thin == THIN_NONE || (a.rdesc[i] & KIND_MASK) != KIND_ALIAS)
+    return;
   uint32_t *m = m_s[wv];
   uint16_t *sm = small_s[wv], *lg = large_s[wv], *al = alias_s[wv];
   for (int j = lane; j < ALIAS_COLS; j += 64) {
@@ -163,7 +170,9 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
   wave_lds_sync();
   if (lane == 0) {
     const double lam = a.lam[i];
-    const double l = !a.thin ? lam : part == 0 ? lam * (1.0 - a.frac) : lam * a.frac;
+    // part 1 exists only for a thinned entry; part 0 of one is its unreddened share
+    const bool thin = part == 1 || (a.rec[i].kk & FLAG_THIN) != 0u;
+    const double l = !thin ? lam : part == 0 ? lam * (1.0 - a.frac) : lam * a.frac;
     double pk = exp(-l);
     double F = pk;
     int klo = -1, J = 0;
@@ -200,7 +209,7 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
     nout_s[wv] = bits | (single ? 0x100 : 0);
     const uint32_t desc = ((uint32_t)klo << 12) | ((uint32_t)bits << 8) | KIND_ALIAS;
     if (part == 0)
-      a.rec[i].kk = desc;
+      a.rec[i].kk = desc | (a.rec[i].kk & FLAG_THIN);
     else
       a.rdesc[i] = desc;
   }
@@ -262,8 +271,8 @@ __global__ void __launch_bounds__(256) k_prep_alias_job(const PrepArgs *__restri
 
 hipError_t launch_prep_alias(const PrepArgs &a, hipStream_t s) {
   // grid.y: part 1 (the reddened part of a thinned entry) exists only when entries are thinned
-  hipLaunchKernelGGL(k_prep_alias, dim3((unsigned)((a.E + ALIAS_WAVES - 1) / ALIAS_WAVES), a.thin ? 2 : 1), dim3(256), 0, s,
-                     a);
+  hipLaunchKernelGGL(k_prep_alias, dim3((unsigned)((a.E + ALIAS_WAVES - 1) / ALIAS_WAVES), a.thin != THIN_NONE ? 2 : 1),
+                     dim3(256), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_prep_alias_job(const PrepArgs *table, int j, int E, int parts, hipStream_t s) {
@@ -331,7 +340,7 @@ __device__ __forceinline__ uint32_t table_draw(uint32_t desc, uint32_t u, const 
                                                const PCMD_CONST PtrsConst *pcp, uint32_t p, uint32_t i, uint32_t tag,
                                                uint32_t k0, uint32_t k1, const float *__restrict__ lnfact,
                                                uint32_t &failed) {
-  if ((desc & 0xFFu) == KIND_ALIAS) {
+  if ((desc & KIND_MASK) == KIND_ALIAS) {
     const uint32_t b = (desc >> 8) & 0xFu;
     const uint32_t c = u >> (32u - b);
     const uint32_t x = tab[c];
@@ -341,8 +350,11 @@ __device__ __forceinline__ uint32_t table_draw(uint32_t desc, uint32_t u, const 
   return ptrs_draw(cst, p, i, tag, k0, k1, lnfact, failed);
 }
 
-// THIN: a split 0 < F < 1, F != 1/2 draws table entries as two independent parts (thinning).
-template <int B, int S, bool DBG, bool THIN>
+// PASS (SamplePass): PASS_ALL draws every entry, the thinned ones (FLAG_THIN: two independent
+// parts, k_prep's choice under a split 0 < F < 1) inline; PASS_MAIN leaves the thinned ones out,
+// and PASS_THIN then draws only those and adds them to the partial sums PASS_MAIN stored, so the
+// thinning code (live state that slows the common path) is not in the main pass.
+template <int B, int S, bool DBG, int PASS>
 __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int chunk) {
   constexpr int BP = B <= 2 ? 2 : 4;
   const PCMD_CONST EntryRec *rec = (const PCMD_CONST EntryRec *)a.rec;
@@ -381,7 +393,8 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
     // sampler's block-rule entries)
     const int gl = slice_group(jb + lane);
     const uint32_t fl = gl < ngrp ? grp[gl].flags : 0u;
-    for (uint64_t pend = __ballot(fl != 0u); pend != 0ull; pend &= pend - 1ull) {
+    const uint32_t want = PASS == PASS_ALL ? 0xFFu : PASS == PASS_MAIN ? (GRP_INV | GRP_PTRS | GRP_ALIAS) : GRP_THIN;
+    for (uint64_t pend = __ballot((fl & want) != 0u); pend != 0ull; pend &= pend - 1ull) {
       const int lsel = (int)__builtin_ctzll(pend);  // wave-uniform
       const int gi = slice_group(jb + lsel);
       const int g0 = gi * GRP;
@@ -395,14 +408,14 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
       // the first thresholds are loaded only now: held across the Philox rounds they pushed the
       // scalar register file into spilling inside this loop
       __builtin_amdgcn_sched_barrier(0);
-      if (!(flags & (GRP_PTRS | GRP_ALIAS)) &&
+      if (PASS != PASS_THIN && !(flags & (GRP_PTRS | GRP_ALIAS | (PASS == PASS_ALL ? GRP_THIN : 0u))) &&
           (__ballot(wa.x > gr->t0m1[0]) | __ballot(wa.y > gr->t0m1[1]) | __ballot(wa.z > gr->t0m1[2]) |
            __ballot(wa.w > gr->t0m1[3]) | __ballot(wb.x > gr->t0m1[4]) | __ballot(wb.y > gr->t0m1[5]) |
            __ballot(wb.z > gr->t0m1[6]) | __ballot(wb.w > gr->t0m1[7])) == 0ull)
         continue;
       // the split bits of the group's 16-entry block: a slow group almost always has a star to
       // split, and the two groups of a block share them
-      if (S == 2 && a.split_mode == SPLIT_HALF && split_blk != (gi >> 1)) {
+      if (S == 2 && PASS != PASS_THIN && a.split_mode == SPLIT_HALF && split_blk != (gi >> 1)) {
         sw = philox10(p, (uint32_t)(gi >> 1), TAG_SPLIT, 0u, a.k0, a.k1);
         split_blk = gi >> 1;
       }
@@ -414,7 +427,7 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
         uint32_t n0[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) n0[q] = word_of(w, q) > gr->t0m1[4 * h + q] ? 1u : 0u;
-        u4 wr{0u, 0u, 0u, 0u};  // THIN: the quad's reddened-part words
+        u4 wr{0u, 0u, 0u, 0u};  // thinned entries: the quad's reddened-part words
         bool wr_ok = false;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -423,7 +436,10 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
           const EntryRec rq = ld_const(rec + i);  // padded to a multiple of GRP
           uint32_t n = 0, red_thin = 0u;
           bool thinned = false;
-          const uint32_t kind = rq.kk & 0xFFu;
+          // a pass leaves out the entries of the other pass (wave-uniform: the record is)
+          if (PASS == PASS_MAIN && (rq.kk & FLAG_THIN)) continue;
+          if (PASS == PASS_THIN && !(rq.kk & FLAG_THIN)) continue;
+          const uint32_t kind = rq.kk & KIND_MASK;
           if (kind <= KIND_INV) {  // inversion; a KIND_ZERO entry never passes its first threshold
             // n = #{k < K : T_k <= u}, walking up while any lane of the wave is still above
             const uint32_t u = word_of(w, q);
@@ -454,7 +470,7 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
             // reddened part, each an alias column read or a rejection draw
             n = table_draw(rq.kk, word_of(w, q), a.alias + (size_t)i * 2 * ALIAS_COLS, pc + 2 * (size_t)i, p, i,
                            TAG_PTRS, a.k0, a.k1, a.lnfact, ptrs_failed);
-            if (S == 2 && THIN) {
+            if (S == 2 && PASS != PASS_MAIN && (rq.kk & FLAG_THIN)) {
               if (!wr_ok) {  // the quad's reddened-part words, drawn once
                 wr = philox10(p, i >> 2, TAG_RED, 0u, a.k0, a.k1);
                 wr_ok = true;
@@ -469,7 +485,8 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
           if (!wave_any(n != 0u)) continue;
           uint32_t red = 0u;
           if (S == 2) {
-            red = THIN && thinned ? red_thin : split_count(n, sq, 8u * q, a.split_mode, a.split_q, p, i, a.k0, a.k1);
+            red = PASS != PASS_MAIN && thinned ? red_thin
+                                                : split_count(n, sq, 8u * q, a.split_mode, a.split_q, p, i, a.k0, a.k1);
           }
           const PCMD_CONST double *f = fl64 + (size_t)i * BP;
           // a stream with no star in any lane adds exact zeros: skipped
@@ -498,36 +515,56 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
   const size_t plane = (size_t)a.npx;
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    a.part[((size_t)(chunk * S + 0) * B + b) * plane + p] = acc_c[b];
-    if (S == 2) a.part[((size_t)(chunk * S + 1) * B + b) * plane + p] = acc_r[b];
+    double *pc = a.part + ((size_t)(chunk * S + 0) * B + b) * plane + p;
+    double *pr = a.part + ((size_t)(chunk * S + 1) * B + b) * plane + p;
+    if (PASS == PASS_THIN) {  // exact zeros change nothing: a slice without thinned stars skips
+      if (acc_c[b] != 0.0) *pc = *pc + acc_c[b];
+      if (S == 2 && acc_r[b] != 0.0) *pr = *pr + acc_r[b];
+    } else {
+      *pc = acc_c[b];
+      if (S == 2) *pr = acc_r[b];
+    }
   }
 }
 
-template <int B, int S, bool DBG, bool THIN>
+template <int B, int S, bool DBG, int PASS>
 __global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
   const int nblk_px = (a.npx + 255) >> 8;
   const int chunk = blockIdx.x / nblk_px;
-  sample_tile<B, S, DBG, THIN>(a, (uint32_t)((blockIdx.x - chunk * nblk_px) * 256 + threadIdx.x), chunk);
+  sample_tile<B, S, DBG, PASS>(a, (uint32_t)((blockIdx.x - chunk * nblk_px) * 256 + threadIdx.x), chunk);
 }
 
+template <int B, int PASS>
+static void launch_sample_pass(const SampleArgs &a, dim3 grid, hipStream_t s) {
+  const bool dbg = a.dbg_counts != nullptr;
+  if (a.S == 2 && dbg)
+    hipLaunchKernelGGL((k_sample<B, 2, true, PASS>), grid, dim3(256), 0, s, a);
+  else if (a.S == 2)
+    hipLaunchKernelGGL((k_sample<B, 2, false, PASS>), grid, dim3(256), 0, s, a);
+  else if (dbg)
+    hipLaunchKernelGGL((k_sample<B, 1, true, PASS_MAIN>), grid, dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_sample<B, 1, false, PASS_MAIN>), grid, dim3(256), 0, s, a);
+}
+
+// Thinning of every table entry (0 < F < 1, F != 1/2): one pass with the thinned entries inline.
+// F = 1/2 (only entries at lambda >= LAM_THIN_HALF thinned): the main pass, then the thinned
+// entries' pass.  Otherwise nothing is thinned: the main pass alone.
 template <int B>
 static hipError_t launch_sample_b(const SampleArgs &a, hipStream_t s) {
   const int nblk_px = (a.npx + 255) / 256;
   dim3 grid((unsigned)(nblk_px * a.nchunks));
-  const bool dbg = a.dbg_counts != nullptr;
-  const bool thin = a.S == 2 && a.split_mode == SPLIT_GENERAL;
-  if (thin && dbg)
-    hipLaunchKernelGGL((k_sample<B, 2, true, true>), grid, dim3(256), 0, s, a);
-  else if (thin)
-    hipLaunchKernelGGL((k_sample<B, 2, false, true>), grid, dim3(256), 0, s, a);
-  else if (a.S == 2 && dbg)
-    hipLaunchKernelGGL((k_sample<B, 2, true, false>), grid, dim3(256), 0, s, a);
-  else if (a.S == 2)
-    hipLaunchKernelGGL((k_sample<B, 2, false, false>), grid, dim3(256), 0, s, a);
-  else if (dbg)
-    hipLaunchKernelGGL((k_sample<B, 1, true, false>), grid, dim3(256), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_sample<B, 1, false, false>), grid, dim3(256), 0, s, a);
+  const int tm = a.S == 2 ? thin_mode_of_split(a.split_mode) : THIN_NONE;
+  if (tm == THIN_TABLE) {
+    launch_sample_pass<B, PASS_ALL>(a, grid, s);
+  } else {
+    launch_sample_pass<B, PASS_MAIN>(a, grid, s);
+    if (tm == THIN_HALF_HIGH) {
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      launch_sample_pass<B, PASS_THIN>(a, grid, s);
+    }
+  }
   return hipGetLastError();
 }
 
@@ -582,12 +619,34 @@ __global__ void __launch_bounds__(256) k_sample_persistent(const BatchSampleJob 
     const int chunk = local / pblocks;
     const int pblk = local - chunk * pblocks;
     const SampleArgs a = ld_const(&cj[j].a);
-    // batch jobs always carry two streams
-    if (a.split_mode == SPLIT_GENERAL)
-      sample_tile<B, 2, false, true>(a, (uint32_t)(pblk * 64) + lane, chunk);
+    // batch jobs always carry two streams; F = 1/2 jobs draw their thinned entries afterwards in
+    // a launch of their own (k_sample_thin_job), as pcmd_simulate does
+    if (thin_mode_of_split(a.split_mode) == THIN_TABLE)
+      sample_tile<B, 2, false, PASS_ALL>(a, (uint32_t)(pblk * 64) + lane, chunk);
     else
-      sample_tile<B, 2, false, false>(a, (uint32_t)(pblk * 64) + lane, chunk);
+      sample_tile<B, 2, false, PASS_MAIN>(a, (uint32_t)(pblk * 64) + lane, chunk);
   }
+}
+
+// The thinned entries' pass of one batch job (position t of the persistent sampler's table).
+template <int B>
+__global__ void __launch_bounds__(256) k_sample_thin_job(const BatchSampleJob *__restrict__ jobs, int t) {
+  const SampleArgs a = jobs[t].a;
+  const int nblk_px = (a.npx + 255) >> 8;
+  const int chunk = blockIdx.x / nblk_px;
+  sample_tile<B, 2, false, PASS_THIN>(a, (uint32_t)((blockIdx.x - chunk * nblk_px) * 256 + threadIdx.x), chunk);
+}
+
+hipError_t launch_sample_thin_job(const BatchSampleJob *jobs, int t, int B, int npx, int nchunks, hipStream_t s) {
+  const dim3 grid((unsigned)((npx + 255) / 256 * nchunks));
+  switch (B) {
+    case 1: hipLaunchKernelGGL(k_sample_thin_job<1>, grid, dim3(256), 0, s, jobs, t); break;
+    case 2: hipLaunchKernelGGL(k_sample_thin_job<2>, grid, dim3(256), 0, s, jobs, t); break;
+    case 3: hipLaunchKernelGGL(k_sample_thin_job<3>, grid, dim3(256), 0, s, jobs, t); break;
+    case 4: hipLaunchKernelGGL(k_sample_thin_job<4>, grid, dim3(256), 0, s, jobs, t); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_sample_persistent(const BatchSampleJob *jobs, int n_jobs, int total_items, int B, uint32_t *counter,

@@ -25,7 +25,7 @@
 namespace pcmd {
 
 // One wave per block: lane l takes entry SBLK b + l.
-__global__ void __launch_bounds__(256) k_prep_block(BlockPrepArgs a) {
+__device__ __forceinline__ void prep_block_body(const BlockPrepArgs &a) {
   __shared__ double lam_s[4][SBLK];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int b = blockIdx.x * 4 + w;
@@ -84,13 +84,24 @@ __global__ void __launch_bounds__(256) k_prep_block(BlockPrepArgs a) {
   if (lane == 0) a.brec[b] = r;
 }
 
+__global__ void __launch_bounds__(256) k_prep_block(BlockPrepArgs a) { prep_block_body(a); }
+// batched: the arguments of job j of a descriptor table
+__global__ void __launch_bounds__(256) k_prep_block_job(const BlockPrepArgs *__restrict__ t, int j) {
+  const BlockPrepArgs a = t[j];
+  prep_block_body(a);
+}
+
 hipError_t launch_prep_block(const BlockPrepArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_prep_block, dim3((unsigned)((a.nb + 3) / 4)), dim3(256), 0, s, a);
   return hipGetLastError();
 }
+hipError_t launch_prep_block_job(const BlockPrepArgs *table, int j, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_prep_block_job, dim3((unsigned)((nb + 3) / 4)), dim3(256), 0, s, table, j);
+  return hipGetLastError();
+}
 
 template <int B, int S, bool DBG>
-__global__ void __launch_bounds__(256) k_sample_block(BlockSampleArgs a) {
+__device__ __forceinline__ void sample_block_body(const BlockSampleArgs &a) {
   constexpr int BP = B <= 2 ? 2 : 4;
   const int nblk_px = (a.npx + 255) >> 8;
   const int chunk = blockIdx.x / nblk_px;
@@ -114,7 +125,7 @@ __global__ void __launch_bounds__(256) k_sample_block(BlockSampleArgs a) {
   // always find their source lane active; branches on N go through wave-wide votes
   for (int b = chunk; b < a.nb; b += a.nchunks) {
     const BlockRec r = ld_const(brec + b);
-    const uint32_t kind = r.kk & 0xFFu;
+    const uint32_t kind = r.kk & KIND_MASK;
     if (kind == KIND_ZERO) continue;
     uint32_t n = 0u;
     if (kind == KIND_INV) {
@@ -190,6 +201,17 @@ __global__ void __launch_bounds__(256) k_sample_block(BlockSampleArgs a) {
   }
 }
 
+template <int B, int S, bool DBG>
+__global__ void __launch_bounds__(256) k_sample_block(BlockSampleArgs a) {
+  sample_block_body<B, S, DBG>(a);
+}
+// batched: job j of a descriptor table, both partial streams (as every batch job)
+template <int B>
+__global__ void __launch_bounds__(256) k_sample_block_job(const BlockSampleArgs *__restrict__ t, int j) {
+  const BlockSampleArgs a = t[j];
+  sample_block_body<B, 2, false>(a);
+}
+
 template <int B>
 static hipError_t launch_sample_block_b(const BlockSampleArgs &a, hipStream_t s) {
   const int nblk_px = (a.npx + 255) / 256;
@@ -214,6 +236,18 @@ hipError_t launch_sample_block(const BlockSampleArgs &a, hipStream_t s) {
     case 4: return launch_sample_block_b<4>(a, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_sample_block_job(const BlockSampleArgs *table, int j, int B, int npx, int nchunks, hipStream_t s) {
+  const dim3 grid((unsigned)((npx + 255) / 256 * nchunks));
+  switch (B) {
+    case 1: hipLaunchKernelGGL(k_sample_block_job<1>, grid, dim3(256), 0, s, table, j); break;
+    case 2: hipLaunchKernelGGL(k_sample_block_job<2>, grid, dim3(256), 0, s, table, j); break;
+    case 3: hipLaunchKernelGGL(k_sample_block_job<3>, grid, dim3(256), 0, s, table, j); break;
+    case 4: hipLaunchKernelGGL(k_sample_block_job<4>, grid, dim3(256), 0, s, table, j); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 }  // namespace pcmd

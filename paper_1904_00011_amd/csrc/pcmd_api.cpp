@@ -129,7 +129,7 @@ void pcmd_destroy(pcmd_ctx *c) {
   batch_destroy(c);
   Buf *bufs[] = {&c->rec,     &c->thr,     &c->pc,      &c->fl64,    &c->part,     &c->F,       &c->G,
                  &c->mom_part, &c->fft,    &c->mlp_act, &c->mlp_pre, &c->mlp_dza, &c->mlp_dzb, &c->mlp_grad,
-                 &c->mlp_part, &c->mlp_ws, &c->ll_part, &c->blk, &c->alias, &c->rdesc};
+                 &c->mlp_part, &c->mlp_ws, &c->mlp_lpart, &c->ll_part, &c->blk, &c->alias, &c->rdesc};
   for (Buf *b : bufs) release(*b);
   if (c->lnfact) (void)hipFree(c->lnfact);
   if (c->lnfact64) (void)hipFree(c->lnfact64);
@@ -154,6 +154,7 @@ int pcmd_sync(pcmd_ctx *c, pcmd_stream stream) {
     if (e != hipSuccess) return hip_fail(c, e, "pcmd_sync");
     if (st & STATUS_BAD_LAMBDA) return fail(c, PCMD_E_INVAL, "an expected star count was negative, not finite or >= 2^22 (drawn as 0)");
     if (st & STATUS_BAD_PSF) return fail(c, PCMD_E_INVAL, "a PSF band has a negative or non-finite value or does not sum to 1 within 1e-3");
+    if (st & STATUS_BAD_ROW) return fail(c, PCMD_E_INVAL, "a training row index was outside the set (row 0 was used)");
     return fail(c, PCMD_E_PTRS_RETRY, "a transformed-rejection draw exhausted its %d attempts", PTRS_MAX_ATTEMPTS);
   }
   c->err.clear();
@@ -178,10 +179,15 @@ static double kroupa_integral(double lo, double hi) {
 }
 
 int pcmd_grid_prepare(int32_t E, int32_t B, const int32_t *iso, const double *mass, const double *absmag, int32_t imf,
-                      double alpha, double *imf_w, float *flux) {
+                      double alpha, double *imf_w, float *flux, int32_t n_iso, double *iso_imf_sum) {
   if (E <= 0 || B < 1 || B > PCMD_MAX_BANDS || !iso || !mass || !absmag || !imf_w || !flux) return PCMD_E_INVAL;
   if (imf != PCMD_IMF_POWER_LAW && imf != PCMD_IMF_KROUPA) return PCMD_E_INVAL;
   if (imf == PCMD_IMF_POWER_LAW && (!(alpha > 1.0) || !isfinite(alpha))) return PCMD_E_INVAL;
+  if (iso_imf_sum) {
+    if (n_iso < 1 || n_iso > PCMD_MAX_ISO) return PCMD_E_INVAL;
+    for (int i = 0; i < E; ++i)
+      if (iso[i] < 0 || iso[i] >= n_iso) return PCMD_E_INVAL;
+  }
   int start = 0;
   while (start < E) {
     int end = start + 1;
@@ -214,6 +220,11 @@ int pcmd_grid_prepare(int32_t E, int32_t B, const int32_t *iso, const double *ma
       if (!isfinite(m)) return PCMD_E_INVAL;
       flux[(size_t)b * E + i] = (float)pow(10.0, -0.4 * m);
     }
+  if (iso_imf_sum) {
+    // the normalisation of the expected counts: the IMF weight summed over each isochrone's points
+    for (int k = 0; k < n_iso; ++k) iso_imf_sum[k] = 0.0;
+    for (int i = 0; i < E; ++i) iso_imf_sum[iso[i]] += imf_w[i];
+  }
   return PCMD_OK;
 }
 
@@ -434,7 +445,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
                 c->status,
                 (uint32_t *)c->alias.p,
                 hybrid ? pb.brec : nullptr,
-                split_mode == SPLIT_GENERAL ? 1 : 0,
+                thin_mode_of_split(split_mode),
                 o->dust_frac,
                 (uint32_t *)c->rdesc.p};
     e = launch_prep(pa, s);

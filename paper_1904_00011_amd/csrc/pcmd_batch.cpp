@@ -21,9 +21,19 @@ namespace {
 struct JobInfo {
   int E, B, N, npx, K, S, nchunks, pblocks, items, grid;
   int alias_parts;  // 2 when table entries are thinned into two parts, else 1
+  int sampler;      // PCMD_SAMPLER_*
+  int thin_mode;    // THIN_*
+  int nb;           // 64-entry blocks (block-skip and hybrid samplers)
   double cost;
-  size_t o_rec, o_thr, o_pc, o_fl, o_part, o_img, o_alias, o_rdesc;
+  size_t o_rec, o_thr, o_pc, o_fl, o_part, o_img, o_alias, o_rdesc, o_blk;
 };
+
+// Bytes of one job's block-skip tables: [nb] BlockRec, [nb][THR_STRIDE] thresholds, [nb] PtrsConst,
+// [nb][SBLK] cumulative thresholds (the layout pcmd_simulate uses).
+size_t blk_rec_bytes(int nb) { return (size_t)nb * sizeof(BlockRec); }
+size_t blk_thr_bytes(int nb) { return (size_t)nb * THR_STRIDE * 4; }
+size_t blk_pc_bytes(int nb) { return (size_t)nb * sizeof(PtrsConst); }
+size_t blk_cth_bytes(int nb) { return (size_t)nb * SBLK * 4; }
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -34,10 +44,10 @@ struct pcmd_batch_plan {
   int n_jobs = 0, B = 0, nbins = 0, total_items = 0, wg = 0, order_mode = 0;
   std::vector<JobInfo> info;
   std::vector<int> order;  // sampler table position -> job
-  Buf rec, thr, pc, fl, part, F, G, mags, hess, mom, mom_part, ll_part, counters, desc, alias, rdesc;
+  Buf rec, thr, pc, fl, part, F, G, mags, hess, mom, mom_part, ll_part, counters, desc, alias, rdesc, blk;
   void *desc_host = nullptr;
   size_t desc_bytes = 0;
-  size_t o_prep = 0, o_samp = 0, o_red = 0, o_conv = 0, o_noise = 0, o_hess = 0, o_ll = 0;
+  size_t o_prep = 0, o_samp = 0, o_red = 0, o_conv = 0, o_noise = 0, o_hess = 0, o_ll = 0, o_bprep = 0, o_bsamp = 0;
   hipStream_t stream = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_desc = nullptr;
   bool desc_pending = false;
@@ -53,7 +63,7 @@ static void plan_free_device(pcmd_batch_plan *p) {
   p->exec = nullptr;
   p->graph = nullptr;
   Buf *bufs[] = {&p->rec, &p->thr, &p->pc, &p->fl, &p->part, &p->F, &p->G, &p->mags, &p->hess, &p->mom, &p->mom_part, &p->ll_part,
-                 &p->counters, &p->desc, &p->alias, &p->rdesc};
+                 &p->counters, &p->desc, &p->alias, &p->rdesc, &p->blk};
   for (Buf *b : bufs) release(*b);
   if (p->desc_host) (void)hipHostFree(p->desc_host);
   p->desc_host = nullptr;
@@ -102,9 +112,6 @@ static int batch_validate(pcmd_ctx *c, int n_jobs, const pcmd_job *jobs, const p
                                               jobs[j].iso.n_bands, B);
     if (uses_fft(&jobs[j].obs))
       return fail(c, PCMD_E_UNSUPPORTED, "%s: job %d resolves to the FFT convolution; batches use the direct path", who, j);
-    if (jobs[j].obs.sampler != PCMD_SAMPLER_POINT)
-      return fail(c, PCMD_E_UNSUPPORTED, "%s: job %d asks for the block-skip or hybrid sampler; batches use the per-point rule",
-                  who, j);
   }
   if (g->b_blue < 0 || g->b_blue >= B || g->b_red < 0 || g->b_red >= B || g->b_mag < 0 || g->b_mag >= B)
     return fail(c, PCMD_E_INVAL, "%s: band index out of range", who);
@@ -121,7 +128,7 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
   p->order_mode = c->tune_order;
   p->info.assign(n_jobs, JobInfo{});
   const int B = p->B, BP = B <= 2 ? 2 : 4;
-  size_t n_rec = 0, n_thr = 0, n_pc = 0, n_fl = 0, n_part = 0, n_img = 0, n_alias = 0, n_rdesc = 0;
+  size_t n_rec = 0, n_thr = 0, n_pc = 0, n_fl = 0, n_part = 0, n_img = 0, n_alias = 0, n_rdesc = 0, n_blk = 0;
   for (int j = 0; j < n_jobs; ++j) {
     JobInfo &ji = p->info[j];
     ji.E = jobs[j].iso.n_entries;
@@ -129,7 +136,8 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
     ji.N = jobs[j].obs.nim;
     ji.npx = ji.N * ji.N;
     ji.K = jobs[j].obs.psf_k;
-    ji.alias_parts = split_mode_of(&jobs[j].obs) == SPLIT_GENERAL ? 2 : 1;
+    ji.thin_mode = thin_mode_of_split(split_mode_of(&jobs[j].obs));
+    ji.alias_parts = ji.thin_mode != THIN_NONE ? 2 : 1;
     ji.grid = psf_grid_of(&jobs[j].obs);
     // Every batch job keeps both partial streams (unreddened, reddened), so the persistent
     // sampler has one instantiation; a job without a split draws no reddened stars, its second
@@ -137,8 +145,12 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
     ji.S = 2;
     ji.nchunks = (ji.E + CHUNK - 1) / CHUNK;
     ji.pblocks = (ji.npx + 63) / 64;  // one persistent-sampler item = one wave's 64 pixels x one slice
-    ji.items = ji.nchunks * ji.pblocks;
-    ji.cost = (double)ji.npx * (double)ji.E * (split_mode_of(&jobs[j].obs) == SPLIT_NONE ? 1.0 : 1.3);
+    ji.sampler = jobs[j].obs.sampler;
+    ji.nb = superblocks(ji.E);
+    // a block-skip job draws everything in its own launch after the persistent sampler
+    ji.items = ji.sampler == PCMD_SAMPLER_BLOCK ? 0 : ji.nchunks * ji.pblocks;
+    ji.cost = ji.items == 0 ? 0.0
+                            : (double)ji.npx * (double)ji.E * (split_mode_of(&jobs[j].obs) == SPLIT_NONE ? 1.0 : 1.3);
     ji.o_rec = n_rec;
     ji.o_thr = n_thr;
     ji.o_pc = n_pc;
@@ -147,6 +159,9 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
     ji.o_img = n_img;
     ji.o_alias = n_alias;
     ji.o_rdesc = n_rdesc;
+    ji.o_blk = n_blk;
+    if (ji.sampler != PCMD_SAMPLER_POINT)
+      n_blk += align256(blk_rec_bytes(ji.nb) + blk_thr_bytes(ji.nb) + blk_pc_bytes(ji.nb) + blk_cth_bytes(ji.nb));
     n_rec += rec_bytes(ji.E) / sizeof(EntryRec);
     n_thr += (size_t)entries_padded(ji.E) * THR_STRIDE;
     n_pc += (size_t)ji.E * 2;
@@ -169,6 +184,7 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
   if ((r = ensure(c, p->pc, n_pc * sizeof(PtrsConst), "batch rejection constants"))) return r;
   if ((r = ensure(c, p->alias, n_alias * 4, "batch alias columns"))) return r;
   if ((r = ensure(c, p->rdesc, n_rdesc * 4, "batch reddened-part descriptors"))) return r;
+  if (n_blk && (r = ensure(c, p->blk, n_blk, "batch block tables"))) return r;
   if ((r = ensure(c, p->fl, n_fl * 8, "batch fluxes"))) return r;
   if ((r = ensure(c, p->part, n_part * 8, "batch partial sums"))) return r;
   if ((r = ensure(c, p->F, n_img * 4, "batch images"))) return r;
@@ -197,6 +213,10 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
   o = align256(o + sizeof(HessArgs) * n_jobs);
   p->o_ll = o;
   o = align256(o + sizeof(LoglikeArgs) * n_jobs);
+  p->o_bprep = o;
+  o = align256(o + sizeof(BlockPrepArgs) * n_jobs);
+  p->o_bsamp = o;
+  o = align256(o + sizeof(BlockSampleArgs) * n_jobs);
   p->desc_bytes = o;
   if ((r = ensure(c, p->desc, o, "batch descriptors"))) return r;
   e = hipHostMalloc(&p->desc_host, o, hipHostMallocDefault);
@@ -221,6 +241,8 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
   NoiseArgs *na = (NoiseArgs *)(h + p->o_noise);
   HessArgs *ha = (HessArgs *)(h + p->o_hess);
   LoglikeArgs *la = (LoglikeArgs *)(h + p->o_ll);
+  BlockPrepArgs *bpa = (BlockPrepArgs *)(h + p->o_bprep);
+  BlockSampleArgs *bsa = (BlockSampleArgs *)(h + p->o_bsamp);
   const int B = p->B, BP = B <= 2 ? 2 : 4;
   int item0 = 0;
   std::vector<int> first_item(p->n_jobs, 0);
@@ -242,6 +264,50 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
     const uint32_t k0 = (uint32_t)(o->seed & 0xFFFFFFFFu), k1 = (uint32_t)(o->seed >> 32);
     GroupRec *grp = (GroupRec *)(rec + entries_padded(ji.E));
     const int sm = split_mode_of(&jobs[j].obs);
+    // block-skip tables (block and hybrid samplers), as pcmd_simulate lays them out
+    BlockPrepArgs bp;
+    memset(&bp, 0, sizeof bp);
+    BlockSampleArgs bs;
+    memset(&bs, 0, sizeof bs);
+    if (ji.sampler != PCMD_SAMPLER_POINT) {
+      char *base = (char *)p->blk.p + ji.o_blk;
+      const size_t r_b = blk_rec_bytes(ji.nb), t_b = blk_thr_bytes(ji.nb), c_b = blk_pc_bytes(ji.nb);
+      bp = BlockPrepArgs{ji.E,
+                         B,
+                         BP,
+                         ji.nb,
+                         jobs[j].iso.lam,
+                         jobs[j].iso.flux,
+                         (BlockRec *)base,
+                         (uint32_t *)(base + r_b),
+                         base + r_b + t_b,
+                         (uint32_t *)(base + r_b + t_b + c_b),
+                         fl,
+                         c->status,
+                         ji.sampler == PCMD_SAMPLER_HYBRID ? 1 : 0};
+      bs.E = ji.E;
+      bs.B = B;
+      bs.BP = BP;
+      bs.npx = ji.npx;
+      bs.nb = ji.nb;
+      bs.nchunks = ji.nchunks;
+      bs.S = ji.S;
+      bs.k0 = k0;
+      bs.k1 = k1;
+      bs.split_mode = sm;
+      bs.split_q = split_q_of(o);
+      bs.brec = bp.brec;
+      bs.thr = bp.thr;
+      bs.pc = bp.pc;
+      bs.cth = bp.cth;
+      bs.fl64 = fl;
+      bs.part = part;
+      bs.status = c->status;
+      bs.lnfact = c->lnfact;
+      bs.accumulate = ji.sampler == PCMD_SAMPLER_HYBRID ? 1 : 0;  // hybrid: after the per-point pass
+    }
+    bpa[j] = bp;
+    bsa[j] = bs;
     pa[j] = PrepArgs{ji.E,
                      B,
                      BP,
@@ -254,8 +320,8 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
                      fl,
                      c->status,
                      (uint32_t *)p->alias.p + ji.o_alias,
-                     nullptr,
-                     sm == SPLIT_GENERAL ? 1 : 0,
+                     ji.sampler == PCMD_SAMPLER_HYBRID ? bp.brec : nullptr,
+                     thin_mode_of_split(sm),
                      jobs[j].obs.dust_frac,
                      (uint32_t *)p->rdesc.p + ji.o_rdesc};
     ReduceArgs rr;
@@ -357,15 +423,33 @@ static hipError_t enqueue(pcmd_ctx *c, pcmd_batch_plan *p, hipStream_t s) {
   const NoiseArgs *na = (const NoiseArgs *)(d + p->o_noise);
   const HessArgs *ha = (const HessArgs *)(d + p->o_hess);
   const LoglikeArgs *la = (const LoglikeArgs *)(d + p->o_ll);
+  const BlockPrepArgs *bpa = (const BlockPrepArgs *)(d + p->o_bprep);
+  const BlockSampleArgs *bsa = (const BlockSampleArgs *)(d + p->o_bsamp);
   uint32_t *persist = (uint32_t *)p->counters.p + p->n_jobs;
   hipError_t e = hipSuccess;
   for (int j = 0; j < p->n_jobs && e == hipSuccess; ++j) {
-    e = launch_prep_job(pa, j, p->info[j].E, s);
-    if (e == hipSuccess) e = launch_prep_alias_job(pa, j, p->info[j].E, p->info[j].alias_parts, s);
+    const JobInfo &ji = p->info[j];
+    // block tables first: the hybrid's per-point tables leave out the blocks the block rule draws
+    if (ji.sampler != PCMD_SAMPLER_POINT) e = launch_prep_block_job(bpa, j, ji.nb, s);
+    if (e == hipSuccess && ji.sampler != PCMD_SAMPLER_BLOCK) {
+      e = launch_prep_job(pa, j, ji.E, s);
+      if (e == hipSuccess) e = launch_prep_alias_job(pa, j, ji.E, ji.alias_parts, s);
+    }
   }
   if (e == hipSuccess) e = launch_reset_counter(persist, s);
   if (e == hipSuccess)
     e = launch_sample_persistent(sa, p->n_jobs, p->total_items, p->B, persist, c->n_cu * p->wg, s);
+  // then, in the order pcmd_simulate takes: the thinned entries of F = 1/2 jobs, added to the
+  // per-point partials, and the block-rule draws, stored (block sampler) or added (hybrid)
+  for (int t = 0; t < p->n_jobs && e == hipSuccess; ++t) {
+    const int j = p->order[t];
+    const JobInfo &ji = p->info[j];
+    if (ji.items > 0 && ji.thin_mode == THIN_HALF_HIGH) e = launch_sample_thin_job(sa, t, ji.B, ji.npx, ji.nchunks, s);
+  }
+  for (int j = 0; j < p->n_jobs && e == hipSuccess; ++j) {
+    const JobInfo &ji = p->info[j];
+    if (ji.sampler != PCMD_SAMPLER_POINT) e = launch_sample_block_job(bsa, j, ji.B, ji.npx, ji.nchunks, s);
+  }
   for (int j = 0; j < p->n_jobs && e == hipSuccess; ++j) {
     const JobInfo &ji = p->info[j];
     e = launch_reduce_job(ra, j, ji.npx, ji.B, s);
@@ -393,7 +477,7 @@ static uint64_t batch_signature(pcmd_ctx *c, int n_jobs, const pcmd_job *jobs, c
     const int sm = split_mode_of(&jobs[j].obs);
     h = fnv(h, ((uint64_t)jobs[j].iso.n_entries << 32) | (uint32_t)jobs[j].obs.nim);
     h = fnv(h, ((uint64_t)jobs[j].obs.psf_k << 32) | (uint32_t)sm);
-    h = fnv(h, (uint64_t)psf_grid_of(&jobs[j].obs));
+    h = fnv(h, ((uint64_t)jobs[j].obs.sampler << 32) | (uint32_t)psf_grid_of(&jobs[j].obs));
   }
   return h;
 }

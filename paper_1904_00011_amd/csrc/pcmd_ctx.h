@@ -30,7 +30,7 @@ struct pcmd_ctx {
   bool timing = false;
   std::vector<TimerRec> timers;
   Buf rec, thr, pc, fl64, part, F, G, mom_part, fft, ll_part, blk, alias, rdesc;
-  Buf mlp_act, mlp_pre, mlp_dza, mlp_dzb, mlp_grad, mlp_part, mlp_ws;
+  Buf mlp_act, mlp_pre, mlp_dza, mlp_dzb, mlp_grad, mlp_part, mlp_ws, mlp_lpart;
   float *lnfact = nullptr;     // [256]
   double *lnfact64 = nullptr;  // [LNFACT64_N] ln k! in FP64 (likelihoods)
   uint32_t *status = nullptr;  // [1]

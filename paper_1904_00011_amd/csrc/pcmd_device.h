@@ -20,8 +20,13 @@ constexpr uint32_t TAG_BLOCK = 6, TAG_BLOCK_PTRS = 7, TAG_STAR = 8, TAG_STAR_SPL
 // thinned entries: the reddened part's word (p, i / 4, TAG_RED, 0) and rejection attempts
 constexpr uint32_t TAG_RED = 10, TAG_PTRS_RED = 11;
 
-// Entry kinds written by the preparation kernel.
+// Entry kinds written by the preparation kernel (low four bits of a record's kk), and the flag of
+// a table entry whose unreddened and reddened counts are drawn as two thinned parts.
 constexpr uint32_t KIND_ZERO = 0, KIND_INV = 1, KIND_PTRS = 2, KIND_ALIAS = 3;
+constexpr uint32_t KIND_MASK = 0x0Fu, FLAG_THIN = 0x80u;
+// Dust split F = 1/2: table entries at or above this lambda are thinned (their stars would each
+// need a split bit); the others keep one bit per star.
+constexpr double LAM_THIN_HALF = 64.0;
 // Alias rule for ALIAS_MIN <= lambda < ALIAS_MAX: M = 2^b <= ALIAS_COLS columns of 2^(32-b) words
 // each (column = top b bits of the inversion word), one packed word per column:
 // height << b | alias.  Each entry's table has room for ALIAS_COLS columns.

@@ -27,10 +27,13 @@ struct EntryRec {
 constexpr int GRP = 8;  // entries per group record (two Philox blocks)
 struct GroupRec {
   uint32_t t0m1[GRP];
-  uint32_t flags;  // GRP_INV | GRP_PTRS
+  uint32_t flags;  // GRP_INV | GRP_PTRS | GRP_ALIAS (entries drawn whole) | GRP_THIN (thinned entries)
   uint32_t pad[7];
 };
-constexpr uint32_t GRP_INV = 1u, GRP_PTRS = 2u, GRP_ALIAS = 4u;
+constexpr uint32_t GRP_INV = 1u, GRP_PTRS = 2u, GRP_ALIAS = 4u, GRP_THIN = 8u;
+// Sampler passes: every entry (thinned ones inline); every entry but the thinned ones; only the
+// thinned ones, added to the partial sums the main pass stored.
+enum SamplePass { PASS_ALL = 0, PASS_MAIN = 1, PASS_THIN = 2 };
 
 // The record table holds E rounded up to a multiple of GRP entry records (the padding records
 // have KIND_ZERO), then one group record per GRP entries and one spare group record (not read
@@ -42,9 +45,15 @@ inline size_t rec_bytes(int E) {
 }
 
 // Device status bits, reported by pcmd_sync.
-constexpr uint32_t STATUS_PTRS_RETRY = 1u, STATUS_BAD_LAMBDA = 2u, STATUS_BAD_PSF = 4u;
+constexpr uint32_t STATUS_PTRS_RETRY = 1u, STATUS_BAD_LAMBDA = 2u, STATUS_BAD_PSF = 4u, STATUS_BAD_ROW = 8u;
 
 enum SplitMode { SPLIT_NONE = 0, SPLIT_HALF = 1, SPLIT_GENERAL = 2, SPLIT_ALL = 3 };
+// Thinned table entries: none; every entry at lambda >= ALIAS_MIN (0 < F < 1, F != 1/2); the
+// entries at lambda >= LAM_THIN_HALF (F = 1/2).
+enum ThinMode { THIN_NONE = 0, THIN_TABLE = 1, THIN_HALF_HIGH = 2 };
+__host__ __device__ inline int thin_mode_of_split(int split_mode) {
+  return split_mode == SPLIT_GENERAL ? THIN_TABLE : split_mode == SPLIT_HALF ? THIN_HALF_HIGH : THIN_NONE;
+}
 
 struct BlockRec;  // block-skip sampler record, below
 
@@ -61,7 +70,7 @@ struct PrepArgs {
   uint32_t *status;
   uint32_t *alias;     // [E][2][ALIAS_COLS] packed alias columns of the same two parts
   const BlockRec *brec;  // hybrid sampler: entries of blocks without pad[0] set are drawn as 0
-  int thin;            // dust split 0 < F < 1, F != 1/2: entries at lambda >= ALIAS_MIN draw two parts
+  int thin;            // THIN_* : which table entries draw two thinned parts
   double frac;         // F
   uint32_t *rdesc;     // [E] reddened part: k_lo << 12 | log2 M << 8 | KIND_ALIAS, or KIND_PTRS
 };
@@ -209,6 +218,11 @@ hipError_t launch_reduce_job(const ReduceArgs *table, int j, int npx, int B, hip
 // k_sample_block.hip
 hipError_t launch_prep_block(const BlockPrepArgs &a, hipStream_t s);
 hipError_t launch_sample_block(const BlockSampleArgs &a, hipStream_t s);
+// batched: the thinned entries' pass (F = 1/2) of the job at position t of the persistent table
+hipError_t launch_sample_thin_job(const BatchSampleJob *jobs, int t, int B, int npx, int nchunks, hipStream_t s);
+// batched: job j of a descriptor table (nb blocks; the sampler's grid covers npx pixels x nchunks)
+hipError_t launch_prep_block_job(const BlockPrepArgs *table, int j, int nb, hipStream_t s);
+hipError_t launch_sample_block_job(const BlockSampleArgs *table, int j, int B, int npx, int nchunks, hipStream_t s);
 
 // k_image.hip
 hipError_t launch_psf_check(const ConvArgs &a, hipStream_t s);

@@ -22,8 +22,8 @@ class Evaluator:
         self.hess_grid = dict(hess_grid)
         self.bands = tuple(bands)
         self.dev = torch.device(device)
-        imf_w, flux = _lib.grid_prepare(grid.iso_of_entry, grid.mass, grid.absmag, imf_alpha, imf)
-        self.iso_imf_sum = np.bincount(grid.iso_of_entry, weights=imf_w, minlength=grid.n_iso)
+        imf_w, flux, self.iso_imf_sum = _lib.grid_prepare(grid.iso_of_entry, grid.mass, grid.absmag, imf_alpha, imf,
+                                                          n_iso=grid.n_iso)
         self.iso_d = torch.from_numpy(np.ascontiguousarray(grid.iso_of_entry, np.int32)).to(self.dev)
         self.imf_d = torch.from_numpy(imf_w).to(self.dev)
         self.flux_d = torch.from_numpy(flux).to(self.dev)

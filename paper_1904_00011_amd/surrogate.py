@@ -58,6 +58,17 @@ class SurrogateNet:
             self.step += 1
         self.ctx.mlp_train_step(self.struct, x, t, lr, max(self.step, 1), loss_out, grad_out, apply_update)
 
+    def train_step_rows(self, x, t, rows, lr: float, grad, loss_out=None):
+        """One Adam step on the batch formed by rows `rows` (int32 device vector) of the set (x, t);
+        the gather runs inside the library's kernels.  grad: [n_params] FP32 device buffer."""
+        self.step += 1
+        self.ctx.mlp_backward(self.struct, x, t, grad, rows=rows, loss_out=loss_out)
+        self.ctx.mlp_adam(self.struct, grad, lr, self.step)
+
+    def loss(self, x, t, mse_out, rows=None):
+        """Mean squared error over the set (x, t) (or its rows `rows`) into mse_out [1] FP64."""
+        self.ctx.mlp_loss(self.struct, x, t, mse_out, rows=rows)
+
     def state(self) -> dict:
         """Checkpoint: master weights, Adam moments and the step count."""
         return dict(dims=self.dims, master=self.master.cpu().numpy(), m=self.m.cpu().numpy(),
@@ -72,11 +83,12 @@ class SurrogateNet:
         self.ctx.mlp_refresh(self.struct)
 
 
-def log_hess_target(hess: torch.Tensor) -> torch.Tensor:
-    """log((H + 1/2) / (N + n_bins / 2)) per row of a [n][n_bins] count tensor (targets)."""
-    h = hess.to(torch.float64)
-    N = h.sum(dim=1, keepdim=True)
-    return torch.log((h + 0.5) / (N + 0.5 * h.shape[1])).to(torch.float32)
+def log_hess_target(ctx: _lib.Context, hess: torch.Tensor) -> torch.Tensor:
+    """log((H + 1/2) / (N + n_bins / 2)) per row of a [n][n_bins] count tensor (the training
+    targets), computed by the library."""
+    out = torch.empty(hess.shape, dtype=torch.float32, device=hess.device)
+    ctx.log_hess_target(hess, out)
+    return out
 
 
 class Standardizer:

@@ -73,7 +73,7 @@ class SurrogateWorkflow:
         return out
 
     def targets(self, hess: torch.Tensor) -> torch.Tensor:
-        return log_hess_target(hess)
+        return log_hess_target(self.ctx, hess)
 
     def inputs(self, thetas: np.ndarray) -> torch.Tensor:
         return torch.from_numpy(self.std(thetas)).to(self.dev)
@@ -85,16 +85,15 @@ class SurrogateWorkflow:
         g = torch.Generator(device="cpu").manual_seed(seed)
         n = x.shape[0]
         loss = torch.empty(1, dtype=torch.float32, device=self.dev)
+        grad = torch.empty(self.net.n_params, dtype=torch.float32, device=self.dev)
         hist = []
-        # every step's batch indices in one copy: a host-to-device copy per step would wait for
-        # the previous step's kernels and leave the GPU idle while the next step is launched
-        all_idx = torch.randint(0, n, (steps, batch), generator=g).to(self.dev)
+        # every step's batch rows in one copy: a host-to-device copy per step would wait for the
+        # previous step's kernels and leave the GPU idle while the next step is launched; the
+        # library reads the batch's rows of x and t itself
+        all_idx = torch.randint(0, n, (steps, batch), generator=g, dtype=torch.int32).to(self.dev)
         for s in range(steps):
-            idx = all_idx[s]
-            xb = x.index_select(0, idx).contiguous()
-            tb = t.index_select(0, idx).contiguous()
             cur = lr * (lr_final / lr) ** (s / max(steps - 1, 1))
-            self.net.train_step(xb, tb, cur, loss_out=loss)
+            self.net.train_step_rows(x, t, all_idx[s], cur, grad, loss_out=loss)
             if log_every and (s % log_every == 0 or s == steps - 1):
                 hist.append((s, float(loss.item())))
         return hist
@@ -117,12 +116,11 @@ class SurrogateWorkflow:
         self.fit(xu, tu, steps, batch=batch, lr=lr, lr_final=lr_final, seed=seed)
         return xu, tu
 
-    def mse(self, x: torch.Tensor, t: torch.Tensor, batch: int = 1024) -> float:
-        se = 0.0
-        for b0 in range(0, x.shape[0], batch):
-            y = self.net.forward(x[b0:b0 + batch].contiguous())
-            se += float(((y - t[b0:b0 + batch]) ** 2).sum().item())
-        return se / (x.shape[0] * t.shape[1])
+    def mse(self, x: torch.Tensor, t: torch.Tensor) -> float:
+        """Mean squared error of the network over the set (computed by the library)."""
+        out = torch.empty(1, dtype=torch.float64, device=self.dev)
+        self.net.loss(x.contiguous(), t.contiguous(), out)
+        return float(out.item())
 
     # ---------------------------------------------------------------- likelihoods
     def surrogate_loglike_batch(self, thetas: np.ndarray) -> np.ndarray:

@@ -183,3 +183,106 @@ def test_batch_graph_replay_when_the_split_mode_changes(ctx):
         ctx.sync()
         assert np.array_equal(h_g.cpu().numpy(), h_s), rep
         assert np.array_equal(ll_g.cpu().numpy(), ll_s), rep
+
+
+def test_batch_at_uneven_full_shapes_against_the_oracle(ctx):
+    """Jobs of the uneven-batch workload's own shapes (sides 64 to 512, 5,000 to 52,500 points,
+    31 x 31 PSF, log-normal dust with F = 1/2, shot noise) through pcmd_batch_run, each against the
+    oracle's whole image run on every host core: the counts and reddened counts of a 1,024-pixel
+    window bit-exact (digests), the Hess pixel by pixel (the GPU magnitudes are those of the
+    sequential call, whose Hess equals the batch's), and the log-likelihood (Appendix A
+    re-simulations go through this call)."""
+    import torch
+    from oracle import hess as oh
+    from oracle import loglike as ol
+    from oracle import parallel as opar
+    from tests import parity_utils as pu
+    dev = torch.device("cuda")
+    base = si.headline_grid()
+    specs = [(64, 5000), (128, 20000), (256, 52500), (512, 12000), (208, 30000)]
+    jobs, host = [], []
+    for k, (N, E) in enumerate(specs):
+        G = base.subsample(max(1, int(round(base.n_entries / E))))
+        model, obs = si.draw_headline_params(600 + k)
+        obs.nim = N
+        lam, _, f32 = oe.build_entries(model, G)
+        host.append((lam, f32, obs))
+        jobs.append(dict(lam=torch.from_numpy(lam).to(dev), flux=torch.from_numpy(f32).to(dev), obs=obs,
+                         psf=torch.from_numpy(obs.psf).to(dev), conv_path=1))
+    # data: the 256 x 256 job at seed 2, Hess grid from its medians
+    lam2, f2, o2 = host[2]
+    d = pu.gpu_simulate(ctx, lam2, f2, dataclasses.replace(o2, seed=2), conv_path=1, want_flux=False)
+    md = d["mags"].astype(np.float64)
+    fin = np.isfinite(md).all(axis=0)
+    hgrid = si.hess_grid_from_median(float(np.median((md[0] - md[1])[fin])), float(np.median(md[1][fin])), 100, 100)
+    hd, momd = pu.gpu_hess(ctx, d["mags"], hgrid)
+    hd_d = torch.from_numpy(hd.astype(np.int32)).to(dev)
+    md_d = torch.from_numpy(momd).to(dev)
+    ll_b = torch.empty(len(jobs), dtype=torch.float64, device=dev)
+    h_b = torch.empty((len(jobs), 100 * 100), dtype=torch.int32, device=dev)
+    ctx.batch_run(jobs, hgrid, hd_d, md_d, ll_b, mode=0, hess_out=h_b)
+    ctx.sync()
+    ll_b, h_b = ll_b.cpu().numpy(), h_b.cpu().numpy()
+    for k, (lam, f32, obs) in enumerate(host):
+        N = obs.nim
+        npx = N * N
+        w0 = (npx // 3) & ~63
+        w1 = min(npx, w0 + 1024)
+        print(f"[case] batch job {k}: nim={N} E={len(lam)} log_npix={si.draw_headline_params(600 + k)[0].log_npix:.2f} "
+              f"window=({w0}, {w1})", flush=True)
+        g = pu.gpu_simulate(ctx, lam, f32, obs, conv_path=1, window=(w0, w1), want_flux=False)
+        hg, momg = pu.gpu_hess(ctx, g["mags"], hgrid)
+        assert np.array_equal(hg.ravel(), h_b[k]), k            # batch == sequential
+        assert h_b[k].sum() == npx
+        ora = opar.simulate(lam, f32, obs, with_digest=True)
+        mult = opar.digest_multipliers(len(lam))
+        assert np.array_equal(opar.count_digest(g["counts"], mult), ora["digest_counts"][w0:w1]), k
+        assert np.array_equal(opar.count_digest(g["red"], mult), ora["digest_red"][w0:w1]), k
+        _, _, moved = pu.assert_hess_per_pixel(g["mags"], ora["mags64"], hgrid, what=f"batch job {k} Hess")
+        ho, momo = oh.hess(ora["mags"], hgrid)
+        lo = ol.loglike(ho, hd, momo, momd, ol.POISSON, 0.01)
+        print(f"[case] batch job {k}: logL batch {ll_b[k]:.6f} oracle {lo:.6f} |d| {abs(ll_b[k] - lo):.2e} "
+              f"(near-edge pixels moved: {moved})", flush=True)
+        assert abs(ll_b[k] - ol.loglike(h_b[k], hd.ravel(), momg, momd, ol.POISSON, 0.01)) <= 1e-9 * abs(ll_b[k])
+        if moved == 0:
+            assert np.array_equal(h_b[k], ho.ravel())
+            assert abs(ll_b[k] - lo) <= pu.LOGL_ATOL
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_batch_with_block_and_hybrid_samplers(ctx, use_graph):
+    """Jobs with the per-point, block-skip and hybrid samplers in one batch: every job's Hess and
+    log-likelihood bit-identical to its sequential call (the hybrid's block-rule stars are added
+    to the per-point partials in the same order), also under graph replay with new seeds; the
+    hybrid job's counts on a window against the hybrid oracle."""
+    import torch
+    from oracle import sampler_block as sb
+    from tests import parity_utils as pu
+    dev = torch.device("cuda")
+    hess_d, mom_d, grid = _data(ctx)
+    base = _jobs(9, 50)
+    for rep in range(3 if use_graph else 1):
+        jobs = []
+        for k, j in enumerate(base):
+            obs = dataclasses.replace(j["obs"], sampler=k % 3, seed=7000 + 100 * rep + k)
+            jobs.append(dict(j, obs=obs))
+        print(f"[case] mixed samplers graph={use_graph} rep={rep} samplers={[j['obs'].sampler for j in jobs]}",
+              flush=True)
+        ll_s, h_s = _sequential(ctx, jobs, grid, hess_d, mom_d, 0)
+        ll_b = torch.empty(len(jobs), dtype=torch.float64, device=dev)
+        h_b = torch.empty((len(jobs), 100 * 100), dtype=torch.int32, device=dev)
+        ctx.batch_run(jobs, grid, hess_d, mom_d, ll_b, hess_out=h_b, use_graph=use_graph)
+        x = torch.ones(1000, device=dev).sum()          # eager work between replays
+        ctx.sync()
+        assert np.array_equal(h_b.cpu().numpy(), h_s), rep
+        assert np.array_equal(ll_b.cpu().numpy(), ll_s), rep
+        assert float(x) == 1000.0
+    # the hybrid job (sampler 2) against the hybrid oracle on its first 64 pixels
+    j = jobs[2]
+    lam = j["lam"].cpu().numpy()
+    f32 = j["flux"].cpu().numpy()
+    o = j["obs"]
+    g = pu.gpu_simulate(ctx, lam, f32, o, conv_path=1, window=(0, 64), want_flux=False)
+    s = sb.sample_pixels_hybrid(lam, f32, o.seed, np.arange(64), o.dust_model, o.dust_frac, want_counts=True)
+    assert np.array_equal(g["counts"], s["counts"])
+    assert np.array_equal(g["red"], s["red"])

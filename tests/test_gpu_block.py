@@ -208,15 +208,17 @@ def test_validation(ctx):
     assert ei.value.code == P._lib.E_INVAL
     # the hybrid rule leaves such a block to the per-point rule: no error
     pu.gpu_simulate(ctx, np.full(64, 1e5), f32, dataclasses.replace(obs, sampler=2), want_flux=False)
-    # batches keep the per-point rule
+    # a batch job with the block rule reports the same block-sum finding at pcmd_sync
     import torch
     dev = torch.device("cuda")
-    lam = torch.full((64,), 0.1, dtype=torch.float64, device=dev)
+    lam = torch.full((64,), 1e5, dtype=torch.float64, device=dev)
     flux = torch.ones((2, 64), dtype=torch.float32, device=dev)
     hd = torch.zeros(16, dtype=torch.int32, device=dev)
     md = torch.zeros(3, dtype=torch.float64, device=dev)
     ll = torch.empty(1, dtype=torch.float64, device=dev)
     hg = dict(x0=0.0, dx=0.5, nx=4, y0=20.0, dy=0.5, ny=4)
+    ctx.batch_run([dict(lam=lam, flux=flux, obs=obs, psf=None, conv_path=P._lib.CONV_DIRECT)], hg, hd, md, ll)
     with pytest.raises(P.PcmdError) as ei:
-        ctx.batch_run([dict(lam=lam, flux=flux, obs=obs, psf=None, conv_path=P._lib.CONV_DIRECT)], hg, hd, md, ll)
-    assert ei.value.code == P._lib.E_UNSUPPORTED
+        ctx.sync()
+    assert ei.value.code == P._lib.E_INVAL
+    ctx.sync()

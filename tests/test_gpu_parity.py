@@ -239,11 +239,14 @@ def test_rule_boundaries(ctx):
     alias / rejection at 512), the widest alias tables (M = 512) and the narrowest, without dust,
     with the F = 1/2 bit split and with thinning (F = 0.3, 0.8): every count against the oracle."""
     lam = np.array([1.9999999, 2.0, 2.0000001, 3.7, 9.99, 10.0, 63.5, 255.0, 300.0, 511.9, 511.999999,
-                    512.0, 512.5, 700.0, 0.0, 0.7, 1000.0, 1500.0, 1e-11, 3e-10, 1e-7])
+                    512.0, 512.5, 700.0, 0.0, 0.7, 1000.0, 1500.0, 1e-11, 3e-10, 1e-7, 63.99999999, 64.0,
+                    1023.9, 1024.0, 5000.0])
     E = len(lam)
     f32 = np.linspace(0.2, 1.0, 2 * E).reshape(2, E).astype(np.float32) * 1e-3
     # F = 0.3 and 0.8 thin the entries at lambda >= 2 into two parts, whose own lambdas fall on
-    # both sides of 512 (700 x 0.8, 1000 x 0.3, 1500 x 0.3) and below 2 (2.0 x 0.3)
+    # both sides of 512 (700 x 0.8, 1000 x 0.3, 1500 x 0.3) and below 2 (2.0 x 0.3); F = 1/2 thins
+    # the entries from lambda = 64 on (halves on both sides of 512: 1023.9, 1024, 5000) and splits
+    # the others one bit per star (63.99999999 on the edge)
     # F = 1e-12 and 1 - 1e-12: one thinned part of every table entry is below 2^-32 per pixel, so
     # its table has the single outcome 0
     for dust, frac in ((0, 0.5), (2, 0.5), (2, 0.3), (1, 0.8), (2, 1e-12), (1, 1.0 - 1e-12)):
@@ -517,3 +520,24 @@ def test_evaluator_writes_into_a_result_slot(ctx):
     assert np.isfinite(ref) and r[2] == ref and np.all(r[[0, 1, 3]] == -7.0)
     with pytest.raises(ValueError):
         ev.loglike(model, obs, dh, dm, out=res[0:2])
+
+
+@pytest.mark.parametrize("K,sub", [(5, False), (9, False), (7, True)])
+def test_direct_conv_one_group_blocks_against_oracle(ctx, K, sub):
+    """1024 x 1024 x 2 bands: enough 64 x 16 tiles (2,048) that the direct convolution runs its
+    one-group blocks (no row split).  The GPU's post-PSF image against the oracle's FP64 periodic
+    sum of the GPU's own pre-PSF image, every pixel; with the 4 x 4 sub-pixel grid too."""
+    from oracle import parallel as opar
+    grid, model, obs = si.small_case(nim=1024, seed=11)
+    lam, _, f32 = oe.build_entries(model, grid)
+    obs.psf = si.psf_subpixel_stack(K, (1.0, 1.3)) if sub else si.psf_stack(K, (1.0, 1.3))
+    _print_case("direct_conv_one_group", N=1024, K=K, subpixel=sub)
+    g = pu.gpu_simulate(ctx, lam, f32, obs, conv_path=1)
+    F = g["flux_pre"].astype(np.float64).reshape(2, 1024, 1024)
+    if sub:
+        Go = ops.convolve_periodic_subpixel(F, obs.psf)
+    else:
+        Go = opar.convolve(F, obs.psf)
+    e = np.max(pu.rel_err(g["flux_psf"], Go.reshape(2, -1)))
+    print(f"[case] direct_conv_one_group K={K} sub={sub}: max rel err {e:.2e}", flush=True)
+    assert e <= pu.FLUX_RTOL

@@ -49,6 +49,11 @@ def test_grid_prepare_matches_oracle():
         assert np.max(np.abs(f.astype(np.float64) / f32.astype(np.float64) - 1)) <= 6e-8
         wk, _ = _lib.grid_prepare(g.iso_of_entry, g.mass, g.absmag, 2.35, imf="kroupa")
         assert np.max(np.abs(wk / oe.imf_weights(g, imf="kroupa") - 1)) < 1e-12
+        # per-isochrone normalisation: the IMF weight summed over each isochrone's points
+        w2, _, sums = _lib.grid_prepare(g.iso_of_entry, g.mass, g.absmag, 2.35, n_iso=g.n_iso)
+        assert np.array_equal(w2, w)
+        for k in range(g.n_iso):
+            assert sums[k] == pytest.approx(wo[g.iso_of_entry == k].sum(), rel=1e-13)
 
 
 def test_iso_weights_match_oracle():
@@ -79,7 +84,10 @@ def test_host_helper_validation():
     mass = np.ascontiguousarray(g.mass, np.float64)
     mag = np.ascontiguousarray(g.absmag, np.float64)
     assert _lib.load().pcmd_grid_prepare(g.n_entries, g.n_bands, iso.ctypes.data, mass.ctypes.data, mag.ctypes.data,
-                                         7, 2.35, w.ctypes.data, f.ctypes.data) != 0  # unknown IMF kind
+                                         7, 2.35, w.ctypes.data, f.ctypes.data, 0, None) != 0  # unknown IMF kind
+    sums = np.empty(g.n_iso)
+    assert _lib.load().pcmd_grid_prepare(g.n_entries, g.n_bands, iso.ctypes.data, mass.ctypes.data, mag.ctypes.data,
+                                         0, 2.35, w.ctypes.data, f.ctypes.data, 0, sums.ctypes.data) != 0  # no isochrones
     bad_mass = g.mass.copy()
     bad_mass[10] = bad_mass[9]
     with pytest.raises(_lib.PcmdError):

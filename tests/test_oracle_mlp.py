@@ -60,3 +60,20 @@ def test_surrogate_loglike_is_poisson():
     lam = d.sum() * np.exp(y) / np.exp(y).sum()
     assert mlp.surrogate_loglike(y, d) == pytest.approx(float(stats.poisson.logpmf(d, lam).sum()), rel=1e-12)
     assert mlp.surrogate_loglike(y + 7.0, d) == pytest.approx(mlp.surrogate_loglike(y, d), rel=1e-12)
+
+
+def test_log_hess_target_pins():
+    # the shares exp(target) of a diagram sum to one; an empty bin gets (1/2) / (N + n/2)
+    r = np.random.default_rng(5)
+    h = r.poisson(3.0, size=(4, 250))
+    h[1] = 0
+    h[2, :200] = 0
+    t = mlp.log_hess_target(h)
+    assert t.shape == (4, 250)
+    assert np.allclose(np.exp(t).sum(axis=1), 1.0, rtol=0, atol=1e-13)
+    assert t[1] == pytest.approx(np.full(250, np.log(1.0 / 250)), rel=1e-14)
+    n2 = h[2].sum()
+    assert t[2, 0] == pytest.approx(np.log(0.5 / (n2 + 125.0)), rel=1e-14)
+    # a hand case: counts (3, 0, 1), N = 4, denominator 5.5
+    assert mlp.log_hess_target([3, 0, 1])[0] == pytest.approx(np.log([3.5 / 5.5, 0.5 / 5.5, 1.5 / 5.5]), rel=1e-15)
+    assert mlp.mse([[1.0, 2.0]], [[0.0, 4.0]]) == pytest.approx(2.5)
