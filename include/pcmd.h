@@ -249,6 +249,17 @@ int pcmd_loglike(pcmd_ctx *ctx, const uint32_t *hess_model, const uint32_t *hess
                  const double *mom_model, const double *mom_data, int32_t mode, double eps,
                  double *out, pcmd_stream stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): pcmd_loglike with its block sums in a static device
+ * array of 256 doubles (2 KiB per GPU, held until the process ends) instead of the context's
+ * scratch.  Same arguments, kernels and results as pcmd_loglike; n_bins at most 65536 (larger:
+ * PCMD_E_INVAL with a message, nothing launched).  It calls no allocating routine.  Every call on
+ * one GPU shares that array, so calls that overlap on one GPU (different streams, or contexts
+ * used from several threads) race; calls ordered on one stream do not. */
+int pcmd_loglike_noalloc(pcmd_ctx *ctx, const uint32_t *hess_model, const uint32_t *hess_data, int32_t n_bins,
+                         const double *mom_model, const double *mom_data, int32_t mode, double eps, double *out,
+                         pcmd_stream stream);
+
 /* ---------------------------------------------------------------------------------------
  * a7: many parameter points in one launch (the paper's fits evaluate the stochastic likelihood
  * at many points and re-simulate the best fit 100 times, Sec. 2.5 and Appendix A).

@@ -15,7 +15,7 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libpcmd.so")
 
 SOURCES = ["pcmd_api.cpp", "pcmd_batch.cpp", "pcmd_mlp.cpp", "k_sample.hip", "k_sample_block.hip", "k_image.hip",
-           "k_hess.hip", "k_fft.hip", "k_mlp.hip"]
+           "k_hess.hip", "k_fft.hip", "k_mlp.hip", "pcmd_noalloc.hip"]
 
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared", "-Wall",
          "-Wno-unused-result", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

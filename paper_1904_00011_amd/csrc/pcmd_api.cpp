@@ -117,6 +117,11 @@ int pcmd_create(pcmd_ctx **out, int hip_device) {
     pcmd_destroy(c);
     return PCMD_E_HIP;
   }
+  // this device's address of the allocation-free call's static scratch (looked up once)
+  if (noalloc_init(c, hip_device) != PCMD_OK) {
+    pcmd_destroy(c);
+    return PCMD_E_HIP;
+  }
   *out = c;
   return PCMD_OK;
 }

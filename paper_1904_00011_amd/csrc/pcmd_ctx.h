@@ -146,5 +146,7 @@ bool uses_fft(const pcmd_obs *o);
 int psf_grid_of(const pcmd_obs *o);  // 1 or 4
 
 void batch_destroy(pcmd_ctx *c);
+// Looks up `device`'s copy of the allocation-free call's static scratch (pcmd_noalloc.hip).
+int noalloc_init(pcmd_ctx *c, int device);
 
 }  // namespace pcmd
