@@ -35,12 +35,13 @@ VALU_LANE_OPS_PEAK = 256 * 64 * 2.4e9
 # with lambda > 0 draw; data-dependent work (accumulation, further thresholds, rejection, dust
 # split) is not counted, so the fraction is a lower bound.
 OPS_PER_DRAW = 40 / 4 + 1
-# HBM bytes per k_sample launch of the first headline step, from FETCH_SIZE and WRITE_SIZE
-# calibrated against a copy of known size (profiles/k_sample_headline_256x256_52500_counters.md).
-# Set to None whenever k_sample changes until the counters are taken again.
-SAMPLE_TRAFFIC_BYTES = None
-# The same for the first 512x512, Npix = 1e6 step (None until its counters are taken).
-LARGE_SAMPLE_TRAFFIC_BYTES = None
+# HBM bytes of the sampler (both k_sample passes) of the first headline step, from FETCH_SIZE
+# and WRITE_SIZE calibrated against a copy of known size
+# (profiles/k_sample_headline_256x256_52500_counters.md).  Set to None whenever k_sample changes
+# until the counters are taken again.
+SAMPLE_TRAFFIC_BYTES = 194.4e6
+# The same for the first 512x512, Npix = 1e6 step (profiles/k_sample_large_512x512_52500_counters.md).
+LARGE_SAMPLE_TRAFFIC_BYTES = 2053e6
 
 
 def parse():
@@ -53,7 +54,7 @@ def parse():
                     help="pixels of the oracle's timed sampler sample (default 32768 headline, 8192 large)")
     ap.add_argument("--conv", type=int, default=0, help="0 auto, 1 direct, 2 fft")
     ap.add_argument("--workload", default="headline",
-                    choices=["headline", "large", "small", "batch", "counters", "surrogate", "scatter", "ablation"],
+                    choices=["headline", "large", "small", "batch", "counters", "surrogate", "scatter", "ablation", "gemm"],
                     help="headline: 256x256 single evaluations; large: 512x512 at Npix = 1e6 with a 63x63 PSF and "
                          "200x200 Hess; small: 64x64, 500 points, the oracle timed on whole evaluations; "
                          "batch: 256 uneven jobs per step; counters: one headline simulation plus a "
@@ -320,6 +321,65 @@ def run_surrogate(args):
         "simulator_loglikes_per_s": sim_rate,
     }
     ctx.close()
+    print(json.dumps(res), flush=True)
+
+
+def run_gemm(args):
+    """The surrogate's dominant matrix product alone, C[8192][10000] = A[8192][512] B[10000][512]^T
+    in BF16 with FP32 output (10 timed launches), and one training step of the configured network
+    (12 -> 4 x 512 -> 10,000) at a batch of 1,024, its products timed by HIP events."""
+    import torch
+
+    import paper_1904_00011_amd as P
+    import synth_inputs as si
+    from paper_1904_00011_amd.surrogate import SurrogateNet
+
+    dev = torch.device("cuda:0")
+    ctx = P.Context(0)
+    g = torch.Generator(device="cpu").manual_seed(5)
+    A = torch.randn((8192, 512), generator=g).to(dev).to(torch.bfloat16)
+    Bw = torch.randn((10000, 512), generator=g).to(dev).to(torch.bfloat16)
+    Cm = torch.empty((8192, 10000), dtype=torch.float32, device=dev)
+    ctx.gemm_bf16(A, Bw, Cm)
+    torch.cuda.synchronize()
+    ctx.timer_enable(True)
+    for _ in range(10):
+        ctx.gemm_bf16(A, Bw, Cm)
+    torch.cuda.synchronize()
+    b_ms, b_n, b_flops = ctx.timer_read(P._lib.TIMER_GEMM)
+    ctx.timer_enable(False)
+    dims = (12, 512, 512, 512, 512, 10000)
+    net = SurrogateNet(ctx, dims, si.mlp_init(dims, 1))
+    x = torch.rand((1024, 12), generator=g).to(dev) * 2 - 1
+    t = torch.randn((1024, 10000), generator=g).to(dev)
+    net.train_step(x, t, 1e-4)
+    torch.cuda.synchronize()
+    ctx.timer_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.train_step(x, t, 1e-4)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    s_ms, s_n, s_flops = ctx.timer_read(P._lib.TIMER_GEMM)
+    ctx.timer_enable(False)
+    ctx.close()
+    avg = b_ms / max(b_n, 1)
+    out_bytes = 8192 * 10000 * 4
+    res = {
+        "metric": "BF16 product 8192x10000x512 (FP32 out), TFLOP/s",
+        "value": b_flops / (b_ms / 1e3) / 1e12, "unit": "TFLOP/s", "n_gpus": 1, "steps": 10, "warmup": 1,
+        "ms_per_step": avg, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "bf16 MFMA, fp32 accumulate", "data": "synthetic",
+        "config": {"workload": "8192x10000x512 product; training step of 12-512-512-512-512-10000 at batch 1024"},
+        "roofline": {"bound": "mfma", "kernel": "k_gemm 8192x10000x512 bf16", "achieved": b_flops / (b_ms / 1e3) / 1e12,
+                     "peak": 2500.0, "unit": "TFLOP/s", "frac": b_flops / (b_ms / 1e3) / 2.5e15, "traffic": None,
+                     "avg_launch_ms": avg,
+                     # the FP32 output alone is 328 MB: at 8 TB/s a 41 us floor
+                     "output_write_floor_ms": out_bytes / 8e12 * 1e3},
+        "train_step_ms": 1e3 * (t1 - t0) / args.steps,
+        "train_step_gemm_ms": s_ms / args.steps,
+        "train_step_gemm_tflops": s_flops / (s_ms / 1e3) / 1e12 if s_ms > 0 else None,
+    }
     print(json.dumps(res), flush=True)
 
 
@@ -642,6 +702,9 @@ def main():
         return
     if args.workload == "small":
         run_small(args)
+        return
+    if args.workload == "gemm":
+        run_gemm(args)
         return
     import torch
 

@@ -160,9 +160,11 @@ enum { PCMD_SAMPLER_POINT = 0, PCMD_SAMPLER_BLOCK = 1, PCMD_SAMPLER_HYBRID = 2 }
  *                 region (ry, rx) = (floor(4 y / nim), floor(4 x / nim)), and the pixels of region
  *                 r = 4 ry + rx take the PSF psf[b][r] (psf is [dev][B][16][K][K]): the paper's
  *                 sub-pixel model, each region with a PSF shifted by a fraction of a pixel
- *                 (Sec. 2.2).  Direct path only (AUTO picks it; FFT is PCMD_E_UNSUPPORTED)
+ *                 (Sec. 2.2).  AUTO takes the direct path for the grid; the FFT path computes it
+ *                 too (one forward transform, an inverse per region: several times the cost)
  *  conv_path      AUTO (direct below K = 48, FFT from 48 on where supported), DIRECT or FFT (FFT
- *                 needs nim a power of two, 8..4096)
+ *                 needs nim a power of two, 8..4096; the context keeps the PSF spectra and
+ *                 rebuilds them on the device whenever the PSF's contents change)
  *  noise_model    NONE, GAUSS_MAG (m += sigma_b z) or SHOT (c = G t_b 10^(0.4 zp_b) + sky_b,
  *                 c' = c + sqrt(c) z, m = -2.5 log10((c' - sky_b)/t_b) + zp_b; +inf if <= 0)
  *  sampler        POINT (0): one Poisson count per (pixel, point), the paper's rule (Sec. 2.1).

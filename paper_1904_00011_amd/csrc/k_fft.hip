@@ -5,6 +5,14 @@
 // (Sec. 2.1 of the paper convolves each band with its PSF).  Transforms are radix-2 in LDS,
 // one row (or a few columns) per workgroup, in FP64 complex arithmetic (full rate on MI355X),
 // so the result agrees with the direct sum to ~1e-15 relative to the image's RMS.
+//
+// The PSF spectra and twiddles are kept between calls: a one-workgroup kernel compares the
+// caller's PSF with the copy the spectra were built from (and takes the new one), and the
+// spectrum kernels return at once unless something changed, so repeated evaluations with one
+// PSF transform only the image.  With the 4 x 4 sub-pixel grid (Sec. 2.2) each of the 16 regions
+// has its own spectrum: the image is transformed forward once, and per region the product is
+// transformed back (all columns, then the rows of the region's band of rows) and only the
+// region's pixels are kept.
 #include <math.h>
 
 #include "pcmd_device.h"
@@ -26,9 +34,32 @@ static int ilog2(int n) {
   return l;
 }
 
-// Scratch layout: [twiddles N/2][image spectrum B N^2][psf spectrum B N^2] (complex doubles)
-size_t fft_scratch_bytes(int B, int N) {
-  return sizeof(cplx) * ((size_t)N / 2 + 2 * (size_t)B * N * N) + 256;
+// Scratch layout (complex doubles unless noted): [twiddles N/2][image spectrum B N^2]
+// [per-region inverse B N^2, sub-pixel grid only][PSF spectra R B N^2][PSF copy R B K K floats]
+// [change flag u32]
+static size_t fft_psf_copy_offset(int B, int N, int R) {
+  return sizeof(cplx) * ((size_t)N / 2 + (size_t)(R > 1 ? 2 : 1) * B * N * N + (size_t)R * B * N * N);
+}
+size_t fft_scratch_bytes(int B, int N, int K, int R) {
+  return fft_psf_copy_offset(B, N, R) + sizeof(float) * (size_t)R * B * K * K + 256;
+}
+
+// flag = force or (any element of psf differs from copy); copy = psf.  One workgroup: each
+// thread compares its elements with their old copies before overwriting them.
+__global__ void __launch_bounds__(1024) k_psf_update(const float *__restrict__ psf, float *__restrict__ copy, int64_t n,
+                                                      int force, uint32_t *__restrict__ flag) {
+  __shared__ int any;
+  if (threadIdx.x == 0) any = force;
+  __syncthreads();
+  int d = 0;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const float v = psf[i];
+    if (__float_as_uint(v) != __float_as_uint(copy[i])) d = 1;
+    copy[i] = v;
+  }
+  if (d) any = 1;
+  __syncthreads();
+  if (threadIdx.x == 0) *flag = (uint32_t)any;
 }
 
 __global__ void k_twiddles(cplx *tw, int N) {
@@ -66,12 +97,16 @@ __device__ __forceinline__ int bitrev(int i, int logn) { return (int)(__brev((un
 
 // Row transforms.  mode 0: real FP32 input rows -> forward -> complex out.
 //                  mode 1: complex in -> inverse -> real FP32 out scaled by 1/N^2.
+// Block x transforms row y0 + x of band y; mode 1 writes only the columns [xa, xb) of it.  With
+// `skip` given, the kernel does nothing unless *skip is non-zero (PSF spectra that are current).
 template <int MODE>
 __global__ void __launch_bounds__(256) k_fft_rows(const float *__restrict__ rin, const cplx *__restrict__ cin,
                                                   cplx *__restrict__ cout, float *__restrict__ rout, int N, int logN,
-                                                  const cplx *__restrict__ tw) {
+                                                  const cplx *__restrict__ tw, int y0, int xa, int xb,
+                                                  const uint32_t *__restrict__ skip) {
   extern __shared__ cplx row[];
-  const int y = blockIdx.x, b = blockIdx.y;
+  if (skip && *skip == 0u) return;
+  const int y = y0 + blockIdx.x, b = blockIdx.y;
   const size_t base = ((size_t)b * N + y) * N;
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     const int r = bitrev(i, logN);
@@ -83,31 +118,33 @@ __global__ void __launch_bounds__(256) k_fft_rows(const float *__restrict__ rin,
   __syncthreads();
   fft_stages(row, 1, logN, N, tw, MODE == 1, threadIdx.x, blockDim.x);
   const double scale = 1.0 / ((double)N * (double)N);
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    if (MODE == 0)
-      cout[base + i] = row[i];
-    else
-      rout[base + i] = (float)(row[i].x * scale);
+  if (MODE == 0) {
+    for (int i = threadIdx.x; i < N; i += blockDim.x) cout[base + i] = row[i];
+  } else {
+    for (int i = xa + threadIdx.x; i < xb; i += blockDim.x) rout[base + i] = (float)(row[i].x * scale);
   }
 }
 
-// Column transforms over CB adjacent columns.  mode 0: forward only (PSF spectrum).
-// mode 1: forward, multiply by the PSF spectrum, inverse.
+// Column transforms over CB adjacent columns.  mode 0: forward only (PSF spectrum; with `skip`
+// given, only when *skip is non-zero).  mode 1: forward, multiply by the PSF spectrum, inverse.
+// mode 2: multiply the forward-transformed columns by the spectrum and inverse, into Y.
 template <int MODE>
 __global__ void __launch_bounds__(256) k_fft_cols(cplx *__restrict__ X, const cplx *__restrict__ S, int N, int logN,
-                                                  int CB, const cplx *__restrict__ tw) {
+                                                  int CB, const cplx *__restrict__ tw, cplx *__restrict__ Y,
+                                                  const uint32_t *__restrict__ skip) {
   extern __shared__ cplx col[];  // [CB][N]
+  if (MODE == 0 && skip && *skip == 0u) return;
   const int x0 = blockIdx.x * CB, b = blockIdx.y;
   const size_t base = (size_t)b * N * N;
   for (int idx = threadIdx.x; idx < N * CB; idx += blockDim.x) {
     const int y = idx / CB, c = idx - y * CB;  // consecutive threads read consecutive columns of a row
-    col[c * N + bitrev(y, logN)] = X[base + (size_t)y * N + x0 + c];
+    col[c * N + (MODE == 2 ? y : bitrev(y, logN))] = X[base + (size_t)y * N + x0 + c];
   }
   __syncthreads();
   // each column's transform is done by blockDim / CB threads
   const int per = blockDim.x / CB;
   const int c = threadIdx.x / per, t = threadIdx.x - c * per;
-  for (int s = 1; s <= logN; ++s) {
+  for (int s = 1; s <= (MODE == 2 ? 0 : logN); ++s) {
     const int len = 1 << s, half = len >> 1, tstep = N >> s;
     if (c < CB) {
       cplx *a = col + c * N;
@@ -122,7 +159,7 @@ __global__ void __launch_bounds__(256) k_fft_cols(cplx *__restrict__ X, const cp
     }
     __syncthreads();
   }
-  if (MODE == 1) {
+  if (MODE >= 1) {
     // multiply by the PSF spectrum, then bit-reverse into a second buffer half for the inverse
     for (int idx = threadIdx.x; idx < N * CB; idx += blockDim.x) {
       const int cc = idx / N, y = idx - cc * N;
@@ -147,15 +184,19 @@ __global__ void __launch_bounds__(256) k_fft_cols(cplx *__restrict__ X, const cp
       __syncthreads();
     }
   }
-  const int off = MODE == 1 ? CB : 0;
+  const int off = MODE >= 1 ? CB : 0;
+  cplx *out = MODE == 2 ? Y : X;
   for (int idx = threadIdx.x; idx < N * CB; idx += blockDim.x) {
     const int y = idx / CB, cc = idx - y * CB;
-    X[base + (size_t)y * N + x0 + cc] = col[(off + cc) * N + y];
+    out[base + (size_t)y * N + x0 + cc] = col[(off + cc) * N + y];
   }
 }
 
 // PSF wrapped onto the N x N torus: Pw[(u - h) mod N][(v - h) mod N] = P[u][v], zero elsewhere.
-__global__ void k_psf_wrap(const float *__restrict__ psf, int K, int N, float *__restrict__ out) {
+// Band b's PSF at psf + b pstride.  Only when *skip is non-zero.
+__global__ void k_psf_wrap(const float *__restrict__ psf, int K, int N, float *__restrict__ out, int64_t pstride,
+                           const uint32_t *__restrict__ skip) {
+  if (*skip == 0u) return;
   const int b = blockIdx.y;
   const size_t NN = (size_t)N * N;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < NN; i += (size_t)gridDim.x * blockDim.x) {
@@ -163,7 +204,7 @@ __global__ void k_psf_wrap(const float *__restrict__ psf, int K, int N, float *_
     const int h = (K - 1) / 2;
     const int u = (y + h) % N, v = (x + h) % N;  // inverse of the wrap
     float val = 0.0f;
-    if (u < K && v < K) val = psf[(size_t)b * K * K + (size_t)u * K + v];
+    if (u < K && v < K) val = psf[(size_t)b * pstride + (size_t)u * K + v];
     out[(size_t)b * NN + i] = val;
   }
 }
@@ -174,31 +215,58 @@ static int cols_per_block(int N) {
   return cb;
 }
 
-hipError_t launch_conv_fft(const float *F, const float *psf, int B, int N, int K, float *G, void *scratch,
-                           hipStream_t s) {
-  if (!fft_supported(N)) return hipErrorInvalidValue;
+hipError_t launch_conv_fft(const float *F, const float *psf, int B, int N, int K, int grid, float *G, void *scratch,
+                           bool fresh, hipStream_t s) {
+  if (!fft_supported(N) || (grid != 1 && grid != 4)) return hipErrorInvalidValue;
+  const int R = grid * grid;
   const int logN = ilog2(N);
+  const size_t NN = (size_t)N * N;
   cplx *tw = (cplx *)scratch;
   cplx *X = tw + N / 2;
-  cplx *Sp = X + (size_t)B * N * N;
+  cplx *Y = X + (size_t)B * NN;                      // sub-pixel grid only
+  cplx *Sp = R > 1 ? Y + (size_t)B * NN : Y;         // [R][B][N][N]
+  float *copy = (float *)((char *)scratch + fft_psf_copy_offset(B, N, R));
+  uint32_t *flag = (uint32_t *)(copy + (size_t)R * B * K * K);
   const int CB = cols_per_block(N);
   if ((size_t)2 * CB * N * sizeof(cplx) > 160 * 1024) return hipErrorInvalidValue;
   const int rthreads = N / 2 < 256 ? N / 2 : 256;
   const int cthreads = 256;
-  hipLaunchKernelGGL(k_twiddles, dim3((N / 2 + 255) / 256), dim3(256), 0, s, tw, N);
-  // PSF spectrum: wrap into G (free at this point), transform rows and columns
-  hipLaunchKernelGGL(k_psf_wrap, dim3(256, B), dim3(256), 0, s, psf, K, N, G);
-  hipLaunchKernelGGL(k_fft_rows<0>, dim3(N, B), dim3(rthreads), N * sizeof(cplx), s, G, nullptr, Sp, nullptr, N, logN,
-                     tw);
-  hipLaunchKernelGGL(k_fft_cols<0>, dim3(N / CB, B), dim3(cthreads), 2 * CB * N * sizeof(cplx), s, Sp, nullptr, N,
-                     logN, CB, tw);
-  // image: rows forward, columns forward x spectrum inverse, rows inverse
-  hipLaunchKernelGGL(k_fft_rows<0>, dim3(N, B), dim3(rthreads), N * sizeof(cplx), s, F, nullptr, X, nullptr, N, logN,
-                     tw);
-  hipLaunchKernelGGL(k_fft_cols<1>, dim3(N / CB, B), dim3(cthreads), 2 * CB * N * sizeof(cplx), s, X, Sp, N, logN,
-                     CB, tw);
-  hipLaunchKernelGGL(k_fft_rows<1>, dim3(N, B), dim3(rthreads), N * sizeof(cplx), s, nullptr, X, nullptr, G, N, logN,
-                     tw);
+  const size_t rl = N * sizeof(cplx), cl = 2 * CB * N * sizeof(cplx);
+  if (fresh) hipLaunchKernelGGL(k_twiddles, dim3((N / 2 + 255) / 256), dim3(256), 0, s, tw, N);
+  // PSF spectra, rebuilt only when the PSF (or the layout: fresh) changed.  psf is
+  // [B][K][K] (grid 1) or [B][16][K][K]: region r of band b at psf + (b R + r) K K.
+  hipLaunchKernelGGL(k_psf_update, dim3(1), dim3(1024), 0, s, psf, copy, (int64_t)R * B * K * K, fresh ? 1 : 0, flag);
+  for (int r = 0; r < R; ++r) {
+    cplx *Sr = Sp + (size_t)r * B * NN;
+    // wrap into G (free at this point), transform rows and columns
+    hipLaunchKernelGGL(k_psf_wrap, dim3(256, B), dim3(256), 0, s, psf + (size_t)r * K * K, K, N, G, (int64_t)R * K * K,
+                       flag);
+    hipLaunchKernelGGL(k_fft_rows<0>, dim3(N, B), dim3(rthreads), rl, s, G, nullptr, Sr, nullptr, N, logN, tw, 0, 0, N,
+                       flag);
+    hipLaunchKernelGGL(k_fft_cols<0>, dim3(N / CB, B), dim3(cthreads), cl, s, Sr, nullptr, N, logN, CB, tw, nullptr,
+                       flag);
+  }
+  // image: rows forward
+  hipLaunchKernelGGL(k_fft_rows<0>, dim3(N, B), dim3(rthreads), rl, s, F, nullptr, X, nullptr, N, logN, tw, 0, 0, N,
+                     nullptr);
+  if (R == 1) {
+    // columns forward x spectrum inverse, rows inverse
+    hipLaunchKernelGGL(k_fft_cols<1>, dim3(N / CB, B), dim3(cthreads), cl, s, X, Sp, N, logN, CB, tw, nullptr, nullptr);
+    hipLaunchKernelGGL(k_fft_rows<1>, dim3(N, B), dim3(rthreads), rl, s, nullptr, X, nullptr, G, N, logN, tw, 0, 0, N,
+                       nullptr);
+    return hipGetLastError();
+  }
+  // sub-pixel grid: columns forward once; per region the product transformed back, the rows of
+  // the region's band of rows, only its columns written
+  hipLaunchKernelGGL(k_fft_cols<0>, dim3(N / CB, B), dim3(cthreads), cl, s, X, nullptr, N, logN, CB, tw, nullptr, nullptr);
+  const int side = N / grid;
+  for (int r = 0; r < R; ++r) {
+    const int ry = r / grid, rx = r - ry * grid;
+    hipLaunchKernelGGL(k_fft_cols<2>, dim3(N / CB, B), dim3(cthreads), cl, s, X, Sp + (size_t)r * B * NN, N, logN, CB, tw,
+                       Y, nullptr);
+    hipLaunchKernelGGL(k_fft_rows<1>, dim3(side, B), dim3(rthreads), rl, s, nullptr, Y, nullptr, G, N, logN, tw,
+                       ry * side, rx * side, (rx + 1) * side, nullptr);
+  }
   return hipGetLastError();
 }
 

@@ -96,10 +96,39 @@ __device__ __forceinline__ void gemm_epilogue(const GemmArgs &g, int row, int co
   }
 }
 
+// The same for four consecutive columns (col a multiple of 4, 16-byte aligned rows).
 template <int EPI>
-__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) __bf16 As[2][GBM * GLDS];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][GBN * GLDS];
+__device__ __forceinline__ void gemm_epilogue4(const GemmArgs &g, int row, int col, float4 v) {
+  float *c = g.C + (size_t)row * g.ldc + col;
+  if (EPI == EPI_STORE) {
+    *reinterpret_cast<float4 *>(c) = v;
+  } else {
+    const float4 b = *reinterpret_cast<const float4 *>(g.bias + col);
+    v.x += b.x;
+    v.y += b.y;
+    v.z += b.z;
+    v.w += b.w;
+    *reinterpret_cast<float4 *>(c) = v;
+    if (EPI == EPI_BIAS_GELU) {
+      bf16x4 o;
+      o[0] = (__bf16)gelu_f(v.x);
+      o[1] = (__bf16)gelu_f(v.y);
+      o[2] = (__bf16)gelu_f(v.z);
+      o[3] = (__bf16)gelu_f(v.w);
+      *reinterpret_cast<bf16x4 *>(g.Cb + (size_t)row * g.ldcb + col) = o;
+    }
+  }
+}
+
+constexpr int GEPI_LD = 72;  // epilogue slab row stride (floats): 32 x 72 x 4 B per wave
+static_assert(4 * 32 * GEPI_LD * 4 <= 2 * (GBM + GBN) * GLDS * 2, "epilogue slabs fit in the tile buffers");
+
+template <int EPI>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_gemm(GemmArgs g) {
+  // the two A and two B tiles, and after the loop the epilogue slabs
+  __shared__ __attribute__((aligned(16))) __bf16 smem[2 * (GBM + GBN) * GLDS];
+  __bf16 (*As)[GBM * GLDS] = reinterpret_cast<__bf16 (*)[GBM * GLDS]>(smem);
+  __bf16 (*Bs)[GBN * GLDS] = reinterpret_cast<__bf16 (*)[GBN * GLDS]>(smem + 2 * GBM * GLDS);
   const int bm = blockIdx.y * GBM, bn = blockIdx.x * GBN;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
@@ -150,23 +179,58 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
     }
     __syncthreads();
   }
-  // accumulator element e of a 32 x 32 tile: row 8 (e / 4) + 4 (lane / 32) + e % 4, column lane % 32
+  // Epilogue through LDS (the A/B buffers are free after the last barrier): accumulator element e
+  // of a 32 x 32 tile sits at row 8 (e / 4) + 4 (lane / 32) + e % 4, column lane % 32, so a lane
+  // holds no two neighbours of a row.  Each wave writes its 64 x 64 sub-tile in two halves of 32
+  // rows into its own LDS slab (row stride GEPI_LD floats: the two half-waves of one store land
+  // in different banks), then reads them back four consecutive columns per lane and writes 16
+  // bytes per lane (C) or 8 bytes (BF16 outputs).
   float *part = g.part ? g.part + (size_t)blockIdx.z * g.M * g.N : nullptr;
+  float *slab = reinterpret_cast<float *>(smem) + wave * (32 * GEPI_LD);
+  const int ldo = part ? g.N : g.ldc;
+  const bool v4 = part ? (g.N % 4 == 0 && ((uintptr_t)part & 15) == 0)
+                       : (EPI != EPI_GELU_GRAD && g.ldc % 4 == 0 && ((uintptr_t)g.C & 15) == 0 &&
+                          (EPI == EPI_STORE || ((uintptr_t)g.bias & 15) == 0) &&
+                          (EPI != EPI_BIAS_GELU || (g.ldcb % 4 == 0 && ((uintptr_t)g.Cb & 7) == 0)));
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < 2; ++mi) {
 #pragma unroll
-    for (int ni = 0; ni < 2; ++ni) {
-      const int col = bn + wn + ni * 32 + (lane & 31);
+    for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int row = bm + wm + mi * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        if (row >= g.M || col >= g.N) continue;
-        if (part)
-          part[(size_t)row * g.N + col] = acc[mi][ni][e];
-        else
-          gemm_epilogue<EPI>(g, row, col, acc[mi][ni][e]);
+      for (int e = 0; e < 16; ++e)
+        slab[(8 * (e >> 2) + 4 * (lane >> 5) + (e & 3)) * GEPI_LD + ni * 32 + (lane & 31)] = acc[mi][ni][e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    // 32 rows x 16 runs of 4 columns = 512 runs, 8 per lane; 16 lanes cover one row
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+      const int idx = it * 64 + lane;
+      const int rr = idx >> 4, c4 = (idx & 15) * 4;
+      const int row = bm + wm + mi * 32 + rr, col = bn + wn + c4;
+      if (row >= g.M) continue;
+      const float4 v = *reinterpret_cast<const float4 *>(&slab[rr * GEPI_LD + c4]);
+      if (v4 && col + 4 <= g.N) {
+        if (part) {
+          *reinterpret_cast<float4 *>(&part[(size_t)row * ldo + col]) = v;
+        } else {
+          gemm_epilogue4<EPI>(g, row, col, v);
+        }
+      } else {
+        const float vv[4] = {v.x, v.y, v.z, v.w};
+        for (int q = 0; q < 4; ++q) {
+          if (col + q >= g.N) break;
+          if (part)
+            part[(size_t)row * ldo + col + q] = vv[q];
+          else
+            gemm_epilogue<EPI>(g, row, col + q, vv[q]);
+        }
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
 }
 
 // Sum of the split-K partial products in split order, then the epilogue.

@@ -53,8 +53,6 @@ int validate_sim(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, const char
   if (K > 1 && !o->psf) return fail(c, PCMD_E_INVAL, "%s: psf is NULL", who);
   if (o->psf_grid != 0 && o->psf_grid != 1 && o->psf_grid != 4)
     return fail(c, PCMD_E_INVAL, "%s: psf_grid %d must be 0, 1 or 4", who, o->psf_grid);
-  if (o->psf_grid == 4 && K > 1 && uses_fft(o))
-    return fail(c, PCMD_E_UNSUPPORTED, "%s: the 4 x 4 sub-pixel PSF grid runs on the direct path", who);
   if (o->conv_path < 0 || o->conv_path > 2) return fail(c, PCMD_E_INVAL, "%s: bad conv_path", who);
   if (o->noise_model < 0 || o->noise_model > 2) return fail(c, PCMD_E_INVAL, "%s: bad noise_model", who);
   if (o->sampler < PCMD_SAMPLER_POINT || o->sampler > PCMD_SAMPLER_HYBRID)
@@ -377,7 +375,8 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   if ((r = ensure(c, c->part, (size_t)nchunks * S * B * npx * 8, "partial sums"))) return r;
   if ((r = ensure(c, c->F, (size_t)B * npx * 4, "image"))) return r;
   if ((r = ensure(c, c->G, (size_t)B * npx * 4, "convolved image"))) return r;
-  if (K > 1 && use_fft && (r = ensure(c, c->fft, fft_scratch_bytes(B, N), "fft"))) return r;
+  const int R = psf_grid_of(o) * psf_grid_of(o);
+  if (K > 1 && use_fft && (r = ensure(c, c->fft, fft_scratch_bytes(B, N, K, R), "fft"))) return r;
 
   const uint32_t k0 = (uint32_t)(o->seed & 0xFFFFFFFFu), k1 = (uint32_t)(o->seed >> 32);
   hipError_t e = hipSuccess;
@@ -513,9 +512,17 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
     e = launch_psf_check(ca, s);
     if (e != hipSuccess) return hip_fail(c, e, "psf check");
     ScopedTimer tm(c, PCMD_TIMER_CONV, 2.0 * (double)B * (double)npx, s);
-    if (use_fft)
-      e = launch_conv_fft((const float *)c->F.p, o->psf, B, N, K, (float *)c->G.p, c->fft.p, s);
-    else
+    if (use_fft) {
+      const bool fresh = c->fft_buf != c->fft.p || c->fft_B != B || c->fft_N != N || c->fft_K != K || c->fft_R != R;
+      e = launch_conv_fft((const float *)c->F.p, o->psf, B, N, K, psf_grid_of(o), (float *)c->G.p, c->fft.p, fresh, s);
+      if (e == hipSuccess) {
+        c->fft_buf = c->fft.p;
+        c->fft_B = B;
+        c->fft_N = N;
+        c->fft_K = K;
+        c->fft_R = R;
+      }
+    } else
       e = launch_conv_direct(ca, s);
     if (e != hipSuccess) return hip_fail(c, e, "convolution");
     Gp = (const float *)c->G.p;

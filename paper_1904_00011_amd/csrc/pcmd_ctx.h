@@ -38,6 +38,10 @@ struct pcmd_ctx {
   pcmd_batch_plan *batch = nullptr;
   int tune_wg_per_cu = 4;      // persistent sampler workgroups per CU
   int tune_order = 0;          // 0 most expensive job first, 1 submission order
+  // shape whose twiddles, PSF copy and spectra the FFT scratch holds (the spectra are rebuilt on
+  // the device whenever the PSF's contents differ from the copy)
+  const void *fft_buf = nullptr;
+  int fft_B = 0, fft_N = 0, fft_K = 0, fft_R = 0;
 };
 
 namespace pcmd {

@@ -236,9 +236,10 @@ hipError_t launch_copy_f32(const float *src, float *dst, int64_t n, hipStream_t 
 
 // k_fft.hip
 int fft_supported(int N);
-size_t fft_scratch_bytes(int B, int N);
-hipError_t launch_conv_fft(const float *F, const float *psf, int B, int N, int K, float *G, void *scratch,
-                           hipStream_t s);
+size_t fft_scratch_bytes(int B, int N, int K, int R);
+// fresh: the scratch's twiddles, PSF copy and spectra are not those of this (B, N, K, grid)
+hipError_t launch_conv_fft(const float *F, const float *psf, int B, int N, int K, int grid, float *G, void *scratch,
+                           bool fresh, hipStream_t s);
 
 // k_hess.hip
 hipError_t launch_fill_u32(uint32_t *p, uint32_t v, int64_t n, hipStream_t s);

@@ -478,8 +478,7 @@ def test_multi_cmd_loglike(ctx):
 def test_subpixel_psf_grid(ctx, N):
     """The 4 x 4 grid of sub-pixel PSFs (Sec. 2.2) on the direct path: the whole pipeline against
     the oracle (N = 50: regions of 13 and 12 pixels); sixteen copies of one PSF reproduce the
-    single-PSF image bit for bit; the FFT path refuses the grid."""
-    import paper_1904_00011_amd as P
+    single-PSF image bit for bit."""
     G, lam, f32, obs = _headline_lam(3.0, seed=1008, stride=25)
     obs.nim = N
     obs.psf = si.psf_subpixel_stack(7, (1.0, 1.2, 1.4))
@@ -491,9 +490,51 @@ def test_subpixel_psf_grid(ctx, N):
     obs.psf = np.ascontiguousarray(np.repeat(one[:, None], 16, axis=1))
     b = pu.gpu_simulate(ctx, lam, f32, obs, conv_path=1)
     assert np.array_equal(a["flux_psf"], b["flux_psf"])
-    obs.nim = 64  # a power of two, so only the grid makes the FFT path refuse
-    with pytest.raises(P.PcmdError):
-        pu.gpu_simulate(ctx, lam, f32, obs, conv_path=2)
+
+
+@pytest.mark.parametrize("N,K", [(64, 7), (128, 31)])
+def test_subpixel_psf_grid_fft(ctx, N, K):
+    """The 4 x 4 sub-pixel grid on the FFT path (one forward transform, an inverse per region)
+    against the oracle's region-by-region periodic sum of the GPU's own pre-PSF image."""
+    G, lam, f32, obs = _headline_lam(3.0, seed=1009, stride=25)
+    obs.nim = N
+    obs.psf = si.psf_subpixel_stack(K, (1.0, 1.2, 1.4))
+    _print_case("subpixel_psf_fft", N=N, K=K)
+    g = pu.gpu_simulate(ctx, lam, f32, obs, conv_path=2)
+    Go = ops.convolve_periodic_subpixel(g["flux_pre"].astype(np.float64).reshape(3, N, N), obs.psf).reshape(3, N * N)
+    assert np.max(pu.rel_err(g["flux_psf"], Go)) <= pu.FLUX_RTOL
+    assert pu.mags_close(g["mags"], on.magnitudes(Go, obs)).all()
+    d = pu.gpu_simulate(ctx, lam, f32, obs, conv_path=1)
+    assert np.max(pu.rel_err(g["flux_psf"], d["flux_psf"])) <= 1e-6
+
+
+def test_fft_psf_spectra_follow_the_psf(ctx):
+    """The FFT path keeps its PSF spectra between calls: a new PSF in the same buffer, a PSF
+    in another buffer and back, and a change of image size each give the oracle's convolution."""
+    import torch
+    G, lam, f32, obs = _headline_lam(3.0, seed=1010, stride=25)
+    dev = torch.device("cuda")
+    lam_d = torch.from_numpy(lam).to(dev)
+    flux_d = torch.from_numpy(f32).to(dev)
+    pa = si.psf_stack(9, (1.0, 1.2, 1.4))
+    pb = si.psf_stack(9, (2.0, 1.5, 1.1))
+    buf = torch.from_numpy(pa).to(dev)
+    other = torch.from_numpy(pb).to(dev)
+    # (side, PSF, buffer): `buf` is first given the PSF's contents, `other` always holds pb
+    for N, psf_np, psf_d in ((64, pa, buf), (64, pa, buf), (64, pb, buf), (64, pb, other), (64, pa, buf),
+                             (128, pa, buf), (128, pa, buf)):
+        if psf_d is buf:
+            buf.copy_(torch.from_numpy(psf_np))
+        o = dataclasses.replace(obs, nim=N, psf=psf_np)
+        mags = torch.empty((3, N * N), dtype=torch.float32, device=dev)
+        pre = torch.empty_like(mags)
+        post = torch.empty_like(mags)
+        ctx.simulate(lam_d, flux_d, o, mags, psf=psf_d, conv_path=2, flux_pre=pre, flux_psf=post)
+        ctx.sync()
+        Fo = pre.cpu().numpy().astype(np.float64).reshape(3, N, N)
+        Go = ops.convolve_periodic(Fo, psf_np).reshape(3, N * N)
+        _print_case("fft_psf_cache", N=N)
+        assert np.max(pu.rel_err(post.cpu().numpy(), Go)) <= pu.FLUX_RTOL
 
 
 def test_evaluator_writes_into_a_result_slot(ctx):
