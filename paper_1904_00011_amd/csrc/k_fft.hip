@@ -2,9 +2,10 @@
 //
 // G_b = IFFT2( FFT2(F_b) * FFT2(P~_b) ) / N^2, where P~_b is the K x K PSF wrapped onto the N x N
 // torus with its centre at the origin; this is the same periodic convolution as the direct sum
-// (Sec. 2.1 of the paper convolves each band with its PSF).  Transforms are radix-2 in LDS,
-// one row (or a few columns) per workgroup, in FP64 complex arithmetic (full rate on MI355X),
-// so the result agrees with the direct sum to ~1e-15 relative to the image's RMS.
+// (Sec. 2.1 of the paper convolves each band with its PSF).  Transforms run in LDS, two
+// radix-2 stages per pass, one row (or a few columns) per workgroup, in FP64 complex arithmetic
+// (full rate on MI355X), so the result agrees with the direct sum to ~1e-15 relative to the
+// image's RMS.
 //
 // The PSF spectra and twiddles are kept between calls: a one-workgroup kernel compares the
 // caller's PSF with the copy the spectra were built from (and takes the new one), and the
@@ -71,24 +72,52 @@ __global__ void k_twiddles(cplx *tw, int N) {
   }
 }
 
-// In-LDS radix-2 decimation-in-time transform of n = 2^logn points stored at a[0], a[stride],
-// ... (input already in bit-reversed order).  inv = conjugate twiddles.
-__device__ __forceinline__ void fft_stages(cplx *a, int stride, int logn, int N, const cplx *__restrict__ tw, bool inv,
-                                           int tid, int nthr) {
+// In-LDS decimation-in-time transform of n = 2^logn points a[0], a[1], ... (input already in
+// bit-reversed order), by threads t = 0 .. per-1 of the block (active ones; every thread of the
+// block reaches the barriers).  inv = conjugate twiddles.  Stages go two at a time (radix 2^2):
+// from blocks of length L, one thread takes x0..x3 = a[base + {0, L, 2L, 3L}] and applies both
+// radix-2 stages, y0,1 = x0 +- w1 x1, y2,3 = x2 +- w1 x3 (w1 = W_2L^pos), then
+// a[base], a[base + 2L] = y0 +- w2 y2 and a[base + L], a[base + 3L] = y1 -+ i w2 y3 (w2 = W_4L^pos;
+// +i for the inverse), so each element goes through LDS once per two stages and there is one
+// barrier per two stages.  An odd logn starts with one radix-2 stage.
+__device__ __forceinline__ void fft_stages(cplx *a, int logn, int N, const cplx *__restrict__ tw, bool inv, int t,
+                                           int per, bool active) {
   const int n = 1 << logn;
-  for (int s = 1; s <= logn; ++s) {
-    const int len = 1 << s, half = len >> 1;
-    const int tstep = N >> s;  // twiddle index step: exp(-2 pi i pos / len) = tw[pos * N / len]
-    for (int k = tid; k < n / 2; k += nthr) {
-      const int grp = k >> (s - 1), pos = k & (half - 1);
-      const int i = grp * len + pos, j = i + half;
-      cplx w = tw[pos * tstep];
-      if (inv) w.y = -w.y;
-      const cplx u = a[i * stride];
-      const cplx v = cmul(w, a[j * stride]);
-      a[i * stride] = cplx{u.x + v.x, u.y + v.y};
-      a[j * stride] = cplx{u.x - v.x, u.y - v.y};
-    }
+  int s = 1;
+  if (logn & 1) {
+    if (active)
+      for (int k = t; k < n / 2; k += per) {
+        const int i = 2 * k;
+        const cplx u = a[i], v = a[i + 1];  // first stage: twiddle 1
+        a[i] = cplx{u.x + v.x, u.y + v.y};
+        a[i + 1] = cplx{u.x - v.x, u.y - v.y};
+      }
+    __syncthreads();
+    s = 2;
+  }
+  for (; s < logn; s += 2) {
+    const int L = 1 << (s - 1);
+    const int ts1 = N >> s, ts2 = N >> (s + 1);  // W_2L^pos = tw[pos N / 2L], W_4L^pos = tw[pos N / 4L]
+    if (active)
+      for (int k = t; k < n / 4; k += per) {
+        const int pos = k & (L - 1);
+        const int base = (k >> (s - 1)) * 4 * L + pos;
+        cplx w1 = tw[pos * ts1], w2 = tw[pos * ts2];
+        if (inv) {
+          w1.y = -w1.y;
+          w2.y = -w2.y;
+        }
+        const cplx x0 = a[base], x1 = a[base + L], x2 = a[base + 2 * L], x3 = a[base + 3 * L];
+        const cplx t1 = cmul(w1, x1), t3 = cmul(w1, x3);
+        const cplx y0{x0.x + t1.x, x0.y + t1.y}, y1{x0.x - t1.x, x0.y - t1.y};
+        const cplx y2{x2.x + t3.x, x2.y + t3.y}, y3{x2.x - t3.x, x2.y - t3.y};
+        const cplx u2 = cmul(w2, y2), u3 = cmul(w2, y3);
+        const cplx v3 = inv ? cplx{-u3.y, u3.x} : cplx{u3.y, -u3.x};  // (+i or -i) u3
+        a[base] = cplx{y0.x + u2.x, y0.y + u2.y};
+        a[base + 2 * L] = cplx{y0.x - u2.x, y0.y - u2.y};
+        a[base + L] = cplx{y1.x + v3.x, y1.y + v3.y};
+        a[base + 3 * L] = cplx{y1.x - v3.x, y1.y - v3.y};
+      }
     __syncthreads();
   }
 }
@@ -116,7 +145,7 @@ __global__ void __launch_bounds__(256) k_fft_rows(const float *__restrict__ rin,
       row[i] = cin[base + r];
   }
   __syncthreads();
-  fft_stages(row, 1, logN, N, tw, MODE == 1, threadIdx.x, blockDim.x);
+  fft_stages(row, logN, N, tw, MODE == 1, threadIdx.x, blockDim.x, true);
   const double scale = 1.0 / ((double)N * (double)N);
   if (MODE == 0) {
     for (int i = threadIdx.x; i < N; i += blockDim.x) cout[base + i] = row[i];
@@ -144,51 +173,30 @@ __global__ void __launch_bounds__(256) k_fft_cols(cplx *__restrict__ X, const cp
   // each column's transform is done by blockDim / CB threads
   const int per = blockDim.x / CB;
   const int c = threadIdx.x / per, t = threadIdx.x - c * per;
-  for (int s = 1; s <= (MODE == 2 ? 0 : logN); ++s) {
-    const int len = 1 << s, half = len >> 1, tstep = N >> s;
-    if (c < CB) {
-      cplx *a = col + c * N;
-      for (int k = t; k < N / 2; k += per) {
-        const int grp = k >> (s - 1), pos = k & (half - 1);
-        const int i = grp * len + pos, j = i + half;
-        const cplx w = tw[pos * tstep];
-        const cplx u = a[i], v = cmul(w, a[j]);
-        a[i] = cplx{u.x + v.x, u.y + v.y};
-        a[j] = cplx{u.x - v.x, u.y - v.y};
-      }
-    }
-    __syncthreads();
-  }
+  if (MODE != 2) fft_stages(col + (c < CB ? c : 0) * N, logN, N, tw, false, t, per, c < CB);
   if (MODE >= 1) {
-    // multiply by the PSF spectrum, then bit-reverse into a second buffer half for the inverse
+    // multiply by the PSF spectrum in place, bit-reverse in place (the thread of the smaller
+    // index of each pair swaps it), then the inverse transform
     for (int idx = threadIdx.x; idx < N * CB; idx += blockDim.x) {
       const int cc = idx / N, y = idx - cc * N;
-      const cplx v = cmul(col[cc * N + y], S[base + (size_t)y * N + x0 + cc]);
-      col[(CB + cc) * N + bitrev(y, logN)] = v;
+      col[cc * N + y] = cmul(col[cc * N + y], S[base + (size_t)y * N + x0 + cc]);
     }
     __syncthreads();
-    for (int s = 1; s <= logN; ++s) {
-      const int len = 1 << s, half = len >> 1, tstep = N >> s;
-      if (c < CB) {
-        cplx *a = col + (CB + c) * N;
-        for (int k = t; k < N / 2; k += per) {
-          const int grp = k >> (s - 1), pos = k & (half - 1);
-          const int i = grp * len + pos, j = i + half;
-          cplx w = tw[pos * tstep];
-          w.y = -w.y;
-          const cplx u = a[i], v = cmul(w, a[j]);
-          a[i] = cplx{u.x + v.x, u.y + v.y};
-          a[j] = cplx{u.x - v.x, u.y - v.y};
-        }
+    for (int idx = threadIdx.x; idx < N * CB; idx += blockDim.x) {
+      const int cc = idx / N, y = idx - cc * N, r = bitrev(y, logN);
+      if (y < r) {
+        const cplx u = col[cc * N + y];
+        col[cc * N + y] = col[cc * N + r];
+        col[cc * N + r] = u;
       }
-      __syncthreads();
     }
+    __syncthreads();
+    fft_stages(col + (c < CB ? c : 0) * N, logN, N, tw, true, t, per, c < CB);
   }
-  const int off = MODE >= 1 ? CB : 0;
   cplx *out = MODE == 2 ? Y : X;
   for (int idx = threadIdx.x; idx < N * CB; idx += blockDim.x) {
     const int y = idx / CB, cc = idx - y * CB;
-    out[base + (size_t)y * N + x0 + cc] = col[(off + cc) * N + y];
+    out[base + (size_t)y * N + x0 + cc] = col[cc * N + y];
   }
 }
 
@@ -211,7 +219,7 @@ __global__ void k_psf_wrap(const float *__restrict__ psf, int K, int N, float *_
 
 static int cols_per_block(int N) {
   int cb = 8;
-  while (cb > 1 && (size_t)2 * cb * N * sizeof(cplx) > 160 * 1024) cb >>= 1;
+  while (cb > 1 && (size_t)cb * N * sizeof(cplx) > 160 * 1024) cb >>= 1;
   return cb;
 }
 
@@ -228,10 +236,10 @@ hipError_t launch_conv_fft(const float *F, const float *psf, int B, int N, int K
   float *copy = (float *)((char *)scratch + fft_psf_copy_offset(B, N, R));
   uint32_t *flag = (uint32_t *)(copy + (size_t)R * B * K * K);
   const int CB = cols_per_block(N);
-  if ((size_t)2 * CB * N * sizeof(cplx) > 160 * 1024) return hipErrorInvalidValue;
+  if ((size_t)CB * N * sizeof(cplx) > 160 * 1024) return hipErrorInvalidValue;
   const int rthreads = N / 2 < 256 ? N / 2 : 256;
   const int cthreads = 256;
-  const size_t rl = N * sizeof(cplx), cl = 2 * CB * N * sizeof(cplx);
+  const size_t rl = N * sizeof(cplx), cl = CB * N * sizeof(cplx);
   if (fresh) hipLaunchKernelGGL(k_twiddles, dim3((N / 2 + 255) / 256), dim3(256), 0, s, tw, N);
   // PSF spectra, rebuilt only when the PSF (or the layout: fresh) changed.  psf is
   // [B][K][K] (grid 1) or [B][16][K][K]: region r of band b at psf + (b R + r) K K.
