@@ -20,7 +20,9 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 
 // ---------------------------------------------------------------------------------------
 // C[M][N] = sum_k A[m][k] B[n][k] on v_mfma_f32_32x32x16_bf16 (both operands K-contiguous).
-// 128 x 128 block tile, 4 waves of 64 x 64 (2 x 2 MFMA tiles of 32 x 32), K step 32 staged in
+// (64 MI) x 128 block tile, 4 waves of (32 MI) x 64 (MI x 2 MFMA tiles of 32 x 32): MI = 2 for
+// most products, MI = 4 for large ones, where a wave's larger share of A halves the LDS reads per
+// multiply-add of B.  K step 32 staged in
 // LDS as [row][k] (row stride 40 halves = 80 bytes, so every 8-element run is 16-byte aligned).
 // Two LDS buffers: the next K step's global loads are issued into registers before the MFMAs of
 // the current one and written to the other buffer after them, one barrier per K step.  An
@@ -28,18 +30,19 @@ __device__ __forceinline__ float gelu_grad_f(float z) {
 // k_transpose_bf16, so that every product runs this one layout with 16-byte loads and stores.
 // ---------------------------------------------------------------------------------------
 constexpr int GBM = 128, GBN = 128, GBK = 32, GLDS = GBK + 8;
-constexpr int GRUNS = GBM * GBK / (256 * 8);  // 8-element runs per thread and operand
 
-// One thread's share of a GBM x GBK operand tile: GRUNS runs of 8 elements.
+// One thread's share of a (rows) x GBK operand tile: RUNS = rows GBK / (256 8) runs of 8 elements.
+template <int RUNS>
 struct TileRegs {
-  bf16x8 v[GRUNS];
+  bf16x8 v[RUNS];
 };
 
 // rows x K row-major: run idx takes row idx / (GBK / 8), k run idx mod (GBK / 8)
-__device__ __forceinline__ void load_regs(TileRegs &t, const __bf16 *__restrict__ src, int ld, int rows, int K,
+template <int RUNS>
+__device__ __forceinline__ void load_regs(TileRegs<RUNS> &t, const __bf16 *__restrict__ src, int ld, int rows, int K,
                                           int r0, int k0, bool vec_ok) {
 #pragma unroll
-  for (int it = 0; it < GRUNS; ++it) {
+  for (int it = 0; it < RUNS; ++it) {
     const int idx = threadIdx.x + 256 * it;
     const int gr = r0 + idx / (GBK / 8), gk = k0 + (idx % (GBK / 8)) * 8;
     if (vec_ok && gr < rows && gk + 8 <= K) {
@@ -51,9 +54,10 @@ __device__ __forceinline__ void load_regs(TileRegs &t, const __bf16 *__restrict_
   }
 }
 
-__device__ __forceinline__ void store_lds(__bf16 *lds, const TileRegs &t) {
+template <int RUNS>
+__device__ __forceinline__ void store_lds(__bf16 *lds, const TileRegs<RUNS> &t) {
 #pragma unroll
-  for (int it = 0; it < GRUNS; ++it) {
+  for (int it = 0; it < RUNS; ++it) {
     const int idx = threadIdx.x + 256 * it;
     *reinterpret_cast<bf16x8 *>(lds + (idx / (GBK / 8)) * GLDS + (idx % (GBK / 8)) * 8) = t.v[it];
   }
@@ -123,20 +127,23 @@ __device__ __forceinline__ void gemm_epilogue4(const GemmArgs &g, int row, int c
 constexpr int GEPI_LD = 72;  // epilogue slab row stride (floats): 32 x 72 x 4 B per wave
 static_assert(4 * 32 * GEPI_LD * 4 <= 2 * (GBM + GBN) * GLDS * 2, "epilogue slabs fit in the tile buffers");
 
-template <int EPI>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) k_gemm(GemmArgs g) {
+// MI = 2: 64 VGPRs of accumulators, compiled for four waves per SIMD; MI = 4: 128, two waves.
+template <int EPI, int MI>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MI == 2 ? 4 : 2, 8))) k_gemm(GemmArgs g) {
+  constexpr int BM = 64 * MI;                          // block tile rows
+  constexpr int RA = BM * GBK / (256 * 8), RB = GBN * GBK / (256 * 8);
   // the two A and two B tiles, and after the loop the epilogue slabs
-  __shared__ __attribute__((aligned(16))) __bf16 smem[2 * (GBM + GBN) * GLDS];
-  __bf16 (*As)[GBM * GLDS] = reinterpret_cast<__bf16 (*)[GBM * GLDS]>(smem);
-  __bf16 (*Bs)[GBN * GLDS] = reinterpret_cast<__bf16 (*)[GBN * GLDS]>(smem + 2 * GBM * GLDS);
-  const int bm = blockIdx.y * GBM, bn = blockIdx.x * GBN;
+  __shared__ __attribute__((aligned(16))) __bf16 smem[2 * (BM + GBN) * GLDS];
+  __bf16 (*As)[BM * GLDS] = reinterpret_cast<__bf16 (*)[BM * GLDS]>(smem);
+  __bf16 (*Bs)[GBN * GLDS] = reinterpret_cast<__bf16 (*)[GBN * GLDS]>(smem + 2 * BM * GLDS);
+  const int bm = blockIdx.y * BM, bn = blockIdx.x * GBN;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  const int wm = (wave >> 1) * 32 * MI, wn = (wave & 1) * 64;
   const bool va = (g.lda % 8 == 0) && (((uintptr_t)g.A & 15) == 0);
   const bool vb = (g.ldb % 8 == 0) && (((uintptr_t)g.B & 15) == 0);
-  f32x16 acc[2][2];
+  f32x16 acc[MI][2];
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi)
+  for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
@@ -146,7 +153,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
   const int kb = g.part ? (int)blockIdx.z * g.kchunk : 0;
   const int ke = g.part ? min(g.K, kb + g.kchunk) : g.K;
   const int nk = (ke - kb + GBK - 1) / GBK;
-  TileRegs ra, rb;
+  TileRegs<RA> ra;
+  TileRegs<RB> rb;
   load_regs(ra, g.A, g.lda, g.M, ke, bm, kb, va);
   load_regs(rb, g.B, g.ldb, g.N, ke, bn, kb, vb);
   store_lds(As[0], ra);
@@ -163,13 +171,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
     const __bf16 *bs = Bs[cur];
 #pragma unroll
     for (int ks = 0; ks < GBK; ks += 16) {
-      bf16x8 a[2], b[2];
+      bf16x8 a[MI], b[2];
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi) a[mi] = *reinterpret_cast<const bf16x8 *>(&as[(wm + mi * 32 + r) * GLDS + ks + kh]);
+      for (int mi = 0; mi < MI; ++mi) a[mi] = *reinterpret_cast<const bf16x8 *>(&as[(wm + mi * 32 + r) * GLDS + ks + kh]);
 #pragma unroll
       for (int ni = 0; ni < 2; ++ni) b[ni] = *reinterpret_cast<const bf16x8 *>(&bs[(wn + ni * 32 + r) * GLDS + ks + kh]);
 #pragma unroll
-      for (int mi = 0; mi < 2; ++mi)
+      for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 2; ++ni) acc[mi][ni] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mi], b[ni], acc[mi][ni], 0, 0, 0);
     }
@@ -181,7 +189,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
   }
   // Epilogue through LDS (the A/B buffers are free after the last barrier): accumulator element e
   // of a 32 x 32 tile sits at row 8 (e / 4) + 4 (lane / 32) + e % 4, column lane % 32, so a lane
-  // holds no two neighbours of a row.  Each wave writes its 64 x 64 sub-tile in two halves of 32
+  // holds no two neighbours of a row.  Each wave writes its (32 MI) x 64 sub-tile in MI parts of 32
   // rows into its own LDS slab (row stride GEPI_LD floats: the two half-waves of one store land
   // in different banks), then reads them back four consecutive columns per lane and writes 16
   // bytes per lane (C) or 8 bytes (BF16 outputs).
@@ -193,7 +201,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))
                           (EPI == EPI_STORE || ((uintptr_t)g.bias & 15) == 0) &&
                           (EPI != EPI_BIAS_GELU || (g.ldcb % 4 == 0 && ((uintptr_t)g.Cb & 7) == 0)));
 #pragma unroll
-  for (int mi = 0; mi < 2; ++mi) {
+  for (int mi = 0; mi < MI; ++mi) {
 #pragma unroll
     for (int ni = 0; ni < 2; ++ni)
 #pragma unroll
@@ -304,11 +312,16 @@ hipError_t launch_gemm(const GemmArgs &g0, bool at, bool bt, int epi, void *ws, 
   const bool split = splits > 1;
   g.part = split ? (float *)w : nullptr;
   g.kchunk = split ? kchunk : g.K;
-  dim3 grid((g.N + GBN - 1) / GBN, (g.M + GBM - 1) / GBM, split ? splits : 1);
+  // 256-row block tiles where the product is large enough to keep every CU busy with them
+  const bool tall = !split && g.M >= 4096 && g.N >= 2048;
+  dim3 grid((g.N + GBN - 1) / GBN, (g.M + (tall ? 2 * GBM : GBM) - 1) / (tall ? 2 * GBM : GBM), split ? splits : 1);
   const unsigned rblocks = (unsigned)(((int64_t)g.M * g.N + 255) / 256);
 #define PCMD_GEMM_CASE(E_)                                                                             \
   if (epi == E_) {                                                                                     \
-    hipLaunchKernelGGL((k_gemm<E_>), grid, dim3(256), 0, s, g);                                        \
+    if (tall)                                                                                          \
+      hipLaunchKernelGGL((k_gemm<E_, 4>), grid, dim3(256), 0, s, g);                                   \
+    else                                                                                               \
+      hipLaunchKernelGGL((k_gemm<E_, 2>), grid, dim3(256), 0, s, g);                                   \
     if (split) hipLaunchKernelGGL((k_gemm_splitk_reduce<E_>), dim3(rblocks), dim3(256), 0, s, g, splits); \
     return hipGetLastError();                                                                          \
   }

@@ -5,9 +5,10 @@
 // isochrone point, the stars' fluxes are reddened by dust, dimmed by the distance modulus and
 // summed into the pixel.  One lane owns one pixel; the entry table is wave-uniform, so it is
 // read through the scalar cache.  A wave handles 64 pixels x one chunk of CHUNK entries and
-// keeps the per-band sums in FP64 registers; chunk partials are written once and combined in
-// ascending chunk order by the reduction kernel, which fixes the summation order independently
-// of the launch shape.
+// keeps the per-band sums in FP64 registers; chunk partials are written once, rounded to FP32
+// (a relative error of at most 2^-24 per partial, and the partials are non-negative, so the
+// pixel sum keeps that bound), and combined in FP64 in ascending chunk order by the reduction
+// kernel, which fixes the summation order independently of the launch shape.
 #include <math.h>
 
 #include "pcmd_device.h"
@@ -515,14 +516,14 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
   const size_t plane = (size_t)a.npx;
 #pragma unroll
   for (int b = 0; b < B; ++b) {
-    double *pc = a.part + ((size_t)(chunk * S + 0) * B + b) * plane + p;
-    double *pr = a.part + ((size_t)(chunk * S + 1) * B + b) * plane + p;
+    float *pc = a.part + ((size_t)(chunk * S + 0) * B + b) * plane + p;
+    float *pr = a.part + ((size_t)(chunk * S + 1) * B + b) * plane + p;
     if (PASS == PASS_THIN) {  // exact zeros change nothing: a slice without thinned stars skips
-      if (acc_c[b] != 0.0) *pc = *pc + acc_c[b];
-      if (S == 2 && acc_r[b] != 0.0) *pr = *pr + acc_r[b];
+      if (acc_c[b] != 0.0) *pc = (float)((double)*pc + acc_c[b]);
+      if (S == 2 && acc_r[b] != 0.0) *pr = (float)((double)*pr + acc_r[b]);
     } else {
-      *pc = acc_c[b];
-      if (S == 2) *pr = acc_r[b];
+      *pc = (float)acc_c[b];
+      if (S == 2) *pr = (float)acc_r[b];
     }
   }
 }
@@ -675,16 +676,16 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs &a, int idx) {
   const int b = idx / npx, p = idx - b * npx;
   const size_t plane = (size_t)npx;
   const size_t step = (size_t)a.S * a.B * plane;  // from one slice to the next
-  const double *pc = a.part + (size_t)b * plane + p;
-  const double *pr = pc + (size_t)a.B * plane;  // reddened stream (S == 2)
+  const float *pc = a.part + (size_t)b * plane + p;
+  const float *pr = pc + (size_t)a.B * plane;  // reddened stream (S == 2)
   double c = 0.0, r = 0.0;
   int ch = 0;
   for (; ch + RED_BATCH <= a.nchunks; ch += RED_BATCH) {
     double xc[RED_BATCH], xr[RED_BATCH];
 #pragma unroll
     for (int k = 0; k < RED_BATCH; ++k) {
-      xc[k] = pc[(size_t)(ch + k) * step];
-      xr[k] = a.S == 2 ? pr[(size_t)(ch + k) * step] : 0.0;
+      xc[k] = (double)pc[(size_t)(ch + k) * step];
+      xr[k] = a.S == 2 ? (double)pr[(size_t)(ch + k) * step] : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < RED_BATCH; ++k) {
@@ -693,8 +694,8 @@ __device__ __forceinline__ void reduce_body(const ReduceArgs &a, int idx) {
     }
   }
   for (; ch < a.nchunks; ++ch) {
-    c += pc[(size_t)ch * step];
-    if (a.S == 2) r += pr[(size_t)ch * step];
+    c += (double)pc[(size_t)ch * step];
+    if (a.S == 2) r += (double)pr[(size_t)ch * step];
   }
   double F;
   if (a.dust_model == PCMD_DUST_NONE) {

@@ -192,11 +192,11 @@ __device__ __forceinline__ void sample_block_body(const BlockSampleArgs &a) {
   const size_t plane = (size_t)a.npx;
 #pragma unroll
   for (int k = 0; k < B; ++k) {
-    double *pc = a.part + ((size_t)(chunk * S + 0) * B + k) * plane + p;
-    *pc = a.accumulate ? *pc + acc_c[k] : acc_c[k];
+    float *pc = a.part + ((size_t)(chunk * S + 0) * B + k) * plane + p;
+    *pc = (float)(a.accumulate ? (double)*pc + acc_c[k] : acc_c[k]);
     if (S == 2) {
-      double *pr = a.part + ((size_t)(chunk * S + 1) * B + k) * plane + p;
-      *pr = a.accumulate ? *pr + acc_r[k] : acc_r[k];
+      float *pr = a.part + ((size_t)(chunk * S + 1) * B + k) * plane + p;
+      *pr = (float)(a.accumulate ? (double)*pr + acc_r[k] : acc_r[k]);
     }
   }
 }

@@ -372,7 +372,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
     if ((r = ensure(c, c->rdesc, (size_t)E * 4, "reddened-part descriptors"))) return r;
   }
   if ((r = ensure(c, c->fl64, (size_t)E * BP * 8, "fluxes"))) return r;
-  if ((r = ensure(c, c->part, (size_t)nchunks * S * B * npx * 8, "partial sums"))) return r;
+  if ((r = ensure(c, c->part, (size_t)nchunks * S * B * npx * 4, "partial sums"))) return r;
   if ((r = ensure(c, c->F, (size_t)B * npx * 4, "image"))) return r;
   if ((r = ensure(c, c->G, (size_t)B * npx * 4, "convolved image"))) return r;
   const int R = psf_grid_of(o) * psf_grid_of(o);
@@ -423,7 +423,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
     ab.pc = pb.pc;
     ab.cth = pb.cth;
     ab.fl64 = pb.fl64;
-    ab.part = (double *)c->part.p;
+    ab.part = (float *)c->part.p;
     ab.dbg_counts = dbg ? dbg->counts : nullptr;
     ab.dbg_red = dbg ? dbg->reddened : nullptr;
     ab.px0 = px0;
@@ -471,7 +471,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
     a.thr = pa.thr;
     a.pc = pa.pc;
     a.fl64 = pa.fl64;
-    a.part = (double *)c->part.p;
+    a.part = (float *)c->part.p;
     a.dbg_counts = dbg ? dbg->counts : nullptr;
     a.dbg_red = dbg ? dbg->reddened : nullptr;
     a.px0 = px0;
@@ -491,7 +491,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   ra.npx = (int)npx;
   ra.nchunks = nchunks;
   ra.S = S;
-  ra.part = (const double *)c->part.p;
+  ra.part = (const float *)c->part.p;
   ra.F = (float *)c->F.p;
   ra.dist = pow(10.0, -0.4 * o->dmod);
   ra.dust_model = o->dust_model;

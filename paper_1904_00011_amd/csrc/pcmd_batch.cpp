@@ -186,7 +186,7 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
   if ((r = ensure(c, p->rdesc, n_rdesc * 4, "batch reddened-part descriptors"))) return r;
   if (n_blk && (r = ensure(c, p->blk, n_blk, "batch block tables"))) return r;
   if ((r = ensure(c, p->fl, n_fl * 8, "batch fluxes"))) return r;
-  if ((r = ensure(c, p->part, n_part * 8, "batch partial sums"))) return r;
+  if ((r = ensure(c, p->part, n_part * 4, "batch partial sums"))) return r;
   if ((r = ensure(c, p->F, n_img * 4, "batch images"))) return r;
   if ((r = ensure(c, p->G, n_img * 4, "batch convolved images"))) return r;
   if ((r = ensure(c, p->mags, n_img * 4, "batch magnitudes"))) return r;
@@ -257,7 +257,7 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
     uint32_t *thr = (uint32_t *)p->thr.p + ji.o_thr;
     PtrsConst *pc = (PtrsConst *)p->pc.p + ji.o_pc;
     double *fl = (double *)p->fl.p + ji.o_fl;
-    double *part = (double *)p->part.p + ji.o_part;
+    float *part = (float *)p->part.p + ji.o_part;
     float *F = (float *)p->F.p + ji.o_img;
     float *G = (float *)p->G.p + ji.o_img;
     float *mags = (float *)p->mags.p + ji.o_img;
@@ -401,7 +401,7 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
     s.thr = (uint32_t *)p->thr.p + ji.o_thr;
     s.pc = (PtrsConst *)p->pc.p + ji.o_pc;
     s.fl64 = (double *)p->fl.p + ji.o_fl;
-    s.part = (double *)p->part.p + ji.o_part;
+    s.part = (float *)p->part.p + ji.o_part;
     s.status = c->status;
     s.lnfact = c->lnfact;
     s.alias = (const uint32_t *)p->alias.p + ji.o_alias;

@@ -86,7 +86,7 @@ struct SampleArgs {
   const uint32_t *thr;  // [THR_STRIDE][EP], k-major as in PrepArgs
   const void *pc;
   const double *fl64;
-  double *part;  // [nchunks][S][B][npx]
+  float *part;  // [nchunks][S][B][npx] slice partial sums (FP64 in registers, stored FP32)
   uint32_t *dbg_counts, *dbg_red;
   int64_t px0, px1;
   uint32_t *status;
@@ -130,7 +130,7 @@ struct BlockSampleArgs {
   const void *pc;
   const uint32_t *cth;
   const double *fl64;
-  double *part;  // [nchunks][S][B][npx], as SampleArgs
+  float *part;  // [nchunks][S][B][npx], as SampleArgs
   uint32_t *dbg_counts, *dbg_red;
   int64_t px0, px1;
   uint32_t *status;
@@ -141,7 +141,7 @@ struct BlockSampleArgs {
 // Chunk reduction and dust / distance epilogue (k_reduce).
 struct ReduceArgs {
   int B, npx, nchunks, S;
-  const double *part;
+  const float *part;
   float *F;  // [B][npx]
   double dist;
   int dust_model;

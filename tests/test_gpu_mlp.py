@@ -273,3 +273,40 @@ def test_configured_network_against_oracle(ctx):
         assert err <= 1e-2
         assert np.corrcoef(gl, ol_)[0, 1] > 0.9999
         o += k
+
+
+@pytest.mark.parametrize("M,N,K", [(4500, 2100, 100), (4096, 10000, 512)])
+def test_gemm_tall_tiles_against_fp64(ctx, M, N, K):
+    """Products large enough for the 256-row block tiles (ragged in M and N for the first):
+    sampled rows against FP64."""
+    import torch
+    r = np.random.default_rng(M + N + K)
+    A = om.bf16_round(r.normal(size=(M, K)).astype(np.float32)).astype(np.float64)
+    B = om.bf16_round(r.normal(size=(N, K)).astype(np.float32)).astype(np.float64)
+    Cd = torch.full((M, N), float("nan"), dtype=torch.float32, device=torch.device("cuda"))
+    print(f"[case] gemm tall M={M} N={N} K={K}", flush=True)
+    ctx.gemm_bf16(_bf16_tensor(A), _bf16_tensor(B), Cd)
+    ctx.sync()
+    rows = np.unique(np.concatenate([r.integers(0, M, 200), [0, 255, 256, M - 1]]))
+    got = Cd.cpu().numpy()[rows].astype(np.float64)
+    ref = A[rows] @ B.T
+    assert np.all(np.isfinite(got))
+    assert np.max(np.abs(got - ref)) <= 1e-5 * np.sqrt(K) + 1e-6
+
+
+def test_configured_network_forward_at_a_large_batch(ctx):
+    """The configured network's forward pass at a batch of 4,100 (its 10,000-wide output layer on
+    the 256-row tiles, ragged last tile): sampled rows against the oracle network."""
+    import torch
+    dims = (12, 512, 512, 512, 512, 10000)
+    net, master = _net(ctx, dims, 31)
+    r = np.random.default_rng(32)
+    x = r.uniform(-1, 1, (4100, 12)).astype(np.float32)
+    y = net.forward(torch.from_numpy(x).cuda())
+    ctx.sync()
+    rows = np.unique(np.concatenate([r.integers(0, 4100, 48), [0, 4095, 4096, 4099]]))
+    yo, _ = om.forward(master.astype(np.float32).astype(np.float64), dims, x[rows])
+    got = y.cpu().numpy()[rows]
+    err = np.max(np.abs(got - yo)) / np.max(np.abs(yo))
+    print(f"[case] configured network forward at 4100: rel err {err:.2e}", flush=True)
+    assert err <= 2e-3
