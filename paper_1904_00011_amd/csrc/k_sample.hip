@@ -49,12 +49,12 @@ hipError_t launch_entries(const pcmd_grid *g, const double *scale, double *lam, 
 // ---------------------------------------------------------------------------------------
 // Per-entry tables: inversion thresholds (lambda < ALIAS_MIN), an alias marker (the columns come
 // from k_prep_alias) or rejection constants (lambda >= ALIAS_MAX)
-// and FP64 star fluxes laid out [E][BP] for scalar loads.
+// and the FP64 star fluxes, in each entry's record.
 // ---------------------------------------------------------------------------------------
 __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
   // every lane of the block takes part in the group summary below (no early return)
-  const int E = a.E, B = a.B, BP = a.BP;
-  EntryRec r{{0u, 0u, 0u}, KIND_ZERO};
+  const int E = a.E, B = a.B;
+  EntryRec r{{0u, 0u, 0u}, KIND_ZERO, {0.0, 0.0, 0.0, 0.0}};
   if (i < E) {
     // every load before the first store (the output could alias the inputs for the compiler,
     // which otherwise waits for each load in turn)
@@ -66,7 +66,8 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
     }
     double l = a.lam[i];
     const bool block_rule = a.brec && a.brec[i / SBLK].pad[0] == 0u;  // hybrid: the block rule draws it
-    for (int b = 0; b < BP; ++b) a.fl64[(size_t)i * BP + b] = fv[b];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) r.fl[b] = fv[b];
     if (!(l >= 0.0 && l < 4194304.0)) {  // NaN, negative or too large: drawn as zero, reported
       atomicOr(a.status, STATUS_BAD_LAMBDA);
       l = 0.0;
@@ -357,11 +358,9 @@ __device__ __forceinline__ uint32_t table_draw(uint32_t desc, uint32_t u, const 
 // thinning code (live state that slows the common path) is not in the main pass.
 template <int B, int S, bool DBG, int PASS>
 __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int chunk) {
-  constexpr int BP = B <= 2 ? 2 : 4;
   const PCMD_CONST EntryRec *rec = (const PCMD_CONST EntryRec *)a.rec;
   const PCMD_CONST uint32_t *thr = (const PCMD_CONST uint32_t *)a.thr;
   const PCMD_CONST PtrsConst *pc = (const PCMD_CONST PtrsConst *)a.pc;
-  const PCMD_CONST double *fl64 = (const PCMD_CONST double *)a.fl64;
   const PCMD_CONST uint32_t *rdesc = (const PCMD_CONST uint32_t *)a.rdesc;
   const bool live = p < (uint32_t)a.npx;
   const bool dbg = DBG && live && (int64_t)p >= a.px0 && (int64_t)p < a.px1;
@@ -397,7 +396,8 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
     const uint32_t want = PASS == PASS_ALL ? 0xFFu : PASS == PASS_MAIN ? (GRP_INV | GRP_PTRS | GRP_ALIAS) : GRP_THIN;
     for (uint64_t pend = __ballot((fl & want) != 0u); pend != 0ull; pend &= pend - 1ull) {
       const int lsel = (int)__builtin_ctzll(pend);  // wave-uniform
-      const int gi = slice_group(jb + lsel);
+      // slice_group(jb + lsel), read from lane lsel: one vector instruction instead of seven scalar
+      const int gi = __builtin_amdgcn_readlane(gl, lsel);
       const int g0 = gi * GRP;
       const PCMD_CONST GroupRec *gr = grp + gi;
       // at small lambda most groups end after two Philox blocks and eight compares, without
@@ -434,7 +434,7 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
         for (int q = 0; q < 4; ++q) {
           const uint32_t i = (uint32_t)(q0 + q);
           // one record at a time keeps the scalar registers of the loop below the spill point
-          const EntryRec rq = ld_const(rec + i);  // padded to a multiple of GRP
+          const EntryHead rq = ld_const((const PCMD_CONST EntryHead *)(rec + i));  // padded to a multiple of GRP
           uint32_t n = 0, red_thin = 0u;
           bool thinned = false;
           // a pass leaves out the entries of the other pass (wave-uniform: the record is)
@@ -489,18 +489,24 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
             red = PASS != PASS_MAIN && thinned ? red_thin
                                                 : split_count(n, sq, 8u * q, a.split_mode, a.split_q, p, i, a.k0, a.k1);
           }
-          const PCMD_CONST double *f = fl64 + (size_t)i * BP;
-          // a stream with no star in any lane adds exact zeros: skipped
+          // the entry's fluxes, loaded once for both streams
+          const PCMD_CONST double *f = rec[i].fl;
+          double fv[B];
+#pragma unroll
+          for (int b = 0; b < B; ++b) fv[b] = f[b];
+          // the unreddened stream has a star whenever the entry has one, nearly always: added
+          // without a test (zero counts add exact zeros); the reddened stream is skipped when no
+          // lane has a reddened star
           const uint32_t nc = n - red;
-          if (S == 1 || wave_any(nc != 0u)) {
+          {
             const double dc = (double)nc;
 #pragma unroll
-            for (int b = 0; b < B; ++b) acc_c[b] = fma(dc, f[b], acc_c[b]);
+            for (int b = 0; b < B; ++b) acc_c[b] = fma(dc, fv[b], acc_c[b]);
           }
           if (S == 2 && wave_any(red != 0u)) {
             const double dr = (double)red;
 #pragma unroll
-            for (int b = 0; b < B; ++b) acc_r[b] = fma(dr, f[b], acc_r[b]);
+            for (int b = 0; b < B; ++b) acc_r[b] = fma(dr, fv[b], acc_r[b]);
           }
           if (DBG && dbg) {
             const size_t o = (size_t)((int64_t)p - a.px0) * (size_t)a.E + i;
@@ -528,8 +534,13 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
   }
 }
 
+// The scalar unit issues about as many instructions as the vector unit here, so scalar-load
+// latency is hidden by other waves: the main pass is held to the 80 scalar registers that allow 8
+// waves per SIMD (the compiler moves the rest into vector-register lanes), which measured faster
+// than 7 waves without those moves; the thinned-entry pass keeps the compiler's choice.
 template <int B, int S, bool DBG, int PASS>
-__global__ void __launch_bounds__(256) k_sample(SampleArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS == PASS_THIN ? 1 : 8, 8)))
+k_sample(SampleArgs a) {
   const int nblk_px = (a.npx + 255) >> 8;
   const int chunk = blockIdx.x / nblk_px;
   sample_tile<B, S, DBG, PASS>(a, (uint32_t)((blockIdx.x - chunk * nblk_px) * 256 + threadIdx.x), chunk);

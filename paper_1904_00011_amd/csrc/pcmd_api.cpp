@@ -470,7 +470,6 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
     a.grp = pa.grp;
     a.thr = pa.thr;
     a.pc = pa.pc;
-    a.fl64 = pa.fl64;
     a.part = (float *)c->part.p;
     a.dbg_counts = dbg ? dbg->counts : nullptr;
     a.dbg_red = dbg ? dbg->reddened : nullptr;

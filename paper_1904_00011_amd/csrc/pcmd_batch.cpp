@@ -162,7 +162,7 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
     ji.o_blk = n_blk;
     if (ji.sampler != PCMD_SAMPLER_POINT)
       n_blk += align256(blk_rec_bytes(ji.nb) + blk_thr_bytes(ji.nb) + blk_pc_bytes(ji.nb) + blk_cth_bytes(ji.nb));
-    n_rec += rec_bytes(ji.E) / sizeof(EntryRec);
+    n_rec += (rec_bytes(ji.E) + sizeof(EntryRec) - 1) / sizeof(EntryRec);
     n_thr += (size_t)entries_padded(ji.E) * THR_STRIDE;
     n_pc += (size_t)ji.E * 2;
     n_fl += (size_t)ji.E * BP;
@@ -400,7 +400,6 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
     s.grp = (const GroupRec *)(s.rec + entries_padded(ji.E));
     s.thr = (uint32_t *)p->thr.p + ji.o_thr;
     s.pc = (PtrsConst *)p->pc.p + ji.o_pc;
-    s.fl64 = (double *)p->fl.p + ji.o_fl;
     s.part = (float *)p->part.p + ji.o_part;
     s.status = c->status;
     s.lnfact = c->lnfact;

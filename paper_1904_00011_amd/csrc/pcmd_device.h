@@ -38,10 +38,10 @@ constexpr int PTRS_MAX_ATTEMPTS = 64;
 
 struct u4 { uint32_t x, y, z, w; };
 
-// Every counter used here is (lane-varying word, uniform, uniform, uniform), so the first two
-// rounds still mix uniform words (their XORs go to the scalar unit); from the third round on all
+// Every counter used here is (lane-varying word, uniform, uniform, uniform), so the first three
+// rounds still mix uniform words (their XORs go to the scalar unit); from the fourth round on all
 // three XOR inputs are per lane and one v_bitop3_b32 (truth table 0x96 = a ^ b ^ c) replaces two
-// v_xor_b32.
+// v_xor_b32.  The XOR order does not change the result.
 __device__ __forceinline__ uint32_t xor3_lane(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96u);
 }
@@ -56,6 +56,12 @@ __device__ __forceinline__ u4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
     if (r < 2) {
       n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
       n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    } else if (r == 2) {
+      // c3 is still uniform here (the low half of a product of uniform words): XOR it into the
+      // key on the scalar unit first, since a vector instruction reads at most one scalar
+      // operand and a three-input XOR of two would need a v_mov
+      n0 = xor3_lane((uint32_t)(p1 >> 32), c1, k0);
+      n2 = (uint32_t)(p0 >> 32) ^ (c3 ^ k1);
     } else {
       n0 = xor3_lane((uint32_t)(p1 >> 32), c1, k0);
       n2 = xor3_lane((uint32_t)(p0 >> 32), c3, k1);

@@ -13,12 +13,20 @@
 
 namespace pcmd {
 
-// One entry's sampler record (16 bytes, read with scalar loads): the first three inversion
-// thresholds inline (the rest in the threshold table) and K << 8 | kind.
-struct EntryRec {
+// One entry's sampler record (48 bytes, read with scalar loads): the first three inversion
+// thresholds inline (the rest in the threshold table), K << 8 | kind, and the entry's star flux
+// in each band (FP64; bands past B are zero).  The fluxes sit in the record so that the
+// sampler reads them from the record address it already holds.
+struct EntryHead {
   uint32_t T[3];  // T_0..T_2 (valid below K)
   uint32_t kk;    // (number of thresholds K, or k_lo of an alias entry) << 8 | kind
 };
+struct EntryRec {
+  uint32_t T[3];
+  uint32_t kk;
+  double fl[4];
+};
+static_assert(sizeof(EntryRec) == 48 && sizeof(EntryHead) == 16, "record layout");
 
 // Summary of eight consecutive entries (64 bytes, scalar loads), enough to finish a group in
 // which no pixel of the wave draws a star: T_0 - 1 of each entry drawn by inversion
@@ -66,7 +74,7 @@ struct PrepArgs {
   GroupRec *grp;       // [entries_padded(E) / GRP + 1]
   uint32_t *thr;       // [THR_STRIDE][EP]: threshold k of entry i at k EP + i (EP = E padded to GRP)
   void *pc;            // [E][2] PtrsConst: the entry (or its unreddened part), its reddened part
-  double *fl64;        // [E][BP]
+  double *fl64;        // [E][BP] (block-skip sampler only; the point sampler's fluxes are in rec)
   uint32_t *status;
   uint32_t *alias;     // [E][2][ALIAS_COLS] packed alias columns of the same two parts
   const BlockRec *brec;  // hybrid sampler: entries of blocks without pad[0] set are drawn as 0
@@ -85,7 +93,6 @@ struct SampleArgs {
   const GroupRec *grp;
   const uint32_t *thr;  // [THR_STRIDE][EP], k-major as in PrepArgs
   const void *pc;
-  const double *fl64;
   float *part;  // [nchunks][S][B][npx] slice partial sums (FP64 in registers, stored FP32)
   uint32_t *dbg_counts, *dbg_red;
   int64_t px0, px1;
