@@ -54,7 +54,7 @@ hipError_t launch_entries(const pcmd_grid *g, const double *scale, double *lam, 
 __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
   // every lane of the block takes part in the group summary below (no early return)
   const int E = a.E, B = a.B;
-  EntryRec r{{0u, 0u, 0u}, KIND_ZERO, {0.0, 0.0, 0.0, 0.0}};
+  EntryRec r{{0xFFFFFFFFu, 0u, 0u}, KIND_ZERO, {0.0, 0.0, 0.0, 0.0}};
   if (i < E) {
     // every load before the first store (the output could alias the inputs for the compiler,
     // which otherwise waits for each load in turn)
@@ -101,7 +101,9 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
       uint32_t first[3] = {0u, 0u, 0u};
       const uint32_t K = inversion_table(l, a.thr + i, (size_t)entries_padded(E), first);
       if (K > 0) {
-        for (uint32_t k = 0; k < 3 && k < K; ++k) r.T[k] = first[k];
+        // T_0 >= 1 below ALIAS_MIN, so u >= T_0 is exactly u > T_0 - 1
+        r.T[0] = first[0] - 1u;
+        for (uint32_t k = 1; k < 3 && k < K; ++k) r.T[k] = first[k];
         r.kk = (K << 8) | KIND_INV;
       }
     }
@@ -110,7 +112,7 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
   if (i < EP) a.rec[i] = r;
   // group of entries GRP g .. GRP g + GRP - 1 = neighbouring lanes of one wave (256-thread blocks)
   const uint32_t kind = r.kk & KIND_MASK;
-  const uint32_t t0m1 = kind == KIND_INV ? r.T[0] - 1u : 0xFFFFFFFFu;
+  const uint32_t t0m1 = r.T[0];  // 0xFFFFFFFF unless drawn by inversion
   const uint32_t fl = (r.kk & FLAG_THIN) ? GRP_THIN
                       : kind == KIND_INV ? GRP_INV : kind == KIND_PTRS ? GRP_PTRS : kind == KIND_ALIAS ? GRP_ALIAS : 0u;
   const int first = (int)(threadIdx.x & 63u) & ~(GRP - 1);
@@ -425,9 +427,6 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
         const int q0 = g0 + 4 * h;  // first entry of the quad
         const u4 &w = h ? wb : wa;
         const uint32_t sq = word_of(sw, 2 * (gi & 1) + h);  // the quad's word of the split block
-        uint32_t n0[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) n0[q] = word_of(w, q) > gr->t0m1[4 * h + q] ? 1u : 0u;
         u4 wr{0u, 0u, 0u, 0u};  // thinned entries: the quad's reddened-part words
         bool wr_ok = false;
 #pragma unroll
@@ -445,7 +444,7 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
             // n = #{k < K : T_k <= u}, walking up while any lane of the wave is still above
             const uint32_t u = word_of(w, q);
             const uint32_t K = rq.kk >> 8;
-            n = n0[q];
+            n = u > rq.T[0] ? 1u : 0u;
             if (!wave_any(n != 0u)) continue;
             if (K > 1) {
               uint32_t c = u >= rq.T[1] ? 1u : 0u;
@@ -535,11 +534,11 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
 }
 
 // The scalar unit issues about as many instructions as the vector unit here, so scalar-load
-// latency is hidden by other waves: the main pass is held to the 80 scalar registers that allow 8
-// waves per SIMD (the compiler moves the rest into vector-register lanes), which measured faster
-// than 7 waves without those moves; the thinned-entry pass keeps the compiler's choice.
+// latency is hidden by other waves: the sampler kernels are held to the 80 scalar registers that
+// allow 8 waves per SIMD (the compiler moves the rest into vector-register lanes), which measured
+// faster than 7 waves without those moves.
 template <int B, int S, bool DBG, int PASS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS == PASS_THIN ? 1 : 8, 8)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_sample(SampleArgs a) {
   const int nblk_px = (a.npx + 255) >> 8;
   const int chunk = blockIdx.x / nblk_px;
@@ -607,7 +606,7 @@ hipError_t launch_reset_counter(uint32_t *counter, hipStream_t s) {
 // atomic counter until none is left, so no wave waits for another (items of one job are
 // consecutive; jobs come in the host's order).
 template <int B>
-__global__ void __launch_bounds__(256) k_sample_persistent(const BatchSampleJob *__restrict__ jobs, int n_jobs,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) k_sample_persistent(const BatchSampleJob *__restrict__ jobs, int n_jobs,
                                                            int total_items, uint32_t *__restrict__ counter) {
   const PCMD_CONST BatchSampleJob *cj = (const PCMD_CONST BatchSampleJob *)jobs;
   const uint32_t lane = threadIdx.x & 63u;

@@ -14,11 +14,11 @@
 namespace pcmd {
 
 // One entry's sampler record (48 bytes, read with scalar loads): the first three inversion
-// thresholds inline (the rest in the threshold table), K << 8 | kind, and the entry's star flux
+// thresholds inline (the first as T_0 - 1; the rest in the threshold table), K << 8 | kind, and the entry's star flux
 // in each band (FP64; bands past B are zero).  The fluxes sit in the record so that the
 // sampler reads them from the record address it already holds.
 struct EntryHead {
-  uint32_t T[3];  // T_0..T_2 (valid below K)
+  uint32_t T[3];  // T_0 - 1, T_1, T_2 (valid below K); T[0] = 0xFFFFFFFF unless drawn by inversion
   uint32_t kk;    // (number of thresholds K, or k_lo of an alias entry) << 8 | kind
 };
 struct EntryRec {
