@@ -11,6 +11,8 @@
 // kernel, which fixes the summation order independently of the launch shape.
 #include <math.h>
 
+#include <algorithm>
+
 #include "pcmd_device.h"
 #include "pcmd_internal.h"
 
@@ -135,18 +137,23 @@ __global__ void __launch_bounds__(256) k_prep_job(const PrepArgs *__restrict__ t
 }
 
 // Alias columns of the entries with ALIAS_MIN <= lambda < ALIAS_MAX (rule C1b), one wave per
-// entry.  Lane 0 runs the inversion rule's FP64 recurrence without its cap until T_k reaches
-// 2^32 - 1 (that threshold then counts as 2^32: the FP64 sum can stall just below 1); with
+// entry at a time.  The wave runs the inversion rule's FP64 recurrence without its cap until T_k
+// reaches 2^32 - 1 (that threshold then counts as 2^32: the FP64 sum can stall just below 1); with
 // k_lo = #{k : T_k = 0}, outcome k_lo + j has mass m_j = T_{k_lo+j} - T_{k_lo+j-1}
 // (T_{k_lo-1} = 0).  M = the smallest power of two >= the number of outcomes, at least 16.
 // Vose's construction then splits the masses over M columns of 2^32 / M words: "small"
 // (m < 2^32 / M) and "large" column stacks, both filled in ascending order; pop s from small and
 // l from large, column s keeps height m_s and alias l, m_l -= 2^32 / M - m_s, and l goes back on
-// the stack its mass now selects; columns left on the large stack are full.  All integer: the
-// table selects every outcome on exactly m_j of the 2^32 words.  A part so small (below about
+// the stack its mass now selects; columns left on the large stack are full (the wave computes the
+// same table from prefix sums, below).  All integer: the table selects every outcome on exactly
+// m_j of the 2^32 words.  A part so small (below about
 // 2^-32) that T_0 already reaches 2^32 - 1 has the single outcome 0: every column then holds
 // height 0 and alias 0.  The record keeps k_lo << 12 | log2 M << 8 | KIND_ALIAS.
-constexpr int ALIAS_WAVES = 4;  // entries per 256-thread block
+// Each wave walks entries w, w + W, w + 2W, ... (W = waves in the grid), reusing its LDS: a grid
+// of one launch per entry held most of its blocks' LDS for waves without an alias part and
+// dispatched tens of thousands of blocks that had nothing to do.
+constexpr int ALIAS_WAVES = 4;      // waves per 256-thread block
+constexpr int ALIAS_BLOCKS = 1024;  // blocks over both parts: 4 per CU (bound by LDS) on 256 CUs
 
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -154,11 +161,37 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Inclusive prefix sums, in pop order (list position n - 1 - k for pop index k), of the deficits
+// cap - m (small) or excesses m - cap (large) of the n listed columns: dst[k] for k < n (every
+// partial sum is below 2^32).  Each
+// lane sums a run of consecutive pop indices, then a wave scan of the run totals offsets them.
+__device__ __forceinline__ void scan_pop_order(const uint16_t *list, int n, const uint32_t *m, uint32_t cap,
+                                               bool small, uint32_t *dst, int lane) {
+  const int per = (n + 63) >> 6;
+  const int k0 = min(n, lane * per), k1 = min(n, k0 + per);
+  uint32_t tot = 0u;
+  for (int k = k0; k < k1; ++k) {
+    const uint32_t c = m[list[n - 1 - k]];
+    tot += small ? cap - c : c - cap;
+  }
+  uint32_t x = tot;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = (uint32_t)__shfl_up((int)x, (unsigned)d, 64);
+    if (lane >= d) x += y;
+  }
+  uint32_t run = x - tot;
+  for (int k = k0; k < k1; ++k) {
+    const uint32_t c = m[list[n - 1 - k]];
+    run += small ? cap - c : c - cap;
+    dst[k] = run;
+  }
+}
+
 __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int part) {
   __shared__ uint32_t m_s[ALIAS_WAVES][ALIAS_COLS];
-  __shared__ uint16_t small_s[ALIAS_WAVES][ALIAS_COLS], large_s[ALIAS_WAVES][ALIAS_COLS],
-      alias_s[ALIAS_WAVES][ALIAS_COLS];
-  __shared__ int nout_s[ALIAS_WAVES];
+  __shared__ uint16_t small_s[ALIAS_WAVES][ALIAS_COLS], large_s[ALIAS_WAVES][ALIAS_COLS];
+  __shared__ uint32_t D_s[ALIAS_WAVES][ALIAS_COLS + 1], E_s[ALIAS_WAVES][ALIAS_COLS];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (i >= a.E) return;  // whole waves: i is wave-uniform
   // part 0: the entry's count (or its unreddened part); part 1: the reddened part (thinned)
@@ -166,51 +199,61 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
   if (part == 0 ? (a.rec[i].kk & KIND_MASK) != KIND_ALIAS : a.thin == THIN_NONE || (a.rdesc[i] & KIND_MASK) != KIND_ALIAS)
     return;
   uint32_t *m = m_s[wv];
-  uint16_t *sm = small_s[wv], *lg = large_s[wv], *al = alias_s[wv];
-  for (int j = lane; j < ALIAS_COLS; j += 64) {
-    m[j] = 0u;
-    al[j] = (uint16_t)j;
-  }
+  uint16_t *sm = small_s[wv], *lg = large_s[wv];
+  for (int j = lane; j < ALIAS_COLS; j += 64) m[j] = 0u;
   wave_lds_sync();
-  if (lane == 0) {
-    const double lam = a.lam[i];
-    // part 1 exists only for a thinned entry; part 0 of one is its unreddened share
-    const bool thin = part == 1 || (a.rec[i].kk & FLAG_THIN) != 0u;
-    const double l = !thin ? lam : part == 0 ? lam * (1.0 - a.frac) : lam * a.frac;
-    double pk = exp(-l);
-    double F = pk;
-    int klo = -1, J = 0;
-    bool single = false;
-    uint32_t prev = 0u;
-    for (int k = 0;; ++k) {
-      if (k > 0) {
-        pk = pk * l / (double)k;
-        F = F + pk;
+  // Every lane runs the recurrence on the same values (a wave issues the same instructions for
+  // one lane as for 64) and the loop's decisions are read from lane 0 into scalar registers, so
+  // its branches are uniform; lane 0 stores the masses.
+  const double lam = a.lam[i];
+  // part 1 exists only for a thinned entry; part 0 of one is its unreddened share
+  const bool thin = part == 1 || (a.rec[i].kk & FLAG_THIN) != 0u;
+  const double l = !thin ? lam : part == 0 ? lam * (1.0 - a.frac) : lam * a.frac;
+  double pk = exp(-l);
+  double F = pk;
+  int klo = -1, J = 0;
+  bool single = false;
+  uint32_t prev = 0u;
+  for (int k = 0;; ++k) {
+    // the loop's integers are the same in every lane: said so, they stay in scalar registers
+    klo = __builtin_amdgcn_readfirstlane(klo);
+    J = __builtin_amdgcn_readfirstlane(J);
+    prev = (uint32_t)__builtin_amdgcn_readfirstlane((int)prev);
+    if (k > 0) {
+      pk = pk * l / (double)k;
+      F = F + pk;
+    }
+    const double t = floor(F * 4294967296.0);
+    if (__builtin_amdgcn_readfirstlane(t >= 4294967295.0 ? 1 : 0)) {
+      // the last word or more: the rest of the mass goes to outcome k
+      if (klo < 0) {  // all of it (a part below about 2^-32): every word draws k
+        klo = k;
+        single = true;
+      } else {
+        if (lane == 0) m[J] = 0u - prev;  // 2^32 - T_{k-1}; prev >= 1 here (T_{klo} > 0)
+        ++J;
       }
-      const double t = floor(F * 4294967296.0);
-      if (t >= 4294967295.0) {  // the last word or more: the rest of the mass goes to outcome k
-        if (klo < 0) {          // all of it (a part below about 2^-32): every word draws k
-          klo = k;
-          single = true;
-        } else {
-          m[J++] = 0u - prev;   // 2^32 - T_{k-1}; prev >= 1 here (T_{klo} > 0)
-        }
+      break;
+    }
+    // converted before the read (the empty asm keeps the compiler from reading the double and
+    // converting in a vector register), so T and everything computed from it stay scalar
+    uint32_t Tv = (uint32_t)t;
+    asm volatile("" : "+v"(Tv));
+    const uint32_t T = (uint32_t)__builtin_amdgcn_readfirstlane((int)Tv);
+    if (klo < 0 && T > 0u) klo = k;
+    if (klo >= 0) {
+      if (lane == 0) m[J] = T - prev;
+      ++J;
+      prev = T;
+      if (J == ALIAS_COLS) {  // wider than the table (not reached below ALIAS_MAX)
+        if (lane == 0) atomicOr(a.status, STATUS_BAD_LAMBDA);
         break;
       }
-      const uint32_t T = (uint32_t)t;
-      if (klo < 0 && T > 0u) klo = k;
-      if (klo >= 0) {
-        m[J++] = T - prev;
-        prev = T;
-        if (J == ALIAS_COLS) {  // wider than the table (not reached below ALIAS_MAX)
-          atomicOr(a.status, STATUS_BAD_LAMBDA);
-          break;
-        }
-      }
     }
-    int bits = 4;
-    while ((1 << bits) < J) ++bits;
-    nout_s[wv] = bits | (single ? 0x100 : 0);
+  }
+  int bits = 4;
+  while ((1 << bits) < J) ++bits;
+  if (lane == 0) {
     const uint32_t desc = ((uint32_t)klo << 12) | ((uint32_t)bits << 8) | KIND_ALIAS;
     if (part == 0)
       a.rec[i].kk = desc | (a.rec[i].kk & FLAG_THIN);
@@ -218,11 +261,10 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
       a.rdesc[i] = desc;
   }
   wave_lds_sync();
-  const int bits = nout_s[wv] & 0xFF;
   const int M = 1 << bits;
   const uint32_t cap = 1u << (32 - bits);
   uint32_t *out = a.alias + ((size_t)i * 2 + part) * ALIAS_COLS;
-  if (nout_s[wv] & 0x100) {  // one outcome: height 0 and alias 0 in every column, n = k_lo always
+  if (single) {  // one outcome: height 0 and alias 0 in every column, n = k_lo always
     for (int j = lane; j < M; j += 64) out[j] = 0u;
     return;
   }
@@ -242,47 +284,76 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
     nl += __popcll(bl);
   }
   wave_lds_sync();
-  if (lane == 0) {
-    while (ns > 0 && nl > 0) {
-      const int sj = sm[--ns];
-      const int lj = lg[--nl];
-      al[sj] = (uint16_t)lj;
-      const uint32_t ml = m[lj] - (cap - m[sj]);
-      m[lj] = ml;
-      if (ml < cap)
-        sm[ns++] = (uint16_t)lj;
-      else
-        lg[nl++] = (uint16_t)lj;
-    }
-  }
+  // Vose's loop pops both lists from the top (highest column first): a large column takes the
+  // small columns in pop order until its excess m - cap is used up, then is itself the next small
+  // column, taken by the next large one.  With D(i) the deficits cap - m of the first i smalls
+  // popped and E(j) the excesses of the first j larges, the i-th small gets the first large j with
+  // E(j) >= D(i - 1); the j-th large turns small after the first small a with D(a) > E(j), keeping
+  // height cap + E(j) - D(a) and the alias large j + 1; larges that never turn small are full.
+  // The sums are exact integers below 2^32 (the total deficit equals the total excess, and that
+  // is below M cap = 2^32), so prefix sums and searches give the loop's table exactly, every lane
+  // working instead of one walking the loop through LDS.
+  uint32_t *Dp = D_s[wv], *Ep = E_s[wv];
+  if (lane == 0) Dp[0] = 0u;
+  scan_pop_order(sm, ns, m, cap, true, Dp + 1, lane);  // Dp[k] = D(k)
+  scan_pop_order(lg, nl, m, cap, false, Ep, lane);     // Ep[j] = E(j + 1)
   wave_lds_sync();
-  // a column whose alias is itself is full (2^32 / M words, stored as 2^32 / M - 1: the last word
-  // then falls to the alias, the column itself)
-  for (int j = lane; j < M; j += 64) {
-    const uint32_t h = al[j] == (uint16_t)j ? cap - 1u : m[j];
-    out[j] = (h << bits) | (uint32_t)al[j];
+  for (int i = lane; i < ns; i += 64) {  // pop index i: small number i + 1
+    const int col = sm[ns - 1 - i];
+    const uint32_t need = Dp[i];
+    int lo = 0, hi = nl - 1;  // first j with Ep[j] >= need
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (Ep[mid] >= need)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    const uint32_t al = nl > 0 ? (uint32_t)lg[nl - 1 - lo] : (uint32_t)col;  // nl = 0 only for malformed masses
+    out[col] = (m[col] << bits) | al;
+  }
+  for (int j = lane; j < nl; j += 64) {  // pop index j: large number j + 1
+    const int col = lg[nl - 1 - j];
+    const uint32_t ex = Ep[j];
+    int lo = 1, hi = ns + 1;  // first k in [1, ns] with Dp[k] > ex (ns + 1: none)
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (Dp[mid] > ex)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    // a column whose alias is itself is full (2^32 / M words, stored as 2^32 / M - 1: the last
+    // word then falls to the alias, the column itself)
+    uint32_t word = ((cap - 1u) << bits) | (uint32_t)col;
+    if (lo <= ns && j + 1 < nl) word = ((cap - (Dp[lo] - ex)) << bits) | (uint32_t)lg[nl - 2 - j];  // Dp[lo] - ex <= cap
+    out[col] = word;
   }
 }
 
-// grid.y = 2: the second row of blocks builds the reddened parts of thinned entries
-__global__ void __launch_bounds__(256) k_prep_alias(PrepArgs a) {
-  prep_alias_body(a, (int)(blockIdx.x * ALIAS_WAVES + (threadIdx.x >> 6)), (int)blockIdx.y);
+__device__ __forceinline__ void prep_alias_walk(const PrepArgs &a) {
+  const int stride = (int)gridDim.x * ALIAS_WAVES;
+  for (int i = (int)blockIdx.x * ALIAS_WAVES + (int)(threadIdx.x >> 6); i < a.E; i += stride)
+    prep_alias_body(a, i, (int)blockIdx.y);
 }
-__global__ void __launch_bounds__(256) k_prep_alias_job(const PrepArgs *__restrict__ t, int j) {
+__global__ void __launch_bounds__(64 * ALIAS_WAVES) k_prep_alias(PrepArgs a) { prep_alias_walk(a); }
+__global__ void __launch_bounds__(64 * ALIAS_WAVES) k_prep_alias_job(const PrepArgs *__restrict__ t, int j) {
   const PrepArgs a = t[j];
-  prep_alias_body(a, (int)(blockIdx.x * ALIAS_WAVES + (threadIdx.x >> 6)), (int)blockIdx.y);
+  prep_alias_walk(a);
 }
 
+static dim3 prep_alias_grid(int E, int parts) {
+  const int per_part = ALIAS_BLOCKS / parts;
+  return dim3((unsigned)std::min((E + ALIAS_WAVES - 1) / ALIAS_WAVES, per_part), (unsigned)parts);
+}
 hipError_t launch_prep_alias(const PrepArgs &a, hipStream_t s) {
   // grid.y: part 1 (the reddened part of a thinned entry) exists only when entries are thinned
-  hipLaunchKernelGGL(k_prep_alias, dim3((unsigned)((a.E + ALIAS_WAVES - 1) / ALIAS_WAVES), a.thin != THIN_NONE ? 2 : 1),
-                     dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_prep_alias, prep_alias_grid(a.E, a.thin != THIN_NONE ? 2 : 1), dim3(64 * ALIAS_WAVES), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_prep_alias_job(const PrepArgs *table, int j, int E, int parts, hipStream_t s) {
   if (parts != 1 && parts != 2) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_prep_alias_job, dim3((unsigned)((E + ALIAS_WAVES - 1) / ALIAS_WAVES), parts), dim3(256), 0, s,
-                     table, j);
+  hipLaunchKernelGGL(k_prep_alias_job, prep_alias_grid(E, parts), dim3(64 * ALIAS_WAVES), 0, s, table, j);
   return hipGetLastError();
 }
 
