@@ -10,6 +10,8 @@ namespace pcmd {
 
 // One block per PSF (band, and region of the sub-pixel grid): check that it is finite,
 // non-negative and sums to one within 1e-3 (a failure sets a status bit reported by pcmd_sync).
+// The FFT path runs this kernel; the direct convolution makes the same check in its first tile of
+// each PSF (psf_check_wave).
 __device__ __forceinline__ void psf_check_body(const ConvArgs &a) {
   __shared__ double red[256];
   __shared__ int bad;
@@ -33,17 +35,9 @@ __device__ __forceinline__ void psf_check_body(const ConvArgs &a) {
 }
 
 __global__ void __launch_bounds__(256) k_psf_check(ConvArgs a) { psf_check_body(a); }
-__global__ void __launch_bounds__(256) k_psf_check_job(const ConvArgs *__restrict__ t, int j) {
-  const ConvArgs a = t[j];
-  psf_check_body(a);
-}
 
 hipError_t launch_psf_check(const ConvArgs &a, hipStream_t s) {
   hipLaunchKernelGGL(k_psf_check, dim3(a.B * a.grid * a.grid), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_psf_check_job(const ConvArgs *table, int j, int B, int grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_psf_check_job, dim3(B * grid * grid), dim3(256), 0, s, table, j);
   return hipGetLastError();
 }
 
@@ -82,6 +76,23 @@ static size_t conv_split_lds_bytes(int K) {
   return conv_direct_lds_bytes(K) + (size_t)(CONV_RS - 1) * 256 * 4 * sizeof(double);
 }
 
+// The PSF check of psf_check_body done by one wave (the direct convolution's first tile of each
+// PSF runs it beside its own work, which saves the check's launch): per-lane FP64 sums, then a
+// shuffle reduction.
+__device__ __forceinline__ void psf_check_wave(const ConvArgs &a, int b) {
+  const int KK = a.K * a.K, lane = (int)(threadIdx.x & 63u);
+  double s = 0.0;
+  bool bad = false;
+  for (int i = lane; i < KK; i += 64) {
+    const float v = a.psf[(size_t)b * KK + i];
+    if (!(v >= 0.0f) || !isfinite(v)) bad = true;
+    s += (double)v;
+  }
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) s += __shfl_xor(s, d, 64);
+  if (lane == 0 && (__ballot(bad) != 0ull || !(fabs(s - 1.0) <= 1e-3))) atomicOr(a.status, STATUS_BAD_PSF);
+}
+
 template <int RS>
 __device__ __forceinline__ void conv_direct_body(const ConvArgs &ca) {
   extern __shared__ float4 lds4[];
@@ -98,6 +109,7 @@ __device__ __forceinline__ void conv_direct_body(const ConvArgs &ca) {
   const int x0r = (rx * N + ca.grid - 1) / ca.grid, x1r = ((rx + 1) * N + ca.grid - 1) / ca.grid;
   const int ox = x0r + blockIdx.x * CT_X, oy = y0r + blockIdx.y * CT_Y;
   if (ox >= x1r || oy >= y1r) return;  // the grid is sized for the largest region
+  if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x < 64) psf_check_wave(ca, (int)blockIdx.z);
   const int h = (K - 1) >> 1;
   const int TW = conv_tile_w(K), TH = CT_Y + K - 1;
   float *Pf = tile + TW * TH;  // Pf[a][c] = P[K-1-a][K-1-c], 0 for c >= K

@@ -90,6 +90,7 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
       }
       if (thin) {
         r.kk |= FLAG_THIN;
+        if (a.thin_seen) *a.thin_seen = a.gen;  // every writer stores the same value
         const double l1 = l * a.frac;
         if (l1 >= ALIAS_MAX) {
           ((PtrsConst *)a.pc)[2 * (size_t)i + 1] = ptrs_constants(l1);
@@ -611,6 +612,7 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
 template <int B, int S, bool DBG, int PASS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8)))
 k_sample(SampleArgs a) {
+  if (PASS == PASS_THIN && a.thin_seen && *(const PCMD_CONST uint32_t *)a.thin_seen != a.gen) return;  // nothing thinned
   const int nblk_px = (a.npx + 255) >> 8;
   const int chunk = blockIdx.x / nblk_px;
   sample_tile<B, S, DBG, PASS>(a, (uint32_t)((blockIdx.x - chunk * nblk_px) * 256 + threadIdx.x), chunk);

@@ -451,7 +451,9 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
                 hybrid ? pb.brec : nullptr,
                 thin_mode_of_split(split_mode),
                 o->dust_frac,
-                (uint32_t *)c->rdesc.p};
+                (uint32_t *)c->rdesc.p,
+                c->status + 1,
+                ++c->thin_gen};
     e = launch_prep(pa, s);
     if (e == hipSuccess) e = launch_prep_alias(pa, s);
     if (e != hipSuccess) return hip_fail(c, e, "k_prep");
@@ -479,6 +481,8 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
     a.lnfact = c->lnfact;
     a.alias = pa.alias;
     a.rdesc = pa.rdesc;
+    a.thin_seen = pa.thin_seen;
+    a.gen = pa.gen;
     ScopedTimer tm(c, PCMD_TIMER_SAMPLE, (double)npx * (double)E, s);
     e = launch_sample(a, s);
     if (e == hipSuccess && hybrid) e = launch_sample_block(ab, s);
@@ -508,8 +512,10 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   const float *Gp = (const float *)c->F.p;
   if (K > 1) {
     ConvArgs ca{B, N, K, (const float *)c->F.p, o->psf, (float *)c->G.p, c->status, psf_grid_of(o)};
-    e = launch_psf_check(ca, s);
-    if (e != hipSuccess) return hip_fail(c, e, "psf check");
+    if (use_fft) {  // the direct convolution checks the PSF itself
+      e = launch_psf_check(ca, s);
+      if (e != hipSuccess) return hip_fail(c, e, "psf check");
+    }
     ScopedTimer tm(c, PCMD_TIMER_CONV, 2.0 * (double)B * (double)npx, s);
     if (use_fft) {
       const bool fresh = c->fft_buf != c->fft.p || c->fft_B != B || c->fft_N != N || c->fft_K != K || c->fft_R != R;

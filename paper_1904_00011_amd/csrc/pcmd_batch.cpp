@@ -452,7 +452,6 @@ static hipError_t enqueue(pcmd_ctx *c, pcmd_batch_plan *p, hipStream_t s) {
   for (int j = 0; j < p->n_jobs && e == hipSuccess; ++j) {
     const JobInfo &ji = p->info[j];
     e = launch_reduce_job(ra, j, ji.npx, ji.B, s);
-    if (e == hipSuccess && ji.K > 1) e = launch_psf_check_job(ca, j, ji.B, ji.grid, s);
     if (e == hipSuccess && ji.K > 1) e = launch_conv_direct_job(ca, j, ji.B, ji.N, ji.K, ji.grid, s);
     if (e == hipSuccess) e = launch_noise_mag_job(na, j, ji.npx, s);
   }

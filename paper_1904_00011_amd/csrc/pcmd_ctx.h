@@ -33,7 +33,8 @@ struct pcmd_ctx {
   Buf mlp_act, mlp_pre, mlp_dza, mlp_dzb, mlp_grad, mlp_part, mlp_ws, mlp_lpart;
   float *lnfact = nullptr;     // [256]
   double *lnfact64 = nullptr;  // [LNFACT64_N] ln k! in FP64 (likelihoods)
-  uint32_t *status = nullptr;  // [1]
+  uint32_t *status = nullptr;  // [2]: status bits; the generation of the last call that thinned an entry
+  uint32_t thin_gen = 0;       // generation of the last pcmd_simulate call
   uint32_t *counter = nullptr; // [1]
   pcmd_batch_plan *batch = nullptr;
   int tune_wg_per_cu = 4;      // persistent sampler workgroups per CU

@@ -81,6 +81,8 @@ struct PrepArgs {
   int thin;            // THIN_* : which table entries draw two thinned parts
   double frac;         // F
   uint32_t *rdesc;     // [E] reddened part: k_lo << 12 | log2 M << 8 | KIND_ALIAS, or KIND_PTRS
+  uint32_t *thin_seen;  // set to gen when an entry is thinned (null: not recorded)
+  uint32_t gen;
 };
 
 // Sampler over (pixel block of 256, chunk of CHUNK entries) tiles (k_sample).
@@ -100,6 +102,10 @@ struct SampleArgs {
   const float *lnfact;
   const uint32_t *alias;  // [E][2][ALIAS_COLS]
   const uint32_t *rdesc;  // [E]
+  // the thinned-entry pass returns at once unless *thin_seen == gen, i.e. k_prep of this call
+  // thinned an entry (null: always runs)
+  const uint32_t *thin_seen;
+  uint32_t gen;
 };
 
 // Block-skip sampler (Poisson superposition, Sec. 2.1 footnote): per pixel and per block of
@@ -233,7 +239,6 @@ hipError_t launch_sample_block_job(const BlockSampleArgs *table, int j, int B, i
 
 // k_image.hip
 hipError_t launch_psf_check(const ConvArgs &a, hipStream_t s);
-hipError_t launch_psf_check_job(const ConvArgs *table, int j, int B, int grid, hipStream_t s);
 size_t conv_direct_lds_bytes(int K);
 hipError_t launch_conv_direct(const ConvArgs &a, hipStream_t s);
 hipError_t launch_conv_direct_job(const ConvArgs *table, int j, int B, int N, int K, int grid, hipStream_t s);

@@ -280,9 +280,21 @@ def test_device_side_validation(ctx):
         with pytest.raises(P.PcmdError) as ei:
             pu.gpu_simulate(ctx, bad, f32, obs, want_flux=False)
         assert ei.value.code == P._lib.E_INVAL
-    obs.psf = (si.psf_stack(3, (1.0, 1.0)) * 1.1).astype(np.float32)
-    with pytest.raises(P.PcmdError):
-        pu.gpu_simulate(ctx, np.array([1.0, 0.5, 0.1]), f32, obs, want_flux=False)
+    good = si.psf_stack(3, (1.0, 1.0)).astype(np.float32)
+    neg = good.copy()   # a negative weight, the sum kept at one
+    neg[1, 2, 2] += good[1, 0, 0] + 0.02
+    neg[1, 0, 0] = -0.02
+    nan = good.copy()
+    nan[0, 1, 1] = np.nan
+    # the direct path checks the PSF inside the convolution, the FFT path in its own kernel
+    for path in (P._lib.CONV_DIRECT, P._lib.CONV_FFT):
+        for psf in ((good * 1.1).astype(np.float32), neg, nan):
+            obs.psf = psf
+            with pytest.raises(P.PcmdError) as ei:
+                pu.gpu_simulate(ctx, np.array([1.0, 0.5, 0.1]), f32, obs, conv_path=path, want_flux=False)
+            assert ei.value.code == P._lib.E_INVAL
+        obs.psf = good
+        pu.gpu_simulate(ctx, np.array([1.0, 0.5, 0.1]), f32, obs, conv_path=path, want_flux=False)
     ctx.sync()
 
 
