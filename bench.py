@@ -14,7 +14,9 @@ Prints one JSON line.  `--gpus N` with N > 1 is refused: the library runs on one
 from __future__ import annotations
 
 import argparse
+import contextlib
 import dataclasses
+import gc
 import json
 import os
 import sys
@@ -25,6 +27,21 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+
+
+@contextlib.contextmanager
+def collector_paused():
+    """Python's cyclic garbage collector paused over a timed loop, as timeit does: a full
+    collection with torch loaded takes tens of milliseconds, which a loop whose GPU work is
+    shorter than its host work (the 64x64 workload) would otherwise count as evaluation time."""
+    was = gc.isenabled()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
+
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 # MI355X published figures: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.3e12 VALU lane-instructions/s.
@@ -124,12 +141,13 @@ def run_batch(args):
         ctx.batch_run(jobs, hgrid, data_hess, data_mom, ll, use_graph=use_graph)
     torch.cuda.synchronize()
     ctx.timer_enable(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        entries_all()
-        ctx.batch_run(jobs, hgrid, data_hess, data_mom, ll, use_graph=use_graph)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    with collector_paused():
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            entries_all()
+            ctx.batch_run(jobs, hgrid, data_hess, data_mom, ll, use_graph=use_graph)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     b_ms, b_n, b_units = ctx.timer_read(P._lib.TIMER_BATCH)
     ctx.timer_enable(False)
     ll_batch = ll.cpu().numpy().copy()
@@ -153,10 +171,11 @@ def run_batch(args):
     sequential()
     torch.cuda.synchronize()
     ctx.timer_enable(True)
-    s0 = time.perf_counter()
-    sequential()
-    torch.cuda.synchronize()
-    s1 = time.perf_counter()
+    with collector_paused():
+        s0 = time.perf_counter()
+        sequential()
+        torch.cuda.synchronize()
+        s1 = time.perf_counter()
     seq_sample_ms, _, seq_draws = ctx.timer_read(P._lib.TIMER_SAMPLE)
     ctx.timer_enable(False)
     identical = bool(np.array_equal(ll_seq.cpu().numpy(), ll_batch))
@@ -638,11 +657,12 @@ def run_small(args):
     torch.cuda.synchronize()
     ctx.timer_enable(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.warmup, args.warmup + args.steps):
-        ev.loglike(model, obss[k], data_hess, data_mom, P.LL_POISSON, 0.01, out=logls[k:k + 1])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    with collector_paused():
+        t0 = time.perf_counter()
+        for k in range(args.warmup, args.warmup + args.steps):
+            ev.loglike(model, obss[k], data_hess, data_mom, P.LL_POISSON, 0.01, out=logls[k:k + 1])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     ctx.sync()
     s_ms, s_n, s_units = ctx.timer_read(P._lib.TIMER_SAMPLE)
     c_ms, c_n, _ = ctx.timer_read(P._lib.TIMER_CONV)
@@ -741,12 +761,13 @@ def main():
     torch.cuda.synchronize()
     ctx.timer_enable(True)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.warmup, args.warmup + args.steps):
-        m, o = params[k]
-        ev.loglike(m, o, data_hess, data_mom, P.LL_POISSON, 0.01, args.conv, out=logls[k:k + 1])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    with collector_paused():
+        t0 = time.perf_counter()
+        for k in range(args.warmup, args.warmup + args.steps):
+            m, o = params[k]
+            ev.loglike(m, o, data_hess, data_mom, P.LL_POISSON, 0.01, args.conv, out=logls[k:k + 1])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
     ctx.sync()
     s_ms, s_n, s_units = ctx.timer_read(P._lib.TIMER_SAMPLE)
     c_ms, c_n, _ = ctx.timer_read(P._lib.TIMER_CONV)

@@ -75,7 +75,7 @@ int validate_sim(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, const char
 
 extern "C" {
 
-const char *pcmd_version(void) { return "pcmd gfx950 HIP 1.1 (philox4x32-10, 1024-entry slices)"; }
+const char *pcmd_version(void) { return "pcmd gfx950 HIP 1.1 (philox4x32-10, slices of up to 1024 entries)"; }
 
 int pcmd_create(pcmd_ctx **out, int hip_device) {
   if (!out) return PCMD_E_INVAL;
@@ -129,6 +129,8 @@ void pcmd_destroy(pcmd_ctx *c) {
   DeviceGuard g(c->device);
   (void)hipDeviceSynchronize();
   clear_timers(c);
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  c->ev_pool.clear();
   batch_destroy(c);
   Buf *bufs[] = {&c->rec,     &c->thr,     &c->pc,      &c->fl64,    &c->part,     &c->F,       &c->G,
                  &c->mom_part, &c->fft,    &c->mlp_act, &c->mlp_pre, &c->mlp_dza, &c->mlp_dzb, &c->mlp_grad,
@@ -353,7 +355,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
   hipStream_t s = (hipStream_t)stream;
   DeviceGuard dg(c->device);
   const int BP = B <= 2 ? 2 : 4;
-  const int nchunks = (E + CHUNK - 1) / CHUNK;
+  const int nchunks = sample_slices(E, npx);
   const int split_mode = split_mode_of(o);
   const int S = split_mode == SPLIT_NONE ? 1 : 2;
   const bool block = o->sampler == PCMD_SAMPLER_BLOCK, hybrid = o->sampler == PCMD_SAMPLER_HYBRID;
@@ -628,6 +630,12 @@ int pcmd_timer_enable(pcmd_ctx *c, int on) {
   if (on) {
     (void)hipDeviceSynchronize();
     clear_timers(c);
+    // events for 512 timed launches between reads, created here rather than inside a timed loop
+    while (c->ev_pool.size() < 1024) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return hip_fail(c, hipErrorOutOfMemory, "pcmd_timer_enable: event");
+      c->ev_pool.push_back(e);
+    }
   }
   c->timing = on != 0;
   return PCMD_OK;
@@ -649,8 +657,8 @@ int pcmd_timer_read(pcmd_ctx *c, int which, double *total_ms, int64_t *launches,
     float dt = 0.0f;
     hipError_t e = hipEventSynchronize(t.stop);
     if (e == hipSuccess) e = hipEventElapsedTime(&dt, t.start, t.stop);
-    (void)hipEventDestroy(t.start);
-    (void)hipEventDestroy(t.stop);
+    give_event(c, t.start);
+    give_event(c, t.stop);
     if (e != hipSuccess) return hip_fail(c, e, "pcmd_timer_read");
     ms += dt;
     u += t.units;

@@ -143,7 +143,7 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
     // sampler has one instantiation; a job without a split draws no reddened stars, its second
     // stream holds zeros and the reduction's sums are unchanged (c + 0 = c).
     ji.S = 2;
-    ji.nchunks = (ji.E + CHUNK - 1) / CHUNK;
+    ji.nchunks = sample_slices(ji.E, ji.npx);
     ji.pblocks = (ji.npx + 63) / 64;  // one persistent-sampler item = one wave's 64 pixels x one slice
     ji.sampler = jobs[j].obs.sampler;
     ji.nb = superblocks(ji.E);

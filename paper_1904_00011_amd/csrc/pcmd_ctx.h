@@ -29,6 +29,9 @@ struct pcmd_ctx {
   std::string err;
   bool timing = false;
   std::vector<TimerRec> timers;
+  // timer events not in use: recycled, and created ahead when timing is switched on, because
+  // creating events inside a timed loop stalled the host for tens of milliseconds now and then
+  std::vector<hipEvent_t> ev_pool;
   Buf rec, thr, pc, fl64, part, F, G, mom_part, fft, ll_part, blk, alias, rdesc;
   Buf mlp_act, mlp_pre, mlp_dza, mlp_dzb, mlp_grad, mlp_part, mlp_ws, mlp_lpart;
   float *lnfact = nullptr;     // [256]
@@ -99,6 +102,19 @@ struct DeviceGuard {
 };
 
 // Event pair around one launch when timing is enabled.
+inline hipEvent_t take_event(pcmd_ctx *c) {
+  if (!c->ev_pool.empty()) {
+    const hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+inline void give_event(pcmd_ctx *c, hipEvent_t e) {
+  if (e) c->ev_pool.push_back(e);
+}
+
 struct ScopedTimer {
   pcmd_ctx *c;
   hipStream_t s;
@@ -108,7 +124,11 @@ struct ScopedTimer {
     if (!on) return;
     r.which = which;
     r.units = units;
-    if (hipEventCreate(&r.start) != hipSuccess || hipEventCreate(&r.stop) != hipSuccess) {
+    r.start = take_event(c);
+    r.stop = take_event(c);
+    if (!r.start || !r.stop) {
+      give_event(c, r.start);
+      give_event(c, r.stop);
       on = false;
       return;
     }
@@ -123,8 +143,8 @@ struct ScopedTimer {
 
 inline void clear_timers(pcmd_ctx *c) {
   for (auto &t : c->timers) {
-    (void)hipEventDestroy(t.start);
-    (void)hipEventDestroy(t.stop);
+    give_event(c, t.start);
+    give_event(c, t.stop);
   }
   c->timers.clear();
 }

@@ -33,8 +33,19 @@ constexpr double LAM_THIN_HALF = 64.0;
 constexpr double ALIAS_MIN = 2.0, ALIAS_MAX = 512.0;
 constexpr int ALIAS_COLS = 512;
 constexpr int THR_STRIDE = 64;       // thresholds per entry slot (K <= 63)
-constexpr int CHUNK = 1024;          // entries per slice (the number of slices is ceil(E / CHUNK))
+constexpr int CHUNK = 1024;          // entries per slice, at most (sample_slices)
 constexpr int PTRS_MAX_ATTEMPTS = 64;
+
+// Slices of the sampler for E entries over npx pixels: one per CHUNK entries, more for small
+// images (up to one per 16-entry block) until the 256-pixel blocks x slices reach 512 workgroups,
+// so that a small image still spreads over the chip.  A function of (E, npx) alone: a batch job
+// gets the slices of the same single call, and so the same partial sums.
+__host__ __device__ inline int sample_slices(int E, int64_t npx) {
+  const int64_t base = (E + CHUNK - 1) / CHUNK, blocks16 = (E + 15) / 16;
+  const int64_t pblocks = (npx + 255) / 256, want = (512 + pblocks - 1) / pblocks;
+  const int64_t small = blocks16 < want ? blocks16 : want;
+  return (int)(base > small ? base : small);
+}
 
 struct u4 { uint32_t x, y, z, w; };
 
