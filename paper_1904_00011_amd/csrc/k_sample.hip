@@ -57,6 +57,7 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
   // every lane of the block takes part in the group summary below (no early return)
   const int E = a.E, B = a.B;
   EntryRec r{{0xFFFFFFFFu, 0u, 0u}, KIND_ZERO, {0.0, 0.0, 0.0, 0.0}};
+  bool red_alias = false;  // the entry is thinned and its reddened part is on the alias rule
   if (i < E) {
     // every load before the first store (the output could alias the inputs for the compiler,
     // which otherwise waits for each load in turn)
@@ -97,6 +98,7 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
           a.rdesc[i] = KIND_PTRS;
         } else {
           a.rdesc[i] = KIND_ALIAS;
+          red_alias = true;
         }
       }
     } else if (l > 0.0) {
@@ -113,6 +115,26 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
   }
   const int EP = entries_padded(E);
   if (i < EP) a.rec[i] = r;
+  if (a.alias_list) {
+    // the alias parts (i << 1 | part) to the call's list, one reservation per wave; a count word
+    // not prepared for this generation (the previous call stopped early) is left alone, and
+    // k_prep_alias then walks every entry
+    const bool al0 = i < E && (r.kk & KIND_MASK) == KIND_ALIAS, al1 = i < E && red_alias;
+    const uint64_t b0 = __ballot(al0), b1 = __ballot(al1);
+    const uint32_t cnt = (uint32_t)(__popcll(b0) + __popcll(b1));
+    if (cnt != 0u) {
+      unsigned long long old = 0ull;
+      if ((threadIdx.x & 63u) == 0u) old = atomicAdd(a.alias_n + (a.gen & 1u), (unsigned long long)cnt);
+      const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(old >> 32), 0, 64);
+      const uint32_t base = (uint32_t)__shfl((int)(uint32_t)old, 0, 64);
+      if (hi == a.gen && (uint64_t)base + cnt <= 2ull * (uint64_t)E) {
+        const uint64_t below = (1ull << (threadIdx.x & 63u)) - 1ull;
+        if (al0) a.alias_list[base + (uint32_t)__popcll(b0 & below)] = (uint32_t)i << 1;
+        if (al1) a.alias_list[base + (uint32_t)__popcll(b0) + (uint32_t)__popcll(b1 & below)] = ((uint32_t)i << 1) | 1u;
+      }
+    }
+  }
+
   // group of entries GRP g .. GRP g + GRP - 1 = neighbouring lanes of one wave (256-thread blocks)
   const uint32_t kind = r.kk & KIND_MASK;
   const uint32_t t0m1 = r.T[0];  // 0xFFFFFFFF unless drawn by inversion
@@ -333,9 +355,23 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
 }
 
 __device__ __forceinline__ void prep_alias_walk(const PrepArgs &a) {
-  const int stride = (int)gridDim.x * ALIAS_WAVES;
-  for (int i = (int)blockIdx.x * ALIAS_WAVES + (int)(threadIdx.x >> 6); i < a.E; i += stride)
-    prep_alias_body(a, i, (int)blockIdx.y);
+  const int w = (int)blockIdx.x * ALIAS_WAVES + (int)(threadIdx.x >> 6), stride = (int)gridDim.x * ALIAS_WAVES;
+  if (a.alias_list) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0)  // the next call's count word
+      a.alias_n[(a.gen + 1u) & 1u] = (unsigned long long)(a.gen + 1u) << 32;
+    const unsigned long long v = a.alias_n[a.gen & 1u];
+    const uint32_t n = (uint32_t)v;
+    // the list, when k_prep filled it in this call and it has at most one part per wave of the
+    // first grid row (a longer one, spread by arrival order, balanced worse than the entry walk)
+    if ((uint32_t)(v >> 32) == a.gen && n <= (uint32_t)stride && n <= 2u * (uint32_t)a.E) {
+      if (blockIdx.y == 0 && w < (int)n) {
+        const uint32_t it = a.alias_list[w];
+        prep_alias_body(a, (int)(it >> 1), (int)(it & 1u));
+      }
+      return;
+    }
+  }
+  for (int i = w; i < a.E; i += stride) prep_alias_body(a, i, (int)blockIdx.y);  // grid.y: the part
 }
 __global__ void __launch_bounds__(64 * ALIAS_WAVES) k_prep_alias(PrepArgs a) { prep_alias_walk(a); }
 __global__ void __launch_bounds__(64 * ALIAS_WAVES) k_prep_alias_job(const PrepArgs *__restrict__ t, int j) {

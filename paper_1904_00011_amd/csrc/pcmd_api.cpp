@@ -101,16 +101,16 @@ int pcmd_create(pcmd_ctx **out, int hip_device) {
   // ln k! in FP64 for the likelihoods' ln d_j! (k < LNFACT64_N; lgamma beyond)
   std::vector<double> lf(LNFACT64_N);
   for (int k = 0; k < LNFACT64_N; ++k) lf[k] = std::lgamma((double)k + 1.0);
-  if (hipMalloc(&c->lnfact, sizeof tab) != hipSuccess || hipMalloc(&c->status, 8) != hipSuccess ||
+  if (hipMalloc(&c->lnfact, sizeof tab) != hipSuccess || hipMalloc(&c->status, 32) != hipSuccess ||
       hipMalloc(&c->counter, 8) != hipSuccess || hipMalloc(&c->lnfact64, LNFACT64_N * sizeof(double)) != hipSuccess) {
     (void)hipGetLastError();
     pcmd_destroy(c);
     return PCMD_E_NOMEM;
   }
-  uint32_t zeros[2] = {0u, 0u};
+  uint32_t zeros[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
   if (hipMemcpy(c->lnfact, tab, sizeof tab, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->lnfact64, lf.data(), LNFACT64_N * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->status, zeros, 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->status, zeros, 32, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(c->counter, zeros, 8, hipMemcpyHostToDevice) != hipSuccess) {
     pcmd_destroy(c);
     return PCMD_E_HIP;
@@ -134,7 +134,7 @@ void pcmd_destroy(pcmd_ctx *c) {
   batch_destroy(c);
   Buf *bufs[] = {&c->rec,     &c->thr,     &c->pc,      &c->fl64,    &c->part,     &c->F,       &c->G,
                  &c->mom_part, &c->fft,    &c->mlp_act, &c->mlp_pre, &c->mlp_dza, &c->mlp_dzb, &c->mlp_grad,
-                 &c->mlp_part, &c->mlp_ws, &c->mlp_lpart, &c->ll_part, &c->blk, &c->alias, &c->rdesc};
+                 &c->mlp_part, &c->mlp_ws, &c->mlp_lpart, &c->ll_part, &c->blk, &c->alias, &c->rdesc, &c->alias_list};
   for (Buf *b : bufs) release(*b);
   if (c->lnfact) (void)hipFree(c->lnfact);
   if (c->lnfact64) (void)hipFree(c->lnfact64);
@@ -372,6 +372,7 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
     if ((r = ensure(c, c->pc, (size_t)E * 2 * sizeof(PtrsConst), "rejection constants"))) return r;
     if ((r = ensure(c, c->alias, (size_t)E * 2 * ALIAS_COLS * 4, "alias columns"))) return r;
     if ((r = ensure(c, c->rdesc, (size_t)E * 4, "reddened-part descriptors"))) return r;
+    if ((r = ensure(c, c->alias_list, (size_t)E * 2 * 4, "alias-part list"))) return r;
   }
   if ((r = ensure(c, c->fl64, (size_t)E * BP * 8, "fluxes"))) return r;
   if ((r = ensure(c, c->part, (size_t)nchunks * S * B * npx * 4, "partial sums"))) return r;
@@ -455,7 +456,9 @@ int pcmd_simulate(pcmd_ctx *c, const pcmd_iso *iso, const pcmd_obs *o, float *ma
                 o->dust_frac,
                 (uint32_t *)c->rdesc.p,
                 c->status + 1,
-                ++c->thin_gen};
+                ++c->thin_gen,
+                (uint32_t *)c->alias_list.p,
+                (unsigned long long *)(c->status + 2)};
     e = launch_prep(pa, s);
     if (e == hipSuccess) e = launch_prep_alias(pa, s);
     if (e != hipSuccess) return hip_fail(c, e, "k_prep");

@@ -32,11 +32,14 @@ struct pcmd_ctx {
   // timer events not in use: recycled, and created ahead when timing is switched on, because
   // creating events inside a timed loop stalled the host for tens of milliseconds now and then
   std::vector<hipEvent_t> ev_pool;
-  Buf rec, thr, pc, fl64, part, F, G, mom_part, fft, ll_part, blk, alias, rdesc;
+  Buf rec, thr, pc, fl64, part, F, G, mom_part, fft, ll_part, blk, alias, rdesc, alias_list;
   Buf mlp_act, mlp_pre, mlp_dza, mlp_dzb, mlp_grad, mlp_part, mlp_ws, mlp_lpart;
   float *lnfact = nullptr;     // [256]
   double *lnfact64 = nullptr;  // [LNFACT64_N] ln k! in FP64 (likelihoods)
-  uint32_t *status = nullptr;  // [2]: status bits; the generation of the last call that thinned an entry
+  // [6]: status bits; the generation of the last call that thinned an entry; then two 64-bit
+  // words generation << 32 | length of the list of alias parts that k_prep builds (the word of
+  // generation g is g & 1, and k_prep_alias of call g prepares the other one for call g + 1)
+  uint32_t *status = nullptr;
   uint32_t thin_gen = 0;       // generation of the last pcmd_simulate call
   uint32_t *counter = nullptr; // [1]
   pcmd_batch_plan *batch = nullptr;

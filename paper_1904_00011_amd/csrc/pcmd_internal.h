@@ -83,6 +83,11 @@ struct PrepArgs {
   uint32_t *rdesc;     // [E] reddened part: k_lo << 12 | log2 M << 8 | KIND_ALIAS, or KIND_PTRS
   uint32_t *thin_seen;  // set to gen when an entry is thinned (null: not recorded)
   uint32_t gen;
+  // k_prep appends the alias parts (i << 1 | part) to alias_list, counting them in
+  // alias_n[gen & 1] = gen << 32 | count (set to gen << 32 by the previous call's k_prep_alias);
+  // k_prep_alias walks that list when it is valid and short, else every entry.  Null: no list.
+  uint32_t *alias_list;          // [2E]
+  unsigned long long *alias_n;   // [2]
 };
 
 // Sampler over (pixel block of 256, chunk of CHUNK entries) tiles (k_sample).
