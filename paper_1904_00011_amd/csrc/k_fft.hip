@@ -16,6 +16,8 @@
 // region's pixels are kept.
 #include <math.h>
 
+#include <algorithm>
+
 #include "pcmd_device.h"
 #include "pcmd_internal.h"
 
@@ -126,13 +128,16 @@ __device__ __forceinline__ int bitrev(int i, int logn) { return (int)(__brev((un
 
 // Row transforms.  mode 0: real FP32 input rows -> forward -> complex out.
 //                  mode 1: complex in -> inverse -> real FP32 out scaled by 1/N^2.
+//                  mode 2: complex in -> forward, times the row of S (cin2), inverse -> complex out.
+//                  mode 3: complex in -> forward -> complex out.
 // Block x transforms row y0 + x of band y; mode 1 writes only the columns [xa, xb) of it.  With
 // `skip` given, the kernel does nothing unless *skip is non-zero (PSF spectra that are current).
+// Modes 2 and 3 read their whole row before writing it, so cout may be cin.
 template <int MODE>
-__global__ void __launch_bounds__(256) k_fft_rows(const float *__restrict__ rin, const cplx *__restrict__ cin,
-                                                  cplx *__restrict__ cout, float *__restrict__ rout, int N, int logN,
+__global__ void __launch_bounds__(1024) k_fft_rows(const float *__restrict__ rin, const cplx *cin, cplx *cout,
+                                                  float *__restrict__ rout, int N, int logN,
                                                   const cplx *__restrict__ tw, int y0, int xa, int xb,
-                                                  const uint32_t *__restrict__ skip) {
+                                                  const uint32_t *__restrict__ skip, const cplx *__restrict__ cin2) {
   extern __shared__ cplx row[];
   if (skip && *skip == 0u) return;
   const int y = y0 + blockIdx.x, b = blockIdx.y;
@@ -146,11 +151,51 @@ __global__ void __launch_bounds__(256) k_fft_rows(const float *__restrict__ rin,
   }
   __syncthreads();
   fft_stages(row, logN, N, tw, MODE == 1, threadIdx.x, blockDim.x, true);
+  if (MODE == 2) {
+    // times the spectrum, in-place bit reversal (the thread of the smaller index of each pair
+    // swaps it), inverse
+    for (int i = threadIdx.x; i < N; i += blockDim.x) row[i] = cmul(row[i], cin2[base + i]);
+    __syncthreads();
+    for (int i = threadIdx.x; i < N; i += blockDim.x) {
+      const int r = bitrev(i, logN);
+      if (i < r) {
+        const cplx u = row[i];
+        row[i] = row[r];
+        row[r] = u;
+      }
+    }
+    __syncthreads();
+    fft_stages(row, logN, N, tw, true, threadIdx.x, blockDim.x, true);
+  }
   const double scale = 1.0 / ((double)N * (double)N);
-  if (MODE == 0) {
+  if (MODE != 1) {
     for (int i = threadIdx.x; i < N; i += blockDim.x) cout[base + i] = row[i];
   } else {
     for (int i = xa + threadIdx.x; i < xb; i += blockDim.x) rout[base + i] = (float)(row[i].x * scale);
+  }
+}
+
+// In-place transpose of each band's N x N complex matrix: the block at (i, j), i < j, swaps
+// the 32 x 32 tiles (i, j) and (j, i) through LDS (rows of 32 elements, 512 contiguous bytes per
+// access); a diagonal block transposes its tile; blocks below the diagonal return.  It turns the
+// column transform into a row transform over contiguous memory: the column pass over 4096-point
+// columns held two columns per workgroup and read 32 bytes of every 64 KB row.
+constexpr int TT = 32;
+__global__ void __launch_bounds__(256) k_transpose_c(cplx *X, int N, const uint32_t *__restrict__ skip) {
+  __shared__ cplx ta[TT][TT + 1], tb[TT][TT + 1];
+  if (skip && *skip == 0u) return;
+  const int i = blockIdx.y, j = blockIdx.x;
+  if (i > j) return;
+  cplx *M = X + (size_t)blockIdx.z * N * N;
+  const int tx = threadIdx.x & (TT - 1), ty = threadIdx.x >> 5;  // 32 x 8 threads
+  for (int r = ty; r < TT; r += 8) {
+    ta[r][tx] = M[(size_t)(i * TT + r) * N + j * TT + tx];
+    if (i != j) tb[r][tx] = M[(size_t)(j * TT + r) * N + i * TT + tx];
+  }
+  __syncthreads();
+  for (int r = ty; r < TT; r += 8) {
+    M[(size_t)(j * TT + r) * N + i * TT + tx] = ta[tx][r];
+    if (i != j) M[(size_t)(i * TT + r) * N + j * TT + tx] = tb[tx][r];
   }
 }
 
@@ -158,7 +203,7 @@ __global__ void __launch_bounds__(256) k_fft_rows(const float *__restrict__ rin,
 // given, only when *skip is non-zero).  mode 1: forward, multiply by the PSF spectrum, inverse.
 // mode 2: multiply the forward-transformed columns by the spectrum and inverse, into Y.
 template <int MODE>
-__global__ void __launch_bounds__(256) k_fft_cols(cplx *__restrict__ X, const cplx *__restrict__ S, int N, int logN,
+__global__ void __launch_bounds__(1024) k_fft_cols(cplx *__restrict__ X, const cplx *__restrict__ S, int N, int logN,
                                                   int CB, const cplx *__restrict__ tw, cplx *__restrict__ Y,
                                                   const uint32_t *__restrict__ skip) {
   extern __shared__ cplx col[];  // [CB][N]
@@ -237,31 +282,55 @@ hipError_t launch_conv_fft(const float *F, const float *psf, int B, int N, int K
   uint32_t *flag = (uint32_t *)(copy + (size_t)R * B * K * K);
   const int CB = cols_per_block(N);
   if ((size_t)CB * N * sizeof(cplx) > 160 * 1024) return hipErrorInvalidValue;
-  const int rthreads = N / 2 < 256 ? N / 2 : 256;
-  const int cthreads = 256;
+  // one thread per radix-2^2 butterfly (N / 4 per transform) up to 1024: a 4096-point row holds
+  // 64 KB of LDS, so two blocks fit a CU, and 256 threads left two waves per SIMD to hide the
+  // LDS and barrier latency of the stages
+  const int rthreads = std::min(std::max(N / 4, 64), 1024);
+  const int cthreads = std::min(std::max(CB * N / 4, 64), 1024);
   const size_t rl = N * sizeof(cplx), cl = CB * N * sizeof(cplx);
   if (fresh) hipLaunchKernelGGL(k_twiddles, dim3((N / 2 + 255) / 256), dim3(256), 0, s, tw, N);
   // PSF spectra, rebuilt only when the PSF (or the layout: fresh) changed.  psf is
   // [B][K][K] (grid 1) or [B][16][K][K]: region r of band b at psf + (b R + r) K K.
   hipLaunchKernelGGL(k_psf_update, dim3(1), dim3(1024), 0, s, psf, copy, (int64_t)R * B * K * K, fresh ? 1 : 0, flag);
+  // One PSF and N >= 1024: the column transforms run as row transforms of the transposed matrix
+  // (its spectrum is kept transposed); the sub-pixel grid and smaller N keep the column kernels
+  // (at 512 the two transposes cost more than the strided column reads they save).
+  const bool tr = R == 1 && N >= 1024;
+  const dim3 tgrid((unsigned)(N / TT), (unsigned)(N / TT), (unsigned)B);
   for (int r = 0; r < R; ++r) {
     cplx *Sr = Sp + (size_t)r * B * NN;
     // wrap into G (free at this point), transform rows and columns
     hipLaunchKernelGGL(k_psf_wrap, dim3(256, B), dim3(256), 0, s, psf + (size_t)r * K * K, K, N, G, (int64_t)R * K * K,
                        flag);
     hipLaunchKernelGGL(k_fft_rows<0>, dim3(N, B), dim3(rthreads), rl, s, G, nullptr, Sr, nullptr, N, logN, tw, 0, 0, N,
-                       flag);
-    hipLaunchKernelGGL(k_fft_cols<0>, dim3(N / CB, B), dim3(cthreads), cl, s, Sr, nullptr, N, logN, CB, tw, nullptr,
-                       flag);
+                       flag, nullptr);
+    if (tr) {
+      hipLaunchKernelGGL(k_transpose_c, tgrid, dim3(256), 0, s, Sr, N, flag);
+      hipLaunchKernelGGL(k_fft_rows<3>, dim3(N, B), dim3(rthreads), rl, s, nullptr, Sr, Sr, nullptr, N, logN, tw, 0, 0,
+                         N, flag, nullptr);
+    } else {
+      hipLaunchKernelGGL(k_fft_cols<0>, dim3(N / CB, B), dim3(cthreads), cl, s, Sr, nullptr, N, logN, CB, tw, nullptr,
+                         flag);
+    }
   }
   // image: rows forward
   hipLaunchKernelGGL(k_fft_rows<0>, dim3(N, B), dim3(rthreads), rl, s, F, nullptr, X, nullptr, N, logN, tw, 0, 0, N,
-                     nullptr);
+                     nullptr, nullptr);
+  if (tr) {
+    // transpose, columns forward x spectrum inverse as rows, transpose back, rows inverse
+    hipLaunchKernelGGL(k_transpose_c, tgrid, dim3(256), 0, s, X, N, nullptr);
+    hipLaunchKernelGGL(k_fft_rows<2>, dim3(N, B), dim3(rthreads), rl, s, nullptr, X, X, nullptr, N, logN, tw, 0, 0, N,
+                       nullptr, Sp);
+    hipLaunchKernelGGL(k_transpose_c, tgrid, dim3(256), 0, s, X, N, nullptr);
+    hipLaunchKernelGGL(k_fft_rows<1>, dim3(N, B), dim3(rthreads), rl, s, nullptr, X, nullptr, G, N, logN, tw, 0, 0, N,
+                       nullptr, nullptr);
+    return hipGetLastError();
+  }
   if (R == 1) {
     // columns forward x spectrum inverse, rows inverse
     hipLaunchKernelGGL(k_fft_cols<1>, dim3(N / CB, B), dim3(cthreads), cl, s, X, Sp, N, logN, CB, tw, nullptr, nullptr);
     hipLaunchKernelGGL(k_fft_rows<1>, dim3(N, B), dim3(rthreads), rl, s, nullptr, X, nullptr, G, N, logN, tw, 0, 0, N,
-                       nullptr);
+                       nullptr, nullptr);
     return hipGetLastError();
   }
   // sub-pixel grid: columns forward once; per region the product transformed back, the rows of
@@ -273,7 +342,7 @@ hipError_t launch_conv_fft(const float *F, const float *psf, int B, int N, int K
     hipLaunchKernelGGL(k_fft_cols<2>, dim3(N / CB, B), dim3(cthreads), cl, s, X, Sp + (size_t)r * B * NN, N, logN, CB, tw,
                        Y, nullptr);
     hipLaunchKernelGGL(k_fft_rows<1>, dim3(side, B), dim3(rthreads), rl, s, nullptr, Y, nullptr, G, N, logN, tw,
-                       ry * side, rx * side, (rx + 1) * side, nullptr);
+                       ry * side, rx * side, (rx + 1) * side, nullptr, nullptr);
   }
   return hipGetLastError();
 }

@@ -393,7 +393,7 @@ def test_large_config_sampled(ctx):
     assert np.array_equal(hg, ho)  # identical magnitudes bin identically
 
 
-@pytest.mark.parametrize("N,K", [(64, 5), (64, 31), (64, 63), (128, 31), (32, 1)])
+@pytest.mark.parametrize("N,K", [(64, 5), (64, 31), (64, 63), (128, 31), (32, 1), (32, 7), (16, 5)])
 def test_fft_path_against_oracle(ctx, N, K):
     """FFT convolution (power-of-two sides) against the oracle's direct periodic sum."""
     G, lam, f32, obs = _headline_lam(3.5, seed=1005, stride=25)
