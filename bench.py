@@ -56,7 +56,7 @@ OPS_PER_DRAW = 40 / 4 + 1
 # and WRITE_SIZE calibrated against a copy of known size
 # (profiles/k_sample_headline_256x256_52500_counters.md).  Set to None whenever k_sample changes
 # until the counters are taken again.
-SAMPLE_TRAFFIC_BYTES = 114.7e6
+SAMPLE_TRAFFIC_BYTES = 111.3e6
 # The same for the first 512x512, Npix = 1e6 step (profiles/k_sample_large_512x512_52500_counters.md).
 LARGE_SAMPLE_TRAFFIC_BYTES = 1072.2e6
 
