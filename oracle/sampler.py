@@ -40,9 +40,10 @@ How a Poisson count is drawn is not fixed by the paper.  The rule here:
   Stirling series.  Both sides of the parity test take the same FP32 steps.
 * C3b, thinning -- for an entry drawn by C1b or C2 under a split 0 < F < 1 --
   every such entry (lambda >= 2) when F is not 1/2; at F = 1/2 the entries with
-  lambda >= 64 (below that the one-bit-per-star rule of C3 is cheaper: most of their
-  stars take bits of a block shared by 16 entries; above it a few hundred stars
-  would each need a bit) -- the unreddened and reddened counts
+  lambda >= 4, the lowest lambda whose halves still take the alias rule (below
+  that nearly all stars take bits of a block shared by 16 entries; from about
+  there on most entries have more stars than those 8 bits, and the rest would
+  each need a bit of a block of their own) -- the unreddened and reddened counts
   are drawn directly as independent
   Poisson((1 - F) lambda) and Poisson(F lambda) counts (the two products in
   FP64): the first with the entry's inversion word, the second with word
@@ -82,7 +83,7 @@ from .rng import (TAG_DUST, TAG_MAIN, TAG_PTRS, TAG_PTRS_RED, TAG_RED, TAG_SPLIT
                   philox4x32_10, u01_open_f32)
 
 LAM_SWITCH = 10.0
-LAM_THIN_HALF = 64.0     # F = 1/2: entries at or above this lambda are thinned (C3b)
+LAM_THIN_HALF = 4.0      # F = 1/2: entries at or above this lambda are thinned (C3b)
 KMAX = 63
 TWO32 = 2 ** 32
 F32 = np.float32
@@ -412,7 +413,7 @@ def sample_pixels(lam: np.ndarray, flux32: np.ndarray, seed: int, px: np.ndarray
             cols = inv[sel]
             n[:, cols] = (U[:, cols, None] >= T[None, :, :]).sum(axis=-1)
         tab = np.nonzero(lb >= ALIAS_MIN)[0]          # entries drawn by C1b or C2
-        # C3b: the thinned entries (all of tab when F != 1/2; those at lambda >= 64 when F = 1/2)
+        # C3b: the thinned entries (all of tab when F != 1/2; those at lambda >= 4 when F = 1/2)
         if split and 0.0 < frac < 1.0:
             thin = tab if frac != 0.5 else np.nonzero(lb >= LAM_THIN_HALF)[0]
         else:

@@ -53,9 +53,13 @@ struct pcmd_batch_plan {
   bool desc_pending = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  uint32_t thin_gen = 0;  // generation of the current call's thinned-entry words
 };
 
 namespace pcmd {
+
+// job j's thinned-entry word: k_prep stores the call's generation there when it thins an entry
+static uint32_t *thin_word(pcmd_batch_plan *p, int j) { return (uint32_t *)p->counters.p + p->n_jobs + 1 + j; }
 
 static void plan_free_device(pcmd_batch_plan *p) {
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
@@ -195,8 +199,10 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
   if ((r = ensure(c, p->mom_part, (size_t)n_jobs * hess_max_blocks() * 3 * 8, "batch moment partials"))) return r;
   if ((r = ensure(c, p->ll_part, (size_t)n_jobs * loglike_blocks(g->nx * g->ny) * 8, "batch likelihood partials")))
     return r;
-  if ((r = ensure(c, p->counters, (size_t)(n_jobs + 1) * 4, "batch counters"))) return r;
-  hipError_t e = hipMemsetAsync(p->counters.p, 0, (size_t)(n_jobs + 1) * 4, p->stream);  // outside any graph
+  // [n_jobs] Hess block counters, the persistent sampler's item counter, [n_jobs] thinned-entry
+  // generation words
+  if ((r = ensure(c, p->counters, (size_t)(2 * n_jobs + 1) * 4, "batch counters"))) return r;
+  hipError_t e = hipMemsetAsync(p->counters.p, 0, (size_t)(2 * n_jobs + 1) * 4, p->stream);  // outside any graph
   if (e != hipSuccess) return hip_fail(c, e, "clearing batch counters");
   size_t o = 0;
   p->o_prep = o;
@@ -244,6 +250,9 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
   BlockPrepArgs *bpa = (BlockPrepArgs *)(h + p->o_bprep);
   BlockSampleArgs *bsa = (BlockSampleArgs *)(h + p->o_bsamp);
   const int B = p->B, BP = B <= 2 ? 2 : 4;
+  // a new generation per call: a job's word equals it only if this call's k_prep thinned one of
+  // its entries (a stale match would only cost the sampler a scan of the group flags)
+  ++p->thin_gen;
   int item0 = 0;
   std::vector<int> first_item(p->n_jobs, 0);
   for (int t = 0; t < p->n_jobs; ++t) {
@@ -323,7 +332,9 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
                      ji.sampler == PCMD_SAMPLER_HYBRID ? bp.brec : nullptr,
                      thin_mode_of_split(sm),
                      jobs[j].obs.dust_frac,
-                     (uint32_t *)p->rdesc.p + ji.o_rdesc};
+                     (uint32_t *)p->rdesc.p + ji.o_rdesc,
+                     thin_word(p, j),
+                     p->thin_gen};
     ReduceArgs rr;
     memset(&rr, 0, sizeof rr);
     rr.B = B;
@@ -405,6 +416,8 @@ static void fill_descriptors(pcmd_ctx *c, pcmd_batch_plan *p, const pcmd_job *jo
     s.lnfact = c->lnfact;
     s.alias = (const uint32_t *)p->alias.p + ji.o_alias;
     s.rdesc = (const uint32_t *)p->rdesc.p + ji.o_rdesc;
+    s.thin_seen = thin_word(p, j);
+    s.gen = p->thin_gen;
     bj.item0 = first_item[j];
     bj.items = ji.items;
     bj.pblocks = ji.pblocks;
@@ -439,7 +452,8 @@ static hipError_t enqueue(pcmd_ctx *c, pcmd_batch_plan *p, hipStream_t s) {
   if (e == hipSuccess)
     e = launch_sample_persistent(sa, p->n_jobs, p->total_items, p->B, persist, c->n_cu * p->wg, s);
   // then, in the order pcmd_simulate takes: the thinned entries of F = 1/2 jobs, added to the
-  // per-point partials, and the block-rule draws, stored (block sampler) or added (hybrid)
+  // per-point partials (a launch per job; a job whose k_prep thinned nothing returns at once),
+  // and the block-rule draws, stored (block sampler) or added (hybrid)
   for (int t = 0; t < p->n_jobs && e == hipSuccess; ++t) {
     const int j = p->order[t];
     const JobInfo &ji = p->info[j];

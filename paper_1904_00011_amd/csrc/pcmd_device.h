@@ -24,9 +24,12 @@ constexpr uint32_t TAG_RED = 10, TAG_PTRS_RED = 11;
 // a table entry whose unreddened and reddened counts are drawn as two thinned parts.
 constexpr uint32_t KIND_ZERO = 0, KIND_INV = 1, KIND_PTRS = 2, KIND_ALIAS = 3;
 constexpr uint32_t KIND_MASK = 0x0Fu, FLAG_THIN = 0x80u;
-// Dust split F = 1/2: table entries at or above this lambda are thinned (their stars would each
-// need a split bit); the others keep one bit per star.
-constexpr double LAM_THIN_HALF = 64.0;
+// Dust split F = 1/2: table entries at or above this lambda are thinned; the others keep one bit
+// per star.  4 is the lowest lambda whose halves (>= ALIAS_MIN) still take the alias rule, and
+// from about there on nearly every 64-pixel wave has a lane with more than the 8 stars that the
+// shared split block covers, so a bit per star would cost a Philox block per entry, where the
+// thinned entry costs a quarter block and a second table read.
+constexpr double LAM_THIN_HALF = 4.0;
 // Alias rule for ALIAS_MIN <= lambda < ALIAS_MAX: M = 2^b <= ALIAS_COLS columns of 2^(32-b) words
 // each (column = top b bits of the inversion word), one packed word per column:
 // height << b | alias.  Each entry's table has room for ALIAS_COLS columns.

@@ -127,6 +127,35 @@ def test_batch_graph_replay_with_new_parameters(ctx):
         assert float(x) == 1000.0
 
 
+def test_batch_draws_the_thinned_entries_of_the_jobs_that_have_them(ctx):
+    """F = 1/2 jobs with many entries at lambda >= 4 (log Npix 4.5, thinned) among jobs with none
+    (log Npix 1): the thinned-entry pass runs for the jobs whose preparation of this call thinned
+    an entry (the others' launches return at once), bit-identical to sequential calls; then the
+    two kinds swap places under the replayed graph."""
+    import torch
+    dev = torch.device("cuda")
+    hess_d, mom_d, grid = _data(ctx)
+    for rep in range(2):
+        jobs, n_thin = [], []
+        for k, (g, model, obs) in enumerate(si.batch_workload(10, 80, nim_log2=(4.0, 5.6), entries=(400, 2500),
+                                                              psf_k=7)):
+            model.log_npix = 4.5 if (k + rep) % 2 == 0 else 1.0
+            obs.dust_model, obs.dust_frac, obs.seed = 2, 0.5, 900 + 10 * rep + k
+            lam, _, f32 = oe.build_entries(model, g)
+            n_thin.append(int((lam >= 4.0).sum()))
+            jobs.append(dict(lam=torch.from_numpy(lam).to(dev), flux=torch.from_numpy(f32).to(dev), obs=obs,
+                             psf=torch.from_numpy(obs.psf).to(dev), conv_path=1))
+        assert min(n_thin) == 0 and min(n_thin[(rep % 2)::2]) > 50, n_thin
+        print(f"[case] batch thinned jobs rep={rep} thinned entries per job={n_thin}", flush=True)
+        ll_s, h_s = _sequential(ctx, jobs, grid, hess_d, mom_d, 0)
+        ll_b = torch.empty(len(jobs), dtype=torch.float64, device=dev)
+        h_b = torch.empty((len(jobs), 100 * 100), dtype=torch.int32, device=dev)
+        ctx.batch_run(jobs, grid, hess_d, mom_d, ll_b, mode=0, hess_out=h_b, use_graph=True)
+        ctx.sync()
+        assert np.array_equal(h_b.cpu().numpy(), h_s)
+        assert np.array_equal(ll_b.cpu().numpy(), ll_s)
+
+
 def test_batch_autotune_and_validation(ctx):
     import torch
     import paper_1904_00011_amd as P

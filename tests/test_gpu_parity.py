@@ -240,13 +240,13 @@ def test_rule_boundaries(ctx):
     with the F = 1/2 bit split and with thinning (F = 0.3, 0.8): every count against the oracle."""
     lam = np.array([1.9999999, 2.0, 2.0000001, 3.7, 9.99, 10.0, 63.5, 255.0, 300.0, 511.9, 511.999999,
                     512.0, 512.5, 700.0, 0.0, 0.7, 1000.0, 1500.0, 1e-11, 3e-10, 1e-7, 63.99999999, 64.0,
-                    1023.9, 1024.0, 5000.0])
+                    1023.9, 1024.0, 5000.0, 3.99999999, 4.0, 4.0000001])
     E = len(lam)
     f32 = np.linspace(0.2, 1.0, 2 * E).reshape(2, E).astype(np.float32) * 1e-3
     # F = 0.3 and 0.8 thin the entries at lambda >= 2 into two parts, whose own lambdas fall on
     # both sides of 512 (700 x 0.8, 1000 x 0.3, 1500 x 0.3) and below 2 (2.0 x 0.3); F = 1/2 thins
-    # the entries from lambda = 64 on (halves on both sides of 512: 1023.9, 1024, 5000) and splits
-    # the others one bit per star (63.99999999 on the edge)
+    # the entries from lambda = 4 on (halves on both sides of 512: 1023.9, 1024, 5000) and splits
+    # the others one bit per star (3.99999999 on the edge)
     # F = 1e-12 and 1 - 1e-12: one thinned part of every table entry is below 2^-32 per pixel, so
     # its table has the single outcome 0
     for dust, frac in ((0, 0.5), (2, 0.5), (2, 0.3), (1, 0.8), (2, 1e-12), (1, 1.0 - 1e-12)):

@@ -299,9 +299,9 @@ def test_lognormal_dust_draws():
 
 
 @pytest.mark.parametrize("lam,frac", [(40.0, 0.3), (5.0, 0.7), (2000.0, 0.6), (700.0, 0.8), (64.0, 0.5),
-                                      (3000.0, 0.5)])
+                                      (3000.0, 0.5), (4.0, 0.5), (10.0, 0.5)])
 def test_thinning_parts_are_independent_poisson(lam, frac):
-    """C3b: for an entry at lambda >= 2 under a split 0 < F < 1 (at F = 1/2: lambda >= 64) the
+    """C3b: for an entry at lambda >= 2 under a split 0 < F < 1 (at F = 1/2: lambda >= 4) the
     unreddened and reddened counts are independent Poisson((1 - F) lambda) and Poisson(F lambda)
     (alias parts below 512, rejection above), so the total is Poisson(lambda) and each star is
     reddened with probability F."""
@@ -338,10 +338,11 @@ def test_thinning_uses_its_own_words():
     assert np.array_equal(s["counts"][:, 2] - s["red"][:, 2], want_c)
 
 
-@pytest.mark.parametrize("lam,thinned", [(64.0, True), (63.9, False), (1500.0, True), (10.0, False)])
-def test_half_split_thins_from_lambda_64(lam, thinned):
-    """At F = 1/2 an entry at lambda >= 64 draws its two halves from its own words through the
-    tables of lambda / 2 (C3b); below 64 its count is drawn whole and split one bit per star
+@pytest.mark.parametrize("lam,thinned", [(4.0, True), (3.999, False), (1500.0, True), (10.0, True), (64.0, True),
+                                         (2.5, False)])
+def test_half_split_thins_from_lambda_4(lam, thinned):
+    """At F = 1/2 an entry at lambda >= 4 draws its two halves from its own words through the
+    tables of lambda / 2 (C3b); below 4 its count is drawn whole and split one bit per star
     (C3), so the reddened count is the popcount of its split bits."""
     seed = 78
     px = np.arange(256)
