@@ -448,18 +448,87 @@ __device__ __forceinline__ uint32_t split_count(uint32_t n, uint32_t word, uint3
 // Poisson count of one table part: desc = k_lo << 12 | log2 M << 8 | KIND_ALIAS (one column of
 // the alias table: n = k_lo + (c if r < height_c else alias_c), u = c << (32 - b) | r) or
 // KIND_PTRS (transformed rejection on (p, i, tag, j) with the part's constants).
+__device__ __forceinline__ uint32_t alias_column_of(uint32_t desc, uint32_t u) { return u >> (32u - ((desc >> 8) & 0xFu)); }
+// the count from column word x of the column that u selects
+__device__ __forceinline__ uint32_t alias_count(uint32_t desc, uint32_t u, uint32_t x) {
+  const uint32_t b = (desc >> 8) & 0xFu;
+  const uint32_t c = u >> (32u - b);
+  return (desc >> 12) + ((u & (0xFFFFFFFFu >> b)) < (x >> b) ? c : (x & ((1u << b) - 1u)));
+}
+
 __device__ __forceinline__ uint32_t table_draw(uint32_t desc, uint32_t u, const uint32_t *__restrict__ tab,
                                                const PCMD_CONST PtrsConst *pcp, uint32_t p, uint32_t i, uint32_t tag,
                                                uint32_t k0, uint32_t k1, const float *__restrict__ lnfact,
                                                uint32_t &failed) {
-  if ((desc & KIND_MASK) == KIND_ALIAS) {
-    const uint32_t b = (desc >> 8) & 0xFu;
-    const uint32_t c = u >> (32u - b);
-    const uint32_t x = tab[c];
-    return (desc >> 12) + ((u & (0xFFFFFFFFu >> b)) < (x >> b) ? c : (x & ((1u << b) - 1u)));
-  }
+  if ((desc & KIND_MASK) == KIND_ALIAS) return alias_count(desc, u, tab[alias_column_of(desc, u)]);
   const PtrsConst cst = ld_const(pcp);
   return ptrs_draw(cst, p, i, tag, k0, k1, lnfact, failed);
+}
+
+// The thinned entries of quad q0 .. q0 + 3 in the thinned-entry pass (F = 1/2), with the quad's
+// inversion words w: the same counts and sums as the entry-by-entry path, but the column reads of
+// every alias part of the quad (up to eight) are issued before the first is used, so that their
+// latencies overlap instead of adding up.
+template <int B, bool DBG>
+__device__ __forceinline__ void thin_quad(const SampleArgs &a, uint32_t q0, const u4 &w, uint32_t p, bool dbg,
+                                          double (&acc_c)[B], double (&acc_r)[B], uint32_t &ptrs_failed) {
+  const PCMD_CONST EntryRec *rec = (const PCMD_CONST EntryRec *)a.rec;
+  const PCMD_CONST PtrsConst *pc = (const PCMD_CONST PtrsConst *)a.pc;
+  const PCMD_CONST uint32_t *rdesc = (const PCMD_CONST uint32_t *)a.rdesc;
+  uint32_t kk[4], d[4];
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    kk[q] = rec[q0 + q].kk;  // q0 + 3 < EP: the table is padded to whole groups
+    d[q] = (kk[q] & FLAG_THIN) ? rdesc[q0 + q] : 0u;
+    any = any || (kk[q] & FLAG_THIN);
+  }
+  if (!any) return;
+  // the quad's reddened-part words: counters (p, i / 4, TAG_RED, 0)
+  const u4 wr = philox10(p, q0 >> 2, TAG_RED, 0u, a.k0, a.k1);
+  uint32_t x0[4], x1[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const size_t i = q0 + (uint32_t)q;
+    x0[q] = 0u;
+    x1[q] = 0u;
+    if (!(kk[q] & FLAG_THIN)) continue;
+    if ((kk[q] & KIND_MASK) == KIND_ALIAS) x0[q] = a.alias[i * 2 * ALIAS_COLS + alias_column_of(kk[q], word_of(w, q))];
+    if ((d[q] & KIND_MASK) == KIND_ALIAS)
+      x1[q] = a.alias[(i * 2 + 1) * ALIAS_COLS + alias_column_of(d[q], word_of(wr, q))];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (!(kk[q] & FLAG_THIN)) continue;
+    const uint32_t i = q0 + (uint32_t)q;
+    const uint32_t nc = (kk[q] & KIND_MASK) == KIND_ALIAS
+                            ? alias_count(kk[q], word_of(w, q), x0[q])
+                            : ptrs_draw(ld_const(pc + 2 * (size_t)i), p, i, TAG_PTRS, a.k0, a.k1, a.lnfact, ptrs_failed);
+    const uint32_t red = (d[q] & KIND_MASK) == KIND_ALIAS
+                             ? alias_count(d[q], word_of(wr, q), x1[q])
+                             : ptrs_draw(ld_const(pc + 2 * (size_t)i + 1), p, i, TAG_PTRS_RED, a.k0, a.k1, a.lnfact,
+                                         ptrs_failed);
+    if (DBG && dbg) {
+      const size_t o = (size_t)((int64_t)p - a.px0) * (size_t)a.E + i;
+      a.dbg_counts[o] = nc + red;
+      if (a.dbg_red) a.dbg_red[o] = red;
+    }
+    if (!wave_any(nc + red != 0u)) continue;
+    const PCMD_CONST double *f = rec[i].fl;
+    double fv[B];
+#pragma unroll
+    for (int b = 0; b < B; ++b) fv[b] = f[b];
+    {
+      const double dc = (double)nc;
+#pragma unroll
+      for (int b = 0; b < B; ++b) acc_c[b] = fma(dc, fv[b], acc_c[b]);
+    }
+    if (wave_any(red != 0u)) {
+      const double dr = (double)red;
+#pragma unroll
+      for (int b = 0; b < B; ++b) acc_r[b] = fma(dr, fv[b], acc_r[b]);
+    }
+  }
 }
 
 // PASS (SamplePass): PASS_ALL draws every entry, the thinned ones (FLAG_THIN: two independent
@@ -524,6 +593,11 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
            __ballot(wa.w > gr->t0m1[3]) | __ballot(wb.x > gr->t0m1[4]) | __ballot(wb.y > gr->t0m1[5]) |
            __ballot(wb.z > gr->t0m1[6]) | __ballot(wb.w > gr->t0m1[7])) == 0ull)
         continue;
+      if (PASS == PASS_THIN) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) thin_quad<B, DBG>(a, (uint32_t)(g0 + 4 * h), h ? wb : wa, p, dbg, acc_c, acc_r, ptrs_failed);
+        continue;
+      }
       // the split bits of the group's 16-entry block: a slow group almost always has a star to
       // split, and the two groups of a block share them
       if (S == 2 && PASS != PASS_THIN && a.split_mode == SPLIT_HALF && split_blk != (gi >> 1)) {
