@@ -58,7 +58,7 @@ OPS_PER_DRAW = 40 / 4 + 1
 # until the counters are taken again.
 SAMPLE_TRAFFIC_BYTES = 111.3e6
 # The same for the first 512x512, Npix = 1e6 step (profiles/k_sample_large_512x512_52500_counters.md).
-LARGE_SAMPLE_TRAFFIC_BYTES = 1075.7e6
+LARGE_SAMPLE_TRAFFIC_BYTES = 1076.2e6
 
 
 def parse():
