@@ -98,7 +98,9 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
           a.rdesc[i] = KIND_PTRS;
         } else {
           a.rdesc[i] = KIND_ALIAS;
-          red_alias = true;
+          // F = 1/2: both halves have the same lambda and so the same table, which k_prep_alias
+          // builds once, with the unreddened half, and writes to both slots
+          red_alias = a.thin != THIN_HALF_HIGH;
         }
       }
     } else if (l > 0.0) {
@@ -219,7 +221,9 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
   if (i >= a.E) return;  // whole waves: i is wave-uniform
   // part 0: the entry's count (or its unreddened part); part 1: the reddened part (thinned)
   // (rdesc holds KIND_ZERO for every entry that is not thinned whenever thinning is on)
-  if (part == 0 ? (a.rec[i].kk & KIND_MASK) != KIND_ALIAS : a.thin == THIN_NONE || (a.rdesc[i] & KIND_MASK) != KIND_ALIAS)
+  // (at F = 1/2 the reddened half's table is the unreddened half's, written with it)
+  if (part == 0 ? (a.rec[i].kk & KIND_MASK) != KIND_ALIAS
+                : a.thin != THIN_TABLE || (a.rdesc[i] & KIND_MASK) != KIND_ALIAS)
     return;
   uint32_t *m = m_s[wv];
   uint16_t *sm = small_s[wv], *lg = large_s[wv];
@@ -231,6 +235,9 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
   const double lam = a.lam[i];
   // part 1 exists only for a thinned entry; part 0 of one is its unreddened share
   const bool thin = part == 1 || (a.rec[i].kk & FLAG_THIN) != 0u;
+  // F = 1/2, thinned, and the reddened half also on the alias rule (it has the same lambda): the
+  // table goes to both slots and the descriptor to both records
+  const bool twin = part == 0 && thin && a.thin == THIN_HALF_HIGH && (a.rdesc[i] & KIND_MASK) == KIND_ALIAS;
   const double l = !thin ? lam : part == 0 ? lam * (1.0 - a.frac) : lam * a.frac;
   double pk = exp(-l);
   double F = pk;
@@ -280,15 +287,19 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
     const uint32_t desc = ((uint32_t)klo << 12) | ((uint32_t)bits << 8) | KIND_ALIAS;
     if (part == 0)
       a.rec[i].kk = desc | (a.rec[i].kk & FLAG_THIN);
-    else
-      a.rdesc[i] = desc;
+    if (part == 1 || twin) a.rdesc[i] = desc;
   }
   wave_lds_sync();
   const int M = 1 << bits;
   const uint32_t cap = 1u << (32 - bits);
   uint32_t *out = a.alias + ((size_t)i * 2 + part) * ALIAS_COLS;
+  // column j's word to this part's slot and, for a twin, to the reddened half's slot after it
+  auto put = [&](int j, uint32_t word) {
+    out[j] = word;
+    if (twin) out[ALIAS_COLS + j] = word;
+  };
   if (single) {  // one outcome: height 0 and alias 0 in every column, n = k_lo always
-    for (int j = lane; j < M; j += 64) out[j] = 0u;
+    for (int j = lane; j < M; j += 64) put(j, 0u);
     return;
   }
   // stacks in ascending column order: each lane takes one column of every 64, ballots give the
@@ -333,7 +344,7 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
         lo = mid + 1;
     }
     const uint32_t al = nl > 0 ? (uint32_t)lg[nl - 1 - lo] : (uint32_t)col;  // nl = 0 only for malformed masses
-    out[col] = (m[col] << bits) | al;
+    put(col, (m[col] << bits) | al);
   }
   for (int j = lane; j < nl; j += 64) {  // pop index j: large number j + 1
     const int col = lg[nl - 1 - j];
@@ -350,7 +361,7 @@ __device__ __forceinline__ void prep_alias_body(const PrepArgs &a, int i, int pa
     // word then falls to the alias, the column itself)
     uint32_t word = ((cap - 1u) << bits) | (uint32_t)col;
     if (lo <= ns && j + 1 < nl) word = ((cap - (Dp[lo] - ex)) << bits) | (uint32_t)lg[nl - 2 - j];  // Dp[lo] - ex <= cap
-    out[col] = word;
+    put(col, word);
   }
 }
 
@@ -384,8 +395,9 @@ static dim3 prep_alias_grid(int E, int parts) {
   return dim3((unsigned)std::min((E + ALIAS_WAVES - 1) / ALIAS_WAVES, per_part), (unsigned)parts);
 }
 hipError_t launch_prep_alias(const PrepArgs &a, hipStream_t s) {
-  // grid.y: part 1 (the reddened part of a thinned entry) exists only when entries are thinned
-  hipLaunchKernelGGL(k_prep_alias, prep_alias_grid(a.E, a.thin != THIN_NONE ? 2 : 1), dim3(64 * ALIAS_WAVES), 0, s, a);
+  // grid.y: part 1 (the reddened part of a thinned entry) has a table of its own only when
+  // 0 < F < 1 and F != 1/2
+  hipLaunchKernelGGL(k_prep_alias, prep_alias_grid(a.E, a.thin == THIN_TABLE ? 2 : 1), dim3(64 * ALIAS_WAVES), 0, s, a);
   return hipGetLastError();
 }
 hipError_t launch_prep_alias_job(const PrepArgs *table, int j, int E, int parts, hipStream_t s) {

@@ -141,7 +141,7 @@ static int plan_build(pcmd_ctx *c, pcmd_batch_plan *p, int n_jobs, const pcmd_jo
     ji.npx = ji.N * ji.N;
     ji.K = jobs[j].obs.psf_k;
     ji.thin_mode = thin_mode_of_split(split_mode_of(&jobs[j].obs));
-    ji.alias_parts = ji.thin_mode != THIN_NONE ? 2 : 1;
+    ji.alias_parts = ji.thin_mode == THIN_TABLE ? 2 : 1;  // F = 1/2: the halves share one table
     ji.grid = psf_grid_of(&jobs[j].obs);
     // Every batch job keeps both partial streams (unreddened, reddened), so the persistent
     // sampler has one instantiation; a job without a split draws no reddened stars, its second
