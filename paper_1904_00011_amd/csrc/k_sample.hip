@@ -58,6 +58,7 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
   const int E = a.E, B = a.B;
   EntryRec r{{0xFFFFFFFFu, 0u, 0u}, KIND_ZERO, {0.0, 0.0, 0.0, 0.0}};
   bool red_alias = false;  // the entry is thinned and its reddened part is on the alias rule
+  double lam_inv = 0.0;    // lambda of an entry drawn by inversion (the group's density flag)
   if (i < E) {
     // every load before the first store (the output could alias the inputs for the compiler,
     // which otherwise waits for each load in turn)
@@ -112,6 +113,7 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
         r.T[0] = first[0] - 1u;
         for (uint32_t k = 1; k < 3 && k < K; ++k) r.T[k] = first[k];
         r.kk = (K << 8) | KIND_INV;
+        lam_inv = l;
       }
     }
   }
@@ -145,11 +147,14 @@ __device__ __forceinline__ void prep_body(const PrepArgs &a, int i) {
   const int first = (int)(threadIdx.x & 63u) & ~(GRP - 1);
   GroupRec gr;
   gr.flags = 0u;
+  double gsum = 0.0;
 #pragma unroll
   for (int q = 0; q < GRP; ++q) {
     gr.t0m1[q] = (uint32_t)__shfl((int)t0m1, first + q, 64);
     gr.flags |= (uint32_t)__shfl((int)fl, first + q, 64);
+    gsum += __shfl(lam_inv, first + q, 64);
   }
+  if (64.0 * gsum >= GRP_DENSE_LAMBDA64) gr.flags |= GRP_DENSE;
 #pragma unroll
   for (int q = 0; q < 7; ++q) gr.pad[q] = 0u;
   if ((i & (GRP - 1)) == 0 && i < EP) a.grp[i / GRP] = gr;
@@ -600,7 +605,7 @@ __device__ __forceinline__ void sample_tile(const SampleArgs &a, uint32_t p, int
       // the first thresholds are loaded only now: held across the Philox rounds they pushed the
       // scalar register file into spilling inside this loop
       __builtin_amdgcn_sched_barrier(0);
-      if (PASS != PASS_THIN && !(flags & (GRP_PTRS | GRP_ALIAS | (PASS == PASS_ALL ? GRP_THIN : 0u))) &&
+      if (PASS != PASS_THIN && !(flags & (GRP_PTRS | GRP_ALIAS | GRP_DENSE | (PASS == PASS_ALL ? GRP_THIN : 0u))) &&
           (__ballot(wa.x > gr->t0m1[0]) | __ballot(wa.y > gr->t0m1[1]) | __ballot(wa.z > gr->t0m1[2]) |
            __ballot(wa.w > gr->t0m1[3]) | __ballot(wb.x > gr->t0m1[4]) | __ballot(wb.y > gr->t0m1[5]) |
            __ballot(wb.z > gr->t0m1[6]) | __ballot(wb.w > gr->t0m1[7])) == 0ull)

@@ -39,6 +39,10 @@ struct GroupRec {
   uint32_t pad[7];
 };
 constexpr uint32_t GRP_INV = 1u, GRP_PTRS = 2u, GRP_ALIAS = 4u, GRP_THIN = 8u;
+// The group's inversion entries are dense enough (64 sum lambda >= GRP_DENSE_LAMBDA64) that a
+// 64-pixel wave almost surely draws a star from one of them: the sampler skips its no-star test.
+constexpr uint32_t GRP_DENSE = 16u;
+constexpr double GRP_DENSE_LAMBDA64 = 3.0;
 // Sampler passes: every entry (thinned ones inline); every entry but the thinned ones; only the
 // thinned ones, added to the partial sums the main pass stored.
 enum SamplePass { PASS_ALL = 0, PASS_MAIN = 1, PASS_THIN = 2 };
