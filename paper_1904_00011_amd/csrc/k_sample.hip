@@ -437,6 +437,10 @@ __device__ __forceinline__ uint32_t split_count(uint32_t n, uint32_t word, uint3
   if (mode == SPLIT_NONE) return 0u;
   uint32_t red = 0;
   if (mode == SPLIT_HALF) {
+    // no lane with more than one star (most entries of a sparse field): the byte's first bit
+    if (!wave_any(n > 1u)) return n & __builtin_amdgcn_ubfe(word, shift, 1u);
+    // no lane with more stars than the byte has bits
+    if (!wave_any(n > SPLIT_FIRST_BITS)) return __popc(__builtin_amdgcn_ubfe(word, shift, n));
     // the entry's byte sits at bit `shift` of `word`; its low min(n, 8) bits decide the first stars
     red = __popc(__builtin_amdgcn_ubfe(word, shift, min(n, SPLIT_FIRST_BITS)));
     const uint32_t extra = n > SPLIT_FIRST_BITS ? n - SPLIT_FIRST_BITS : 0u;
