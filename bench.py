@@ -56,9 +56,9 @@ OPS_PER_DRAW = 40 / 4 + 1
 # and WRITE_SIZE calibrated against a copy of known size
 # (profiles/k_sample_headline_256x256_52500_counters.md).  Set to None whenever k_sample changes
 # until the counters are taken again.
-SAMPLE_TRAFFIC_BYTES = 111.1e6
+SAMPLE_TRAFFIC_BYTES = 111.2e6
 # The same for the first 512x512, Npix = 1e6 step (profiles/k_sample_large_512x512_52500_counters.md).
-LARGE_SAMPLE_TRAFFIC_BYTES = 1076.0e6
+LARGE_SAMPLE_TRAFFIC_BYTES = 1076.2e6
 
 
 def parse():
