@@ -116,6 +116,27 @@ int pcmd_grid_prepare(int32_t n_entries, int32_t n_bands, const int32_t *iso_of_
 /* Host helper: per-isochrone SFH x MDF weight and Npix for `model` (Sec. 2.2). w_out [host][n_iso]. */
 int pcmd_iso_weights(const pcmd_model *model, const pcmd_isoset *set, double *w_out, double *npix_out);
 
+/* ---- Stochastic likelihood after a nested-sampling fit (App. A), host only, no context ----
+ * A simulated diagram is one random realisation, so a point's log-likelihood scatters from call to
+ * call with a long upper tail.  App. A re-simulates the best-fit point many times, takes the median
+ * as a ceiling L_max, caps every dead point's log-likelihood at L_max and recomputes the posterior
+ * weights and the remaining-evidence stopping criterion.  All arrays are host FP64 owned by the
+ * caller; NaN inputs, empty arrays and all-(-inf) masses return PCMD_E_INVAL with no output
+ * written (these calls take no context, so pcmd_last_error is not set).
+ *
+ * pcmd_lmax_ceiling: median of logl[n] (mean of the two middle values for even n).
+ * pcmd_cap_loglikes: out[i] = min(logl[i], lmax); out may alias logl; n = 0 allowed.
+ * pcmd_nested_weights: w_out[i] = L_i dX_i / sum_j L_j dX_j from logl[n] and log_dx[n] (the log
+ *   prior-volume width of each dead point), computed with the largest term factored out.
+ * pcmd_remaining_evidence: ln(Z + L_max,live X_final) - ln Z with Z = sum_i L_i dX_i.
+ * pcmd_effective_sample_size: Kish's 1 / sum w_i^2 of normalised weights w[n]. */
+int pcmd_lmax_ceiling(const double *logl, int64_t n, double *lmax_out);
+int pcmd_cap_loglikes(const double *logl, int64_t n, double lmax, double *out);
+int pcmd_nested_weights(const double *logl, const double *log_dx, int64_t n, double *w_out);
+int pcmd_remaining_evidence(const double *logl, const double *log_dx, int64_t n, double log_x_final,
+                            double logl_max_live, double *dlnz_out);
+int pcmd_effective_sample_size(const double *w, int64_t n, double *ess_out);
+
 /* Device grid: per-point isochrone index and IMF weight, uploaded once per fit. */
 typedef struct {
   int32_t n_entries, n_iso;

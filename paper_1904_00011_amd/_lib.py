@@ -114,6 +114,11 @@ def load(path: str = LIB_PATH):
         "pcmd_version": (C.c_char_p, []),
         "pcmd_grid_prepare": (C.c_int, [i32, i32, vp, vp, vp, i32, dbl, vp, vp, i32, vp]),
         "pcmd_iso_weights": (C.c_int, [C.POINTER(ModelS), C.POINTER(IsoSet), vp, C.POINTER(dbl)]),
+        "pcmd_lmax_ceiling": (C.c_int, [vp, i64, C.POINTER(dbl)]),
+        "pcmd_cap_loglikes": (C.c_int, [vp, i64, dbl, vp]),
+        "pcmd_nested_weights": (C.c_int, [vp, vp, i64, vp]),
+        "pcmd_remaining_evidence": (C.c_int, [vp, vp, i64, dbl, dbl, C.POINTER(dbl)]),
+        "pcmd_effective_sample_size": (C.c_int, [vp, i64, C.POINTER(dbl)]),
         "pcmd_entries": (C.c_int, [vp, C.POINTER(GridS), vp, dbl, vp, vp]),
         "pcmd_simulate": (C.c_int, [vp, C.POINTER(IsoS), C.POINTER(ObsS), vp, C.POINTER(DebugS), vp]),
         "pcmd_hess": (C.c_int, [vp, vp, i32, i64, C.POINTER(HessGridS), vp, vp, vp]),

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -671,6 +672,79 @@ int pcmd_timer_read(pcmd_ctx *c, int which, double *total_ms, int64_t *launches,
   *total_ms = ms;
   *launches = n;
   *units = u;
+  return PCMD_OK;
+}
+
+/* ---- Appendix A: the stochastic likelihood after a nested-sampling fit (host only) ---- */
+
+static bool any_nan(const double *x, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (std::isnan(x[i])) return true;
+  return false;
+}
+
+int pcmd_lmax_ceiling(const double *logl, int64_t n, double *lmax_out) {
+  if (!logl || !lmax_out || n < 1 || any_nan(logl, n)) return PCMD_E_INVAL;
+  std::vector<double> v(logl, logl + n);
+  const int64_t h = n / 2;
+  std::nth_element(v.begin(), v.begin() + h, v.end());
+  double med = v[h];
+  if (n % 2 == 0) {  // even count: the mean of the two middle values
+    const double lo = *std::max_element(v.begin(), v.begin() + h);
+    med = (lo + med) / 2.0;
+  }
+  *lmax_out = med;
+  return PCMD_OK;
+}
+
+int pcmd_cap_loglikes(const double *logl, int64_t n, double lmax, double *out) {
+  if (!logl || !out || n < 0 || std::isnan(lmax) || any_nan(logl, n)) return PCMD_E_INVAL;
+  for (int64_t i = 0; i < n; ++i) out[i] = logl[i] > lmax ? lmax : logl[i];
+  return PCMD_OK;
+}
+
+/* max and log-sum-exp of a_i = logl_i + log_dx_i; false when every a_i is -inf */
+static bool log_mass(const double *logl, const double *log_dx, int64_t n, double *amax, double *lse) {
+  double m = -INFINITY;
+  for (int64_t i = 0; i < n; ++i) m = std::fmax(m, logl[i] + log_dx[i]);
+  if (!(m > -INFINITY) || std::isinf(m)) return false;
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += std::exp(logl[i] + log_dx[i] - m);
+  *amax = m;
+  *lse = m + std::log(s);
+  return true;
+}
+
+int pcmd_nested_weights(const double *logl, const double *log_dx, int64_t n, double *w_out) {
+  if (!logl || !log_dx || !w_out || n < 1 || any_nan(logl, n) || any_nan(log_dx, n)) return PCMD_E_INVAL;
+  double m, lse;
+  if (!log_mass(logl, log_dx, n, &m, &lse)) return PCMD_E_INVAL;
+  double s = 0.0;
+  for (int64_t i = 0; i < n; ++i) s += (w_out[i] = std::exp(logl[i] + log_dx[i] - m));
+  for (int64_t i = 0; i < n; ++i) w_out[i] /= s;
+  return PCMD_OK;
+}
+
+int pcmd_remaining_evidence(const double *logl, const double *log_dx, int64_t n, double log_x_final,
+                            double logl_max_live, double *dlnz_out) {
+  if (!logl || !log_dx || !dlnz_out || n < 1 || any_nan(logl, n) || any_nan(log_dx, n) ||
+      std::isnan(log_x_final) || std::isnan(logl_max_live))
+    return PCMD_E_INVAL;
+  double m, lnz;
+  if (!log_mass(logl, log_dx, n, &m, &lnz)) return PCMD_E_INVAL;
+  const double r = logl_max_live + log_x_final;  // log of the evidence the live points could still add
+  const double hi = std::fmax(lnz, r), lo = std::fmin(lnz, r);
+  const double both = lo == -INFINITY ? hi : hi + std::log1p(std::exp(lo - hi));
+  *dlnz_out = both - lnz;
+  return PCMD_OK;
+}
+
+int pcmd_effective_sample_size(const double *w, int64_t n, double *ess_out) {
+  if (!w || !ess_out || n < 1 || any_nan(w, n)) return PCMD_E_INVAL;
+  double s2 = 0.0;
+  for (int64_t i = 0; i < n; ++i) s2 += w[i] * w[i];
+  if (!(s2 > 0.0)) return PCMD_E_INVAL;
+  *ess_out = 1.0 / s2;
   return PCMD_OK;
 }
 

@@ -10,6 +10,7 @@ study of the scatter against the image size (larger images average over more rar
 """
 from __future__ import annotations
 
+import ctypes as C
 import dataclasses
 
 import numpy as np
@@ -39,37 +40,60 @@ def resimulate_loglikes(ctx: _lib.Context, ev: Evaluator, model, obs, data_hess:
     return out
 
 
-def lmax_ceiling(resimulated: np.ndarray) -> float:
+def _f64(x) -> np.ndarray:
+    return np.ascontiguousarray(x, dtype=np.float64)
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != _lib.OK:
+        raise _lib.PcmdError(rc, f"{what} rejected its arguments (NaN, empty, or no finite mass)")
+
+
+def lmax_ceiling(resimulated) -> float:
     """The ceiling L_max: the median of the best-fit point's re-simulated log-likelihoods."""
-    return float(np.median(np.asarray(resimulated, dtype=np.float64)))
+    v = _f64(resimulated)
+    out = C.c_double(0.0)
+    _check(_lib.load().pcmd_lmax_ceiling(v.ctypes.data, v.size, C.byref(out)), "pcmd_lmax_ceiling")
+    return out.value
 
 
 def cap_loglikes(logl, lmax: float) -> np.ndarray:
     """Every log-likelihood above L_max is set to L_max (positive fluctuations carry no weight)."""
-    return np.minimum(np.asarray(logl, dtype=np.float64), float(lmax))
+    v = _f64(logl)
+    out = np.empty_like(v)
+    _check(_lib.load().pcmd_cap_loglikes(v.ctypes.data, v.size, float(lmax), out.ctypes.data), "pcmd_cap_loglikes")
+    return out
 
 
 def nested_weights(logl, log_dx) -> np.ndarray:
     """Normalised posterior weights w_i = L_i dX_i / sum_j L_j dX_j of nested-sampling dead points
     (log-likelihoods logl, log prior-volume widths log_dx)."""
-    a = np.asarray(logl, dtype=np.float64) + np.asarray(log_dx, dtype=np.float64)
-    a = a - a.max()
-    w = np.exp(a)
-    return w / w.sum()
+    a, d = _f64(logl), _f64(log_dx)
+    if a.shape != d.shape:
+        raise ValueError("logl and log_dx differ in shape")
+    w = np.empty_like(a)
+    _check(_lib.load().pcmd_nested_weights(a.ctypes.data, d.ctypes.data, a.size, w.ctypes.data), "pcmd_nested_weights")
+    return w
 
 
 def remaining_evidence(logl, log_dx, log_x_final: float, logl_max_live: float) -> float:
     """Delta ln Z: ln(Z + L_max,live X_final) - ln Z, the stopping criterion of nested sampling
     (evidence that could still lie in the remaining prior volume X_final)."""
-    a = np.asarray(logl, dtype=np.float64) + np.asarray(log_dx, dtype=np.float64)
-    lnz = np.logaddexp.reduce(a)
-    return float(np.logaddexp(lnz, logl_max_live + log_x_final) - lnz)
+    a, d = _f64(logl), _f64(log_dx)
+    if a.shape != d.shape:
+        raise ValueError("logl and log_dx differ in shape")
+    out = C.c_double(0.0)
+    _check(_lib.load().pcmd_remaining_evidence(a.ctypes.data, d.ctypes.data, a.size, float(log_x_final),
+                                               float(logl_max_live), C.byref(out)), "pcmd_remaining_evidence")
+    return out.value
 
 
 def effective_sample_size(w) -> float:
     """Kish's effective sample size of normalised weights, 1 / sum w^2."""
-    w = np.asarray(w, dtype=np.float64)
-    return float(1.0 / np.sum(w * w))
+    v = _f64(w)
+    out = C.c_double(0.0)
+    _check(_lib.load().pcmd_effective_sample_size(v.ctypes.data, v.size, C.byref(out)), "pcmd_effective_sample_size")
+    return out.value
 
 
 def scatter_vs_image_size(ctx: _lib.Context, grid, model, obs, nims, n_seeds: int, hess_bins: int = 100,
