@@ -121,8 +121,8 @@ int pcmd_iso_weights(const pcmd_model *model, const pcmd_isoset *set, double *w_
  * call with a long upper tail.  App. A re-simulates the best-fit point many times, takes the median
  * as a ceiling L_max, caps every dead point's log-likelihood at L_max and recomputes the posterior
  * weights and the remaining-evidence stopping criterion.  All arrays are host FP64 owned by the
- * caller; NaN inputs, empty arrays and all-(-inf) masses return PCMD_E_INVAL with no output
- * written (these calls take no context, so pcmd_last_error is not set).
+ * caller; NaN inputs, empty arrays, masses logl_i + log_dx_i that are all -inf or include +inf or
+ * -inf + inf return PCMD_E_INVAL with no output written (these calls take no context, so pcmd_last_error is not set).
  *
  * pcmd_lmax_ceiling: median of logl[n] (mean of the two middle values for even n).
  * pcmd_cap_loglikes: out[i] = min(logl[i], lmax); out may alias logl; n = 0 allowed.

@@ -703,10 +703,15 @@ int pcmd_cap_loglikes(const double *logl, int64_t n, double lmax, double *out) {
   return PCMD_OK;
 }
 
-/* max and log-sum-exp of a_i = logl_i + log_dx_i; false when every a_i is -inf */
+/* max and log-sum-exp of a_i = logl_i + log_dx_i; false when every a_i is -inf, or one is +inf or
+ * undefined (-inf + inf) */
 static bool log_mass(const double *logl, const double *log_dx, int64_t n, double *amax, double *lse) {
   double m = -INFINITY;
-  for (int64_t i = 0; i < n; ++i) m = std::fmax(m, logl[i] + log_dx[i]);
+  for (int64_t i = 0; i < n; ++i) {
+    const double a = logl[i] + log_dx[i];
+    if (std::isnan(a)) return false;
+    m = std::fmax(m, a);
+  }
   if (!(m > -INFINITY) || std::isinf(m)) return false;
   double s = 0.0;
   for (int64_t i = 0; i < n; ++i) s += std::exp(logl[i] + log_dx[i] - m);

@@ -64,6 +64,8 @@ def test_helpers_against_library_routines_and_edge_cases(built_lib):
     for bad in (lambda: st.lmax_ceiling([]), lambda: st.lmax_ceiling([1.0, np.nan]),
                 lambda: st.nested_weights([-np.inf, -np.inf], np.zeros(2)),
                 lambda: st.nested_weights([np.inf, 0.0], np.zeros(2)),
+                lambda: st.nested_weights([-np.inf, 0.0], [np.inf, 0.0]),
+                lambda: st.remaining_evidence([0.0, 1.0], [0.0, np.inf], 0.0, 0.0),
                 lambda: st.remaining_evidence([0.0], [0.0], np.nan, 0.0),
                 lambda: st.cap_loglikes([0.0], np.nan), lambda: st.effective_sample_size([0.0, 0.0])):
         with pytest.raises(_lib.PcmdError):
